@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for the symmetric split of the tomographic system.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the reconstruction library imports,
+calls or links this package; only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark use it.  It shares no code, table or helper
+with the GPU path: the two meet only through the seeded inputs of
+``paper_1902_10559_amd.inputs`` (which hold none of the method's arithmetic)
+and through arrays handed from here to the library under test.
+
+Contents, each written from the paper (Alikhanov et al., "About one method of
+parallelization of calculations during the reconstruction of a tomographic
+image", arXiv:1902.10559) or, where the paper only names a method, from the
+method's standard published definition:
+
+* ``geometry``  -- vertical-snake voxel numbering (Section 2, Fig. 1 reading),
+  symmetric ray ordering, Siddon intersection lengths, the system matrix A of
+  eq. (1) and the symmetry check of eq. (2).
+* ``split``     -- the fold of A and p into the two quarter-size systems (3)
+  and (4), the recombination of Theorem 1, eq. (5), and its inverse.
+* ``sart``      -- simultaneous SART (Andersen & Kak, the paper's ref. [001];
+  convergence for lambda in (0, 2) per ref. [003]) on the full system and on
+  the split pair, with relative-residual histories.
+
+Pins: every function here is checked by ``tests/test_oracle_*.py`` against
+values the paper prints (Example 1), closed forms, invariants and brute force.
+Parity unpinned: nothing in this package (the stochastic parts of the
+learned-initialiser workload live elsewhere).
+"""
