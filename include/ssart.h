@@ -1,0 +1,293 @@
+/*
+ * ssart.h -- symmetric-split SART for mirror-symmetric tomographic systems,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Alikhanov et al., arXiv:1902.10559, Section 2): when the scan
+ * positions are pairwise symmetric about the OZ axis and voxels are numbered
+ * by the vertical-snake rule, the system matrix A (M x N) of eq. (1), A f = p,
+ * satisfies eq. (2), w[i,j] = w[M-i+1, N-j+1].  Then A folds into two
+ * independent (M/2) x (N/2) systems (3) and (4), A(1) f(1) = p(1) and
+ * A(2) f(2) = p(2), with
+ *     w1[i,j] = w[i,j] - w[M-i+1,j],   w2[i,j] = w[i,j] + w[M-i+1,j],
+ *     p1[i]   = p[i]   - p[M-i+1],     p2[i]   = p[i]   + p[M-i+1],
+ * and the solution of (1) is recombined from f(1), f(2) by Theorem 1, eq. (5):
+ *     f[j] = (f2[j] + f1[j]) / 2,   f[N-j+1] = (f2[j] - f1[j]) / 2.
+ * The paper solves the halves with SART (its refs. [001], [003]); this library
+ * runs simultaneous SART on both halves at once on one GPU.
+ *
+ * Index convention at this interface: 0-based.  Ray i pairs with ray M-1-i,
+ * voxel j with voxel N-1-j; m = M/2, n = N/2.
+ *
+ * Conventions for every call:
+ *   - Return value: SS_OK (0) on success; > 0 is a warning and the results
+ *     are valid; < 0 is an error, and then no output has been written (for
+ *     the asynchronous device calls: no work has been enqueued).  The text of
+ *     the last error on the calling thread is returned by ss_last_error().
+ *   - "device" pointers are caller-owned device memory of the current HIP
+ *     device; the library never frees caller memory, and device calls never
+ *     allocate device memory (scratch comes from caller workspaces).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device calls only enqueue work on it, except where a call says that it
+ *     synchronises.
+ *   - Calls are reentrant; the only shared state is the thread-local error
+ *     text and an internal cache of instantiated HIP graphs (mutex-guarded).
+ */
+#ifndef SSART_H
+#define SSART_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ss_status;
+enum {
+  SS_OK = 0,
+  SS_NOT_CONVERGED = 1,   /* warning: a solve reached max_iter above tol    */
+  SS_E_ARG = -1,          /* NULL pointer, bad size, bad option             */
+  SS_E_ODD = -2,          /* M, N or nx odd: the fold needs even sizes      */
+  SS_E_ASYM = -3,         /* A violates eq. (2) (bitwise, pattern included) */
+  SS_E_SHAPE = -4,        /* arrays inconsistent (unsorted, out of range,
+                             CSR and CSC holding different entries)         */
+  SS_E_NONFINITE = -5,    /* NaN or Inf in A or p                           */
+  SS_E_NOMEM = -6,        /* host allocation failed                         */
+  SS_E_HIP = -7,          /* a HIP runtime call failed                      */
+  SS_E_WORKSPACE = -8     /* workspace too small                            */
+};
+
+/* storage type of matrix values */
+enum { SS_F32 = 0, SS_BF16 = 1, SS_F16 = 2 };
+
+const char* ss_last_error(void);
+const char* ss_version(void);
+
+/* ------------------------------------------------------------------------
+ * Geometry and the system matrix A of eq. (1)  (host; setup, not timed)
+ * ---------------------------------------------------------------------- */
+
+/* A 2D slice of nx x nz square voxels of side `pitch` (mm), centred on OZ in
+ * x, bottom face at z = 0.  Voxel (column c, row r), c = 0 at the most
+ * negative x and r = 0 at the top, has the vertical-snake index
+ *     j = c*nz + (c even ? r : nz-1-r),
+ * so that its mirror (nx-1-c, r) has index N-1-j (needs nx even).  This is
+ * the paper's numbering rule of Section 2 (Fig. 1). */
+typedef struct {
+  int32_t nx, nz;
+  double pitch;
+} ss_grid;
+
+/* K point sources (src_x ascending, src_x[K-1-k] == -src_x[k] bitwise,
+ * src_z[K-1-k] == src_z[k]) and B detector bins at height det_z (bin_x
+ * ascending, bin_x[B-1-b] == -bin_x[b] bitwise): positions pairwise
+ * symmetric about OZ as Section 2 requires.  Ray i = k*B + b runs from source
+ * k to the centre of bin b, so ray M-1-i is the mirror of ray i. */
+typedef struct {
+  int32_t K;
+  const double* src_x;
+  const double* src_z;
+  int32_t B;
+  const double* bin_x;
+  double det_z;
+} ss_geometry;
+
+/* Host CSR + CSC copy of A (M = K*B rows, N = nx*nz columns); columns ascend
+ * within a row and rows within a column.  Arrays are owned by the library
+ * and released by ss_matrix_free. */
+typedef struct {
+  int64_t M, N, nnz;
+  int64_t* row_ptr;   /* M+1 */
+  int32_t* col_idx;   /* nnz */
+  float* val;         /* nnz */
+  int64_t* col_ptr;   /* N+1 */
+  int32_t* row_idx;   /* nnz */
+  float* val_t;       /* nnz */
+} ss_matrix;
+
+/* Builds A for the scan: w[i,j] = length (mm) of ray i inside voxel j by
+ * Siddon's method (FP64 plane-crossing parameters, segments <= 1e-9 mm
+ * dropped), rounded to FP32.  Mirror-exact inputs give an A that satisfies
+ * eq. (2) bitwise.  `nthreads` <= 0 uses all hardware threads.
+ * Errors: SS_E_ARG (NULL, non-positive sizes, pitch <= 0), SS_E_ODD (nx, K or
+ * B odd), SS_E_ASYM (sources or bins not mirror-exact), SS_E_NOMEM. */
+ss_status ss_build_system(const ss_grid* grid, const ss_geometry* geom,
+                          int32_t nthreads, ss_matrix* out);
+void ss_matrix_free(ss_matrix* A);
+
+/* snake[r*nx + c] = vertical-snake index of voxel (c, r), for all nx*nz
+ * voxels (host array of nx*nz entries, caller-owned).  Section 2, Fig. 1. */
+ss_status ss_snake_order(const ss_grid* grid, int64_t* snake);
+
+/* ------------------------------------------------------------------------
+ * Device-side A, the fold into systems (3)-(4), and the solver's system
+ * ---------------------------------------------------------------------- */
+
+/* A in device memory (caller-owned), CSR and CSC as in ss_matrix. */
+typedef struct {
+  int64_t M, N, nnz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const float* val;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const float* val_t;
+} ss_matrix_dev;
+
+/* One linear system as the SART solver consumes it, all arrays device memory
+ * owned by the caller.
+ *   nvals = 2: the folded pair (A(1), A(2)) of systems (3) and (4), stored on
+ *              ONE shared sparsity pattern (the union of the positions of
+ *              w[i,j] and w[M-1-i,j]; A(1) keeps its cancelled entries as
+ *              +0.0).  Per entry the two values are interleaved: val[2k] is
+ *              A(1)'s, val[2k+1] is A(2)'s; likewise p[2i] = p1[i],
+ *              p[2i+1] = p2[i], and images are interleaved (f1[j], f2[j]).
+ *   nvals = 1: a single system (the unsplit A, the baseline).
+ * m x n: system size; nnz: stored pattern entries.
+ * wdtype: SS_F32, SS_BF16 or SS_F16 storage of val/val_t (FP32 arithmetic).
+ * row_ptr (m+1), col_idx (nnz), val (nvals*nnz): CSR, columns ascending.
+ * col_ptr (n+1), row_idx (nnz), val_t (nvals*nnz): CSC of the same entries.
+ * p (nvals*m): right-hand side.
+ * inv_row (m), inv_col (n): FP32 reciprocals of the FP64 row and column sums
+ *   of A (which equal those of A(2)), 0 where a sum is 0; SART normalises
+ *   both halves with them. */
+typedef struct {
+  int64_t m, n, nnz;
+  int32_t nvals;
+  int32_t wdtype;
+  int64_t* row_ptr;
+  int32_t* col_idx;
+  void* val;
+  int64_t* col_ptr;
+  int32_t* row_idx;
+  void* val_t;
+  float* p;
+  float* inv_row;
+  float* inv_col;
+} ss_system;
+
+/* Bytes of workspace ss_fold_size needs for an M x N matrix. */
+ss_status ss_fold_workspace_bytes(int64_t M, int64_t N, size_t* bytes);
+
+/* Validates A (and p, if not NULL) and returns the size of the shared pattern
+ * of A(1)/A(2) in *nnz_half.  Checks: M, N even (SS_E_ODD); rows and columns
+ * sorted and in range, and CSR and CSC holding the same entries (SS_E_SHAPE);
+ * eq. (2) bitwise for every stored entry of both copies (SS_E_ASYM); finite
+ * values (SS_E_NONFINITE).  SYNCHRONISES the stream once. */
+ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* workspace,
+                       size_t workspace_bytes, int64_t* nnz_half,
+                       void* stream);
+
+/* The fold of Section 2: fills `out` (nvals = 2, m = M/2, n = N/2, nnz =
+ * *nnz_half from ss_fold_size, wdtype chosen by the caller; every array
+ * allocated by the caller with the sizes listed at ss_system).  Values are
+ * one correctly rounded FP32 subtraction/addition per entry, then rounded to
+ * nearest-even for BF16/FP16 storage; p1/p2 likewise in FP32; inv_row/inv_col
+ * from FP64 sums of A's FP32 entries.  A must have passed ss_fold_size.
+ * Asynchronous. */
+ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out,
+                  void* stream);
+
+/* The unsplit baseline: fills a single system (nvals = 1, m = M, n = N) for
+ * A itself.  The caller sets out->m, n, nnz, nvals = 1, wdtype and every
+ * pointer; row_ptr/col_idx/col_ptr/row_idx may alias A's arrays, and val/
+ * val_t may alias A's when wdtype = SS_F32 (otherwise they receive the
+ * rounded values).  Writes p (copy unless aliased), inv_row, inv_col.
+ * Asynchronous. */
+ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
+                     void* stream);
+
+/* ------------------------------------------------------------------------
+ * SART on one or many systems (the paper's solver, refs. [001], [003])
+ * ---------------------------------------------------------------------- */
+
+/* Simultaneous SART, every ray in every iteration:
+ *     f <- f + lambda * V^-1 A^T W^-1 (p - A f)
+ * applied to every half of every system (for nvals = 2 this is SART on (3)
+ * and (4) with the sums of A; recombined by eq. (5) it is SART on (1)).
+ * Options:
+ *   lambda       relaxation, 0 < lambda < 2 (ref. [003])
+ *   max_iter     update cap (>= 0)
+ *   tol          stop at the first k with rel_res(f^k) <= tol (<= 0: never)
+ *   check_every  iterations between host checks for early exit when tol > 0
+ *   use_graph    1: replay the iterations as an instantiated HIP graph
+ *   rows_per_wave  forward projection rows per 64-lane wavefront: 1,2,4,8
+ *                  (0 = choose from the row-length statistics)
+ *   cols_per_wave  back projection columns per wavefront: 1,2,4,8,16 (0 =
+ *                  choose)
+ *   xcd_remap    1: give each of the 8 XCDs a contiguous range of rows or
+ *                columns (the hardware deals workgroups round-robin)
+ * rel_res(f^k) = ||p - A f^k|| / ||p||, from the halves as
+ *   sqrt((||r1||^2 + ||r2||^2) / (||p1||^2 + ||p2||^2)), FP64. */
+typedef struct {
+  float lambda;
+  int32_t max_iter;
+  double tol;
+  int32_t check_every;
+  int32_t use_graph;
+  int32_t rows_per_wave;
+  int32_t cols_per_wave;
+  int32_t xcd_remap;
+} ss_sart_opts;
+
+/* Workspace bytes for solving `nsys` systems together with these options. */
+ss_status ss_sart_workspace_bytes(const ss_system* sys, int32_t nsys,
+                                  const ss_sart_opts* opts, size_t* bytes);
+
+/* Solves nsys independent systems in the same launches.
+ *   f[s]        device, nvals*n floats: start image on entry (interleaved
+ *               halves; zero for f^0 = 0, or ss_image_fold of a start),
+ *               final iterate on return.
+ *   res_hist[s] device, max_iter+1 doubles: res_hist[s][k] = rel_res(f^k)
+ *               for k = 0 .. iters[s]; entries after that are not written.
+ *   iters       host, nsys ints, or NULL: updates applied per system.
+ * With tol <= 0 and iters == NULL the call is asynchronous; otherwise it
+ * synchronises the stream (every check_every iterations when tol > 0, and
+ * once at the end to read iters).  Returns SS_NOT_CONVERGED if tol > 0 and a
+ * system ended at max_iter above tol. */
+ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* const* f,
+                        double* const* res_hist, const ss_sart_opts* opts,
+                        int32_t* iters, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* Times the two solver kernels over `reps` launches each on `stream` with
+ * HIP events and returns their mean durations in milliseconds: the forward
+ * projection + residual kernel and the back projection + update kernel.
+ * The images f are used as scratch (their contents change). Synchronises. */
+ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys,
+                               float* const* f, const ss_sart_opts* opts,
+                               int32_t reps, double* fp_ms, double* bp_ms,
+                               void* workspace, size_t workspace_bytes,
+                               void* stream);
+
+/* Picks rows_per_wave, cols_per_wave and xcd_remap for these systems by
+ * timing every candidate (ss_sart_time_kernels) and writes them into
+ * *opts.  Results are cached per (nvals, wdtype, shape statistics).
+ * The images f are used as scratch.  Synchronises. */
+ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f,
+                           ss_sart_opts* opts, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Images
+ * ---------------------------------------------------------------------- */
+
+/* Theorem 1, eq. (5): f (N = 2n floats) from the interleaved halves f12 (n
+ * pairs): f[j] = (f2[j] + f1[j]) / 2, f[N-1-j] = (f2[j] - f1[j]) / 2, FP32.
+ * Asynchronous. */
+ss_status ss_recombine(const float* f12, int64_t n, float* f, void* stream);
+
+/* Inverse of eq. (5) (the transform in the proof of Theorem 1): f12 from f,
+ * f1[j] = f[j] - f[N-1-j], f2[j] = f[j] + f[N-1-j], FP32.  Asynchronous. */
+ss_status ss_image_fold(const float* f, int64_t N, float* f12, void* stream);
+
+/* Forward projection q = A f of eq. (1) (device, FP32 accumulation): q has M
+ * entries, f has N.  Asynchronous. */
+ss_status ss_project(const ss_matrix_dev* A, const float* f, float* q,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSART_H */

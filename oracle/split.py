@@ -173,3 +173,36 @@ def image_fold(f: np.ndarray, precision: str = "fp64"):
     if precision == "fp32":
         return f1.astype(np.float32), f2.astype(np.float32)
     return f1, f2
+
+
+def round_storage(v32: np.ndarray, dtype: str) -> np.ndarray:
+    """FP32 values rounded to nearest-even 16-bit storage, returned as FP64
+    numbers (dtype 'bf16' or 'f16').
+
+    bf16 keeps FP32's exponent and 8 significand bits: the two bf16 numbers
+    bracketing x are x's FP32 bits truncated to the top 16 (toward zero) and
+    the next bf16 away from zero; the nearer wins, and on a tie the one whose
+    last kept bit is 0.  f16 uses numpy's IEEE binary16 conversion, which
+    rounds to nearest-even."""
+    v32 = np.asarray(v32, dtype=np.float32)
+    if dtype == "f16":
+        return v32.astype(np.float16).astype(np.float64)
+    assert dtype == "bf16"
+    bits = v32.view(np.uint32).astype(np.uint64)
+    lo_bits = (bits & 0xFFFF0000).astype(np.uint32)
+    hi_bits = (lo_bits.astype(np.uint64) + 0x10000).astype(np.uint32)
+    lo = lo_bits.view(np.float32).astype(np.float64)
+    hi = hi_bits.view(np.float32).astype(np.float64)
+    x = v32.astype(np.float64)
+    dlo, dhi = np.abs(x - lo), np.abs(hi - x)
+    lo_even = (lo_bits & 0x10000) == 0
+    pick_lo = (dlo < dhi) | ((dlo == dhi) & lo_even)
+    return np.where(pick_lo, lo, hi)
+
+
+def storage_bits(v32: np.ndarray, dtype: str) -> np.ndarray:
+    """uint16 bit patterns of ``round_storage``."""
+    r = round_storage(v32, dtype)
+    if dtype == "f16":
+        return r.astype(np.float16).view(np.uint16)
+    return (r.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)

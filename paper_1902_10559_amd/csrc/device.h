@@ -1,0 +1,151 @@
+// Device-side helpers for gfx950 (CDNA4, 64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ssart.h"
+
+namespace ss {
+
+constexpr int kWave = 64;
+
+__device__ inline int lane_id() { return static_cast<int>(threadIdx.x) & (kWave - 1); }
+__device__ inline int wave_id() { return static_cast<int>(threadIdx.x) / kWave; }
+__device__ inline uint64_t lanemask_lt() { return (uint64_t{1} << lane_id()) - 1; }
+
+// Sum over groups of G adjacent lanes (G a power of two <= 64); every lane of
+// a group ends with the group's sum.  Fixed butterfly order: deterministic.
+template <int G>
+__device__ inline float group_sum(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <int G>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Block-wide FP64 sum in a fixed order (wave butterflies, then waves in
+// index order); the result is valid in thread 0.  `red` holds one double
+// per wave.
+template <int WPB>
+__device__ inline double block_sum(double v, double* red) {
+  v = group_sum<kWave>(v);
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < WPB; ++w) t += red[w];
+  }
+  return t;
+}
+
+// Round to nearest-even FP32 -> BF16 bits (NaN kept quiet).
+__device__ inline uint32_t bf16_bits_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ inline uint32_t f16_bits_rne(float x) {
+  return static_cast<uint32_t>(__half_as_ushort(__float2half_rn(x)));
+}
+
+// Round a value pair to storage type WT and store it at element k.
+template <int WT>
+__device__ inline void store_pair(void* base, int64_t k, float a, float b) {
+  if constexpr (WT == SS_F32) {
+    reinterpret_cast<float2*>(base)[k] = make_float2(a, b);
+  } else if constexpr (WT == SS_BF16) {
+    reinterpret_cast<uint32_t*>(base)[k] = bf16_bits_rne(a) | (bf16_bits_rne(b) << 16);
+  } else {
+    reinterpret_cast<uint32_t*>(base)[k] = f16_bits_rne(a) | (f16_bits_rne(b) << 16);
+  }
+}
+
+template <int WT>
+__device__ inline void store_one(void* base, int64_t k, float a) {
+  if constexpr (WT == SS_F32) {
+    reinterpret_cast<float*>(base)[k] = a;
+  } else if constexpr (WT == SS_BF16) {
+    reinterpret_cast<uint16_t*>(base)[k] = static_cast<uint16_t>(bf16_bits_rne(a));
+  } else {
+    reinterpret_cast<uint16_t*>(base)[k] = static_cast<uint16_t>(f16_bits_rne(a));
+  }
+}
+
+// NV FP32 numbers: the two halves of the folded pair (NV = 2) or one system.
+template <int NV>
+struct Vec {
+  float v[NV];
+};
+
+template <int NV>
+__device__ inline Vec<NV> load_vec(const float* p, int64_t i) {
+  Vec<NV> r;
+  if constexpr (NV == 2) {
+    const float2 t = reinterpret_cast<const float2*>(p)[i];
+    r.v[0] = t.x;
+    r.v[1] = t.y;
+  } else {
+    r.v[0] = p[i];
+  }
+  return r;
+}
+
+template <int NV>
+__device__ inline void store_vec(float* p, int64_t i, const Vec<NV>& x) {
+  if constexpr (NV == 2) {
+    reinterpret_cast<float2*>(p)[i] = make_float2(x.v[0], x.v[1]);
+  } else {
+    p[i] = x.v[0];
+  }
+}
+
+// Matrix values of entry k widened to FP32.
+template <int NV, int WT>
+__device__ inline Vec<NV> load_vals(const void* base, int64_t k) {
+  Vec<NV> r;
+  if constexpr (NV == 2) {
+    if constexpr (WT == SS_F32) {
+      const float2 t = reinterpret_cast<const float2*>(base)[k];
+      r.v[0] = t.x;
+      r.v[1] = t.y;
+    } else if constexpr (WT == SS_BF16) {
+      const uint32_t u = reinterpret_cast<const uint32_t*>(base)[k];
+      r.v[0] = __uint_as_float(u << 16);
+      r.v[1] = __uint_as_float(u & 0xffff0000u);
+    } else {
+      const __half2 h = reinterpret_cast<const __half2*>(base)[k];
+      const float2 t = __half22float2(h);
+      r.v[0] = t.x;
+      r.v[1] = t.y;
+    }
+  } else {
+    if constexpr (WT == SS_F32) {
+      r.v[0] = reinterpret_cast<const float*>(base)[k];
+    } else if constexpr (WT == SS_BF16) {
+      r.v[0] = __uint_as_float(static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(base)[k]) << 16);
+    } else {
+      r.v[0] = __half2float(reinterpret_cast<const __half*>(base)[k]);
+    }
+  }
+  return r;
+}
+
+}  // namespace ss
+
+#define SS_HIP_TRY(expr)                                                            \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ss::fail(SS_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)

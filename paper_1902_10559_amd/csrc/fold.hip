@@ -1,0 +1,482 @@
+// The fold of Section 2: A -> (A(1), A(2)) on one shared pattern, p -> (p1,
+// p2), the SART normalisation sums, and the checks of eq. (2).
+//
+// Output row i (< m) of the pair is the union of two sorted index lists:
+//   X = columns < n of row i of A,   Y = columns < n of row M-1-i of A,
+// with v1 = a - b, v2 = a + b (a from X, b from Y, an absent term is +0.0).
+// Output column j (< n) of the CSC copy is built column-locally from column j
+// of A's CSC: X = its rows < m, Y = its rows >= m mapped to M-1-row (which
+// reverses them into ascending order).  Both copies hold the same entries.
+//
+// One 64-lane wavefront merges one list pair without shared memory.  With
+// dX[k] = 1 when X[k] is also in Y (dY likewise), and exclusive prefix counts
+// of those flags taken with ballots:
+//   union position of X[k]       = k + lower_bound(Y, X[k]) - prefix_dX[k]
+//   union position of Y[l] not in X = lower_bound(X, Y[l]) + l - prefix_dY[l]
+// (the union elements below a value are those of X and of Y below it, minus
+// the common ones counted twice).  The union size is |X| + |Y| - #common.
+
+#include "device.h"
+#include "internal.h"
+
+namespace ss {
+namespace {
+
+constexpr int kFoldWaves = 4;  // wavefronts per block; one list pair each
+
+enum : uint32_t { kFlagAsym = 1u, kFlagShape = 2u, kFlagNonfinite = 4u };
+
+struct FoldCheck {
+  uint32_t flags;
+  uint32_t pad;
+  unsigned long long sum_csr, sum_csc;   // order-free checksums of entries
+  unsigned long long cnt_csr, cnt_csc;   // union sizes from the two copies
+};
+
+// A sorted list of (index, value).  FLIP = true reads a stored ascending list
+// backwards and maps each index t to base - t.
+template <bool FLIP>
+struct Seq {
+  const int32_t* idx;
+  const float* val;
+  int64_t len;
+  int32_t base;
+  __device__ int32_t key(int64_t l) const {
+    if constexpr (FLIP) return base - idx[len - 1 - l];
+    else return idx[l];
+  }
+  __device__ float value(int64_t l) const {
+    if constexpr (FLIP) return val[len - 1 - l];
+    else return val[l];
+  }
+  // number of elements < k
+  __device__ int64_t lower_bound(int32_t k) const {
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (key(mid) < k) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  }
+};
+
+__device__ inline int64_t lower_bound_idx(const int32_t* idx, int64_t len, int32_t k) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (idx[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Merges X and Y as described at the top of the file.  FILL writes every
+// union entry at out_base + position: its index and the pair (a - b, a + b)
+// in storage type WT.  Returns the union size (in every lane) and adds each
+// entry's FP64 a + b to the lane's `sum`.
+template <bool FILL, int WT, bool FLIPY>
+__device__ int64_t wave_merge(const Seq<false>& X, const Seq<FLIPY>& Y,
+                              int64_t out_base, int32_t* out_idx, void* out_val,
+                              double& sum) {
+  const int lane = lane_id();
+  int64_t common = 0;
+  for (int64_t base = 0; base < X.len; base += kWave) {
+    const int64_t k = base + lane;
+    const bool valid = k < X.len;
+    int32_t x = 0;
+    int64_t r = 0;
+    bool dup = false;
+    if (valid) {
+      x = X.key(k);
+      r = Y.lower_bound(x);
+      dup = r < Y.len && Y.key(r) == x;
+    }
+    const uint64_t mask = __ballot(dup);
+    if (FILL && valid) {
+      const int64_t before = common + __popcll(mask & lanemask_lt());
+      const int64_t pos = k + r - before;
+      const float a = X.value(k);
+      const float b = dup ? Y.value(r) : 0.0f;
+      out_idx[out_base + pos] = x;
+      store_pair<WT>(out_val, out_base + pos, a - b, a + b);
+      sum += static_cast<double>(a) + static_cast<double>(b);
+    }
+    common += __popcll(mask);
+  }
+  int64_t seen = 0;
+  for (int64_t base = 0; base < Y.len; base += kWave) {
+    const int64_t l = base + lane;
+    const bool valid = l < Y.len;
+    int32_t y = 0;
+    int64_t s = 0;
+    bool dup = false;
+    if (valid) {
+      y = Y.key(l);
+      s = X.lower_bound(y);
+      dup = s < X.len && X.key(s) == y;
+    }
+    const uint64_t mask = __ballot(dup);
+    if (FILL && valid && !dup) {
+      const int64_t before = seen + __popcll(mask & lanemask_lt());
+      const int64_t pos = s + l - before;
+      const float b = Y.value(l);
+      out_idx[out_base + pos] = y;
+      store_pair<WT>(out_val, out_base + pos, 0.0f - b, 0.0f + b);
+      sum += static_cast<double>(b);
+    }
+    seen += __popcll(mask);
+  }
+  return X.len + Y.len - common;
+}
+
+// The two lists of output row i (CSR side).
+struct RowLists {
+  Seq<false> X;
+  Seq<false> Y;
+};
+
+__device__ inline RowLists row_lists(const ss_matrix_dev& A, int64_t i) {
+  const int64_t n = A.N / 2;
+  const int64_t rs = A.row_ptr[i], re = A.row_ptr[i + 1];
+  const int64_t i2 = A.M - 1 - i;
+  const int64_t ys = A.row_ptr[i2], ye = A.row_ptr[i2 + 1];
+  RowLists L;
+  L.X = {A.col_idx + rs, A.val + rs, lower_bound_idx(A.col_idx + rs, re - rs, static_cast<int32_t>(n)), 0};
+  L.Y = {A.col_idx + ys, A.val + ys, lower_bound_idx(A.col_idx + ys, ye - ys, static_cast<int32_t>(n)), 0};
+  return L;
+}
+
+// The two lists of output column j (CSC side).
+struct ColLists {
+  Seq<false> X;
+  Seq<true> Y;
+};
+
+__device__ inline ColLists col_lists(const ss_matrix_dev& A, int64_t j) {
+  const int64_t m = A.M / 2;
+  const int64_t cs = A.col_ptr[j], ce = A.col_ptr[j + 1];
+  const int64_t split = lower_bound_idx(A.row_idx + cs, ce - cs, static_cast<int32_t>(m));
+  ColLists L;
+  L.X = {A.row_idx + cs, A.val_t + cs, split, 0};
+  L.Y = {A.row_idx + cs + split, A.val_t + cs + split, ce - cs - split, static_cast<int32_t>(A.M - 1)};
+  return L;
+}
+
+__device__ inline unsigned long long mix64(unsigned long long z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ inline unsigned long long entry_hash(int64_t i, int64_t j, float v) {
+  return mix64((static_cast<unsigned long long>(i) << 32) ^ static_cast<unsigned long long>(j) ^
+               mix64(__float_as_uint(v)));
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__global__ void k_zero_check(FoldCheck* c) {
+  if (threadIdx.x == 0) {
+    c->flags = 0;
+    c->sum_csr = c->sum_csc = 0;
+    c->cnt_csr = c->cnt_csc = 0;
+  }
+}
+
+// One wavefront per pair of mirrored lines (rows i and M-1-i of the CSR, or
+// columns j and N-1-j of the CSC): checks eq. (2), order, range and
+// finiteness, accumulates the entry checksum and the union size.
+template <bool COLS>
+__global__ __launch_bounds__(kWave* kFoldWaves) void k_check_pairs(ss_matrix_dev A, const float* p,
+                                                                   FoldCheck* chk) {
+  const int64_t lines = COLS ? A.N : A.M;
+  const int64_t other = COLS ? A.M : A.N;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
+  if (t >= lines / 2) return;
+  const int64_t* ptr = COLS ? A.col_ptr : A.row_ptr;
+  const int32_t* idx = COLS ? A.row_idx : A.col_idx;
+  const float* val = COLS ? A.val_t : A.val;
+  const int lane = lane_id();
+  uint32_t flags = 0;
+  const int64_t t2 = lines - 1 - t;
+  const int64_t as = ptr[t], ae = ptr[t + 1], bs = ptr[t2], be = ptr[t2 + 1];
+  if (t == 0 && lane == 0 && (ptr[0] != 0 || ptr[lines] != A.nnz)) flags |= kFlagShape;
+  const bool ranges_ok = as >= 0 && as <= ae && ae <= A.nnz && bs >= 0 && bs <= be && be <= A.nnz;
+  unsigned long long h = 0;
+  if (!ranges_ok) {
+    flags |= kFlagShape;
+  } else {
+    if (ae - as != be - bs) flags |= kFlagAsym;
+    const int64_t la = ae - as;
+    for (int64_t k = lane; k < la; k += kWave) {
+      const int32_t ca = idx[as + k];
+      const float va = val[as + k];
+      if (ca < 0 || ca >= other) flags |= kFlagShape;
+      if (k + 1 < la && idx[as + k + 1] <= ca) flags |= kFlagShape;
+      if (!isfinite(va)) flags |= kFlagNonfinite;
+      h += COLS ? entry_hash(ca, t, va) : entry_hash(t, ca, va);
+      if (ae - as == be - bs) {
+        const int32_t cb = idx[bs + la - 1 - k];
+        const float vb = val[bs + la - 1 - k];
+        if (cb != other - 1 - ca || __float_as_uint(vb) != __float_as_uint(va)) flags |= kFlagAsym;
+      }
+    }
+    for (int64_t k = lane; k < be - bs; k += kWave) {
+      const int32_t cb = idx[bs + k];
+      const float vb = val[bs + k];
+      if (cb < 0 || cb >= other) flags |= kFlagShape;
+      if (k + 1 < be - bs && idx[bs + k + 1] <= cb) flags |= kFlagShape;
+      if (!isfinite(vb)) flags |= kFlagNonfinite;
+      h += COLS ? entry_hash(cb, t2, vb) : entry_hash(t2, cb, vb);
+    }
+  }
+  if (!COLS && p != nullptr && lane == 0 && (!isfinite(p[t]) || !isfinite(p[t2]))) flags |= kFlagNonfinite;
+  // union size of the output line, only once the lines are known to be sane
+  const bool sane = __ballot(flags & kFlagShape) == 0;
+  int64_t cnt = 0;
+  if (sane) {
+    double unused = 0.0;
+    if constexpr (COLS) {
+      const ColLists L = col_lists(A, t);
+      cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
+    } else {
+      const RowLists L = row_lists(A, t);
+      cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
+    }
+  }
+  h = wave_sum_u64(h);
+  unsigned f = flags;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, kWave);
+  if (lane == 0) {
+    if (f) atomicOr(&chk->flags, f);
+    atomicAdd(COLS ? &chk->sum_csc : &chk->sum_csr, h);
+    atomicAdd(COLS ? &chk->cnt_csc : &chk->cnt_csr, static_cast<unsigned long long>(cnt));
+  }
+}
+
+// Union size of every output line into ptr[t + 1]; ptr[0] = 0.
+template <bool COLS>
+__global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(ss_matrix_dev A, int64_t* ptr) {
+  const int64_t lines = COLS ? A.N / 2 : A.M / 2;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
+  if (t >= lines) return;
+  double unused = 0.0;
+  int64_t cnt;
+  if constexpr (COLS) {
+    const ColLists L = col_lists(A, t);
+    cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
+  } else {
+    const RowLists L = row_lists(A, t);
+    cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
+  }
+  if (lane_id() == 0) {
+    ptr[t + 1] = cnt;
+    if (t == 0) ptr[0] = 0;
+  }
+}
+
+// In-place inclusive scan of ptr[1..len]: ptr becomes the offsets array.
+// One block; thread t scans a contiguous chunk, chunk totals are scanned in
+// shared memory.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_scan(int64_t* ptr, int64_t len) {
+  __shared__ int64_t tot[kScanThreads];
+  const int64_t chunk = (len + kScanThreads - 1) / kScanThreads;
+  const int64_t s = 1 + static_cast<int64_t>(threadIdx.x) * chunk;
+  const int64_t e = s + chunk < len + 1 ? s + chunk : len + 1;
+  int64_t acc = 0;
+  for (int64_t i = s; i < e; ++i) acc += ptr[i];
+  tot[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const int64_t v = threadIdx.x >= static_cast<unsigned>(o) ? tot[threadIdx.x - o] : 0;
+    __syncthreads();
+    tot[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = threadIdx.x > 0 ? tot[threadIdx.x - 1] : 0;
+  for (int64_t i = s; i < e; ++i) {
+    run += ptr[i];
+    ptr[i] = run;
+  }
+}
+
+__device__ inline float recip_or_zero(double s) {
+  return s != 0.0 ? static_cast<float>(1.0 / s) : 0.0f;
+}
+
+// Fills output rows (CSR side) or columns (CSC side) at the scanned offsets,
+// with the FP32 reciprocal of the FP64 line sum of A (rows: W_i = sum over
+// row i of A = sum of a + b over the union; columns: V_j likewise), and for
+// rows also the folded p.
+template <bool COLS, int WT>
+__global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_fill(ss_matrix_dev A, const float* p,
+                                                                 ss_system out) {
+  const int64_t lines = COLS ? out.n : out.m;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
+  if (t >= lines) return;
+  double sum = 0.0;
+  if constexpr (COLS) {
+    const ColLists L = col_lists(A, t);
+    wave_merge<true, WT>(L.X, L.Y, out.col_ptr[t], out.row_idx, out.val_t, sum);
+  } else {
+    const RowLists L = row_lists(A, t);
+    wave_merge<true, WT>(L.X, L.Y, out.row_ptr[t], out.col_idx, out.val, sum);
+  }
+  sum = group_sum<kWave>(sum);
+  if (lane_id() == 0) {
+    if constexpr (COLS) {
+      out.inv_col[t] = recip_or_zero(sum);
+    } else {
+      out.inv_row[t] = recip_or_zero(sum);
+      const float a = p[t], b = p[A.M - 1 - t];
+      reinterpret_cast<float2*>(out.p)[t] = make_float2(a - b, a + b);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- unsplit
+template <bool COLS>
+__global__ __launch_bounds__(kWave* kFoldWaves) void k_line_recip(const int64_t* ptr, const float* val,
+                                                                  int64_t lines, float* inv) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
+  if (t >= lines) return;
+  double s = 0.0;
+  for (int64_t k = ptr[t] + lane_id(); k < ptr[t + 1]; k += kWave) s += static_cast<double>(val[k]);
+  s = group_sum<kWave>(s);
+  if (lane_id() == 0) inv[t] = recip_or_zero(s);
+}
+
+template <int WT>
+__global__ void k_convert(const float* src, int64_t count, void* dst) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < count) store_one<WT>(dst, k, src[k]);
+}
+
+__global__ void k_copy_f32(const float* src, int64_t count, float* dst) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < count) dst[k] = src[k];
+}
+
+inline unsigned blocks_for(int64_t lines) {
+  return static_cast<unsigned>((lines + kFoldWaves - 1) / kFoldWaves);
+}
+
+ss_status check_dev_matrix(const ss_matrix_dev* A, const char* fn) {
+  if (!A || !A->row_ptr || !A->col_idx || !A->val || !A->col_ptr || !A->row_idx || !A->val_t)
+    return fail(SS_E_ARG, "%s: NULL matrix array", fn);
+  if (A->M <= 0 || A->N <= 0 || A->nnz < 0) return fail(SS_E_ARG, "%s: bad matrix size", fn);
+  if (A->M > INT32_MAX || A->N > INT32_MAX) return fail(SS_E_ARG, "%s: M and N must fit in int32", fn);
+  return SS_OK;
+}
+
+template <bool COLS>
+void launch_fill(int wt, const ss_matrix_dev& A, const float* p, const ss_system& out, unsigned nb,
+                 hipStream_t st) {
+  if (wt == SS_F32) k_fold_fill<COLS, SS_F32><<<nb, kWave * kFoldWaves, 0, st>>>(A, p, out);
+  else if (wt == SS_BF16) k_fold_fill<COLS, SS_BF16><<<nb, kWave * kFoldWaves, 0, st>>>(A, p, out);
+  else k_fold_fill<COLS, SS_F16><<<nb, kWave * kFoldWaves, 0, st>>>(A, p, out);
+}
+
+}  // namespace
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" ss_status ss_fold_workspace_bytes(int64_t M, int64_t N, size_t* bytes) {
+  clear_error();
+  if (!bytes || M <= 0 || N <= 0) return fail(SS_E_ARG, "ss_fold_workspace_bytes: bad argument");
+  *bytes = 256;
+  return SS_OK;
+}
+
+extern "C" ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* workspace,
+                                  size_t workspace_bytes, int64_t* nnz_half, void* stream) {
+  clear_error();
+  if (ss_status s = check_dev_matrix(A, "ss_fold_size")) return s;
+  if (!nnz_half || !workspace) return fail(SS_E_ARG, "ss_fold_size: NULL argument");
+  if (workspace_bytes < sizeof(FoldCheck)) return fail(SS_E_WORKSPACE, "ss_fold_size: workspace too small");
+  if (A->M % 2 || A->N % 2)
+    return fail(SS_E_ODD, "ss_fold_size: M=%lld and N=%lld must be even", (long long)A->M, (long long)A->N);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  FoldCheck* chk = static_cast<FoldCheck*>(workspace);
+  k_zero_check<<<1, 64, 0, st>>>(chk);
+  k_check_pairs<false><<<blocks_for(A->M / 2), kWave * kFoldWaves, 0, st>>>(*A, p, chk);
+  k_check_pairs<true><<<blocks_for(A->N / 2), kWave * kFoldWaves, 0, st>>>(*A, p, chk);
+  SS_HIP_TRY(hipGetLastError());
+  FoldCheck h{};
+  SS_HIP_TRY(hipMemcpyAsync(&h, chk, sizeof h, hipMemcpyDeviceToHost, st));
+  SS_HIP_TRY(hipStreamSynchronize(st));
+  if (h.flags & kFlagShape)
+    return fail(SS_E_SHAPE, "ss_fold_size: CSR/CSC offsets, order or index range invalid");
+  if (h.flags & kFlagNonfinite) return fail(SS_E_NONFINITE, "ss_fold_size: NaN or Inf in A or p");
+  if (h.flags & kFlagAsym)
+    return fail(SS_E_ASYM, "ss_fold_size: A violates eq. (2), w[i,j] != w[M-1-i,N-1-j]");
+  if (h.sum_csr != h.sum_csc) return fail(SS_E_SHAPE, "ss_fold_size: CSR and CSC hold different entries");
+  if (h.cnt_csr != h.cnt_csc) return fail(SS_E_SHAPE, "ss_fold_size: row and column folds disagree in size");
+  *nnz_half = static_cast<int64_t>(h.cnt_csr);
+  return SS_OK;
+}
+
+extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out, void* stream) {
+  clear_error();
+  if (ss_status s = check_dev_matrix(A, "ss_fold")) return s;
+  if (!p || !out) return fail(SS_E_ARG, "ss_fold: NULL argument");
+  if (A->M % 2 || A->N % 2) return fail(SS_E_ODD, "ss_fold: M and N must be even");
+  if (out->m != A->M / 2 || out->n != A->N / 2 || out->nvals != 2)
+    return fail(SS_E_ARG, "ss_fold: out must be m = M/2, n = N/2, nvals = 2");
+  if (out->wdtype != SS_F32 && out->wdtype != SS_BF16 && out->wdtype != SS_F16)
+    return fail(SS_E_ARG, "ss_fold: unknown wdtype %d", out->wdtype);
+  if (!out->row_ptr || !out->col_idx || !out->val || !out->col_ptr || !out->row_idx || !out->val_t ||
+      !out->p || !out->inv_row || !out->inv_col)
+    return fail(SS_E_ARG, "ss_fold: NULL output array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned nbr = blocks_for(out->m), nbc = blocks_for(out->n);
+  k_fold_count<false><<<nbr, kWave * kFoldWaves, 0, st>>>(*A, out->row_ptr);
+  k_scan<<<1, kScanThreads, 0, st>>>(out->row_ptr, out->m);
+  launch_fill<false>(out->wdtype, *A, p, *out, nbr, st);
+  k_fold_count<true><<<nbc, kWave * kFoldWaves, 0, st>>>(*A, out->col_ptr);
+  k_scan<<<1, kScanThreads, 0, st>>>(out->col_ptr, out->n);
+  launch_fill<true>(out->wdtype, *A, p, *out, nbc, st);
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+extern "C" ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out, void* stream) {
+  clear_error();
+  if (ss_status s = check_dev_matrix(A, "ss_unsplit")) return s;
+  if (!p || !out) return fail(SS_E_ARG, "ss_unsplit: NULL argument");
+  if (out->m != A->M || out->n != A->N || out->nnz != A->nnz || out->nvals != 1)
+    return fail(SS_E_ARG, "ss_unsplit: out must be m = M, n = N, nnz = nnz(A), nvals = 1");
+  if (out->wdtype != SS_F32 && out->wdtype != SS_BF16 && out->wdtype != SS_F16)
+    return fail(SS_E_ARG, "ss_unsplit: unknown wdtype %d", out->wdtype);
+  if (!out->row_ptr || !out->col_idx || !out->val || !out->col_ptr || !out->row_idx || !out->val_t ||
+      !out->p || !out->inv_row || !out->inv_col)
+    return fail(SS_E_ARG, "ss_unsplit: NULL output array");
+  if (out->wdtype == SS_F32 && (out->val != A->val || out->val_t != A->val_t))
+    return fail(SS_E_ARG, "ss_unsplit: FP32 values must alias A's arrays");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  k_line_recip<false><<<blocks_for(A->M), kWave * kFoldWaves, 0, st>>>(A->row_ptr, A->val, A->M, out->inv_row);
+  k_line_recip<true><<<blocks_for(A->N), kWave * kFoldWaves, 0, st>>>(A->col_ptr, A->val_t, A->N, out->inv_col);
+  const unsigned nbv = static_cast<unsigned>((A->nnz + 255) / 256);
+  if (out->wdtype != SS_F32 && A->nnz > 0) {
+    if (out->wdtype == SS_BF16) {
+      k_convert<SS_BF16><<<nbv, 256, 0, st>>>(A->val, A->nnz, out->val);
+      k_convert<SS_BF16><<<nbv, 256, 0, st>>>(A->val_t, A->nnz, out->val_t);
+    } else {
+      k_convert<SS_F16><<<nbv, 256, 0, st>>>(A->val, A->nnz, out->val);
+      k_convert<SS_F16><<<nbv, 256, 0, st>>>(A->val_t, A->nnz, out->val_t);
+    }
+  }
+  if (out->p != p)
+    k_copy_f32<<<static_cast<unsigned>((A->M + 255) / 256), 256, 0, st>>>(p, A->M, out->p);
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}

@@ -1,0 +1,655 @@
+// Simultaneous SART on one or many systems at once (the paper's solver,
+// Section 1 and its refs. [001], [003]):
+//     f <- f + lambda * V^-1 A^T W^-1 (p - A f)
+// run on both halves of the folded pair (systems (3) and (4), interleaved
+// values sharing one index array) or on a single system.
+//
+// One iteration is two kernels:
+//   k_sart_fp  forward projection, residual and scaled residual: per row i,
+//              q = A[i,:] f, r = p[i] - q, z[i] = r * inv_row[i]; FP64 block
+//              partials of |r|^2; the last block of a system to finish (an
+//              atomic ticket) sums the partials in index order, records
+//              rel_res(f^k) and decides whether the system stops.
+//   k_sart_bp  back projection and update from the pre-transposed (CSC)
+//              copy: per column j, b = A[:,j]^T z, f[j] += lambda *
+//              inv_col[j] * b.  Every column is owned by one lane group, so
+//              the update needs no atomics.
+// Rows (columns) are processed by groups of 64/RPW (64/CPW) lanes of a
+// wavefront; lanes stride over the row's entries (coalesced loads of indices
+// and values), partial sums are combined by a fixed butterfly, so results are
+// bitwise reproducible run to run.  A block never straddles two systems; the
+// blocks of all systems form one grid per kernel.
+//
+// Per-system state lives in the caller's workspace: k (index of the current
+// iterate), stop flag, ticket, ||p||^2.  Kernels of a stopped system exit at
+// once, so a replayed graph may overshoot the iteration count harmlessly.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ss {
+namespace {
+
+constexpr int kWPB = 4;          // wavefronts per block
+constexpr int kThreads = kWave * kWPB;
+
+struct SysState {
+  double pnorm2;     // ||p||^2 over all halves
+  double last_res;   // rel_res of the final iterate
+  int32_t k;         // index of the current iterate f^k
+  int32_t stop;      // 1: no more updates
+  uint32_t ticket;   // forward-projection blocks finished this iteration
+  uint32_t pad;
+};
+
+struct SysDesc {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const void* val;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const void* val_t;
+  const float* p;
+  const float* inv_row;
+  const float* inv_col;
+  float* f;
+  float* z;
+  double* res_hist;
+  double* partials;
+  SysState* st;
+  int64_t m, n;
+  int64_t fp_block0, bp_block0;  // first block of this system in each grid
+  int32_t fp_nblocks, bp_nblocks;
+};
+
+struct Params {
+  float lambda;
+  int32_t max_iter;
+  double tol;
+};
+
+constexpr int kDescChunk = 16;
+struct DescChunk {
+  SysDesc d[kDescChunk];
+  int32_t count;
+  int32_t first;
+};
+
+// Workgroups are dealt round-robin to the 8 XCDs; this gives XCD x the
+// contiguous logical range [start(x), start(x) + count(x)).
+__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nblocks) {
+  const uint32_t x = b & 7u, q = b >> 3;
+  const uint32_t per = nblocks >> 3, rem = nblocks & 7u;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+template <bool BP>
+__device__ inline int find_sys(const SysDesc* t, int nsys, int64_t b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b0 = BP ? t[mid].bp_block0 : t[mid].fp_block0;
+    if (b0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Writes up to kDescChunk descriptors into the table and resets each
+// system's state; block b also reduces ||p||^2 of its system.
+template <int NV>
+__global__ __launch_bounds__(kThreads) void k_setup(DescChunk ch, SysDesc* table, Params prm_in,
+                                                    Params* prm) {
+  const int b = blockIdx.x;
+  const SysDesc& d = ch.d[b];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < d.m * NV; i += kThreads) {
+    const double v = d.p[i];
+    s += v * v;
+  }
+  __shared__ double red[kWPB];
+  s = block_sum<kWPB>(s, red);
+  if (threadIdx.x == 0) {
+    table[ch.first + b] = d;
+    d.st->pnorm2 = s;
+    d.st->last_res = 0.0;
+    d.st->k = 0;
+    d.st->stop = 0;
+    d.st->ticket = 0u;
+    if (ch.first == 0 && b == 0) *prm = prm_in;
+  }
+}
+
+template <int NV, int WT, int RPW>
+__global__ __launch_bounds__(kThreads) void k_sart_fp(const Params* prm, const SysDesc* table, int nsys,
+                                                      uint32_t nblocks, int xcd) {
+  const uint32_t b = xcd ? xcd_remap(blockIdx.x, nblocks) : blockIdx.x;
+  const int s = nsys == 1 ? 0 : find_sys<false>(table, nsys, b);
+  const SysDesc& S = table[s];
+  SysState* st = S.st;
+  if (st->stop) return;
+  constexpr int L = kWave / RPW;
+  const int lane = lane_id();
+  const int gl = lane % L;
+  const int64_t local = static_cast<int64_t>(b) - S.fp_block0;
+  const int64_t row = local * (RPW * kWPB) + wave_id() * RPW + lane / L;
+  float acc[NV];
+#pragma unroll
+  for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
+  if (row < S.m) {
+    const int64_t re = S.row_ptr[row + 1];
+    for (int64_t k = S.row_ptr[row] + gl; k < re; k += L) {
+      const int32_t c = S.col_idx[k];
+      const Vec<NV> v = load_vals<NV, WT>(S.val, k);
+      const Vec<NV> fv = load_vec<NV>(S.f, c);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] = fmaf(v.v[h], fv.v[h], acc[h]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
+  double d = 0.0;
+  if (gl == 0 && row < S.m) {
+    const Vec<NV> pv = load_vec<NV>(S.p, row);
+    const float w = S.inv_row[row];
+    Vec<NV> zv;
+#pragma unroll
+    for (int h = 0; h < NV; ++h) {
+      const float r = pv.v[h] - acc[h];
+      zv.v[h] = r * w;
+      d += static_cast<double>(r) * static_cast<double>(r);
+    }
+    store_vec<NV>(S.z, row, zv);
+  }
+  __shared__ double red[kWPB];
+  __shared__ int last;
+  const double tot = block_sum<kWPB>(d, red);
+  if (threadIdx.x == 0) {
+    S.partials[local] = tot;
+    __threadfence();
+    const uint32_t prev = atomicAdd(&st->ticket, 1u);
+    last = prev == static_cast<uint32_t>(S.fp_nblocks - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc2 = 0.0;
+  for (int64_t t = threadIdx.x; t < S.fp_nblocks; t += kThreads) acc2 += S.partials[t];
+  const double rsum = block_sum<kWPB>(acc2, red);
+  if (threadIdx.x == 0) {
+    const double pn = st->pnorm2;
+    const double rel = pn > 0.0 ? sqrt(rsum / pn) : sqrt(rsum);
+    const int k = st->k;
+    if (S.res_hist) S.res_hist[k] = rel;
+    st->last_res = rel;
+    if (rel <= prm->tol || k >= prm->max_iter) st->stop = 1;
+    else st->k = k + 1;
+    st->ticket = 0u;
+  }
+}
+
+template <int NV, int WT, int CPW>
+__global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* prm, const SysDesc* table, int nsys,
+                                                      uint32_t nblocks, int xcd) {
+  const uint32_t b = xcd ? xcd_remap(blockIdx.x, nblocks) : blockIdx.x;
+  const int s = nsys == 1 ? 0 : find_sys<true>(table, nsys, b);
+  const SysDesc& S = table[s];
+  if (S.st->stop) return;
+  constexpr int L = kWave / CPW;
+  const int lane = lane_id();
+  const int gl = lane % L;
+  const int64_t local = static_cast<int64_t>(b) - S.bp_block0;
+  const int64_t col = local * (CPW * kWPB) + wave_id() * CPW + lane / L;
+  float acc[NV];
+#pragma unroll
+  for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
+  if (col < S.n) {
+    const int64_t ce = S.col_ptr[col + 1];
+    for (int64_t k = S.col_ptr[col] + gl; k < ce; k += L) {
+      const int32_t r = S.row_idx[k];
+      const Vec<NV> v = load_vals<NV, WT>(S.val_t, k);
+      const Vec<NV> zv = load_vec<NV>(S.z, r);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] = fmaf(v.v[h], zv.v[h], acc[h]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
+  if (gl == 0 && col < S.n) {
+    const float t = prm->lambda * S.inv_col[col];
+    Vec<NV> fv = load_vec<NV>(S.f, col);
+#pragma unroll
+    for (int h = 0; h < NV; ++h) fv.v[h] = fmaf(t, acc[h], fv.v[h]);
+    store_vec<NV>(S.f, col, fv);
+  }
+}
+
+// ------------------------------------------------------------------ host
+struct Layout {
+  size_t params, table, states, z, partials, total;
+  std::vector<size_t> z_off, part_off;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
+
+Layout make_layout(const ss_system* sys, int nsys) {
+  Layout L;
+  size_t o = 0;
+  L.params = o;
+  o += align256(sizeof(Params));
+  L.table = o;
+  o += align256(sizeof(SysDesc) * nsys);
+  L.states = o;
+  o += align256(sizeof(SysState) * nsys);
+  L.z = o;
+  for (int s = 0; s < nsys; ++s) {
+    L.z_off.push_back(o);
+    o += align256(sizeof(float) * static_cast<size_t>(sys[s].m * sys[s].nvals));
+  }
+  L.partials = o;
+  for (int s = 0; s < nsys; ++s) {
+    L.part_off.push_back(o);
+    // the most forward-projection blocks any configuration uses: 1 row per wave
+    o += align256(sizeof(double) * static_cast<size_t>((sys[s].m + kWPB - 1) / kWPB));
+  }
+  L.total = o;
+  return L;
+}
+
+struct Cfg {
+  int nv, wt, rpw, cpw, xcd;
+};
+
+ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const char* fn) {
+  if (!sys || nsys <= 0 || !o) return fail(SS_E_ARG, "%s: NULL systems or options", fn);
+  for (int s = 0; s < nsys; ++s) {
+    const ss_system& S = sys[s];
+    if (S.m <= 0 || S.n <= 0 || S.nnz < 0) return fail(SS_E_ARG, "%s: system %d has a bad size", fn, s);
+    if (S.nvals != sys[0].nvals || S.wdtype != sys[0].wdtype)
+      return fail(SS_E_ARG, "%s: all systems of one call must share nvals and wdtype", fn);
+    if (S.nvals != 1 && S.nvals != 2) return fail(SS_E_ARG, "%s: nvals must be 1 or 2", fn);
+    if (S.wdtype != SS_F32 && S.wdtype != SS_BF16 && S.wdtype != SS_F16)
+      return fail(SS_E_ARG, "%s: unknown wdtype", fn);
+    if (!S.row_ptr || !S.col_idx || !S.val || !S.col_ptr || !S.row_idx || !S.val_t || !S.p ||
+        !S.inv_row || !S.inv_col)
+      return fail(SS_E_ARG, "%s: system %d has a NULL array", fn, s);
+    if (S.m > INT32_MAX || S.n > INT32_MAX) return fail(SS_E_ARG, "%s: system %d too large", fn, s);
+  }
+  if (!(o->lambda > 0.0f && o->lambda < 2.0f)) return fail(SS_E_ARG, "%s: lambda must be in (0, 2)", fn);
+  if (o->max_iter < 0 || o->max_iter > (1 << 30)) return fail(SS_E_ARG, "%s: bad max_iter", fn);
+  if (o->tol > 0.0 && o->check_every <= 0) return fail(SS_E_ARG, "%s: check_every must be > 0", fn);
+  auto ok_pw = [](int v, int maxv) { return v == 0 || (v > 0 && v <= maxv && (v & (v - 1)) == 0); };
+  if (!ok_pw(o->rows_per_wave, 8)) return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8", fn);
+  if (!ok_pw(o->cols_per_wave, 16)) return fail(SS_E_ARG, "%s: cols_per_wave must be 0,1,2,4,8,16", fn);
+  return SS_OK;
+}
+
+int pick_per_wave(double mean_len, int maxv) {
+  int v = 1;
+  while (v < maxv && mean_len * v < 48.0) v <<= 1;
+  return v;
+}
+
+Cfg choose_cfg(const ss_system* sys, int nsys, const ss_sart_opts* o) {
+  double nnz = 0, m = 0, n = 0;
+  for (int s = 0; s < nsys; ++s) {
+    nnz += static_cast<double>(sys[s].nnz);
+    m += static_cast<double>(sys[s].m);
+    n += static_cast<double>(sys[s].n);
+  }
+  Cfg c;
+  c.nv = sys[0].nvals;
+  c.wt = sys[0].wdtype;
+  c.rpw = o->rows_per_wave ? o->rows_per_wave : pick_per_wave(nnz / m, 8);
+  c.cpw = o->cols_per_wave ? o->cols_per_wave : pick_per_wave(nnz / n, 16);
+  c.xcd = o->xcd_remap ? 1 : 0;
+  return c;
+}
+
+struct Grids {
+  uint32_t fp_blocks, bp_blocks;
+};
+
+// Writes the descriptor table and resets states (stream-ordered kernels).
+ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* res_hist,
+                const Params& prm, const Cfg& c, const Layout& L, char* ws, Grids* g,
+                hipStream_t st) {
+  int64_t fb = 0, bb = 0;
+  const int64_t rpb = static_cast<int64_t>(c.rpw) * kWPB, cpb = static_cast<int64_t>(c.cpw) * kWPB;
+  DescChunk ch{};
+  SysDesc* table = reinterpret_cast<SysDesc*>(ws + L.table);
+  Params* dprm = reinterpret_cast<Params*>(ws + L.params);
+  for (int s = 0; s < nsys; ++s) {
+    const ss_system& S = sys[s];
+    SysDesc d{};
+    d.row_ptr = S.row_ptr;
+    d.col_idx = S.col_idx;
+    d.val = S.val;
+    d.col_ptr = S.col_ptr;
+    d.row_idx = S.row_idx;
+    d.val_t = S.val_t;
+    d.p = S.p;
+    d.inv_row = S.inv_row;
+    d.inv_col = S.inv_col;
+    d.f = f[s];
+    d.z = reinterpret_cast<float*>(ws + L.z_off[s]);
+    d.res_hist = res_hist ? res_hist[s] : nullptr;
+    d.partials = reinterpret_cast<double*>(ws + L.part_off[s]);
+    d.st = reinterpret_cast<SysState*>(ws + L.states) + s;
+    d.m = S.m;
+    d.n = S.n;
+    d.fp_nblocks = static_cast<int32_t>((S.m + rpb - 1) / rpb);
+    d.bp_nblocks = static_cast<int32_t>((S.n + cpb - 1) / cpb);
+    d.fp_block0 = fb;
+    d.bp_block0 = bb;
+    fb += d.fp_nblocks;
+    bb += d.bp_nblocks;
+    ch.d[ch.count++] = d;
+    if (ch.count == kDescChunk || s == nsys - 1) {
+      if (c.nv == 2) k_setup<2><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm);
+      else k_setup<1><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm);
+      ch.first = s + 1;
+      ch.count = 0;
+    }
+  }
+  if (fb > UINT32_MAX || bb > UINT32_MAX) return fail(SS_E_ARG, "SART: grid too large");
+  g->fp_blocks = static_cast<uint32_t>(fb);
+  g->bp_blocks = static_cast<uint32_t>(bb);
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+template <int NV, int WT>
+void launch_fp_t(int rpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, hipStream_t st) {
+  switch (rpw) {
+    case 1: k_sart_fp<NV, WT, 1><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    case 2: k_sart_fp<NV, WT, 2><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    case 4: k_sart_fp<NV, WT, 4><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    default: k_sart_fp<NV, WT, 8><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+  }
+}
+
+template <int NV, int WT>
+void launch_bp_t(int cpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, hipStream_t st) {
+  switch (cpw) {
+    case 1: k_sart_bp<NV, WT, 1><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    case 2: k_sart_bp<NV, WT, 2><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    case 4: k_sart_bp<NV, WT, 4><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    case 8: k_sart_bp<NV, WT, 8><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    default: k_sart_bp<NV, WT, 16><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+  }
+}
+
+template <bool BP>
+void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, hipStream_t st) {
+  const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
+  const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
+#define SS_DISPATCH(NV, WT)                                                         \
+  if (c.nv == NV && c.wt == WT) {                                                   \
+    if (BP) launch_bp_t<NV, WT>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, st);        \
+    else launch_fp_t<NV, WT>(c.rpw, prm, t, nsys, g.fp_blocks, c.xcd, st);           \
+    return;                                                                         \
+  }
+  SS_DISPATCH(2, SS_F32)
+  SS_DISPATCH(2, SS_BF16)
+  SS_DISPATCH(2, SS_F16)
+  SS_DISPATCH(1, SS_F32)
+  SS_DISPATCH(1, SS_BF16)
+  SS_DISPATCH(1, SS_F16)
+#undef SS_DISPATCH
+}
+
+void launch_iterations(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int count,
+                       hipStream_t st) {
+  for (int i = 0; i < count; ++i) {
+    launch_kernel<false>(c, ws, L, nsys, g, st);
+    launch_kernel<true>(c, ws, L, nsys, g, st);
+  }
+}
+
+// ----------------------------------------------------------- graph cache
+struct GraphKey {
+  int device;
+  const void* ws;
+  int nsys;
+  uint32_t fpb, bpb;
+  int nv, wt, rpw, cpw, xcd, count;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, count) <
+           std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.count);
+  }
+};
+
+struct GraphCache {
+  std::mutex mu;
+  std::map<GraphKey, hipGraphExec_t> execs;
+  std::map<int, hipStream_t> capture_streams;
+  uint64_t uses = 0;
+};
+
+GraphCache& graph_cache() {
+  static GraphCache* c = new GraphCache();  // lives until process exit
+  return *c;
+}
+
+ss_status get_graph(const GraphKey& key, const Cfg& c, const char* ws, const Layout& L, const Grids& g,
+                    hipGraphExec_t* out) {
+  GraphCache& gc = graph_cache();
+  std::lock_guard<std::mutex> lock(gc.mu);
+  auto it = gc.execs.find(key);
+  if (it != gc.execs.end()) {
+    *out = it->second;
+    return SS_OK;
+  }
+  if (gc.execs.size() >= 32) {
+    for (auto& kv : gc.execs) (void)hipGraphExecDestroy(kv.second);
+    gc.execs.clear();
+  }
+  hipStream_t cs;
+  auto sit = gc.capture_streams.find(key.device);
+  if (sit == gc.capture_streams.end()) {
+    SS_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    gc.capture_streams[key.device] = cs;
+  } else {
+    cs = sit->second;
+  }
+  SS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  launch_iterations(c, ws, L, key.nsys, g, key.count, cs);
+  hipGraph_t graph;
+  const hipError_t ce = hipStreamEndCapture(cs, &graph);
+  if (ce != hipSuccess) return fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+  hipGraphExec_t exec;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(SS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+  gc.execs[key] = exec;
+  *out = exec;
+  return SS_OK;
+}
+
+ss_status read_states(const char* ws, const Layout& L, int nsys, std::vector<SysState>* h, hipStream_t st) {
+  h->resize(nsys);
+  SS_HIP_TRY(hipMemcpyAsync(h->data(), ws + L.states, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, st));
+  SS_HIP_TRY(hipStreamSynchronize(st));
+  return SS_OK;
+}
+
+}  // namespace
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" ss_status ss_sart_workspace_bytes(const ss_system* sys, int32_t nsys, const ss_sart_opts* opts,
+                                             size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(SS_E_ARG, "ss_sart_workspace_bytes: NULL bytes");
+  if (ss_status s = validate(sys, nsys, opts, "ss_sart_workspace_bytes")) return s;
+  *bytes = make_layout(sys, nsys).total;
+  return SS_OK;
+}
+
+extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* const* f, double* const* res_hist,
+                                   const ss_sart_opts* opts, int32_t* iters, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (ss_status s = validate(sys, nsys, opts, "ss_sart_solve")) return s;
+  if (!f || !workspace) return fail(SS_E_ARG, "ss_sart_solve: NULL images or workspace");
+  for (int s = 0; s < nsys; ++s)
+    if (!f[s] || (res_hist && !res_hist[s])) return fail(SS_E_ARG, "ss_sart_solve: NULL image %d", s);
+  const Layout L = make_layout(sys, nsys);
+  if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_solve: workspace needs %zu bytes", L.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const Cfg c = choose_cfg(sys, nsys, opts);
+  Params prm{opts->lambda, opts->max_iter, opts->tol};
+  Grids g{};
+  if (ss_status s = setup(sys, nsys, f, res_hist, prm, c, L, ws, &g, st)) return s;
+  const int64_t total = static_cast<int64_t>(opts->max_iter) + 1;  // forward passes incl. the final residual
+  const int chunk = opts->tol > 0.0 ? static_cast<int>(std::min<int64_t>(opts->check_every, total))
+                                    : static_cast<int>(std::min<int64_t>(total, 256));
+  hipGraphExec_t exec = nullptr;
+  if (opts->use_graph) {
+    int dev = 0;
+    SS_HIP_TRY(hipGetDevice(&dev));
+    const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, chunk};
+    if (ss_status s = get_graph(key, c, ws, L, g, &exec)) return s;
+  }
+  std::vector<SysState> hs;
+  for (int64_t done = 0; done < total; done += chunk) {
+    if (exec) {
+      SS_HIP_TRY(hipGraphLaunch(exec, st));
+    } else {
+      launch_iterations(c, ws, L, nsys, g, static_cast<int>(std::min<int64_t>(chunk, total - done)), st);
+      SS_HIP_TRY(hipGetLastError());
+    }
+    if (opts->tol > 0.0 && done + chunk < total) {
+      if (ss_status s = read_states(ws, L, nsys, &hs, st)) return s;
+      bool all = true;
+      for (const auto& x : hs) all = all && x.stop;
+      if (all) break;
+    }
+  }
+  if (!iters && opts->tol <= 0.0) return SS_OK;
+  if (ss_status s = read_states(ws, L, nsys, &hs, st)) return s;
+  ss_status result = SS_OK;
+  for (int s = 0; s < nsys; ++s) {
+    if (iters) iters[s] = hs[s].k;
+    if (opts->tol > 0.0 && !(hs[s].last_res <= opts->tol)) result = SS_NOT_CONVERGED;
+  }
+  return result;
+}
+
+extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, float* const* f,
+                                          const ss_sart_opts* opts, int32_t reps, double* fp_ms, double* bp_ms,
+                                          void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (ss_status s = validate(sys, nsys, opts, "ss_sart_time_kernels")) return s;
+  if (!f || !workspace || !fp_ms || !bp_ms || reps <= 0)
+    return fail(SS_E_ARG, "ss_sart_time_kernels: bad argument");
+  const Layout L = make_layout(sys, nsys);
+  if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_time_kernels: workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const Cfg c = choose_cfg(sys, nsys, opts);
+  Params prm{opts->lambda, (1 << 30), -1.0};
+  Grids g{};
+  if (ss_status s = setup(sys, nsys, f, nullptr, prm, c, L, ws, &g, st)) return s;
+  hipEvent_t e0, e1;
+  SS_HIP_TRY(hipEventCreate(&e0));
+  SS_HIP_TRY(hipEventCreate(&e1));
+  float t_fp = 0.f, t_bp = 0.f;
+  launch_kernel<false>(c, ws, L, nsys, g, st);  // warm caches and code
+  launch_kernel<true>(c, ws, L, nsys, g, st);
+  (void)hipEventRecord(e0, st);
+  for (int r = 0; r < reps; ++r) launch_kernel<false>(c, ws, L, nsys, g, st);
+  (void)hipEventRecord(e1, st);
+  (void)hipEventSynchronize(e1);
+  (void)hipEventElapsedTime(&t_fp, e0, e1);
+  (void)hipEventRecord(e0, st);
+  for (int r = 0; r < reps; ++r) launch_kernel<true>(c, ws, L, nsys, g, st);
+  (void)hipEventRecord(e1, st);
+  (void)hipEventSynchronize(e1);
+  (void)hipEventElapsedTime(&t_bp, e0, e1);
+  const hipError_t err = hipGetLastError();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(SS_E_HIP, "ss_sart_time_kernels: %s", hipGetErrorString(err));
+  *fp_ms = static_cast<double>(t_fp) / reps;
+  *bp_ms = static_cast<double>(t_bp) / reps;
+  return SS_OK;
+}
+
+namespace {
+struct TuneKey {
+  int nv, wt, nsys;
+  int64_t m_bucket, row_bucket, col_bucket;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(nv, wt, nsys, m_bucket, row_bucket, col_bucket) <
+           std::tie(o.nv, o.wt, o.nsys, o.m_bucket, o.row_bucket, o.col_bucket);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::tuple<int, int, int>> g_tune;
+}  // namespace
+
+extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f, ss_sart_opts* opts,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (ss_status s = validate(sys, nsys, opts, "ss_sart_autotune")) return s;
+  double nnz = 0, m = 0, n = 0;
+  for (int s = 0; s < nsys; ++s) {
+    nnz += static_cast<double>(sys[s].nnz);
+    m += static_cast<double>(sys[s].m);
+    n += static_cast<double>(sys[s].n);
+  }
+  const TuneKey key{sys[0].nvals, sys[0].wdtype, nsys, static_cast<int64_t>(std::log2(m)),
+                    static_cast<int64_t>(std::log2(1.0 + nnz / m) * 4), static_cast<int64_t>(std::log2(1.0 + nnz / n) * 4)};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      std::tie(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap) = it->second;
+      return SS_OK;
+    }
+  }
+  const int reps = 10;
+  double best_fp = 1e30, best_bp = 1e30;
+  int brpw = 1, bcpw = 1, bxcd_fp = 0, bxcd_bp = 0;
+  for (int xcd = 0; xcd <= 1; ++xcd) {
+    for (int pw = 1; pw <= 16; pw <<= 1) {
+      ss_sart_opts o = *opts;
+      o.xcd_remap = xcd;
+      o.rows_per_wave = pw <= 8 ? pw : 8;
+      o.cols_per_wave = pw;
+      double tf = 0, tb = 0;
+      if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes, stream))
+        return s;
+      if (pw <= 8 && tf < best_fp) {
+        best_fp = tf;
+        brpw = pw;
+        bxcd_fp = xcd;
+      }
+      if (tb < best_bp) {
+        best_bp = tb;
+        bcpw = pw;
+        bxcd_bp = xcd;
+      }
+    }
+  }
+  // one remap flag serves both kernels: take the one of the slower kernel
+  const int xcd = best_fp >= best_bp ? bxcd_fp : bxcd_bp;
+  opts->rows_per_wave = brpw;
+  opts->cols_per_wave = bcpw;
+  opts->xcd_remap = xcd;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[key] = std::make_tuple(brpw, bcpw, xcd);
+  return SS_OK;
+}

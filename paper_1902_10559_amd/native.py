@@ -1,0 +1,404 @@
+"""Python binding of libssart (ctypes): argument marshalling only.
+
+Every computation runs in the library's own code (host C++ for the system
+build, HIP kernels for everything on the device).  PyTorch provides device
+memory and the current stream; nothing here computes on tensors.  Importing
+this module never falls back to anything else: if the library is missing the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libssart.so")
+
+SS_OK, SS_NOT_CONVERGED = 0, 1
+WDTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+
+
+class SSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[ssart {code}] {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nz", C.c_int32), ("pitch", C.c_double)]
+
+
+class GeometryC(C.Structure):
+    _fields_ = [("K", C.c_int32), ("src_x", C.POINTER(C.c_double)),
+                ("src_z", C.POINTER(C.c_double)), ("B", C.c_int32),
+                ("bin_x", C.POINTER(C.c_double)), ("det_z", C.c_double)]
+
+
+class MatrixC(C.Structure):
+    _fields_ = [("M", C.c_int64), ("N", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.POINTER(C.c_int64)), ("col_idx", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_float)), ("col_ptr", C.POINTER(C.c_int64)),
+                ("row_idx", C.POINTER(C.c_int32)), ("val_t", C.POINTER(C.c_float))]
+
+
+class MatrixDevC(C.Structure):
+    _fields_ = [("M", C.c_int64), ("N", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p), ("val_t", C.c_void_p)]
+
+
+class SystemC(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("nvals", C.c_int32), ("wdtype", C.c_int32),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p), ("val_t", C.c_void_p),
+                ("p", C.c_void_p), ("inv_row", C.c_void_p), ("inv_col", C.c_void_p)]
+
+
+class SartOptsC(C.Structure):
+    _fields_ = [("lambda_", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("check_every", C.c_int32), ("use_graph", C.c_int32),
+                ("rows_per_wave", C.c_int32), ("cols_per_wave", C.c_int32),
+                ("xcd_remap", C.c_int32)]
+
+
+_SIGNATURES = {
+    "ss_last_error": (C.c_char_p, []),
+    "ss_version": (C.c_char_p, []),
+    "ss_build_system": (C.c_int32, [C.POINTER(Grid), C.POINTER(GeometryC), C.c_int32,
+                                    C.POINTER(MatrixC)]),
+    "ss_matrix_free": (None, [C.POINTER(MatrixC)]),
+    "ss_snake_order": (C.c_int32, [C.POINTER(Grid), C.POINTER(C.c_int64)]),
+    "ss_fold_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "ss_fold_size": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.c_void_p, C.c_size_t,
+                                 C.POINTER(C.c_int64), C.c_void_p]),
+    "ss_fold": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p]),
+    "ss_unsplit": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p]),
+    "ss_sart_workspace_bytes": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(SartOptsC),
+                                            C.POINTER(C.c_size_t)]),
+    "ss_sart_solve": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_void_p), C.POINTER(SartOptsC),
+                                  C.POINTER(C.c_int32), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ss_sart_time_kernels": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(C.c_void_p),
+                                         C.POINTER(SartOptsC), C.c_int32,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ss_sart_autotune": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(C.c_void_p),
+                                     C.POINTER(SartOptsC), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ss_recombine": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_image_fold": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_project": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.c_void_p, C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library (torch is imported first so that both share one HIP
+    runtime).  Raises if the library has not been built."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the HIP runtime the library links to)
+        if not os.path.exists(LIB_PATH):
+            raise SSError(-7, f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow_warning: bool = False) -> int:
+    if status < 0 or (status > 0 and not allow_warning):
+        raise SSError(status, lib().ss_last_error().decode())
+    return status
+
+
+def _stream(device=None) -> C.c_void_p:
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+# ------------------------------------------------------------------ host
+@dataclasses.dataclass
+class HostMatrix:
+    M: int
+    N: int
+    nnz: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    val: np.ndarray
+    col_ptr: np.ndarray
+    row_idx: np.ndarray
+    val_t: np.ndarray
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col_idx, self.row_ptr), shape=(self.M, self.N))
+
+
+def build_system(geom, nthreads: int = 0) -> HostMatrix:
+    """ss_build_system for a scan described by ``inputs.Geometry``."""
+    g = Grid(geom.nx, geom.nz, float(geom.pitch))
+    sx = np.ascontiguousarray(geom.src_x, dtype=np.float64)
+    sz = np.ascontiguousarray(geom.src_z, dtype=np.float64)
+    bx = np.ascontiguousarray(geom.bin_x, dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    gc = GeometryC(len(sx), sx.ctypes.data_as(dp), sz.ctypes.data_as(dp), len(bx),
+                   bx.ctypes.data_as(dp), float(geom.det_z))
+    m = MatrixC()
+    _check(lib().ss_build_system(C.byref(g), C.byref(gc), int(nthreads), C.byref(m)))
+    try:
+        M, N, nnz = m.M, m.N, m.nnz
+        out = HostMatrix(M, N, nnz,
+                         np.ctypeslib.as_array(m.row_ptr, shape=(M + 1,)).copy(),
+                         np.ctypeslib.as_array(m.col_idx, shape=(max(nnz, 1),))[:nnz].copy(),
+                         np.ctypeslib.as_array(m.val, shape=(max(nnz, 1),))[:nnz].copy(),
+                         np.ctypeslib.as_array(m.col_ptr, shape=(N + 1,)).copy(),
+                         np.ctypeslib.as_array(m.row_idx, shape=(max(nnz, 1),))[:nnz].copy(),
+                         np.ctypeslib.as_array(m.val_t, shape=(max(nnz, 1),))[:nnz].copy())
+    finally:
+        lib().ss_matrix_free(C.byref(m))
+    return out
+
+
+def snake_order(nx: int, nz: int) -> np.ndarray:
+    """snake[r, c] = vertical-snake index of voxel (c, r) (ss_snake_order)."""
+    out = np.empty(nx * nz, dtype=np.int64)
+    g = Grid(nx, nz, 1.0)
+    _check(lib().ss_snake_order(C.byref(g), out.ctypes.data_as(C.POINTER(C.c_int64))))
+    return out.reshape(nz, nx)
+
+
+# ---------------------------------------------------------------- device
+@dataclasses.dataclass
+class DeviceMatrix:
+    M: int
+    N: int
+    nnz: int
+    row_ptr: "torch.Tensor"
+    col_idx: "torch.Tensor"
+    val: "torch.Tensor"
+    col_ptr: "torch.Tensor"
+    row_idx: "torch.Tensor"
+    val_t: "torch.Tensor"
+
+    def c(self) -> MatrixDevC:
+        return MatrixDevC(self.M, self.N, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx),
+                          _ptr(self.val), _ptr(self.col_ptr), _ptr(self.row_idx), _ptr(self.val_t))
+
+
+def to_device(hm, device="cuda") -> DeviceMatrix:
+    """Copies a host CSR+CSC (HostMatrix, or any object with the same fields)
+    into device tensors."""
+    import torch
+
+    def t(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    return DeviceMatrix(int(hm.M), int(hm.N), int(hm.nnz), t(hm.row_ptr, np.int64),
+                        t(hm.col_idx, np.int32), t(hm.val, np.float32), t(hm.col_ptr, np.int64),
+                        t(hm.row_idx, np.int32), t(hm.val_t, np.float32))
+
+
+@dataclasses.dataclass
+class System:
+    """A solver system (ss_system) and the tensors behind it."""
+    m: int
+    n: int
+    nnz: int
+    nvals: int
+    wdtype: str
+    row_ptr: "torch.Tensor"
+    col_idx: "torch.Tensor"
+    val: "torch.Tensor"
+    col_ptr: "torch.Tensor"
+    row_idx: "torch.Tensor"
+    val_t: "torch.Tensor"
+    p: "torch.Tensor"
+    inv_row: "torch.Tensor"
+    inv_col: "torch.Tensor"
+
+    def c(self) -> SystemC:
+        return SystemC(self.m, self.n, self.nnz, self.nvals, WDTYPES[self.wdtype],
+                       _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.val),
+                       _ptr(self.col_ptr), _ptr(self.row_idx), _ptr(self.val_t),
+                       _ptr(self.p), _ptr(self.inv_row), _ptr(self.inv_col))
+
+    def new_image(self):
+        import torch
+        shape = (self.n, 2) if self.nvals == 2 else (self.n,)
+        return torch.zeros(shape, dtype=torch.float32, device=self.p.device)
+
+
+def fold_size(A: DeviceMatrix, p=None) -> int:
+    """ss_fold_size: validates A (and p) and returns the shared-pattern size."""
+    import torch
+    nb = C.c_size_t()
+    _check(lib().ss_fold_workspace_bytes(A.M, A.N, C.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=A.val.device)
+    out = C.c_int64()
+    mc = A.c()
+    _check(lib().ss_fold_size(C.byref(mc), _ptr(p), _ptr(ws), nb.value, C.byref(out),
+                              _stream(A.val.device)))
+    return int(out.value)
+
+
+def _value_tensor(count: int, wdtype: str, device):
+    import torch
+    if wdtype == "f32":
+        return torch.empty(count, dtype=torch.float32, device=device)
+    return torch.empty(count, dtype=torch.int16, device=device)  # raw 16-bit storage
+
+
+def fold(A: DeviceMatrix, p, wdtype: str = "f32", nnz_half: int | None = None) -> System:
+    """ss_fold: the split pair (A(1), A(2)), (p1, p2) and the SART sums."""
+    import torch
+    dev = A.val.device
+    if nnz_half is None:
+        nnz_half = fold_size(A, p)
+    m, n = A.M // 2, A.N // 2
+    S = System(m, n, nnz_half, 2, wdtype,
+               torch.empty(m + 1, dtype=torch.int64, device=dev),
+               torch.empty(nnz_half, dtype=torch.int32, device=dev),
+               _value_tensor(2 * nnz_half, wdtype, dev),
+               torch.empty(n + 1, dtype=torch.int64, device=dev),
+               torch.empty(nnz_half, dtype=torch.int32, device=dev),
+               _value_tensor(2 * nnz_half, wdtype, dev),
+               torch.empty(2 * m, dtype=torch.float32, device=dev),
+               torch.empty(m, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev))
+    fold_into(A, p, S)
+    return S
+
+
+def fold_into(A: DeviceMatrix, p, S: System) -> None:
+    """ss_fold into an existing system's arrays (same sizes)."""
+    mc, sc = A.c(), S.c()
+    _check(lib().ss_fold(C.byref(mc), _ptr(p), C.byref(sc), _stream(A.val.device)))
+
+
+def unsplit(A: DeviceMatrix, p, wdtype: str = "f32") -> System:
+    """ss_unsplit: A itself as a single system (the unsplit baseline)."""
+    import torch
+    dev = A.val.device
+    if wdtype == "f32":
+        val, val_t = A.val, A.val_t
+    else:
+        val, val_t = _value_tensor(A.nnz, wdtype, dev), _value_tensor(A.nnz, wdtype, dev)
+    S = System(A.M, A.N, A.nnz, 1, wdtype, A.row_ptr, A.col_idx, val, A.col_ptr, A.row_idx,
+               val_t, torch.empty(A.M, dtype=torch.float32, device=dev),
+               torch.empty(A.M, dtype=torch.float32, device=dev),
+               torch.empty(A.N, dtype=torch.float32, device=dev))
+    mc, sc = A.c(), S.c()
+    _check(lib().ss_unsplit(C.byref(mc), _ptr(p), C.byref(sc), _stream(dev)))
+    return S
+
+
+@dataclasses.dataclass
+class SartOptions:
+    lam: float = 0.5
+    max_iter: int = 20
+    tol: float = 0.0
+    check_every: int = 50
+    use_graph: bool = True
+    rows_per_wave: int = 0
+    cols_per_wave: int = 0
+    xcd_remap: int = 0
+
+    def c(self) -> SartOptsC:
+        return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
+                         int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
+                         self.xcd_remap)
+
+
+class Solver:
+    """Marshals ss_sart_solve / ss_sart_time_kernels / ss_sart_autotune for a
+    fixed list of systems, owning the workspace."""
+
+    def __init__(self, systems, opts: SartOptions | None = None):
+        import torch
+        self.systems = list(systems)
+        self.opts = opts or SartOptions()
+        self._arr = (SystemC * len(self.systems))(*[s.c() for s in self.systems])
+        nb = C.c_size_t()
+        oc = self.opts.c()
+        _check(lib().ss_sart_workspace_bytes(self._arr, len(self.systems), C.byref(oc), C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.systems[0].p.device)
+
+    def _imgs(self, f):
+        assert len(f) == len(self.systems)
+        for s, t in zip(self.systems, f):
+            assert t.is_contiguous() and t.numel() == s.n * s.nvals and t.dtype.itemsize == 4
+        return (C.c_void_p * len(f))(*[t.data_ptr() for t in f])
+
+    def solve(self, f, res_hist=None, want_iters: bool = True):
+        """Runs SART in place on the images ``f``; returns (status, iters)."""
+        o = self.opts
+        oc = o.c()
+        if res_hist is not None:
+            for s, h in zip(self.systems, res_hist):
+                assert h.numel() >= o.max_iter + 1 and h.dtype.itemsize == 8
+            rh = (C.c_void_p * len(res_hist))(*[h.data_ptr() for h in res_hist])
+        else:
+            rh = None
+        it = (C.c_int32 * len(self.systems))() if want_iters else None
+        st = lib().ss_sart_solve(self._arr, len(self.systems), self._imgs(f), rh, C.byref(oc),
+                                 it, _ptr(self.ws), self.ws_bytes, _stream(self.ws.device))
+        _check(st, allow_warning=True)
+        return st, (list(it) if it is not None else None)
+
+    def time_kernels(self, f, reps: int = 20):
+        fp, bp = C.c_double(), C.c_double()
+        oc = self.opts.c()
+        _check(lib().ss_sart_time_kernels(self._arr, len(self.systems), self._imgs(f), C.byref(oc),
+                                          reps, C.byref(fp), C.byref(bp), _ptr(self.ws),
+                                          self.ws_bytes, _stream(self.ws.device)))
+        return fp.value, bp.value
+
+    def autotune(self, f):
+        oc = self.opts.c()
+        _check(lib().ss_sart_autotune(self._arr, len(self.systems), self._imgs(f), C.byref(oc),
+                                      _ptr(self.ws), self.ws_bytes, _stream(self.ws.device)))
+        self.opts.rows_per_wave = oc.rows_per_wave
+        self.opts.cols_per_wave = oc.cols_per_wave
+        self.opts.xcd_remap = oc.xcd_remap
+        return self.opts
+
+
+def recombine(f12, out=None):
+    """ss_recombine: Theorem 1, eq. (5)."""
+    import torch
+    n = f12.shape[0]
+    if out is None:
+        out = torch.empty(2 * n, dtype=torch.float32, device=f12.device)
+    _check(lib().ss_recombine(_ptr(f12), n, _ptr(out), _stream(f12.device)))
+    return out
+
+
+def image_fold(f, out=None):
+    """ss_image_fold: the inverse of eq. (5)."""
+    import torch
+    N = f.shape[0]
+    if out is None:
+        out = torch.empty((N // 2, 2), dtype=torch.float32, device=f.device)
+    _check(lib().ss_image_fold(_ptr(f), N, _ptr(out), _stream(f.device)))
+    return out
+
+
+def project(A: DeviceMatrix, f, out=None):
+    """ss_project: q = A f."""
+    import torch
+    if out is None:
+        out = torch.empty(A.M, dtype=torch.float32, device=f.device)
+    mc = A.c()
+    _check(lib().ss_project(C.byref(mc), _ptr(f), _ptr(out), _stream(f.device)))
+    return out

@@ -1,0 +1,124 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, builds A on the host exactly like the oracle, and
+rejects bad arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle import geometry as G
+from paper_1902_10559_amd import inputs, native
+
+HEADER = os.path.join(ROOT, "include", "ssart.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ss_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = _declared_functions()
+    for required in ("ss_build_system", "ss_fold", "ss_sart_solve", "ss_recombine"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = native.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+        assert name in native._SIGNATURES, f"binding misses {name}"
+    assert native.lib().ss_version().decode().startswith("ssart")
+
+
+@pytest.mark.parametrize("cfg", [1, 5])
+def test_host_build_system_matches_oracle_bitwise(cfg):
+    g = inputs.geometry_for(cfg)
+    hm = native.build_system(g, nthreads=4)
+    A = G.to_fp32(G.system_matrix(g))
+    assert (hm.M, hm.N, hm.nnz) == (A.shape[0], A.shape[1], A.nnz)
+    assert np.array_equal(hm.row_ptr, A.indptr)
+    assert np.array_equal(hm.col_idx, A.indices)
+    assert np.array_equal(hm.val.view(np.uint32), A.data.view(np.uint32))
+    Ac = A.tocsc()
+    Ac.sort_indices()
+    assert np.array_equal(hm.col_ptr, Ac.indptr)
+    assert np.array_equal(hm.row_idx, Ac.indices)
+    assert np.array_equal(hm.val_t.view(np.uint32), Ac.data.view(np.uint32))
+
+
+def test_host_build_system_is_symmetric_and_thread_count_independent():
+    g = inputs.geometry_cfg1()
+    a = native.build_system(g, nthreads=1)
+    b = native.build_system(g, nthreads=7)
+    assert np.array_equal(a.val, b.val) and np.array_equal(a.col_idx, b.col_idx)
+    assert G.is_symmetric(a.to_scipy())
+
+
+def test_snake_order_matches_oracle_numbering():
+    for nx, nz in [(4, 3), (64, 64), (512, 128)]:
+        s = native.snake_order(nx, nz)
+        c, r = np.meshgrid(np.arange(nx), np.arange(nz))
+        assert np.array_equal(s, G.snake_index(c, r, nz))
+
+
+def _geom(**kw):
+    g = inputs.geometry_cfg1()
+    d = dict(nx=g.nx, nz=g.nz, pitch=g.pitch, src_x=g.src_x, src_z=g.src_z,
+             bin_x=g.bin_x, det_z=g.det_z)
+    d.update(kw)
+    return inputs.Geometry(**d)
+
+
+def test_build_system_rejects_odd_and_asymmetric_geometries():
+    with pytest.raises(native.SSError) as e:
+        native.build_system(_geom(nx=63))
+    assert e.value.code == -2
+    src = inputs.geometry_cfg1().src_x.copy()
+    src[0] += 1e-9
+    with pytest.raises(native.SSError) as e:
+        native.build_system(_geom(src_x=src))
+    assert e.value.code == -3
+    with pytest.raises(native.SSError) as e:
+        native.build_system(_geom(pitch=0.0))
+    assert e.value.code == -1
+
+
+def _fake_system(m=4, n=6, nvals=2):
+    # host-side validation rejects these before any device work, so the
+    # pointers are never dereferenced
+    one = C.c_void_p(16)
+    return native.SystemC(m, n, 10, nvals, 0, one, one, one, one, one, one, one, one, one)
+
+
+def test_sart_options_are_validated_on_the_host():
+    L = native.lib()
+    arr = (native.SystemC * 1)(_fake_system())
+    nb = C.c_size_t()
+    for bad in [dict(lambda_=0.0), dict(lambda_=2.0), dict(max_iter=-1),
+                dict(rows_per_wave=3), dict(cols_per_wave=32),
+                dict(tol=1e-3, check_every=0)]:
+        o = native.SartOptions().c()
+        for k, v in bad.items():
+            setattr(o, k, v)
+        assert L.ss_sart_workspace_bytes(arr, 1, C.byref(o), C.byref(nb)) == -1, bad
+    o = native.SartOptions().c()
+    assert L.ss_sart_workspace_bytes(arr, 1, C.byref(o), C.byref(nb)) == 0
+    assert nb.value > 0
+    mixed = (native.SystemC * 2)(_fake_system(), _fake_system(nvals=1))
+    assert L.ss_sart_workspace_bytes(mixed, 2, C.byref(o), C.byref(nb)) == -1
+
+
+def test_fold_rejects_odd_sizes_before_device_work():
+    L = native.lib()
+    one = C.c_void_p(16)
+    A = native.MatrixDevC(5, 6, 3, one, one, one, one, one, one)
+    n = C.c_int64()
+    st = L.ss_fold_size(C.byref(A), None, one, 4096, C.byref(n), None)
+    assert st == -2
+    assert "even" in L.ss_last_error().decode()
+    assert L.ss_image_fold(one, 7, one, None) == -2

@@ -1,0 +1,182 @@
+"""GPU fold (ss_fold_size / ss_fold / ss_unsplit) against the oracle.
+
+Bar: the shared pattern and every folded value bit-exact (one FP32 add or
+subtract per entry, then round-to-nearest-even for 16-bit storage), p1/p2
+bit-exact, and the reciprocal sums within one FP32 ulp (the FP64 sums are
+taken in a different order on each side)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from conftest import GOLDEN
+from gpu_util import banner, device, oracle_fold32, problem, random_problem, split_values, to_np
+from oracle import split as OSp
+from paper_1902_10559_amd import native
+
+pytestmark = pytest.mark.gpu
+
+
+def _fold(A, p, wdtype="f32"):
+    import torch
+    Ad = device(A)
+    pd = torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).cuda()
+    return Ad, pd, native.fold(Ad, pd, wdtype)
+
+
+def _ulps(a, b):
+    a = np.asarray(a, np.float32).view(np.int32).astype(np.int64)
+    b = np.asarray(b, np.float32).view(np.int32).astype(np.int64)
+    return np.abs(a - b)
+
+
+def _check_against_oracle(A, p, S, wdtype="f32"):
+    ref = oracle_fold32(A)
+    assert S.nnz == ref.nnz
+    assert np.array_equal(to_np(S.row_ptr), ref.indptr)
+    assert np.array_equal(to_np(S.col_idx), ref.indices)
+    assert np.array_equal(to_np(S.col_ptr), ref.cindptr)
+    assert np.array_equal(to_np(S.row_idx), ref.cindices)
+    v1, v2 = split_values(S)
+    c1, c2 = split_values(S, csc=True)
+    if wdtype == "f32":
+        want = [ref.v1, ref.v2, ref.cv1, ref.cv2]
+        got = [v1, v2, c1, c2]
+        for g, w in zip(got, want):
+            assert np.array_equal(g.astype(np.float32).view(np.uint32), w.view(np.uint32))
+    else:
+        for g, w in zip([v1, v2, c1, c2], [ref.v1, ref.v2, ref.cv1, ref.cv2]):
+            assert np.array_equal(g, OSp.round_storage(w, wdtype))
+    p1, p2 = OSp.fold_p(p, "fp32")
+    pp = to_np(S.p).reshape(-1, 2)
+    assert np.array_equal(pp[:, 0].view(np.uint32), p1.view(np.uint32))
+    assert np.array_equal(pp[:, 1].view(np.uint32), p2.view(np.uint32))
+    inv_r = OSp.reciprocal(ref.W, "fp32")
+    inv_c = OSp.reciprocal(ref.V, "fp32")
+    assert _ulps(to_np(S.inv_row), inv_r).max() <= 1
+    assert _ulps(to_np(S.inv_col), inv_c).max() <= 1
+    assert np.array_equal(to_np(S.inv_row) == 0, inv_r == 0)
+
+
+def test_fold_example1_reproduces_the_printed_systems():
+    banner("fold example 1")
+    ex = json.load(open(os.path.join(GOLDEN, "example1.json")))
+    A = sp.csr_matrix(np.array(ex["A"], np.float32))
+    p = np.array(ex["p"], np.float32)
+    _, _, S = _fold(A, p)
+    v1, v2 = split_values(S)
+    rows = np.repeat(np.arange(S.m), np.diff(to_np(S.row_ptr)))
+    D1 = np.zeros((S.m, S.n))
+    D2 = np.zeros((S.m, S.n))
+    D1[rows, to_np(S.col_idx)] = v1
+    D2[rows, to_np(S.col_idx)] = v2
+    assert np.array_equal(D1, ex["A1"]) and np.array_equal(D2, ex["A2"])
+    pp = to_np(S.p).reshape(-1, 2)
+    assert np.array_equal(pp[:, 0], ex["p1"]) and np.array_equal(pp[:, 1], ex["p2"])
+
+
+@pytest.mark.parametrize("seed,M,N,density", [(1, 18, 22, 0.3), (2, 130, 98, 0.1),
+                                              (3, 1002, 514, 0.02), (4, 64, 4, 0.9)])
+def test_fold_random_symmetric_systems_bit_exact(seed, M, N, density):
+    banner(f"fold random seed={seed} M={M} N={N}")
+    pr = random_problem(seed, M, N, density)
+    Ad, pd, S = _fold(pr.A, pr.p)
+    _check_against_oracle(pr.A, pr.p, S)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fold_full_size_configs_bit_exact(cfg):
+    banner(f"fold cfg{cfg}")
+    pr = problem(cfg)
+    Ad, pd, S = _fold(pr.A, pr.p)
+    _check_against_oracle(pr.A, pr.p, S)
+
+
+@pytest.mark.parametrize("wdtype", ["bf16", "f16"])
+def test_fold_16bit_storage_is_rne_of_the_fp32_fold(wdtype):
+    banner(f"fold 16-bit {wdtype}")
+    pr = problem(1)
+    Ad, pd, S = _fold(pr.A, pr.p, wdtype)
+    _check_against_oracle(pr.A, pr.p, S, wdtype)
+
+
+def test_fold_is_deterministic():
+    banner("fold determinism")
+    pr = random_problem(5, 300, 200, 0.05)
+    _, _, S1 = _fold(pr.A, pr.p)
+    _, _, S2 = _fold(pr.A, pr.p)
+    for a, b in [(S1.val, S2.val), (S1.val_t, S2.val_t), (S1.inv_row, S2.inv_row),
+                 (S1.inv_col, S2.inv_col)]:
+        assert np.array_equal(to_np(a).view(np.uint32), to_np(b).view(np.uint32))
+
+
+def _expect_error(A_host, p, code):
+    import torch
+    Ad = native.to_device(A_host, "cuda")
+    pd = torch.from_numpy(p).cuda()
+    with pytest.raises(native.SSError) as e:
+        native.fold_size(Ad, pd)
+    assert e.value.code == code, str(e.value)
+
+
+def test_fold_size_rejects_bad_inputs():
+    from gpu_util import host_matrix
+    banner("fold error paths")
+    pr = random_problem(6, 40, 30, 0.2)
+    base = host_matrix(pr.A)
+    # eq. (2) violated by one weight
+    h = host_matrix(pr.A)
+    h.val = h.val.copy()
+    h.val[3] = np.nextafter(h.val[3], np.float32(10))
+    _expect_error(h, pr.p, -3)
+    # CSC copy symmetric but holding other values than the CSR copy
+    h = host_matrix(pr.A)
+    h.val_t = h.val_t.copy()
+    N = h.N
+    j = int(np.argmax(np.diff(h.col_ptr) > 0))
+    q = h.col_ptr[j]
+    jm = N - 1 - j
+    qm = h.col_ptr[jm + 1] - 1 - (q - h.col_ptr[j])
+    h.val_t[q] *= 2
+    h.val_t[qm] *= 2
+    _expect_error(h, pr.p, -4)
+    # CSC copy breaking eq. (2)
+    h = host_matrix(pr.A)
+    h.val_t = h.val_t.copy()
+    h.val_t[q] *= 2
+    _expect_error(h, pr.p, -3)
+    # NaN in p
+    p = pr.p.copy()
+    p[7] = np.nan
+    _expect_error(base, p, -5)
+    # unsorted row
+    h = host_matrix(pr.A)
+    h.col_idx = h.col_idx.copy()
+    s = h.row_ptr[1]
+    if h.row_ptr[2] - s >= 2:
+        h.col_idx[s], h.col_idx[s + 1] = h.col_idx[s + 1], h.col_idx[s]
+        _expect_error(h, pr.p, -4)
+    # offsets past nnz
+    h = host_matrix(pr.A)
+    h.row_ptr = h.row_ptr.copy()
+    h.row_ptr[-1] += 5
+    _expect_error(h, pr.p, -4)
+
+
+def test_unsplit_sums_match_oracle():
+    import torch
+    banner("unsplit sums")
+    pr = problem(1)
+    Ad = device(pr.A)
+    pd = torch.from_numpy(pr.p).cuda()
+    S = native.unsplit(Ad, pd)
+    W = np.asarray(pr.A.astype(np.float64).sum(axis=1)).ravel()
+    V = np.asarray(pr.A.astype(np.float64).sum(axis=0)).ravel()
+    assert _ulps(to_np(S.inv_row), OSp.reciprocal(W, "fp32")).max() <= 1
+    assert _ulps(to_np(S.inv_col), OSp.reciprocal(V, "fp32")).max() <= 1
+    assert np.array_equal(to_np(S.p), pr.p)
+    Sb = native.unsplit(Ad, pd, "bf16")
+    bits = to_np(Sb.val).view(np.uint16)
+    assert np.array_equal(bits, OSp.storage_bits(pr.A.data, "bf16"))

@@ -1,0 +1,167 @@
+"""GPU SART (ss_sart_solve) against the FP64 oracle.
+
+Bars: the recombined FP32 image within 1e-5 relative L2 of the FP64 oracle
+after 20 iterations, the residual history within 1e-5 relative; batched
+solves bitwise equal to solo solves; graph replay bitwise equal to plain
+launches; resumed runs bitwise equal to one long run."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, device, problem, random_problem, rel_l2, to_np
+from oracle import sart as OS
+from oracle import split as OSp
+from paper_1902_10559_amd import native
+
+pytestmark = pytest.mark.gpu
+
+
+def _split_system(pr, wdtype="f32"):
+    import torch
+    Ad = device(pr.A)
+    pd = torch.from_numpy(pr.p).cuda()
+    return Ad, pd, native.fold(Ad, pd, wdtype)
+
+
+def _solve(systems, iters, f=None, hist=True, **kw):
+    import torch
+    opts = native.SartOptions(lam=kw.pop("lam", 0.5), max_iter=iters, **kw)
+    sol = native.Solver(systems, opts)
+    if f is None:
+        f = [S.new_image() for S in systems]
+    h = [torch.full((iters + 1,), -1.0, dtype=torch.float64, device="cuda") for _ in systems] if hist else None
+    status, it = sol.solve(f, h)
+    return f, h, status, it
+
+
+@pytest.mark.parametrize("cfg,iters", [(1, 20), (2, 20)])
+def test_split_sart_matches_fp64_oracle(cfg, iters):
+    banner(f"split SART cfg{cfg} {iters} iterations")
+    pr = problem(cfg)
+    _, _, S = _split_system(pr)
+    f, h, status, it = _solve([S], iters)
+    assert status == 0 and it == [iters]
+    img = to_np(native.recombine(f[0]))
+    f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, iters)
+    assert rel_l2(img, f_ref) <= 1e-5
+    assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=0)
+    # the halves themselves against the oracle's split iteration
+    Sref = OSp.fold(pr.A)
+    p1, p2 = OSp.fold_p(pr.p)
+    g1, g2, res_s = OS.sart_split(Sref, p1, p2, 0.5, iters)
+    f12 = to_np(f[0])
+    assert rel_l2(f12[:, 0], g1) <= 1e-5 and rel_l2(f12[:, 1], g2) <= 1e-5
+
+
+def test_split_sart_cfg2_100_iterations_matches_oracle():
+    # the benchmark workload at full size and iteration count
+    banner("split SART cfg2 100 iterations")
+    pr = problem(2)
+    _, _, S = _split_system(pr)
+    f, h, status, it = _solve([S], 100)
+    f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 100)
+    err = rel_l2(to_np(native.recombine(f[0])), f_ref)
+    banner(f"cfg2 100 iterations rel L2 {err:.3e}")
+    assert err <= 1e-4
+    assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=0)
+
+
+def test_unsplit_sart_matches_fp64_oracle():
+    import torch
+    banner("unsplit SART cfg1")
+    pr = problem(1)
+    Ad = device(pr.A)
+    pd = torch.from_numpy(pr.p).cuda()
+    U = native.unsplit(Ad, pd)
+    f, h, status, it = _solve([U], 20)
+    f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20)
+    assert rel_l2(to_np(f[0]), f_ref) <= 1e-5
+    assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=0)
+
+
+def test_random_ragged_systems_match_oracle():
+    banner("split SART random ragged")
+    for seed, M, N in [(11, 1002, 514), (12, 66, 130), (13, 2, 2)]:
+        pr = random_problem(seed, M, N, 0.05 if M > 100 else 0.3)
+        _, _, S = _split_system(pr)
+        f, h, status, it = _solve([S], 20)
+        f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20)
+        if np.linalg.norm(f_ref) > 0:
+            assert rel_l2(to_np(native.recombine(f[0])), f_ref) <= 1e-5
+        assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=1e-12)
+
+
+def test_batched_solve_equals_solo_solves_bitwise():
+    banner("batched vs solo")
+    probs = [problem(1), random_problem(21, 1002, 514, 0.05), random_problem(22, 130, 98, 0.1)]
+    systems = [_split_system(pr)[2] for pr in probs]
+    fb, hb, _, itb = _solve(systems, 15)
+    for k, S in enumerate(systems):
+        fs, hs, _, its = _solve([S], 15)
+        assert np.array_equal(to_np(fb[k]).view(np.uint32), to_np(fs[0]).view(np.uint32))
+        assert np.array_equal(to_np(hb[k]), to_np(hs[0]))
+
+
+def test_graph_replay_and_plain_launches_agree_bitwise_and_runs_repeat():
+    banner("graph vs plain, determinism")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    a, ha, _, _ = _solve([S], 25, use_graph=True)
+    b, hb, _, _ = _solve([S], 25, use_graph=False)
+    c, hc, _, _ = _solve([S], 25, use_graph=True)
+    assert np.array_equal(to_np(a[0]).view(np.uint32), to_np(b[0]).view(np.uint32))
+    assert np.array_equal(to_np(a[0]).view(np.uint32), to_np(c[0]).view(np.uint32))
+    assert np.array_equal(to_np(ha[0]), to_np(hb[0]))
+
+
+def test_resume_from_a_warm_start_equals_one_long_run():
+    banner("warm-start resume")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    a, _, _, _ = _solve([S], 20)
+    b, _, _, _ = _solve([S], 10)
+    b, _, _, _ = _solve([S], 10, f=b)
+    assert np.array_equal(to_np(a[0]).view(np.uint32), to_np(b[0]).view(np.uint32))
+
+
+def test_early_exit_at_tolerance():
+    banner("early exit")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 60)
+    tol = float(np.sqrt(res_ref[37] * res_ref[38]))   # between iterates 37 and 38
+    f, h, status, it = _solve([S], 60, tol=tol, check_every=7)
+    assert status == 0 and it == [38]
+    hist = to_np(h[0])
+    assert hist[38] <= tol < hist[37]
+    assert np.all(hist[39:] == -1.0)       # nothing written after the stop
+    fr, _ = OS.sart_full(pr.A, pr.p, 0.5, 38)
+    assert rel_l2(to_np(native.recombine(f[0])), fr) <= 1e-5
+    # unreachable tolerance: warning status, capped count
+    f, h, status, it = _solve([S], 12, tol=1e-9, check_every=5)
+    assert status == 1 and it == [12]
+
+
+@pytest.mark.parametrize("rpw,cpw,xcd", [(1, 1, 0), (2, 4, 1), (4, 8, 0), (8, 16, 1)])
+def test_launch_shapes_agree_with_oracle(rpw, cpw, xcd):
+    banner(f"launch shape rpw={rpw} cpw={cpw} xcd={xcd}")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    f, h, _, _ = _solve([S], 20, rows_per_wave=rpw, cols_per_wave=cpw, xcd_remap=xcd)
+    f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20)
+    assert rel_l2(to_np(native.recombine(f[0])), f_ref) <= 1e-5
+
+
+def test_autotune_and_kernel_timing_run():
+    banner("autotune")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    sol = native.Solver([S], native.SartOptions(max_iter=20))
+    scratch = [S.new_image()]
+    opts = sol.autotune(scratch)
+    assert opts.rows_per_wave in (1, 2, 4, 8) and opts.cols_per_wave in (1, 2, 4, 8, 16)
+    fp, bp = sol.time_kernels(scratch, reps=5)
+    assert fp > 0 and bp > 0
+    f = [S.new_image()]
+    sol.solve(f)
+    f_ref, _ = OS.sart_full(pr.A, pr.p, 0.5, 20)
+    assert rel_l2(to_np(native.recombine(f[0])), f_ref) <= 1e-5

@@ -141,3 +141,20 @@ def test_shared_pattern_keeps_cancelled_entries_and_csc_matches_csr():
     for j in range(S.n):
         seg = S.cindices[S.cindptr[j]:S.cindptr[j + 1]]
         assert np.all(np.diff(seg) > 0)
+
+
+def test_bf16_and_f16_rounding_match_library_conversions():
+    import torch
+    rng = np.random.default_rng(13)
+    v = (rng.standard_normal(100000) * 10.0 ** rng.integers(-6, 6, 100000)).astype(np.float32)
+    # exact ties: bf16 values plus half a bf16 ulp
+    base = (v.view(np.uint32) & 0xFFFF0000).view(np.float32)
+    ties = (base.view(np.uint32) | 0x8000).view(np.float32)
+    v = np.concatenate([v, ties, np.float32([0.0, -0.0, 1.0, 3.0e38, -1.5e-40])])
+    want = torch.from_numpy(v).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(split.storage_bits(v, "bf16"), want)
+    assert np.array_equal(split.storage_bits(v, "f16"), v.astype(np.float16).view(np.uint16))
+    # rounding is to nearest: error at most half an ulp of 8 (bf16) bits
+    r = split.round_storage(v[:100000], "bf16")
+    nz = v[:100000] != 0
+    assert np.max(np.abs(r[nz] - v[:100000][nz]) / np.abs(v[:100000][nz])) <= 2.0 ** -8
