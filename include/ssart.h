@@ -23,6 +23,7 @@
  *     are valid; < 0 is an error, and then no output has been written (for
  *     the asynchronous device calls: no work has been enqueued).  The text of
  *     the last error on the calling thread is returned by ss_last_error().
+ *   - Arrays of length 0 (an empty matrix, nnz = 0) may be NULL.
  *   - "device" pointers are caller-owned device memory of the current HIP
  *     device; the library never frees caller memory, and device calls never
  *     allocate device memory (scratch comes from caller workspaces).
@@ -217,6 +218,8 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *                  choose)
  *   xcd_remap    1: give each of the 8 XCDs a contiguous range of rows or
  *                columns (the hardware deals workgroups round-robin)
+ *   zero_start   1: start from f^0 = 0 (the solver clears f itself);
+ *                0: start from the image the caller passes
  * rel_res(f^k) = ||p - A f^k|| / ||p||, from the halves as
  *   sqrt((||r1||^2 + ||r2||^2) / (||p1||^2 + ||p2||^2)), FP64. */
 typedef struct {
@@ -228,6 +231,7 @@ typedef struct {
   int32_t rows_per_wave;
   int32_t cols_per_wave;
   int32_t xcd_remap;
+  int32_t zero_start;
 } ss_sart_opts;
 
 /* Workspace bytes for solving `nsys` systems together with these options. */
@@ -236,8 +240,8 @@ ss_status ss_sart_workspace_bytes(const ss_system* sys, int32_t nsys,
 
 /* Solves nsys independent systems in the same launches.
  *   f[s]        device, nvals*n floats: start image on entry (interleaved
- *               halves; zero for f^0 = 0, or ss_image_fold of a start),
- *               final iterate on return.
+ *               halves: zeros, or ss_image_fold of a start; ignored with
+ *               zero_start), final iterate on return.
  *   res_hist[s] device, max_iter+1 doubles: res_hist[s][k] = rel_res(f^k)
  *               for k = 0 .. iters[s]; entries after that are not written.
  *   iters       host, nsys ints, or NULL: updates applied per system.

@@ -370,9 +370,10 @@ inline unsigned blocks_for(int64_t lines) {
 }
 
 ss_status check_dev_matrix(const ss_matrix_dev* A, const char* fn) {
-  if (!A || !A->row_ptr || !A->col_idx || !A->val || !A->col_ptr || !A->row_idx || !A->val_t)
-    return fail(SS_E_ARG, "%s: NULL matrix array", fn);
+  if (!A || !A->row_ptr || !A->col_ptr) return fail(SS_E_ARG, "%s: NULL matrix array", fn);
   if (A->M <= 0 || A->N <= 0 || A->nnz < 0) return fail(SS_E_ARG, "%s: bad matrix size", fn);
+  if (A->nnz > 0 && (!A->col_idx || !A->val || !A->row_idx || !A->val_t))
+    return fail(SS_E_ARG, "%s: NULL matrix array", fn);
   if (A->M > INT32_MAX || A->N > INT32_MAX) return fail(SS_E_ARG, "%s: M and N must fit in int32", fn);
   return SS_OK;
 }
@@ -434,8 +435,8 @@ extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* 
     return fail(SS_E_ARG, "ss_fold: out must be m = M/2, n = N/2, nvals = 2");
   if (out->wdtype != SS_F32 && out->wdtype != SS_BF16 && out->wdtype != SS_F16)
     return fail(SS_E_ARG, "ss_fold: unknown wdtype %d", out->wdtype);
-  if (!out->row_ptr || !out->col_idx || !out->val || !out->col_ptr || !out->row_idx || !out->val_t ||
-      !out->p || !out->inv_row || !out->inv_col)
+  if (!out->row_ptr || !out->col_ptr || !out->p || !out->inv_row || !out->inv_col ||
+      (out->nnz > 0 && (!out->col_idx || !out->val || !out->row_idx || !out->val_t)))
     return fail(SS_E_ARG, "ss_fold: NULL output array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const unsigned nbr = blocks_for(out->m), nbc = blocks_for(out->n);
@@ -457,8 +458,8 @@ extern "C" ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_syste
     return fail(SS_E_ARG, "ss_unsplit: out must be m = M, n = N, nnz = nnz(A), nvals = 1");
   if (out->wdtype != SS_F32 && out->wdtype != SS_BF16 && out->wdtype != SS_F16)
     return fail(SS_E_ARG, "ss_unsplit: unknown wdtype %d", out->wdtype);
-  if (!out->row_ptr || !out->col_idx || !out->val || !out->col_ptr || !out->row_idx || !out->val_t ||
-      !out->p || !out->inv_row || !out->inv_col)
+  if (!out->row_ptr || !out->col_ptr || !out->p || !out->inv_row || !out->inv_col ||
+      (out->nnz > 0 && (!out->col_idx || !out->val || !out->row_idx || !out->val_t)))
     return fail(SS_E_ARG, "ss_unsplit: NULL output array");
   if (out->wdtype == SS_F32 && (out->val != A->val || out->val_t != A->val_t))
     return fail(SS_E_ARG, "ss_unsplit: FP32 values must alias A's arrays");

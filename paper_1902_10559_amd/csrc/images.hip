@@ -67,7 +67,8 @@ extern "C" ss_status ss_image_fold(const float* f, int64_t N, float* f12, void* 
 
 extern "C" ss_status ss_project(const ss_matrix_dev* A, const float* f, float* q, void* stream) {
   clear_error();
-  if (!A || !A->row_ptr || !A->col_idx || !A->val || !f || !q || A->M <= 0 || A->N <= 0)
+  if (!A || !A->row_ptr || !f || !q || A->M <= 0 || A->N <= 0 || A->nnz < 0 ||
+      (A->nnz > 0 && (!A->col_idx || !A->val)))
     return fail(SS_E_ARG, "ss_project: bad argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   k_project<<<static_cast<unsigned>((A->M + kProjWaves - 1) / kProjWaves), kWave * kProjWaves, 0, st>>>(*A, f, q);

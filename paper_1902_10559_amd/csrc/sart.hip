@@ -6,14 +6,21 @@
 //
 // One iteration is two kernels:
 //   k_sart_fp  forward projection, residual and scaled residual: per row i,
-//              q = A[i,:] f, r = p[i] - q, z[i] = r * inv_row[i]; FP64 block
-//              partials of |r|^2; the last block of a system to finish (an
-//              atomic ticket) sums the partials in index order, records
-//              rel_res(f^k) and decides whether the system stops.
+//              q = A[i,:] f, r = p[i] - q, z[i] = r * inv_row[i]; one FP64
+//              partial of |r|^2 per block.
 //   k_sart_bp  back projection and update from the pre-transposed (CSC)
-//              copy: per column j, b = A[:,j]^T z, f[j] += lambda *
+//              copy: per column j, b = A[:,j]^T z, f'[j] = f[j] + lambda *
 //              inv_col[j] * b.  Every column is owned by one lane group, so
-//              the update needs no atomics.
+//              the update needs no atomics.  The first block of each system
+//              also sums the forward partials in index order (the kernel
+//              boundary has made them visible), records rel_res(f^k) and
+//              decides whether the system stops.
+// The iterate alternates between two buffers (the caller's image and one in
+// the workspace): f^k lives in buffer k mod 2.  A stop decided during the
+// back projection of iteration k therefore leaves f^k intact even if other
+// blocks of that launch already wrote f^{k+1} into the other buffer; a final
+// kernel copies f^k into the caller's image when k is odd.  No block ever
+// waits for another, and no cross-XCD fence is needed inside a kernel.
 // Rows (columns) are processed by groups of 64/RPW (64/CPW) lanes of a
 // wavefront; lanes stride over the row's entries (coalesced loads of indices
 // and values), partial sums are combined by a fixed butterfly, so results are
@@ -21,8 +28,10 @@
 // blocks of all systems form one grid per kernel.
 //
 // Per-system state lives in the caller's workspace: k (index of the current
-// iterate), stop flag, ticket, ||p||^2.  Kernels of a stopped system exit at
-// once, so a replayed graph may overshoot the iteration count harmlessly.
+// iterate), stop and pending flags, ||p||^2.  k changes only in the first
+// forward block (so it is constant during a back projection), stop only in
+// the first back-projection block.  Kernels of a stopped system exit at once,
+// so a replayed graph may overshoot the iteration count harmlessly.
 
 #include <algorithm>
 #include <cmath>
@@ -43,11 +52,11 @@ constexpr int kThreads = kWave * kWPB;
 
 struct SysState {
   double pnorm2;     // ||p||^2 over all halves
-  double last_res;   // rel_res of the final iterate
+  double last_res;   // rel_res of the latest evaluated iterate
   int32_t k;         // index of the current iterate f^k
-  int32_t stop;      // 1: no more updates
-  uint32_t ticket;   // forward-projection blocks finished this iteration
-  uint32_t pad;
+  int32_t stop;      // 1: f^k is final (written once, 0 -> 1)
+  int32_t pending;   // 1: the next forward pass moves on to f^{k+1}
+  int32_t pad;
 };
 
 struct SysDesc {
@@ -60,7 +69,7 @@ struct SysDesc {
   const float* p;
   const float* inv_row;
   const float* inv_col;
-  float* f;
+  float* f[2];       // [0] the caller's image, [1] the workspace buffer
   float* z;
   double* res_hist;
   double* partials;
@@ -74,6 +83,10 @@ struct Params {
   float lambda;
   int32_t max_iter;
   double tol;
+};
+
+struct SetupFlags {
+  int32_t zero_start;
 };
 
 constexpr int kDescChunk = 16;
@@ -107,9 +120,11 @@ __device__ inline int find_sys(const SysDesc* t, int nsys, int64_t b) {
 // system's state; block b also reduces ||p||^2 of its system.
 template <int NV>
 __global__ __launch_bounds__(kThreads) void k_setup(DescChunk ch, SysDesc* table, Params prm_in,
-                                                    Params* prm) {
+                                                    Params* prm, SetupFlags fl) {
   const int b = blockIdx.x;
   const SysDesc& d = ch.d[b];
+  if (fl.zero_start)
+    for (int64_t i = threadIdx.x; i < d.n * NV; i += kThreads) d.f[0][i] = 0.0f;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < d.m * NV; i += kThreads) {
     const double v = d.p[i];
@@ -123,23 +138,36 @@ __global__ __launch_bounds__(kThreads) void k_setup(DescChunk ch, SysDesc* table
     d.st->last_res = 0.0;
     d.st->k = 0;
     d.st->stop = 0;
-    d.st->ticket = 0u;
+    d.st->pending = 0;
     if (ch.first == 0 && b == 0) *prm = prm_in;
   }
 }
 
+__device__ inline int load_flag(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void store_flag(int32_t* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int NV, int WT, int RPW>
-__global__ __launch_bounds__(kThreads) void k_sart_fp(const Params* prm, const SysDesc* table, int nsys,
-                                                      uint32_t nblocks, int xcd) {
+__global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* table, int nsys, uint32_t nblocks,
+                                                      int xcd, int parity) {
   const uint32_t b = xcd ? xcd_remap(blockIdx.x, nblocks) : blockIdx.x;
   const int s = nsys == 1 ? 0 : find_sys<false>(table, nsys, b);
   const SysDesc& S = table[s];
   SysState* st = S.st;
-  if (st->stop) return;
+  if (load_flag(&st->stop)) return;
   constexpr int L = kWave / RPW;
   const int lane = lane_id();
   const int gl = lane % L;
   const int64_t local = static_cast<int64_t>(b) - S.fp_block0;
+  if (local == 0 && threadIdx.x == 0 && st->pending) {
+    st->k += 1;
+    st->pending = 0;
+  }
+  const float* f = S.f[parity];
   const int64_t row = local * (RPW * kWPB) + wave_id() * RPW + lane / L;
   float acc[NV];
 #pragma unroll
@@ -149,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_sart_fp(const Params* prm, const S
     for (int64_t k = S.row_ptr[row] + gl; k < re; k += L) {
       const int32_t c = S.col_idx[k];
       const Vec<NV> v = load_vals<NV, WT>(S.val, k);
-      const Vec<NV> fv = load_vec<NV>(S.f, c);
+      const Vec<NV> fv = load_vec<NV>(f, c);
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = fmaf(v.v[h], fv.v[h], acc[h]);
     }
@@ -170,44 +198,50 @@ __global__ __launch_bounds__(kThreads) void k_sart_fp(const Params* prm, const S
     store_vec<NV>(S.z, row, zv);
   }
   __shared__ double red[kWPB];
-  __shared__ int last;
   const double tot = block_sum<kWPB>(d, red);
-  if (threadIdx.x == 0) {
-    S.partials[local] = tot;
-    __threadfence();
-    const uint32_t prev = atomicAdd(&st->ticket, 1u);
-    last = prev == static_cast<uint32_t>(S.fp_nblocks - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double acc2 = 0.0;
-  for (int64_t t = threadIdx.x; t < S.fp_nblocks; t += kThreads) acc2 += S.partials[t];
-  const double rsum = block_sum<kWPB>(acc2, red);
+  if (threadIdx.x == 0) S.partials[local] = tot;
+}
+
+// The first back-projection block of a system: rel_res(f^k) from the forward
+// partials in index order, the history entry, and the stop decision.
+template <int WPB>
+__device__ void finalize_residual(const Params* prm, const SysDesc& S, double* red) {
+  SysState* st = S.st;
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < S.fp_nblocks; t += WPB * kWave) acc += S.partials[t];
+  const double rsum = block_sum<WPB>(acc, red);
   if (threadIdx.x == 0) {
     const double pn = st->pnorm2;
     const double rel = pn > 0.0 ? sqrt(rsum / pn) : sqrt(rsum);
     const int k = st->k;
     if (S.res_hist) S.res_hist[k] = rel;
     st->last_res = rel;
-    if (rel <= prm->tol || k >= prm->max_iter) st->stop = 1;
-    else st->k = k + 1;
-    st->ticket = 0u;
+    if (rel <= prm->tol || k >= prm->max_iter) store_flag(&st->stop, 1);
+    else st->pending = 1;
   }
 }
 
 template <int NV, int WT, int CPW>
 __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* prm, const SysDesc* table, int nsys,
-                                                      uint32_t nblocks, int xcd) {
+                                                      uint32_t nblocks, int xcd, int parity) {
   const uint32_t b = xcd ? xcd_remap(blockIdx.x, nblocks) : blockIdx.x;
   const int s = nsys == 1 ? 0 : find_sys<true>(table, nsys, b);
   const SysDesc& S = table[s];
-  if (S.st->stop) return;
+  SysState* st = S.st;
+  if (load_flag(&st->stop)) return;
+  const int64_t local = static_cast<int64_t>(b) - S.bp_block0;
+  if (local == 0) {
+    __shared__ double red[kWPB];
+    finalize_residual<kWPB>(prm, S, red);
+  }
+  // f^k with k = max_iter is final: its residual is all that was wanted
+  if (st->k >= prm->max_iter) return;
   constexpr int L = kWave / CPW;
   const int lane = lane_id();
   const int gl = lane % L;
-  const int64_t local = static_cast<int64_t>(b) - S.bp_block0;
   const int64_t col = local * (CPW * kWPB) + wave_id() * CPW + lane / L;
+  const float* f = S.f[parity];
+  float* fn = S.f[parity ^ 1];
   float acc[NV];
 #pragma unroll
   for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
@@ -225,17 +259,26 @@ __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* prm, const S
   for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
   if (gl == 0 && col < S.n) {
     const float t = prm->lambda * S.inv_col[col];
-    Vec<NV> fv = load_vec<NV>(S.f, col);
+    Vec<NV> fv = load_vec<NV>(f, col);
 #pragma unroll
     for (int h = 0; h < NV; ++h) fv.v[h] = fmaf(t, acc[h], fv.v[h]);
-    store_vec<NV>(S.f, col, fv);
+    store_vec<NV>(fn, col, fv);
   }
+}
+
+// Copies f^k into the caller's image when it sits in the workspace buffer.
+template <int NV>
+__global__ __launch_bounds__(kThreads) void k_finish(const SysDesc* table) {
+  const SysDesc& S = table[blockIdx.x];
+  if ((S.st->k & 1) == 0) return;
+  const int64_t cnt = S.n * NV;
+  for (int64_t i = threadIdx.x; i < cnt; i += kThreads) S.f[0][i] = S.f[1][i];
 }
 
 // ------------------------------------------------------------------ host
 struct Layout {
   size_t params, table, states, z, partials, total;
-  std::vector<size_t> z_off, part_off;
+  std::vector<size_t> z_off, part_off, f_off;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
@@ -253,6 +296,10 @@ Layout make_layout(const ss_system* sys, int nsys) {
   for (int s = 0; s < nsys; ++s) {
     L.z_off.push_back(o);
     o += align256(sizeof(float) * static_cast<size_t>(sys[s].m * sys[s].nvals));
+  }
+  for (int s = 0; s < nsys; ++s) {
+    L.f_off.push_back(o);
+    o += align256(sizeof(float) * static_cast<size_t>(sys[s].n * sys[s].nvals));
   }
   L.partials = o;
   for (int s = 0; s < nsys; ++s) {
@@ -278,8 +325,8 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
     if (S.nvals != 1 && S.nvals != 2) return fail(SS_E_ARG, "%s: nvals must be 1 or 2", fn);
     if (S.wdtype != SS_F32 && S.wdtype != SS_BF16 && S.wdtype != SS_F16)
       return fail(SS_E_ARG, "%s: unknown wdtype", fn);
-    if (!S.row_ptr || !S.col_idx || !S.val || !S.col_ptr || !S.row_idx || !S.val_t || !S.p ||
-        !S.inv_row || !S.inv_col)
+    if (!S.row_ptr || !S.col_ptr || !S.p || !S.inv_row || !S.inv_col ||
+        (S.nnz > 0 && (!S.col_idx || !S.val || !S.row_idx || !S.val_t)))
       return fail(SS_E_ARG, "%s: system %d has a NULL array", fn, s);
     if (S.m > INT32_MAX || S.n > INT32_MAX) return fail(SS_E_ARG, "%s: system %d too large", fn, s);
   }
@@ -321,7 +368,7 @@ struct Grids {
 // Writes the descriptor table and resets states (stream-ordered kernels).
 ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* res_hist,
                 const Params& prm, const Cfg& c, const Layout& L, char* ws, Grids* g,
-                hipStream_t st) {
+                int zero_start, hipStream_t st) {
   int64_t fb = 0, bb = 0;
   const int64_t rpb = static_cast<int64_t>(c.rpw) * kWPB, cpb = static_cast<int64_t>(c.cpw) * kWPB;
   DescChunk ch{};
@@ -339,7 +386,8 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
     d.p = S.p;
     d.inv_row = S.inv_row;
     d.inv_col = S.inv_col;
-    d.f = f[s];
+    d.f[0] = f[s];
+    d.f[1] = reinterpret_cast<float*>(ws + L.f_off[s]);
     d.z = reinterpret_cast<float*>(ws + L.z_off[s]);
     d.res_hist = res_hist ? res_hist[s] : nullptr;
     d.partials = reinterpret_cast<double*>(ws + L.part_off[s]);
@@ -354,8 +402,9 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
     bb += d.bp_nblocks;
     ch.d[ch.count++] = d;
     if (ch.count == kDescChunk || s == nsys - 1) {
-      if (c.nv == 2) k_setup<2><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm);
-      else k_setup<1><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm);
+      const SetupFlags fl{zero_start};
+      if (c.nv == 2) k_setup<2><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm, fl);
+      else k_setup<1><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm, fl);
       ch.first = s + 1;
       ch.count = 0;
     }
@@ -368,34 +417,36 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
 }
 
 template <int NV, int WT>
-void launch_fp_t(int rpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, hipStream_t st) {
+void launch_fp_t(int rpw, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st) {
   switch (rpw) {
-    case 1: k_sart_fp<NV, WT, 1><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
-    case 2: k_sart_fp<NV, WT, 2><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
-    case 4: k_sart_fp<NV, WT, 4><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
-    default: k_sart_fp<NV, WT, 8><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    case 1: k_sart_fp<NV, WT, 1><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
+    case 2: k_sart_fp<NV, WT, 2><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
+    case 4: k_sart_fp<NV, WT, 4><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
+    default: k_sart_fp<NV, WT, 8><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
   }
 }
 
 template <int NV, int WT>
-void launch_bp_t(int cpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, hipStream_t st) {
+void launch_bp_t(int cpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
+                 hipStream_t st) {
   switch (cpw) {
-    case 1: k_sart_bp<NV, WT, 1><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
-    case 2: k_sart_bp<NV, WT, 2><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
-    case 4: k_sart_bp<NV, WT, 4><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
-    case 8: k_sart_bp<NV, WT, 8><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
-    default: k_sart_bp<NV, WT, 16><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd); break;
+    case 1: k_sart_bp<NV, WT, 1><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
+    case 2: k_sart_bp<NV, WT, 2><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
+    case 4: k_sart_bp<NV, WT, 4><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
+    case 8: k_sart_bp<NV, WT, 8><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
+    default: k_sart_bp<NV, WT, 16><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
   }
 }
 
 template <bool BP>
-void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, hipStream_t st) {
+void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int par,
+                   hipStream_t st) {
   const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
 #define SS_DISPATCH(NV, WT)                                                         \
   if (c.nv == NV && c.wt == WT) {                                                   \
-    if (BP) launch_bp_t<NV, WT>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, st);        \
-    else launch_fp_t<NV, WT>(c.rpw, prm, t, nsys, g.fp_blocks, c.xcd, st);           \
+    if (BP) launch_bp_t<NV, WT>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, par, st);   \
+    else launch_fp_t<NV, WT>(c.rpw, t, nsys, g.fp_blocks, c.xcd, par, st);           \
     return;                                                                         \
   }
   SS_DISPATCH(2, SS_F32)
@@ -407,12 +458,20 @@ void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, cons
 #undef SS_DISPATCH
 }
 
-void launch_iterations(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int count,
-                       hipStream_t st) {
+// `count` iterations; iteration i reads buffer (first + i) mod 2.
+void launch_iterations(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int64_t first,
+                       int count, hipStream_t st) {
   for (int i = 0; i < count; ++i) {
-    launch_kernel<false>(c, ws, L, nsys, g, st);
-    launch_kernel<true>(c, ws, L, nsys, g, st);
+    const int par = static_cast<int>((first + i) & 1);
+    launch_kernel<false>(c, ws, L, nsys, g, par, st);
+    launch_kernel<true>(c, ws, L, nsys, g, par, st);
   }
+}
+
+void launch_finish(const Cfg& c, const char* ws, const Layout& L, int nsys, hipStream_t st) {
+  const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
+  if (c.nv == 2) k_finish<2><<<nsys, kThreads, 0, st>>>(t);
+  else k_finish<1><<<nsys, kThreads, 0, st>>>(t);
 }
 
 // ----------------------------------------------------------- graph cache
@@ -462,7 +521,7 @@ ss_status get_graph(const GraphKey& key, const Cfg& c, const char* ws, const Lay
     cs = sit->second;
   }
   SS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  launch_iterations(c, ws, L, key.nsys, g, key.count, cs);
+  launch_iterations(c, ws, L, key.nsys, g, 0, key.count, cs);
   hipGraph_t graph;
   const hipError_t ce = hipStreamEndCapture(cs, &graph);
   if (ce != hipSuccess) return fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
@@ -511,10 +570,12 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   const Cfg c = choose_cfg(sys, nsys, opts);
   Params prm{opts->lambda, opts->max_iter, opts->tol};
   Grids g{};
-  if (ss_status s = setup(sys, nsys, f, res_hist, prm, c, L, ws, &g, st)) return s;
+  if (ss_status s = setup(sys, nsys, f, res_hist, prm, c, L, ws, &g, opts->zero_start, st)) return s;
   const int64_t total = static_cast<int64_t>(opts->max_iter) + 1;  // forward passes incl. the final residual
-  const int chunk = opts->tol > 0.0 ? static_cast<int>(std::min<int64_t>(opts->check_every, total))
-                                    : static_cast<int>(std::min<int64_t>(total, 256));
+  // an even chunk keeps the buffer parity of every replay aligned
+  int chunk = opts->tol > 0.0 ? static_cast<int>(std::min<int64_t>(opts->check_every, total))
+                              : static_cast<int>(std::min<int64_t>(total, 256));
+  chunk += chunk & 1;
   hipGraphExec_t exec = nullptr;
   if (opts->use_graph) {
     int dev = 0;
@@ -527,7 +588,7 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
     if (exec) {
       SS_HIP_TRY(hipGraphLaunch(exec, st));
     } else {
-      launch_iterations(c, ws, L, nsys, g, static_cast<int>(std::min<int64_t>(chunk, total - done)), st);
+      launch_iterations(c, ws, L, nsys, g, done, static_cast<int>(std::min<int64_t>(chunk, total - done)), st);
       SS_HIP_TRY(hipGetLastError());
     }
     if (opts->tol > 0.0 && done + chunk < total) {
@@ -537,6 +598,8 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
       if (all) break;
     }
   }
+  launch_finish(c, ws, L, nsys, st);
+  SS_HIP_TRY(hipGetLastError());
   if (!iters && opts->tol <= 0.0) return SS_OK;
   if (ss_status s = read_states(ws, L, nsys, &hs, st)) return s;
   ss_status result = SS_OK;
@@ -561,20 +624,20 @@ extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, fl
   const Cfg c = choose_cfg(sys, nsys, opts);
   Params prm{opts->lambda, (1 << 30), -1.0};
   Grids g{};
-  if (ss_status s = setup(sys, nsys, f, nullptr, prm, c, L, ws, &g, st)) return s;
+  if (ss_status s = setup(sys, nsys, f, nullptr, prm, c, L, ws, &g, 0, st)) return s;
   hipEvent_t e0, e1;
   SS_HIP_TRY(hipEventCreate(&e0));
   SS_HIP_TRY(hipEventCreate(&e1));
   float t_fp = 0.f, t_bp = 0.f;
-  launch_kernel<false>(c, ws, L, nsys, g, st);  // warm caches and code
-  launch_kernel<true>(c, ws, L, nsys, g, st);
+  launch_kernel<false>(c, ws, L, nsys, g, 0, st);  // warm caches and code
+  launch_kernel<true>(c, ws, L, nsys, g, 0, st);
   (void)hipEventRecord(e0, st);
-  for (int r = 0; r < reps; ++r) launch_kernel<false>(c, ws, L, nsys, g, st);
+  for (int r = 0; r < reps; ++r) launch_kernel<false>(c, ws, L, nsys, g, 0, st);
   (void)hipEventRecord(e1, st);
   (void)hipEventSynchronize(e1);
   (void)hipEventElapsedTime(&t_fp, e0, e1);
   (void)hipEventRecord(e0, st);
-  for (int r = 0; r < reps; ++r) launch_kernel<true>(c, ws, L, nsys, g, st);
+  for (int r = 0; r < reps; ++r) launch_kernel<true>(c, ws, L, nsys, g, 0, st);
   (void)hipEventRecord(e1, st);
   (void)hipEventSynchronize(e1);
   (void)hipEventElapsedTime(&t_bp, e0, e1);

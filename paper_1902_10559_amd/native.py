@@ -61,7 +61,7 @@ class SartOptsC(C.Structure):
     _fields_ = [("lambda_", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("rows_per_wave", C.c_int32), ("cols_per_wave", C.c_int32),
-                ("xcd_remap", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("zero_start", C.c_int32)]
 
 
 _SIGNATURES = {
@@ -312,11 +312,12 @@ class SartOptions:
     rows_per_wave: int = 0
     cols_per_wave: int = 0
     xcd_remap: int = 0
+    zero_start: bool = False
 
     def c(self) -> SartOptsC:
         return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
                          int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
-                         self.xcd_remap)
+                         self.xcd_remap, int(self.zero_start))
 
 
 class Solver:

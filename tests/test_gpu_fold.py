@@ -180,3 +180,17 @@ def test_unsplit_sums_match_oracle():
     Sb = native.unsplit(Ad, pd, "bf16")
     bits = to_np(Sb.val).view(np.uint16)
     assert np.array_equal(bits, OSp.storage_bits(pr.A.data, "bf16"))
+
+
+def test_empty_matrix_folds_and_solves():
+    import torch
+    banner("empty matrix")
+    A = sp.csr_matrix((8, 6), dtype=np.float32)
+    p = np.arange(8, dtype=np.float32)
+    Ad, pd, S = _fold(A, p)
+    assert S.nnz == 0
+    assert np.array_equal(to_np(S.row_ptr), np.zeros(5)) and np.array_equal(to_np(S.inv_row), np.zeros(4))
+    f = [S.new_image()]
+    h = [torch.zeros(6, dtype=torch.float64, device="cuda")]
+    status, it = native.Solver([S], native.SartOptions(max_iter=5)).solve(f, h)
+    assert it == [5] and np.all(to_np(f[0]) == 0) and np.allclose(to_np(h[0]), 1.0)

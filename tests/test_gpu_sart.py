@@ -7,7 +7,7 @@ launches; resumed runs bitwise equal to one long run."""
 import numpy as np
 import pytest
 
-from gpu_util import banner, device, problem, random_problem, rel_l2, to_np
+from gpu_util import assert_res_close, banner, device, problem, random_problem, rel_l2, to_np
 from oracle import sart as OS
 from oracle import split as OSp
 from paper_1902_10559_amd import native
@@ -43,7 +43,7 @@ def test_split_sart_matches_fp64_oracle(cfg, iters):
     img = to_np(native.recombine(f[0]))
     f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, iters)
     assert rel_l2(img, f_ref) <= 1e-5
-    assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=0)
+    assert_res_close(to_np(h[0]), res_ref)
     # the halves themselves against the oracle's split iteration
     Sref = OSp.fold(pr.A)
     p1, p2 = OSp.fold_p(pr.p)
@@ -62,7 +62,7 @@ def test_split_sart_cfg2_100_iterations_matches_oracle():
     err = rel_l2(to_np(native.recombine(f[0])), f_ref)
     banner(f"cfg2 100 iterations rel L2 {err:.3e}")
     assert err <= 1e-4
-    assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=0)
+    assert_res_close(to_np(h[0]), res_ref)
 
 
 def test_unsplit_sart_matches_fp64_oracle():
@@ -75,7 +75,7 @@ def test_unsplit_sart_matches_fp64_oracle():
     f, h, status, it = _solve([U], 20)
     f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20)
     assert rel_l2(to_np(f[0]), f_ref) <= 1e-5
-    assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=0)
+    assert_res_close(to_np(h[0]), res_ref)
 
 
 def test_random_ragged_systems_match_oracle():
@@ -87,16 +87,18 @@ def test_random_ragged_systems_match_oracle():
         f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20)
         if np.linalg.norm(f_ref) > 0:
             assert rel_l2(to_np(native.recombine(f[0])), f_ref) <= 1e-5
-        assert np.allclose(to_np(h[0]), res_ref, rtol=1e-5, atol=1e-12)
+        assert_res_close(to_np(h[0]), res_ref)
 
 
 def test_batched_solve_equals_solo_solves_bitwise():
+    # same launch shape on both sides: the summation order is then identical
     banner("batched vs solo")
     probs = [problem(1), random_problem(21, 1002, 514, 0.05), random_problem(22, 130, 98, 0.1)]
     systems = [_split_system(pr)[2] for pr in probs]
-    fb, hb, _, itb = _solve(systems, 15)
+    shape = dict(rows_per_wave=2, cols_per_wave=4)
+    fb, hb, _, itb = _solve(systems, 15, **shape)
     for k, S in enumerate(systems):
-        fs, hs, _, its = _solve([S], 15)
+        fs, hs, _, its = _solve([S], 15, **shape)
         assert np.array_equal(to_np(fb[k]).view(np.uint32), to_np(fs[0]).view(np.uint32))
         assert np.array_equal(to_np(hb[k]), to_np(hs[0]))
 
@@ -123,18 +125,20 @@ def test_resume_from_a_warm_start_equals_one_long_run():
     assert np.array_equal(to_np(a[0]).view(np.uint32), to_np(b[0]).view(np.uint32))
 
 
-def test_early_exit_at_tolerance():
-    banner("early exit")
+@pytest.mark.parametrize("kstar", [38, 37])
+def test_early_exit_at_tolerance(kstar):
+    # an odd stop index leaves f^k in the workspace buffer: checks the copy back
+    banner(f"early exit k*={kstar}")
     pr = problem(1)
     _, _, S = _split_system(pr)
     f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 60)
-    tol = float(np.sqrt(res_ref[37] * res_ref[38]))   # between iterates 37 and 38
+    tol = float(np.sqrt(res_ref[kstar - 1] * res_ref[kstar]))
     f, h, status, it = _solve([S], 60, tol=tol, check_every=7)
-    assert status == 0 and it == [38]
+    assert status == 0 and it == [kstar]
     hist = to_np(h[0])
-    assert hist[38] <= tol < hist[37]
-    assert np.all(hist[39:] == -1.0)       # nothing written after the stop
-    fr, _ = OS.sart_full(pr.A, pr.p, 0.5, 38)
+    assert hist[kstar] <= tol < hist[kstar - 1]
+    assert np.all(hist[kstar + 1:] == -1.0)       # nothing written after the stop
+    fr, _ = OS.sart_full(pr.A, pr.p, 0.5, kstar)
     assert rel_l2(to_np(native.recombine(f[0])), fr) <= 1e-5
     # unreachable tolerance: warning status, capped count
     f, h, status, it = _solve([S], 12, tol=1e-9, check_every=5)
