@@ -35,12 +35,17 @@ import scipy.sparse as sp
 from .split import Split, reciprocal
 
 
-def sart_full(A: sp.csr_matrix, p, lam: float, iters: int, f0=None):
+def sart_full(A: sp.csr_matrix, p, lam: float, iters: int, f0=None, sums=None):
+    """``sums`` = (W, V) overrides the row and column sums of A; the 16-bit
+    storage variant keeps the sums of the FP32 weights while iterating with
+    the rounded ones."""
     A = sp.csr_matrix(A, dtype=np.float64)
     At = A.T.tocsr()
     p = np.asarray(p, dtype=np.float64)
-    invW = reciprocal(np.asarray(A.sum(axis=1)).ravel())
-    invV = reciprocal(np.asarray(A.sum(axis=0)).ravel())
+    if sums is None:
+        sums = (np.asarray(A.sum(axis=1)).ravel(), np.asarray(A.sum(axis=0)).ravel())
+    invW = reciprocal(sums[0])
+    invV = reciprocal(sums[1])
     f = np.zeros(A.shape[1]) if f0 is None else np.array(f0, dtype=np.float64)
     pn = np.linalg.norm(p)
     res = np.empty(iters + 1)

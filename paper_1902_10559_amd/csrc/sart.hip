@@ -41,14 +41,20 @@
 #include <tuple>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "device.h"
 #include "internal.h"
 
 namespace ss {
 namespace {
 
+// ---- device code begin
 constexpr int kWPB = 4;          // wavefronts per block
 constexpr int kThreads = kWave * kWPB;
+// entries each lane loads before it uses any of them: the index and value
+// loads of one pass, then the gathers, are all in flight together
+constexpr int kUnroll = 4;
 
 struct SysState {
   double pnorm2;     // ||p||^2 over all halves
@@ -174,12 +180,25 @@ __global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* table, int 
   for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
   if (row < S.m) {
     const int64_t re = S.row_ptr[row + 1];
-    for (int64_t k = S.row_ptr[row] + gl; k < re; k += L) {
-      const int32_t c = S.col_idx[k];
-      const Vec<NV> v = load_vals<NV, WT>(S.val, k);
-      const Vec<NV> fv = load_vec<NV>(f, c);
+    for (int64_t base = S.row_ptr[row] + gl; base < re; base += kUnroll * L) {
+      int32_t c[kUnroll];
+      Vec<NV> v[kUnroll];
 #pragma unroll
-      for (int h = 0; h < NV; ++h) acc[h] = fmaf(v.v[h], fv.v[h], acc[h]);
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t k = base + u * L;
+        c[u] = 0;
+        v[u] = Vec<NV>{};
+        if (k < re) {
+          c[u] = S.col_idx[k];
+          v[u] = load_vals<NV, WT>(S.val, k);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const Vec<NV> fv = load_vec<NV>(f, c[u]);
+#pragma unroll
+        for (int h = 0; h < NV; ++h) acc[h] = fmaf(v[u].v[h], fv.v[h], acc[h]);
+      }
     }
   }
 #pragma unroll
@@ -247,12 +266,25 @@ __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* prm, const S
   for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
   if (col < S.n) {
     const int64_t ce = S.col_ptr[col + 1];
-    for (int64_t k = S.col_ptr[col] + gl; k < ce; k += L) {
-      const int32_t r = S.row_idx[k];
-      const Vec<NV> v = load_vals<NV, WT>(S.val_t, k);
-      const Vec<NV> zv = load_vec<NV>(S.z, r);
+    for (int64_t base = S.col_ptr[col] + gl; base < ce; base += kUnroll * L) {
+      int32_t r[kUnroll];
+      Vec<NV> v[kUnroll];
 #pragma unroll
-      for (int h = 0; h < NV; ++h) acc[h] = fmaf(v.v[h], zv.v[h], acc[h]);
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t k = base + u * L;
+        r[u] = 0;
+        v[u] = Vec<NV>{};
+        if (k < ce) {
+          r[u] = S.row_idx[k];
+          v[u] = load_vals<NV, WT>(S.val_t, k);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const Vec<NV> zv = load_vec<NV>(S.z, r[u]);
+#pragma unroll
+        for (int h = 0; h < NV; ++h) acc[h] = fmaf(v[u].v[h], zv.v[h], acc[h]);
+      }
     }
   }
 #pragma unroll
@@ -274,6 +306,8 @@ __global__ __launch_bounds__(kThreads) void k_finish(const SysDesc* table) {
   const int64_t cnt = S.n * NV;
   for (int64_t i = threadIdx.x; i < cnt; i += kThreads) S.f[0][i] = S.f[1][i];
 }
+
+// ---- device code end
 
 // ------------------------------------------------------------------ host
 struct Layout {
@@ -416,38 +450,53 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
   return SS_OK;
 }
 
+// Launches go through hipExtLaunchKernelGGL so that, when timing, the start
+// and stop events are stamped by the kernel's own dispatch (no marker
+// packets between kernels); with null events it is an ordinary launch.
+struct Stamp {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 template <int NV, int WT>
-void launch_fp_t(int rpw, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st) {
+void launch_fp_t(int rpw, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st,
+                 Stamp e) {
+  auto go = [&](auto kern) {
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, st, e.start, e.stop, 0, t, nsys, nb, xcd, par);
+  };
   switch (rpw) {
-    case 1: k_sart_fp<NV, WT, 1><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
-    case 2: k_sart_fp<NV, WT, 2><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
-    case 4: k_sart_fp<NV, WT, 4><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
-    default: k_sart_fp<NV, WT, 8><<<nb, kThreads, 0, st>>>(t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_fp<NV, WT, 1>); break;
+    case 2: go(k_sart_fp<NV, WT, 2>); break;
+    case 4: go(k_sart_fp<NV, WT, 4>); break;
+    default: go(k_sart_fp<NV, WT, 8>); break;
   }
 }
 
 template <int NV, int WT>
 void launch_bp_t(int cpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
-                 hipStream_t st) {
+                 hipStream_t st, Stamp e) {
+  auto go = [&](auto kern) {
+    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, st, e.start, e.stop, 0, prm, t, nsys, nb, xcd,
+                          par);
+  };
   switch (cpw) {
-    case 1: k_sart_bp<NV, WT, 1><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
-    case 2: k_sart_bp<NV, WT, 2><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
-    case 4: k_sart_bp<NV, WT, 4><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
-    case 8: k_sart_bp<NV, WT, 8><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
-    default: k_sart_bp<NV, WT, 16><<<nb, kThreads, 0, st>>>(prm, t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_bp<NV, WT, 1>); break;
+    case 2: go(k_sart_bp<NV, WT, 2>); break;
+    case 4: go(k_sart_bp<NV, WT, 4>); break;
+    case 8: go(k_sart_bp<NV, WT, 8>); break;
+    default: go(k_sart_bp<NV, WT, 16>); break;
   }
 }
 
 template <bool BP>
 void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int par,
-                   hipStream_t st) {
+                   hipStream_t st, Stamp e = {}) {
   const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
-#define SS_DISPATCH(NV, WT)                                                         \
-  if (c.nv == NV && c.wt == WT) {                                                   \
-    if (BP) launch_bp_t<NV, WT>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, par, st);   \
-    else launch_fp_t<NV, WT>(c.rpw, t, nsys, g.fp_blocks, c.xcd, par, st);           \
-    return;                                                                         \
+#define SS_DISPATCH(NV, WT)                                                           \
+  if (c.nv == NV && c.wt == WT) {                                                     \
+    if (BP) launch_bp_t<NV, WT>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e);  \
+    else launch_fp_t<NV, WT>(c.rpw, t, nsys, g.fp_blocks, c.xcd, par, st, e);          \
+    return;                                                                           \
   }
   SS_DISPATCH(2, SS_F32)
   SS_DISPATCH(2, SS_BF16)
@@ -625,28 +674,31 @@ extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, fl
   Params prm{opts->lambda, (1 << 30), -1.0};
   Grids g{};
   if (ss_status s = setup(sys, nsys, f, nullptr, prm, c, L, ws, &g, 0, st)) return s;
-  hipEvent_t e0, e1;
-  SS_HIP_TRY(hipEventCreate(&e0));
-  SS_HIP_TRY(hipEventCreate(&e1));
-  float t_fp = 0.f, t_bp = 0.f;
+  // the kernels are timed where they run in a solve, forward and back
+  // projection alternating; each launch carries its own start/stop events
+  std::vector<hipEvent_t> ev(4 * static_cast<size_t>(reps));
+  for (auto& e : ev) SS_HIP_TRY(hipEventCreate(&e));
   launch_kernel<false>(c, ws, L, nsys, g, 0, st);  // warm caches and code
   launch_kernel<true>(c, ws, L, nsys, g, 0, st);
-  (void)hipEventRecord(e0, st);
-  for (int r = 0; r < reps; ++r) launch_kernel<false>(c, ws, L, nsys, g, 0, st);
-  (void)hipEventRecord(e1, st);
-  (void)hipEventSynchronize(e1);
-  (void)hipEventElapsedTime(&t_fp, e0, e1);
-  (void)hipEventRecord(e0, st);
-  for (int r = 0; r < reps; ++r) launch_kernel<true>(c, ws, L, nsys, g, 0, st);
-  (void)hipEventRecord(e1, st);
-  (void)hipEventSynchronize(e1);
-  (void)hipEventElapsedTime(&t_bp, e0, e1);
+  for (int r = 0; r < reps; ++r) {
+    const int par = (r + 1) & 1;
+    launch_kernel<false>(c, ws, L, nsys, g, par, st, Stamp{ev[4 * r], ev[4 * r + 1]});
+    launch_kernel<true>(c, ws, L, nsys, g, par, st, Stamp{ev[4 * r + 2], ev[4 * r + 3]});
+  }
+  (void)hipEventSynchronize(ev.back());
+  double t_fp = 0.0, t_bp = 0.0;
+  for (int r = 0; r < reps; ++r) {
+    float a = 0.f, b = 0.f;
+    (void)hipEventElapsedTime(&a, ev[4 * r], ev[4 * r + 1]);
+    (void)hipEventElapsedTime(&b, ev[4 * r + 2], ev[4 * r + 3]);
+    t_fp += a;
+    t_bp += b;
+  }
   const hipError_t err = hipGetLastError();
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   if (err != hipSuccess) return fail(SS_E_HIP, "ss_sart_time_kernels: %s", hipGetErrorString(err));
-  *fp_ms = static_cast<double>(t_fp) / reps;
-  *bp_ms = static_cast<double>(t_bp) / reps;
+  *fp_ms = t_fp / reps;
+  *bp_ms = t_bp / reps;
   return SS_OK;
 }
 
@@ -683,9 +735,13 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
       return SS_OK;
     }
   }
-  const int reps = 10;
-  double best_fp = 1e30, best_bp = 1e30;
-  int brpw = 1, bcpw = 1, bxcd_fp = 0, bxcd_bp = 0;
+  // every candidate is timed in the alternating forward/back sequence; a
+  // candidate replaces the statistics-based default only when it is more
+  // than 3 % faster, so that timing noise does not flip the choice
+  const int reps = 20;
+  const Cfg dflt = choose_cfg(sys, nsys, opts);
+  double best_fp = 1e30, best_bp = 1e30, dflt_fp = 1e30, dflt_bp = 1e30;
+  int brpw = dflt.rpw, bcpw = dflt.cpw, bxcd_fp = 0, bxcd_bp = 0;
   for (int xcd = 0; xcd <= 1; ++xcd) {
     for (int pw = 1; pw <= 16; pw <<= 1) {
       ss_sart_opts o = *opts;
@@ -695,6 +751,8 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
       double tf = 0, tb = 0;
       if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes, stream))
         return s;
+      if (xcd == 0 && o.rows_per_wave == dflt.rpw) dflt_fp = std::min(dflt_fp, tf);
+      if (xcd == 0 && o.cols_per_wave == dflt.cpw) dflt_bp = std::min(dflt_bp, tb);
       if (pw <= 8 && tf < best_fp) {
         best_fp = tf;
         brpw = pw;
@@ -706,6 +764,16 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
         bxcd_bp = xcd;
       }
     }
+  }
+  if (dflt_fp <= 1.03 * best_fp) {
+    brpw = dflt.rpw;
+    bxcd_fp = 0;
+    best_fp = dflt_fp;
+  }
+  if (dflt_bp <= 1.03 * best_bp) {
+    bcpw = dflt.cpw;
+    bxcd_bp = 0;
+    best_bp = dflt_bp;
   }
   // one remap flag serves both kernels: take the one of the slower kernel
   const int xcd = best_fp >= best_bp ? bxcd_fp : bxcd_bp;

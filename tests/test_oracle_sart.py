@@ -118,3 +118,15 @@ def test_cfg1_full_and_split_agree_and_the_residual_falls():
     assert np.max(np.abs(split.recombine(f1, f2) - f)) < 1e-12 * np.abs(f).max()
     assert res[0] == pytest.approx(1.0) and res[-1] < 0.1
     assert np.all(np.diff(res) < 0)
+
+
+def test_explicit_sums_equal_default_sums_when_they_are_the_matrix_sums():
+    A, p = _random_problem(7)
+    W = np.asarray(A.astype(np.float64).sum(axis=1)).ravel()
+    V = np.asarray(A.astype(np.float64).sum(axis=0)).ravel()
+    f, r = sart.sart_full(A, p, 0.5, 15)
+    g, s = sart.sart_full(A, p, 0.5, 15, sums=(W, V))
+    assert np.array_equal(f, g) and np.array_equal(r, s)
+    # and they matter: scaled sums give a different iterate
+    h, _ = sart.sart_full(A, p, 0.5, 15, sums=(2 * W, V))
+    assert np.max(np.abs(h - f)) > 1e-3 * np.abs(f).max()
