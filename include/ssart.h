@@ -167,7 +167,7 @@ typedef struct {
   float* inv_col;
 } ss_system;
 
-/* Bytes of workspace ss_fold_size needs for an M x N matrix. */
+/* Bytes of workspace ss_fold_size and ss_fold need for an M x N matrix. */
 ss_status ss_fold_workspace_bytes(int64_t M, int64_t N, size_t* bytes);
 
 /* Validates A (and p, if not NULL) and returns the size of the shared pattern
@@ -185,9 +185,10 @@ ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* workspace,
  * one correctly rounded FP32 subtraction/addition per entry, then rounded to
  * nearest-even for BF16/FP16 storage; p1/p2 likewise in FP32; inv_row/inv_col
  * from FP64 sums of A's FP32 entries.  A must have passed ss_fold_size.
- * Asynchronous. */
+ * `workspace`: device scratch of ss_fold_workspace_bytes(M, N) bytes (its
+ * contents on entry do not matter).  Asynchronous. */
 ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out,
-                  void* stream);
+                  void* workspace, size_t workspace_bytes, void* stream);
 
 /* The unsplit baseline: fills a single system (nvals = 1, m = M, n = N) for
  * A itself.  The caller sets out->m, n, nnz, nvals = 1, wdtype and every

@@ -16,6 +16,8 @@
 // (the union elements below a value are those of X and of Y below it, minus
 // the common ones counted twice).  The union size is |X| + |Y| - #common.
 
+#include <algorithm>
+
 #include "device.h"
 #include "internal.h"
 
@@ -282,18 +284,58 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(ss_matrix_dev 
   }
 }
 
-// In-place inclusive scan of ptr[1..len]: ptr becomes the offsets array.
-// One block; thread t scans a contiguous chunk, chunk totals are scanned in
-// shared memory.
-constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_scan(int64_t* ptr, int64_t len) {
-  __shared__ int64_t tot[kScanThreads];
-  const int64_t chunk = (len + kScanThreads - 1) / kScanThreads;
-  const int64_t s = 1 + static_cast<int64_t>(threadIdx.x) * chunk;
-  const int64_t e = s + chunk < len + 1 ? s + chunk : len + 1;
+// In-place inclusive scan of ptr[1..len] (ptr[0] = 0): ptr becomes the
+// offsets array.  Two launches over tiles of kScanTile counts: each block
+// first writes its tile's total; then each block adds the totals of the
+// tiles before it (few: len / kScanTile) and scans its own tile in shared
+// memory.  All loads are coalesced.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int64_t* ptr, int64_t len, int64_t* tile_sum) {
+  const int64_t base = 1 + static_cast<int64_t>(blockIdx.x) * kScanTile;
   int64_t acc = 0;
-  for (int64_t i = s; i < e; ++i) acc += ptr[i];
-  tot[threadIdx.x] = acc;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int64_t i = base + threadIdx.x + static_cast<int64_t>(j) * kScanThreads;
+    if (i <= len) acc += ptr[i];
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  __shared__ int64_t red[kScanThreads / kWave];
+  if (lane_id() == 0) red[wave_id()] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) t += red[w];
+    tile_sum[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t* ptr, int64_t len, const int64_t* tile_sum) {
+  __shared__ int64_t vals[kScanTile];
+  __shared__ int64_t tot[kScanThreads];
+  __shared__ int64_t carry;
+  const int64_t base = 1 + static_cast<int64_t>(blockIdx.x) * kScanTile;
+  for (int j = 0; j < kScanPer; ++j) {
+    const int t = threadIdx.x + j * kScanThreads;
+    const int64_t i = base + t;
+    vals[t] = i <= len ? ptr[i] : 0;
+  }
+  if (threadIdx.x == 0) {
+    int64_t c = 0;
+    for (unsigned b = 0; b < blockIdx.x; ++b) c += tile_sum[b];
+    carry = c;
+  }
+  __syncthreads();
+  // each thread scans kScanPer consecutive counts
+  int64_t run = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    run += vals[threadIdx.x * kScanPer + j];
+    vals[threadIdx.x * kScanPer + j] = run;
+  }
+  tot[threadIdx.x] = run;
   __syncthreads();
   for (int o = 1; o < kScanThreads; o <<= 1) {
     const int64_t v = threadIdx.x >= static_cast<unsigned>(o) ? tot[threadIdx.x - o] : 0;
@@ -301,11 +343,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int64_t* ptr, int64_t len
     tot[threadIdx.x] += v;
     __syncthreads();
   }
-  int64_t run = threadIdx.x > 0 ? tot[threadIdx.x - 1] : 0;
-  for (int64_t i = s; i < e; ++i) {
-    run += ptr[i];
-    ptr[i] = run;
+  const int64_t before = carry + (threadIdx.x > 0 ? tot[threadIdx.x - 1] : 0);
+  for (int j = 0; j < kScanPer; ++j) vals[threadIdx.x * kScanPer + j] += before;
+  __syncthreads();
+  for (int j = 0; j < kScanPer; ++j) {
+    const int t = threadIdx.x + j * kScanThreads;
+    const int64_t i = base + t;
+    if (i <= len) ptr[i] = vals[t];
   }
+}
+
+inline int64_t scan_tiles(int64_t len) { return (len + kScanTile - 1) / kScanTile; }
+
+void launch_scan(int64_t* ptr, int64_t len, int64_t* scratch, hipStream_t st) {
+  const unsigned nt = static_cast<unsigned>(std::max<int64_t>(1, scan_tiles(len)));
+  k_scan_tiles<<<nt, kScanThreads, 0, st>>>(ptr, len, scratch);
+  k_scan_apply<<<nt, kScanThreads, 0, st>>>(ptr, len, scratch);
 }
 
 __device__ inline float recip_or_zero(double s) {
@@ -394,7 +447,8 @@ using namespace ss;
 extern "C" ss_status ss_fold_workspace_bytes(int64_t M, int64_t N, size_t* bytes) {
   clear_error();
   if (!bytes || M <= 0 || N <= 0) return fail(SS_E_ARG, "ss_fold_workspace_bytes: bad argument");
-  *bytes = 256;
+  const int64_t tiles = scan_tiles(std::max(M, N) / 2 + 1) + 1;
+  *bytes = std::max<size_t>(256, sizeof(FoldCheck)) + 256 + sizeof(int64_t) * static_cast<size_t>(tiles);
   return SS_OK;
 }
 
@@ -426,7 +480,8 @@ extern "C" ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* 
   return SS_OK;
 }
 
-extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out, void* stream) {
+extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out, void* workspace,
+                             size_t workspace_bytes, void* stream) {
   clear_error();
   if (ss_status s = check_dev_matrix(A, "ss_fold")) return s;
   if (!p || !out) return fail(SS_E_ARG, "ss_fold: NULL argument");
@@ -438,13 +493,17 @@ extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* 
   if (!out->row_ptr || !out->col_ptr || !out->p || !out->inv_row || !out->inv_col ||
       (out->nnz > 0 && (!out->col_idx || !out->val || !out->row_idx || !out->val_t)))
     return fail(SS_E_ARG, "ss_fold: NULL output array");
+  size_t need = 0;
+  ss_fold_workspace_bytes(A->M, A->N, &need);
+  if (!workspace || workspace_bytes < need) return fail(SS_E_WORKSPACE, "ss_fold: workspace needs %zu bytes", need);
+  int64_t* tiles = reinterpret_cast<int64_t*>(static_cast<char*>(workspace) + 512);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const unsigned nbr = blocks_for(out->m), nbc = blocks_for(out->n);
   k_fold_count<false><<<nbr, kWave * kFoldWaves, 0, st>>>(*A, out->row_ptr);
-  k_scan<<<1, kScanThreads, 0, st>>>(out->row_ptr, out->m);
+  launch_scan(out->row_ptr, out->m, tiles, st);
   launch_fill<false>(out->wdtype, *A, p, *out, nbr, st);
   k_fold_count<true><<<nbc, kWave * kFoldWaves, 0, st>>>(*A, out->col_ptr);
-  k_scan<<<1, kScanThreads, 0, st>>>(out->col_ptr, out->n);
+  launch_scan(out->col_ptr, out->n, tiles, st);
   launch_fill<true>(out->wdtype, *A, p, *out, nbc, st);
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;

@@ -74,7 +74,8 @@ _SIGNATURES = {
     "ss_fold_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "ss_fold_size": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_int64), C.c_void_p]),
-    "ss_fold": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p]),
+    "ss_fold": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p,
+                            C.c_size_t, C.c_void_p]),
     "ss_unsplit": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p]),
     "ss_sart_workspace_bytes": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(SartOptsC),
                                             C.POINTER(C.c_size_t)]),
@@ -240,13 +241,10 @@ class System:
 
 def fold_size(A: DeviceMatrix, p=None) -> int:
     """ss_fold_size: validates A (and p) and returns the shared-pattern size."""
-    import torch
-    nb = C.c_size_t()
-    _check(lib().ss_fold_workspace_bytes(A.M, A.N, C.byref(nb)))
-    ws = torch.empty(nb.value, dtype=torch.uint8, device=A.val.device)
+    ws = fold_workspace(A)
     out = C.c_int64()
     mc = A.c()
-    _check(lib().ss_fold_size(C.byref(mc), _ptr(p), _ptr(ws), nb.value, C.byref(out),
+    _check(lib().ss_fold_size(C.byref(mc), _ptr(p), _ptr(ws), ws.numel(), C.byref(out),
                               _stream(A.val.device)))
     return int(out.value)
 
@@ -279,10 +277,26 @@ def fold(A: DeviceMatrix, p, wdtype: str = "f32", nnz_half: int | None = None) -
     return S
 
 
+_fold_ws = {}
+
+
+def fold_workspace(A: DeviceMatrix):
+    """Device scratch for ss_fold_size / ss_fold, cached per (device, M, N)."""
+    import torch
+    key = (str(A.val.device), A.M, A.N)
+    if key not in _fold_ws:
+        nb = C.c_size_t()
+        _check(lib().ss_fold_workspace_bytes(A.M, A.N, C.byref(nb)))
+        _fold_ws[key] = torch.empty(nb.value, dtype=torch.uint8, device=A.val.device)
+    return _fold_ws[key]
+
+
 def fold_into(A: DeviceMatrix, p, S: System) -> None:
     """ss_fold into an existing system's arrays (same sizes)."""
     mc, sc = A.c(), S.c()
-    _check(lib().ss_fold(C.byref(mc), _ptr(p), C.byref(sc), _stream(A.val.device)))
+    ws = fold_workspace(A)
+    _check(lib().ss_fold(C.byref(mc), _ptr(p), C.byref(sc), _ptr(ws), ws.numel(),
+                         _stream(A.val.device)))
 
 
 def unsplit(A: DeviceMatrix, p, wdtype: str = "f32") -> System:
