@@ -221,6 +221,7 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *                columns (the hardware deals workgroups round-robin)
  *   zero_start   1: start from f^0 = 0 (the solver clears f itself);
  *                0: start from the image the caller passes
+ *   unroll       entries each lane has in flight per pass: 4 or 8 (0 = 4)
  * rel_res(f^k) = ||p - A f^k|| / ||p||, from the halves as
  *   sqrt((||r1||^2 + ||r2||^2) / (||p1||^2 + ||p2||^2)), FP64. */
 typedef struct {
@@ -233,6 +234,7 @@ typedef struct {
   int32_t cols_per_wave;
   int32_t xcd_remap;
   int32_t zero_start;
+  int32_t unroll;
 } ss_sart_opts;
 
 /* Workspace bytes for solving `nsys` systems together with these options. */
@@ -265,7 +267,7 @@ ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys,
                                void* workspace, size_t workspace_bytes,
                                void* stream);
 
-/* Picks rows_per_wave, cols_per_wave and xcd_remap for these systems by
+/* Picks rows_per_wave, cols_per_wave, unroll and xcd_remap for these systems by
  * timing every candidate (ss_sart_time_kernels) and writes them into
  * *opts.  Results are cached per (nvals, wdtype, shape statistics).
  * The images f are used as scratch.  Synchronises. */

@@ -12,6 +12,29 @@ namespace ss {
 
 constexpr int kWave = 64;
 
+// Pointers that reach kernels through descriptor tables (or structs) are
+// generic to the compiler, which then emits flat loads: those count against
+// the same wait counter as scalar loads, so every wait for a descriptor
+// field also drains all data loads in flight.  Casting to the global
+// address space gives global loads and stores.
+#define SS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline const SS_GLOBAL T* gl(const T* p) {
+  return (const SS_GLOBAL T*)p;
+}
+template <typename T>
+__device__ inline SS_GLOBAL T* glw(T* p) {
+  return (SS_GLOBAL T*)p;
+}
+
+// FP32 pairs move as one 64-bit word (the vector class has no
+// address-space-qualified copy operators).
+__device__ inline uint64_t pack2(float a, float b) {
+  return static_cast<uint64_t>(__float_as_uint(a)) | (static_cast<uint64_t>(__float_as_uint(b)) << 32);
+}
+__device__ inline float lo_f(uint64_t u) { return __uint_as_float(static_cast<uint32_t>(u)); }
+__device__ inline float hi_f(uint64_t u) { return __uint_as_float(static_cast<uint32_t>(u >> 32)); }
+
 __device__ inline int lane_id() { return static_cast<int>(threadIdx.x) & (kWave - 1); }
 __device__ inline int wave_id() { return static_cast<int>(threadIdx.x) / kWave; }
 __device__ inline uint64_t lanemask_lt() { return (uint64_t{1} << lane_id()) - 1; }
@@ -63,22 +86,22 @@ __device__ inline uint32_t f16_bits_rne(float x) {
 template <int WT>
 __device__ inline void store_pair(void* base, int64_t k, float a, float b) {
   if constexpr (WT == SS_F32) {
-    reinterpret_cast<float2*>(base)[k] = make_float2(a, b);
+    glw(reinterpret_cast<uint64_t*>(base))[k] = pack2(a, b);
   } else if constexpr (WT == SS_BF16) {
-    reinterpret_cast<uint32_t*>(base)[k] = bf16_bits_rne(a) | (bf16_bits_rne(b) << 16);
+    glw(reinterpret_cast<uint32_t*>(base))[k] = bf16_bits_rne(a) | (bf16_bits_rne(b) << 16);
   } else {
-    reinterpret_cast<uint32_t*>(base)[k] = f16_bits_rne(a) | (f16_bits_rne(b) << 16);
+    glw(reinterpret_cast<uint32_t*>(base))[k] = f16_bits_rne(a) | (f16_bits_rne(b) << 16);
   }
 }
 
 template <int WT>
 __device__ inline void store_one(void* base, int64_t k, float a) {
   if constexpr (WT == SS_F32) {
-    reinterpret_cast<float*>(base)[k] = a;
+    glw(reinterpret_cast<float*>(base))[k] = a;
   } else if constexpr (WT == SS_BF16) {
-    reinterpret_cast<uint16_t*>(base)[k] = static_cast<uint16_t>(bf16_bits_rne(a));
+    glw(reinterpret_cast<uint16_t*>(base))[k] = static_cast<uint16_t>(bf16_bits_rne(a));
   } else {
-    reinterpret_cast<uint16_t*>(base)[k] = static_cast<uint16_t>(f16_bits_rne(a));
+    glw(reinterpret_cast<uint16_t*>(base))[k] = static_cast<uint16_t>(f16_bits_rne(a));
   }
 }
 
@@ -92,11 +115,11 @@ template <int NV>
 __device__ inline Vec<NV> load_vec(const float* p, int64_t i) {
   Vec<NV> r;
   if constexpr (NV == 2) {
-    const float2 t = reinterpret_cast<const float2*>(p)[i];
-    r.v[0] = t.x;
-    r.v[1] = t.y;
+    const uint64_t u = gl(reinterpret_cast<const uint64_t*>(p))[i];
+    r.v[0] = lo_f(u);
+    r.v[1] = hi_f(u);
   } else {
-    r.v[0] = p[i];
+    r.v[0] = gl(p)[i];
   }
   return r;
 }
@@ -104,9 +127,9 @@ __device__ inline Vec<NV> load_vec(const float* p, int64_t i) {
 template <int NV>
 __device__ inline void store_vec(float* p, int64_t i, const Vec<NV>& x) {
   if constexpr (NV == 2) {
-    reinterpret_cast<float2*>(p)[i] = make_float2(x.v[0], x.v[1]);
+    glw(reinterpret_cast<uint64_t*>(p))[i] = pack2(x.v[0], x.v[1]);
   } else {
-    p[i] = x.v[0];
+    glw(p)[i] = x.v[0];
   }
 }
 
@@ -116,26 +139,25 @@ __device__ inline Vec<NV> load_vals(const void* base, int64_t k) {
   Vec<NV> r;
   if constexpr (NV == 2) {
     if constexpr (WT == SS_F32) {
-      const float2 t = reinterpret_cast<const float2*>(base)[k];
-      r.v[0] = t.x;
-      r.v[1] = t.y;
+      const uint64_t u = gl(reinterpret_cast<const uint64_t*>(base))[k];
+      r.v[0] = lo_f(u);
+      r.v[1] = hi_f(u);
     } else if constexpr (WT == SS_BF16) {
-      const uint32_t u = reinterpret_cast<const uint32_t*>(base)[k];
+      const uint32_t u = gl(reinterpret_cast<const uint32_t*>(base))[k];
       r.v[0] = __uint_as_float(u << 16);
       r.v[1] = __uint_as_float(u & 0xffff0000u);
     } else {
-      const __half2 h = reinterpret_cast<const __half2*>(base)[k];
-      const float2 t = __half22float2(h);
-      r.v[0] = t.x;
-      r.v[1] = t.y;
+      const uint32_t u = gl(reinterpret_cast<const uint32_t*>(base))[k];
+      r.v[0] = __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xffffu)));
+      r.v[1] = __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16)));
     }
   } else {
     if constexpr (WT == SS_F32) {
-      r.v[0] = reinterpret_cast<const float*>(base)[k];
+      r.v[0] = gl(reinterpret_cast<const float*>(base))[k];
     } else if constexpr (WT == SS_BF16) {
-      r.v[0] = __uint_as_float(static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(base)[k]) << 16);
+      r.v[0] = __uint_as_float(static_cast<uint32_t>(gl(reinterpret_cast<const uint16_t*>(base))[k]) << 16);
     } else {
-      r.v[0] = __half2float(reinterpret_cast<const __half*>(base)[k]);
+      r.v[0] = __half2float(__ushort_as_half(gl(reinterpret_cast<const unsigned short*>(base))[k]));
     }
   }
   return r;

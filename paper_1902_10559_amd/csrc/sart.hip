@@ -52,9 +52,6 @@ namespace {
 // ---- device code begin
 constexpr int kWPB = 4;          // wavefronts per block
 constexpr int kThreads = kWave * kWPB;
-// entries each lane loads before it uses any of them: the index and value
-// loads of one pass, then the gathers, are all in flight together
-constexpr int kUnroll = 4;
 
 struct SysState {
   double pnorm2;     // ||p||^2 over all halves
@@ -114,7 +111,7 @@ template <bool BP>
 __device__ inline int find_sys(const SysDesc* t, int nsys, int64_t b) {
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
+    const int mid = __builtin_amdgcn_readfirstlane((lo + hi + 1) >> 1);
     const int64_t b0 = BP ? t[mid].bp_block0 : t[mid].fp_block0;
     if (b0 <= b) lo = mid;
     else hi = mid - 1;
@@ -157,68 +154,156 @@ __device__ inline void store_flag(int32_t* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int NV, int WT, int RPW>
-__global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* table, int nsys, uint32_t nblocks,
-                                                      int xcd, int parity) {
-  const uint32_t b = xcd ? xcd_remap(blockIdx.x, nblocks) : blockIdx.x;
-  const int s = nsys == 1 ? 0 : find_sys<false>(table, nsys, b);
-  const SysDesc& S = table[s];
-  SysState* st = S.st;
-  if (load_flag(&st->stop)) return;
-  constexpr int L = kWave / RPW;
-  const int lane = lane_id();
-  const int gl = lane % L;
-  const int64_t local = static_cast<int64_t>(b) - S.fp_block0;
-  if (local == 0 && threadIdx.x == 0 && st->pending) {
-    st->k += 1;
-    st->pending = 0;
+// Index and value streams are read once per launch: non-temporal loads keep
+// them from evicting the gathered image and z from L2.
+__device__ inline int32_t ld_stream(const int32_t* p) { return __builtin_nontemporal_load(gl(p)); }
+
+template <int NV, int WT>
+__device__ inline Vec<NV> ld_stream_vals(const void* base, int64_t k) {
+  Vec<NV> r;
+  if constexpr (NV == 2 && WT == SS_F32) {
+    const uint64_t u = __builtin_nontemporal_load(gl(reinterpret_cast<const uint64_t*>(base)) + k);
+    r.v[0] = __uint_as_float(static_cast<uint32_t>(u));
+    r.v[1] = __uint_as_float(static_cast<uint32_t>(u >> 32));
+  } else if constexpr (NV == 2) {
+    const uint32_t u = __builtin_nontemporal_load(gl(reinterpret_cast<const uint32_t*>(base)) + k);
+    if constexpr (WT == SS_BF16) {
+      r.v[0] = __uint_as_float(u << 16);
+      r.v[1] = __uint_as_float(u & 0xffff0000u);
+    } else {
+      r.v[0] = __half2float(__ushort_as_half(static_cast<unsigned short>(u & 0xffffu)));
+      r.v[1] = __half2float(__ushort_as_half(static_cast<unsigned short>(u >> 16)));
+    }
+  } else if constexpr (WT == SS_F32) {
+    r.v[0] = __builtin_nontemporal_load(gl(reinterpret_cast<const float*>(base)) + k);
+  } else {
+    const unsigned short u = __builtin_nontemporal_load(gl(reinterpret_cast<const unsigned short*>(base)) + k);
+    if constexpr (WT == SS_BF16) r.v[0] = __uint_as_float(static_cast<uint32_t>(u) << 16);
+    else r.v[0] = __half2float(__ushort_as_half(u));
   }
-  const float* f = S.f[parity];
-  const int64_t row = local * (RPW * kWPB) + wave_id() * RPW + lane / L;
-  float acc[NV];
+  return r;
+}
+
+// Sum over one line (row or column) of A(s)^T-free form: acc += sum_k val[k] *
+// x[idx[k]] for k in [lo, hi), by the L lanes of a group, U entries per lane
+// in flight per pass.
+template <int NV, int WT, int L, int U>
+__device__ inline void line_dot(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
+                                int glane, float* acc) {
+  for (int64_t base = lo + glane; base < hi; base += U * L) {
+    int32_t c[U];
+    Vec<NV> v[U];
 #pragma unroll
-  for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-  if (row < S.m) {
-    const int64_t re = S.row_ptr[row + 1];
-    for (int64_t base = S.row_ptr[row] + gl; base < re; base += kUnroll * L) {
-      int32_t c[kUnroll];
-      Vec<NV> v[kUnroll];
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = base + u * L;
+      c[u] = 0;
+      v[u] = Vec<NV>{};
+      if (k < hi) {
+        c[u] = ld_stream(idx + k);
+        v[u] = ld_stream_vals<NV, WT>(val, k);
+      }
+    }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int64_t k = base + u * L;
-        c[u] = 0;
-        v[u] = Vec<NV>{};
-        if (k < re) {
-          c[u] = S.col_idx[k];
-          v[u] = load_vals<NV, WT>(S.val, k);
+    for (int u = 0; u < U; ++u) {
+      const Vec<NV> xv = load_vec<NV>(x, c[u]);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] = fmaf(v[u].v[h], xv.v[h], acc[h]);
+    }
+  }
+}
+
+// What a tile needs before its main loads: the system, the tile's index in
+// it, this lane group's line and the line's offsets.  Loaded one tile ahead.
+struct TileCtx {
+  int s;
+  int stop;
+  int64_t local;
+  int64_t line;
+  int64_t lo, hi;
+};
+
+template <bool BP, int PW>
+__device__ inline TileCtx tile_ctx(const SysDesc* table, int nsys, uint32_t t, uint32_t ntiles, int xcd) {
+  TileCtx c;
+  const uint32_t b = __builtin_amdgcn_readfirstlane(xcd ? xcd_remap(t, ntiles) : t);
+  // uniform per block: keep the descriptor in scalar registers
+  c.s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<BP>(table, nsys, b));
+  const SysDesc& S = table[c.s];
+  c.stop = *gl(&S.st->stop);
+  c.local = static_cast<int64_t>(b) - (BP ? S.bp_block0 : S.fp_block0);
+  c.line = c.local * (PW * kWPB) + wave_id() * PW + lane_id() / (kWave / PW);
+  c.lo = c.hi = 0;
+  const int64_t lines = BP ? S.n : S.m;
+  const int64_t* ptr = BP ? S.col_ptr : S.row_ptr;
+  if (c.line < lines) {
+    c.lo = gl(ptr)[c.line];
+    c.hi = gl(ptr)[c.line + 1];
+  }
+  return c;
+}
+
+// Forward projection and residual.  A grid-stride loop over tiles of
+// RPW*kWPB rows.  Per tile: p and 1/W are requested first, then the row
+// sums, then the next tile's context (so its loads overlap this tile's
+// reduction), then the residual, z and the block's FP64 partial.
+template <int NV, int WT, int RPW, int U>
+__global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* __restrict__ table, int nsys,
+                                                      uint32_t ntiles, int xcd, int parity) {
+  constexpr int L = kWave / RPW;
+  __shared__ double red[kWPB];
+  uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  const int glane = lane_id() % L;
+  TileCtx cur = tile_ctx<false, RPW>(table, nsys, t, ntiles, xcd);
+  for (;;) {
+    const uint32_t tn = t + gridDim.x;
+    const bool more = tn < ntiles;
+    TileCtx nxt{};
+    if (!cur.stop) {
+      const SysDesc& S = table[cur.s];
+      const bool owner = glane == 0 && cur.line < S.m;
+      Vec<NV> pv{};
+      float w = 0.0f;
+      if (owner) {
+        pv = load_vec<NV>(S.p, cur.line);
+        w = gl(S.inv_row)[cur.line];
+      }
+      float acc[NV];
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
+      line_dot<NV, WT, L, U>(S.col_idx, S.val, S.f[parity], cur.lo, cur.hi, glane, acc);
+      if (more) nxt = tile_ctx<false, RPW>(table, nsys, tn, ntiles, xcd);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
+      double d = 0.0;
+      if (owner) {
+        Vec<NV> zv;
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+          const float r = pv.v[h] - acc[h];
+          zv.v[h] = r * w;
+          d += static_cast<double>(r) * static_cast<double>(r);
+        }
+        store_vec<NV>(S.z, cur.line, zv);
+      }
+      const double tot = block_sum<kWPB>(d, red);
+      if (threadIdx.x == 0) {
+        glw(S.partials)[cur.local] = tot;
+        // the first tile of the system moves the iterate index on
+        SysState* st = S.st;
+        if (cur.local == 0 && *gl(&st->pending)) {
+          glw(&st->k)[0] += 1;
+          glw(&st->pending)[0] = 0;
         }
       }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const Vec<NV> fv = load_vec<NV>(f, c[u]);
-#pragma unroll
-        for (int h = 0; h < NV; ++h) acc[h] = fmaf(v[u].v[h], fv.v[h], acc[h]);
-      }
+      __syncthreads();  // red is reused by the next tile
+    } else if (more) {
+      nxt = tile_ctx<false, RPW>(table, nsys, tn, ntiles, xcd);
     }
+    if (!more) break;
+    cur = nxt;
+    t = tn;
   }
-#pragma unroll
-  for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
-  double d = 0.0;
-  if (gl == 0 && row < S.m) {
-    const Vec<NV> pv = load_vec<NV>(S.p, row);
-    const float w = S.inv_row[row];
-    Vec<NV> zv;
-#pragma unroll
-    for (int h = 0; h < NV; ++h) {
-      const float r = pv.v[h] - acc[h];
-      zv.v[h] = r * w;
-      d += static_cast<double>(r) * static_cast<double>(r);
-    }
-    store_vec<NV>(S.z, row, zv);
-  }
-  __shared__ double red[kWPB];
-  const double tot = block_sum<kWPB>(d, red);
-  if (threadIdx.x == 0) S.partials[local] = tot;
 }
 
 // The first back-projection block of a system: rel_res(f^k) from the forward
@@ -227,74 +312,71 @@ template <int WPB>
 __device__ void finalize_residual(const Params* prm, const SysDesc& S, double* red) {
   SysState* st = S.st;
   double acc = 0.0;
-  for (int64_t t = threadIdx.x; t < S.fp_nblocks; t += WPB * kWave) acc += S.partials[t];
+  for (int64_t t = threadIdx.x; t < S.fp_nblocks; t += WPB * kWave) acc += gl(S.partials)[t];
   const double rsum = block_sum<WPB>(acc, red);
   if (threadIdx.x == 0) {
-    const double pn = st->pnorm2;
+    const double pn = *gl(&st->pnorm2);
     const double rel = pn > 0.0 ? sqrt(rsum / pn) : sqrt(rsum);
-    const int k = st->k;
-    if (S.res_hist) S.res_hist[k] = rel;
-    st->last_res = rel;
+    const int k = *gl(&st->k);
+    if (S.res_hist) glw(S.res_hist)[k] = rel;
+    glw(&st->last_res)[0] = rel;
     if (rel <= prm->tol || k >= prm->max_iter) store_flag(&st->stop, 1);
-    else st->pending = 1;
+    else glw(&st->pending)[0] = 1;
   }
 }
 
-template <int NV, int WT, int CPW>
-__global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* prm, const SysDesc* table, int nsys,
-                                                      uint32_t nblocks, int xcd, int parity) {
-  const uint32_t b = xcd ? xcd_remap(blockIdx.x, nblocks) : blockIdx.x;
-  const int s = nsys == 1 ? 0 : find_sys<true>(table, nsys, b);
-  const SysDesc& S = table[s];
-  SysState* st = S.st;
-  if (load_flag(&st->stop)) return;
-  const int64_t local = static_cast<int64_t>(b) - S.bp_block0;
-  if (local == 0) {
-    __shared__ double red[kWPB];
-    finalize_residual<kWPB>(prm, S, red);
-  }
-  // f^k with k = max_iter is final: its residual is all that was wanted
-  if (st->k >= prm->max_iter) return;
+// Back projection and update, with the residual finalisation in the first
+// tile of each system.  Grid-stride over tiles of CPW*kWPB columns, with the
+// same ordering as the forward kernel.
+template <int NV, int WT, int CPW, int U>
+__global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* __restrict__ prm,
+                                                      const SysDesc* __restrict__ table, int nsys,
+                                                      uint32_t ntiles, int xcd, int parity) {
   constexpr int L = kWave / CPW;
-  const int lane = lane_id();
-  const int gl = lane % L;
-  const int64_t col = local * (CPW * kWPB) + wave_id() * CPW + lane / L;
-  const float* f = S.f[parity];
-  float* fn = S.f[parity ^ 1];
-  float acc[NV];
+  __shared__ double red[kWPB];
+  uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  const int glane = lane_id() % L;
+  TileCtx cur = tile_ctx<true, CPW>(table, nsys, t, ntiles, xcd);
+  for (;;) {
+    const uint32_t tn = t + gridDim.x;
+    const bool more = tn < ntiles;
+    TileCtx nxt{};
+    bool prefetched = false;
+    if (!cur.stop) {
+      const SysDesc& S = table[cur.s];
+      if (cur.local == 0) {
+        finalize_residual<kWPB>(prm, S, red);
+        __syncthreads();
+      }
+      // f^k with k = max_iter is final: its residual is all that was wanted
+      if (*gl(&S.st->k) < prm->max_iter) {
+        const bool owner = glane == 0 && cur.line < S.n;
+        Vec<NV> fv{};
+        float tl = 0.0f;
+        if (owner) {
+          fv = load_vec<NV>(S.f[parity], cur.line);
+          tl = prm->lambda * gl(S.inv_col)[cur.line];
+        }
+        float acc[NV];
 #pragma unroll
-  for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-  if (col < S.n) {
-    const int64_t ce = S.col_ptr[col + 1];
-    for (int64_t base = S.col_ptr[col] + gl; base < ce; base += kUnroll * L) {
-      int32_t r[kUnroll];
-      Vec<NV> v[kUnroll];
+        for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
+        line_dot<NV, WT, L, U>(S.row_idx, S.val_t, S.z, cur.lo, cur.hi, glane, acc);
+        if (more) nxt = tile_ctx<true, CPW>(table, nsys, tn, ntiles, xcd);
+        prefetched = true;
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int64_t k = base + u * L;
-        r[u] = 0;
-        v[u] = Vec<NV>{};
-        if (k < ce) {
-          r[u] = S.row_idx[k];
-          v[u] = load_vals<NV, WT>(S.val_t, k);
+        for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
+        if (owner) {
+#pragma unroll
+          for (int h = 0; h < NV; ++h) fv.v[h] = fmaf(tl, acc[h], fv.v[h]);
+          store_vec<NV>(S.f[parity ^ 1], cur.line, fv);
         }
       }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const Vec<NV> zv = load_vec<NV>(S.z, r[u]);
-#pragma unroll
-        for (int h = 0; h < NV; ++h) acc[h] = fmaf(v[u].v[h], zv.v[h], acc[h]);
-      }
     }
-  }
-#pragma unroll
-  for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
-  if (gl == 0 && col < S.n) {
-    const float t = prm->lambda * S.inv_col[col];
-    Vec<NV> fv = load_vec<NV>(f, col);
-#pragma unroll
-    for (int h = 0; h < NV; ++h) fv.v[h] = fmaf(t, acc[h], fv.v[h]);
-    store_vec<NV>(fn, col, fv);
+    if (!more) break;
+    if (!prefetched) nxt = tile_ctx<true, CPW>(table, nsys, tn, ntiles, xcd);
+    cur = nxt;
+    t = tn;
   }
 }
 
@@ -346,7 +428,7 @@ Layout make_layout(const ss_system* sys, int nsys) {
 }
 
 struct Cfg {
-  int nv, wt, rpw, cpw, xcd;
+  int nv, wt, rpw, cpw, xcd, u;
 };
 
 ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const char* fn) {
@@ -370,6 +452,7 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
   auto ok_pw = [](int v, int maxv) { return v == 0 || (v > 0 && v <= maxv && (v & (v - 1)) == 0); };
   if (!ok_pw(o->rows_per_wave, 8)) return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8", fn);
   if (!ok_pw(o->cols_per_wave, 16)) return fail(SS_E_ARG, "%s: cols_per_wave must be 0,1,2,4,8,16", fn);
+  if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
   return SS_OK;
 }
 
@@ -392,6 +475,7 @@ Cfg choose_cfg(const ss_system* sys, int nsys, const ss_sart_opts* o) {
   c.rpw = o->rows_per_wave ? o->rows_per_wave : pick_per_wave(nnz / m, 8);
   c.cpw = o->cols_per_wave ? o->cols_per_wave : pick_per_wave(nnz / n, 16);
   c.xcd = o->xcd_remap ? 1 : 0;
+  c.u = o->unroll ? o->unroll : 4;
   return c;
 }
 
@@ -457,33 +541,55 @@ struct Stamp {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 
-template <int NV, int WT>
-void launch_fp_t(int rpw, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st,
-                 Stamp e) {
-  auto go = [&](auto kern) {
-    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, st, e.start, e.stop, 0, t, nsys, nb, xcd, par);
-  };
+// Grid for a grid-stride kernel: one block per tile when every tile fits in
+// one resident wave of blocks, else the resident capacity rounded down to a
+// multiple of 8 (so tile t always runs on XCD t mod 8).
+uint32_t grid_for(const void* kern, uint32_t ntiles) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, uint32_t> cap;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  uint32_t resident;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cap.find({kern, dev});
+    if (it == cap.end()) {
+      int cus = 0, per = 0;
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, 0);
+      const uint32_t r = static_cast<uint32_t>(std::max(1, cus) * std::max(1, per));
+      it = cap.emplace(std::make_pair(kern, dev), std::max<uint32_t>(8, r & ~7u)).first;
+    }
+    resident = it->second;
+  }
+  return ntiles <= resident ? ntiles : resident;
+}
+
+template <typename K, typename... Args>
+void go(K kern, uint32_t ntiles, hipStream_t st, Stamp e, Args... args) {
+  const uint32_t grid = grid_for(reinterpret_cast<const void*>(kern), ntiles);
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, e.start, e.stop, 0, args...);
+}
+
+template <int NV, int WT, int U>
+void launch_fp_u(int rpw, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st, Stamp e) {
   switch (rpw) {
-    case 1: go(k_sart_fp<NV, WT, 1>); break;
-    case 2: go(k_sart_fp<NV, WT, 2>); break;
-    case 4: go(k_sart_fp<NV, WT, 4>); break;
-    default: go(k_sart_fp<NV, WT, 8>); break;
+    case 1: go(k_sart_fp<NV, WT, 1, U>, nb, st, e, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_fp<NV, WT, 2, U>, nb, st, e, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_fp<NV, WT, 4, U>, nb, st, e, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_fp<NV, WT, 8, U>, nb, st, e, t, nsys, nb, xcd, par); break;
   }
 }
 
-template <int NV, int WT>
-void launch_bp_t(int cpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
+template <int NV, int WT, int U>
+void launch_bp_u(int cpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
                  hipStream_t st, Stamp e) {
-  auto go = [&](auto kern) {
-    hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, st, e.start, e.stop, 0, prm, t, nsys, nb, xcd,
-                          par);
-  };
   switch (cpw) {
-    case 1: go(k_sart_bp<NV, WT, 1>); break;
-    case 2: go(k_sart_bp<NV, WT, 2>); break;
-    case 4: go(k_sart_bp<NV, WT, 4>); break;
-    case 8: go(k_sart_bp<NV, WT, 8>); break;
-    default: go(k_sart_bp<NV, WT, 16>); break;
+    case 1: go(k_sart_bp<NV, WT, 1, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_bp<NV, WT, 2, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_bp<NV, WT, 4, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 8: go(k_sart_bp<NV, WT, 8, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_bp<NV, WT, 16, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
   }
 }
 
@@ -492,18 +598,24 @@ void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, cons
                    hipStream_t st, Stamp e = {}) {
   const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
-#define SS_DISPATCH(NV, WT)                                                           \
-  if (c.nv == NV && c.wt == WT) {                                                     \
-    if (BP) launch_bp_t<NV, WT>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e);  \
-    else launch_fp_t<NV, WT>(c.rpw, t, nsys, g.fp_blocks, c.xcd, par, st, e);          \
-    return;                                                                           \
+#define SS_DISPATCH(NV, WT, U)                                                              \
+  if (c.nv == NV && c.wt == WT && c.u == U) {                                               \
+    if (BP) launch_bp_u<NV, WT, U>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e);     \
+    else launch_fp_u<NV, WT, U>(c.rpw, t, nsys, g.fp_blocks, c.xcd, par, st, e);             \
+    return;                                                                                 \
   }
-  SS_DISPATCH(2, SS_F32)
-  SS_DISPATCH(2, SS_BF16)
-  SS_DISPATCH(2, SS_F16)
-  SS_DISPATCH(1, SS_F32)
-  SS_DISPATCH(1, SS_BF16)
-  SS_DISPATCH(1, SS_F16)
+  SS_DISPATCH(2, SS_F32, 4)
+  SS_DISPATCH(2, SS_BF16, 4)
+  SS_DISPATCH(2, SS_F16, 4)
+  SS_DISPATCH(1, SS_F32, 4)
+  SS_DISPATCH(1, SS_BF16, 4)
+  SS_DISPATCH(1, SS_F16, 4)
+  SS_DISPATCH(2, SS_F32, 8)
+  SS_DISPATCH(2, SS_BF16, 8)
+  SS_DISPATCH(2, SS_F16, 8)
+  SS_DISPATCH(1, SS_F32, 8)
+  SS_DISPATCH(1, SS_BF16, 8)
+  SS_DISPATCH(1, SS_F16, 8)
 #undef SS_DISPATCH
 }
 
@@ -529,10 +641,10 @@ struct GraphKey {
   const void* ws;
   int nsys;
   uint32_t fpb, bpb;
-  int nv, wt, rpw, cpw, xcd, count;
+  int nv, wt, rpw, cpw, xcd, u, count;
   bool operator<(const GraphKey& o) const {
-    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, count) <
-           std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.count);
+    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, count) <
+           std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.u, o.count);
   }
 };
 
@@ -629,7 +741,7 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   if (opts->use_graph) {
     int dev = 0;
     SS_HIP_TRY(hipGetDevice(&dev));
-    const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, chunk};
+    const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, chunk};
     if (ss_status s = get_graph(key, c, ws, L, g, &exec)) return s;
   }
   std::vector<SysState> hs;
@@ -712,7 +824,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::tuple<int, int, int>> g_tune;
+std::map<TuneKey, std::tuple<int, int, int, int>> g_tune;
 }  // namespace
 
 extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f, ss_sart_opts* opts,
@@ -731,7 +843,7 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      std::tie(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap) = it->second;
+      std::tie(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll) = it->second;
       return SS_OK;
     }
   }
@@ -740,47 +852,39 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
   // than 3 % faster, so that timing noise does not flip the choice
   const int reps = 20;
   const Cfg dflt = choose_cfg(sys, nsys, opts);
-  double best_fp = 1e30, best_bp = 1e30, dflt_fp = 1e30, dflt_bp = 1e30;
-  int brpw = dflt.rpw, bcpw = dflt.cpw, bxcd_fp = 0, bxcd_bp = 0;
+  struct Best {
+    double t = 1e30;
+    int pw = 1, u = 4, xcd = 0;
+  } bf, bb, df, db;
   for (int xcd = 0; xcd <= 1; ++xcd) {
-    for (int pw = 1; pw <= 16; pw <<= 1) {
-      ss_sart_opts o = *opts;
-      o.xcd_remap = xcd;
-      o.rows_per_wave = pw <= 8 ? pw : 8;
-      o.cols_per_wave = pw;
-      double tf = 0, tb = 0;
-      if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes, stream))
-        return s;
-      if (xcd == 0 && o.rows_per_wave == dflt.rpw) dflt_fp = std::min(dflt_fp, tf);
-      if (xcd == 0 && o.cols_per_wave == dflt.cpw) dflt_bp = std::min(dflt_bp, tb);
-      if (pw <= 8 && tf < best_fp) {
-        best_fp = tf;
-        brpw = pw;
-        bxcd_fp = xcd;
-      }
-      if (tb < best_bp) {
-        best_bp = tb;
-        bcpw = pw;
-        bxcd_bp = xcd;
+    for (int u = 4; u <= 8; u += 4) {
+      for (int pw = 1; pw <= 16; pw <<= 1) {
+        ss_sart_opts o = *opts;
+        o.xcd_remap = xcd;
+        o.unroll = u;
+        o.rows_per_wave = pw <= 8 ? pw : 8;
+        o.cols_per_wave = pw;
+        double tf = 0, tb = 0;
+        if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes,
+                                               stream))
+          return s;
+        if (xcd == 0 && u == 4 && o.rows_per_wave == dflt.rpw && tf < df.t) df = {tf, dflt.rpw, 4, 0};
+        if (xcd == 0 && u == 4 && o.cols_per_wave == dflt.cpw && tb < db.t) db = {tb, dflt.cpw, 4, 0};
+        if (pw <= 8 && tf < bf.t) bf = {tf, pw, u, xcd};
+        if (tb < bb.t) bb = {tb, pw, u, xcd};
       }
     }
   }
-  if (dflt_fp <= 1.03 * best_fp) {
-    brpw = dflt.rpw;
-    bxcd_fp = 0;
-    best_fp = dflt_fp;
-  }
-  if (dflt_bp <= 1.03 * best_bp) {
-    bcpw = dflt.cpw;
-    bxcd_bp = 0;
-    best_bp = dflt_bp;
-  }
-  // one remap flag serves both kernels: take the one of the slower kernel
-  const int xcd = best_fp >= best_bp ? bxcd_fp : bxcd_bp;
-  opts->rows_per_wave = brpw;
-  opts->cols_per_wave = bcpw;
-  opts->xcd_remap = xcd;
+  if (df.t <= 1.03 * bf.t) bf = df;
+  if (db.t <= 1.03 * bb.t) bb = db;
+  // one remap flag and one unroll depth serve both kernels: take those of
+  // the slower kernel
+  const Best& slow = bf.t >= bb.t ? bf : bb;
+  opts->rows_per_wave = bf.pw;
+  opts->cols_per_wave = bb.pw;
+  opts->xcd_remap = slow.xcd;
+  opts->unroll = slow.u;
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  g_tune[key] = std::make_tuple(brpw, bcpw, xcd);
+  g_tune[key] = std::make_tuple(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll);
   return SS_OK;
 }

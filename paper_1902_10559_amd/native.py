@@ -61,7 +61,8 @@ class SartOptsC(C.Structure):
     _fields_ = [("lambda_", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("rows_per_wave", C.c_int32), ("cols_per_wave", C.c_int32),
-                ("xcd_remap", C.c_int32), ("zero_start", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("zero_start", C.c_int32),
+                ("unroll", C.c_int32)]
 
 
 _SIGNATURES = {
@@ -327,11 +328,12 @@ class SartOptions:
     cols_per_wave: int = 0
     xcd_remap: int = 0
     zero_start: bool = False
+    unroll: int = 0
 
     def c(self) -> SartOptsC:
         return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
                          int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
-                         self.xcd_remap, int(self.zero_start))
+                         self.xcd_remap, int(self.zero_start), self.unroll)
 
 
 class Solver:
@@ -386,6 +388,7 @@ class Solver:
         self.opts.rows_per_wave = oc.rows_per_wave
         self.opts.cols_per_wave = oc.cols_per_wave
         self.opts.xcd_remap = oc.xcd_remap
+        self.opts.unroll = oc.unroll
         return self.opts
 
 
