@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
-    ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD",
+    ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT",
                     help="fixed launch shape instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB, so that "
@@ -130,7 +130,8 @@ def main():
     sol = native.Solver(systems, opts)
     scratch = [S.new_image() for S in systems]
     if args.shape:
-        opts.rows_per_wave, opts.cols_per_wave, opts.xcd_remap = map(int, args.shape.split(","))
+        (opts.rows_per_wave, opts.cols_per_wave, opts.xcd_remap, opts.unroll,
+         opts.persistent) = map(int, args.shape.split(","))
     else:
         sol.autotune(scratch)
     f12 = [S.new_image() for S in systems]
@@ -171,7 +172,8 @@ def main():
                                f"+ recombination per step",
                    "slices": len(slices), "nnz": int(nnz_full), "nnz_half": int(nnz_half),
                    "iterations": iters, "rows_per_wave": opts.rows_per_wave,
-                   "cols_per_wave": opts.cols_per_wave, "xcd_remap": opts.xcd_remap},
+                   "cols_per_wave": opts.cols_per_wave, "xcd_remap": opts.xcd_remap,
+                   "unroll": opts.unroll, "persistent": opts.persistent},
     }
     if args.no_extras:
         print(json.dumps(out), flush=True)
@@ -217,7 +219,8 @@ def main():
     out["unsplit"] = {"ms_per_step": ums, "value": iters * nnz_full / (ums * 1e-3),
                       "fp_ms": ufp, "bp_ms": ubp, "bytes_per_iteration": ub,
                       "kernel_gbs_per_iteration": ub / ((ufp + ubp) * 1e-3) / 1e9,
-                      "shape": [uopts.rows_per_wave, uopts.cols_per_wave, uopts.xcd_remap]}
+                      "shape": [uopts.rows_per_wave, uopts.cols_per_wave, uopts.xcd_remap,
+                                uopts.unroll, uopts.persistent]}
     out["split_vs_unsplit"] = ums / ms
     log(f"unsplit step {ums:.3f} ms; split/unsplit speedup {ums / ms:.2f}")
 

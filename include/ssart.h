@@ -222,6 +222,9 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *   zero_start   1: start from f^0 = 0 (the solver clears f itself);
  *                0: start from the image the caller passes
  *   unroll       entries each lane has in flight per pass: 4 or 8 (0 = 4)
+ *   persistent   1: size the grid to the resident capacity and let each block
+ *                loop over tiles (prefetching the next one); 0: one block
+ *                per tile
  * rel_res(f^k) = ||p - A f^k|| / ||p||, from the halves as
  *   sqrt((||r1||^2 + ||r2||^2) / (||p1||^2 + ||p2||^2)), FP64. */
 typedef struct {
@@ -235,6 +238,7 @@ typedef struct {
   int32_t xcd_remap;
   int32_t zero_start;
   int32_t unroll;
+  int32_t persistent;
 } ss_sart_opts;
 
 /* Workspace bytes for solving `nsys` systems together with these options. */
@@ -267,7 +271,7 @@ ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys,
                                void* workspace, size_t workspace_bytes,
                                void* stream);
 
-/* Picks rows_per_wave, cols_per_wave, unroll and xcd_remap for these systems by
+/* Picks rows_per_wave, cols_per_wave, unroll, persistent and xcd_remap by
  * timing every candidate (ss_sart_time_kernels) and writes them into
  * *opts.  Results are cached per (nvals, wdtype, shape statistics).
  * The images f are used as scratch.  Synchronises. */

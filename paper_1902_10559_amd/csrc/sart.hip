@@ -428,7 +428,7 @@ Layout make_layout(const ss_system* sys, int nsys) {
 }
 
 struct Cfg {
-  int nv, wt, rpw, cpw, xcd, u;
+  int nv, wt, rpw, cpw, xcd, u, pers;
 };
 
 ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const char* fn) {
@@ -476,6 +476,7 @@ Cfg choose_cfg(const ss_system* sys, int nsys, const ss_sart_opts* o) {
   c.cpw = o->cols_per_wave ? o->cols_per_wave : pick_per_wave(nnz / n, 16);
   c.xcd = o->xcd_remap ? 1 : 0;
   c.u = o->unroll ? o->unroll : 4;
+  c.pers = o->persistent ? 1 : 0;
   return c;
 }
 
@@ -541,10 +542,11 @@ struct Stamp {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 
-// Grid for a grid-stride kernel: one block per tile when every tile fits in
-// one resident wave of blocks, else the resident capacity rounded down to a
-// multiple of 8 (so tile t always runs on XCD t mod 8).
-uint32_t grid_for(const void* kern, uint32_t ntiles) {
+// Grid for a grid-stride kernel: one block per tile, unless `persistent`
+// and there are more tiles than resident blocks: then the resident capacity
+// rounded down to a multiple of 8 (so tile t always runs on XCD t mod 8).
+uint32_t grid_for(const void* kern, uint32_t ntiles, int persistent) {
+  if (!persistent) return ntiles;
   static std::mutex mu;
   static std::map<std::pair<const void*, int>, uint32_t> cap;
   int dev = 0;
@@ -566,30 +568,31 @@ uint32_t grid_for(const void* kern, uint32_t ntiles) {
 }
 
 template <typename K, typename... Args>
-void go(K kern, uint32_t ntiles, hipStream_t st, Stamp e, Args... args) {
-  const uint32_t grid = grid_for(reinterpret_cast<const void*>(kern), ntiles);
+void go(K kern, uint32_t ntiles, int persistent, hipStream_t st, Stamp e, Args... args) {
+  const uint32_t grid = grid_for(reinterpret_cast<const void*>(kern), ntiles, persistent);
   hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, e.start, e.stop, 0, args...);
 }
 
 template <int NV, int WT, int U>
-void launch_fp_u(int rpw, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st, Stamp e) {
+void launch_fp_u(int rpw, int pers, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st,
+                 Stamp e) {
   switch (rpw) {
-    case 1: go(k_sart_fp<NV, WT, 1, U>, nb, st, e, t, nsys, nb, xcd, par); break;
-    case 2: go(k_sart_fp<NV, WT, 2, U>, nb, st, e, t, nsys, nb, xcd, par); break;
-    case 4: go(k_sart_fp<NV, WT, 4, U>, nb, st, e, t, nsys, nb, xcd, par); break;
-    default: go(k_sart_fp<NV, WT, 8, U>, nb, st, e, t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_fp<NV, WT, 1, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_fp<NV, WT, 2, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_fp<NV, WT, 4, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_fp<NV, WT, 8, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
   }
 }
 
 template <int NV, int WT, int U>
-void launch_bp_u(int cpw, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
+void launch_bp_u(int cpw, int pers, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
                  hipStream_t st, Stamp e) {
   switch (cpw) {
-    case 1: go(k_sart_bp<NV, WT, 1, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 2: go(k_sart_bp<NV, WT, 2, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 4: go(k_sart_bp<NV, WT, 4, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 8: go(k_sart_bp<NV, WT, 8, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
-    default: go(k_sart_bp<NV, WT, 16, U>, nb, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_bp<NV, WT, 1, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_bp<NV, WT, 2, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_bp<NV, WT, 4, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 8: go(k_sart_bp<NV, WT, 8, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_bp<NV, WT, 16, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
   }
 }
 
@@ -600,8 +603,8 @@ void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, cons
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
 #define SS_DISPATCH(NV, WT, U)                                                              \
   if (c.nv == NV && c.wt == WT && c.u == U) {                                               \
-    if (BP) launch_bp_u<NV, WT, U>(c.cpw, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e);     \
-    else launch_fp_u<NV, WT, U>(c.rpw, t, nsys, g.fp_blocks, c.xcd, par, st, e);             \
+    if (BP) launch_bp_u<NV, WT, U>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e); \
+    else launch_fp_u<NV, WT, U>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e);         \
     return;                                                                                 \
   }
   SS_DISPATCH(2, SS_F32, 4)
@@ -641,10 +644,10 @@ struct GraphKey {
   const void* ws;
   int nsys;
   uint32_t fpb, bpb;
-  int nv, wt, rpw, cpw, xcd, u, count;
+  int nv, wt, rpw, cpw, xcd, u, pers, count;
   bool operator<(const GraphKey& o) const {
-    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, count) <
-           std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.u, o.count);
+    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, pers, count) <
+           std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.u, o.pers, o.count);
   }
 };
 
@@ -741,7 +744,8 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   if (opts->use_graph) {
     int dev = 0;
     SS_HIP_TRY(hipGetDevice(&dev));
-    const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, chunk};
+    const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, c.pers,
+                       chunk};
     if (ss_status s = get_graph(key, c, ws, L, g, &exec)) return s;
   }
   std::vector<SysState> hs;
@@ -824,7 +828,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::tuple<int, int, int, int>> g_tune;
+std::map<TuneKey, std::tuple<int, int, int, int, int>> g_tune;
 }  // namespace
 
 extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f, ss_sart_opts* opts,
@@ -843,7 +847,8 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      std::tie(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll) = it->second;
+      std::tie(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll, opts->persistent) =
+          it->second;
       return SS_OK;
     }
   }
@@ -854,37 +859,43 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
   const Cfg dflt = choose_cfg(sys, nsys, opts);
   struct Best {
     double t = 1e30;
-    int pw = 1, u = 4, xcd = 0;
+    int pw = 1, u = 4, xcd = 0, pers = 0;
   } bf, bb, df, db;
-  for (int xcd = 0; xcd <= 1; ++xcd) {
-    for (int u = 4; u <= 8; u += 4) {
-      for (int pw = 1; pw <= 16; pw <<= 1) {
-        ss_sart_opts o = *opts;
-        o.xcd_remap = xcd;
-        o.unroll = u;
-        o.rows_per_wave = pw <= 8 ? pw : 8;
-        o.cols_per_wave = pw;
-        double tf = 0, tb = 0;
-        if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes,
-                                               stream))
-          return s;
-        if (xcd == 0 && u == 4 && o.rows_per_wave == dflt.rpw && tf < df.t) df = {tf, dflt.rpw, 4, 0};
-        if (xcd == 0 && u == 4 && o.cols_per_wave == dflt.cpw && tb < db.t) db = {tb, dflt.cpw, 4, 0};
-        if (pw <= 8 && tf < bf.t) bf = {tf, pw, u, xcd};
-        if (tb < bb.t) bb = {tb, pw, u, xcd};
+  for (int pers = 0; pers <= 1; ++pers) {
+    for (int xcd = 0; xcd <= 1; ++xcd) {
+      for (int u = 4; u <= 8; u += 4) {
+        for (int pw = 1; pw <= 16; pw <<= 1) {
+          ss_sart_opts o = *opts;
+          o.persistent = pers;
+          o.xcd_remap = xcd;
+          o.unroll = u;
+          o.rows_per_wave = pw <= 8 ? pw : 8;
+          o.cols_per_wave = pw;
+          double tf = 0, tb = 0;
+          if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes,
+                                                 stream))
+            return s;
+          const bool base = xcd == 0 && u == 4 && pers == 0;
+          if (base && o.rows_per_wave == dflt.rpw && tf < df.t) df = {tf, dflt.rpw, 4, 0, 0};
+          if (base && o.cols_per_wave == dflt.cpw && tb < db.t) db = {tb, dflt.cpw, 4, 0, 0};
+          if (pw <= 8 && tf < bf.t) bf = {tf, pw, u, xcd, pers};
+          if (tb < bb.t) bb = {tb, pw, u, xcd, pers};
+        }
       }
     }
   }
   if (df.t <= 1.03 * bf.t) bf = df;
   if (db.t <= 1.03 * bb.t) bb = db;
-  // one remap flag and one unroll depth serve both kernels: take those of
-  // the slower kernel
+  // one remap flag, unroll depth and grid mode serve both kernels: take
+  // those of the slower kernel
   const Best& slow = bf.t >= bb.t ? bf : bb;
   opts->rows_per_wave = bf.pw;
   opts->cols_per_wave = bb.pw;
   opts->xcd_remap = slow.xcd;
   opts->unroll = slow.u;
+  opts->persistent = slow.pers;
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  g_tune[key] = std::make_tuple(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll);
+  g_tune[key] = std::make_tuple(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll,
+                                opts->persistent);
   return SS_OK;
 }

@@ -62,7 +62,7 @@ class SartOptsC(C.Structure):
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("rows_per_wave", C.c_int32), ("cols_per_wave", C.c_int32),
                 ("xcd_remap", C.c_int32), ("zero_start", C.c_int32),
-                ("unroll", C.c_int32)]
+                ("unroll", C.c_int32), ("persistent", C.c_int32)]
 
 
 _SIGNATURES = {
@@ -329,11 +329,12 @@ class SartOptions:
     xcd_remap: int = 0
     zero_start: bool = False
     unroll: int = 0
+    persistent: int = 0
 
     def c(self) -> SartOptsC:
         return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
                          int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
-                         self.xcd_remap, int(self.zero_start), self.unroll)
+                         self.xcd_remap, int(self.zero_start), self.unroll, self.persistent)
 
 
 class Solver:
@@ -389,6 +390,7 @@ class Solver:
         self.opts.cols_per_wave = oc.cols_per_wave
         self.opts.xcd_remap = oc.xcd_remap
         self.opts.unroll = oc.unroll
+        self.opts.persistent = oc.persistent
         return self.opts
 
 
