@@ -297,6 +297,77 @@ ss_status ss_image_fold(const float* f, int64_t N, float* f12, void* stream);
 ss_status ss_project(const ss_matrix_dev* A, const float* f, float* q,
                      void* stream);
 
+
+/* ------------------------------------------------------------------------
+ * Learned initialiser: the kernels of a small convolutional network that
+ * maps an early split-SART image to a later one (used to start SART closer
+ * to its limit).  Not part of the paper's method; SART itself stays the
+ * arbiter (a learned start is only kept if its residual is lower).
+ * Tensors are NHWC; activations BF16 (stored as uint16 bit patterns),
+ * gradients that accumulate FP32.  3x3 convolutions, stride 1, one pixel of
+ * zero padding.  FP32 master weights are laid out [O][3][3][C].  All calls
+ * are asynchronous and allocate nothing.
+ * ---------------------------------------------------------------------- */
+
+/* fold of the right-hand side only: p12[2i] = p[i] - p[M-1-i],
+ * p12[2i+1] = p[i] + p[M-1-i] (Section 2), for systems that share a folded
+ * matrix and differ in p. */
+ss_status ss_fold_rhs(const float* p, int64_t M, float* p12, void* stream);
+
+/* BF16 forward weights [O][9][Cp] and the flipped, transposed copy
+ * [C][9][Op] (w_bwd[c][t][o] = w[o][8-t][c]) that computes the input
+ * gradient as a forward convolution; Cp, Op = C, O rounded up to 8 with
+ * zero padding. */
+ss_status ss_nn_prep_weights(const float* w, int32_t O, int32_t C, void* w_fwd, void* w_bwd, void* stream);
+
+/* y = act(bias + conv3x3(x, w)), x (N,H,W,C) BF16, w [O][9][Cp] BF16, bias FP32
+ * or NULL, relu 0/1, y (N,H,W,O) BF16 (y_f32 = 0) or FP32 (y_f32 = 1).
+ * FP32 accumulation on the matrix cores.  N*H <= 65535. */
+ss_status ss_nn_conv3x3(const void* x, int32_t N, int32_t H, int32_t W, int32_t C, const void* w,
+                        const float* bias, int32_t O, int32_t relu, void* y, int32_t y_f32, void* stream);
+
+/* gw [O][3][3][C] += sum over pixels of gy (x) shifted x; gb [O] += sum of gy
+ * (gb may be NULL).  x (N,H,W,C), gy (N,H,W,O), both BF16; FP32 atomics, so
+ * the summation order is not fixed. */
+ss_status ss_nn_conv3x3_wgrad(const void* x, const void* gy, int32_t N, int32_t H, int32_t W, int32_t C,
+                              int32_t O, float* gw, float* gb, void* stream);
+
+/* out = BF16(g * [y > 0]) for the ReLU output y (BF16), or BF16(g) if y is
+ * NULL. */
+ss_status ss_nn_relu_mask(const float* g, const void* y, int64_t n, void* out, void* stream);
+
+/* 2x2 average pool of x (N,H,W,C) into y (N,H/2,W/2,C), BF16; and its
+ * gradient gx (N,H,W,C) (+)= gy/4, FP32. */
+ss_status ss_nn_pool2(const void* x, int32_t N, int32_t H, int32_t W, int32_t C, void* y, void* stream);
+ss_status ss_nn_pool2_grad(const float* gy, int32_t N, int32_t H, int32_t W, int32_t C, float* gx,
+                           int32_t accumulate, void* stream);
+
+/* Channel-slice copies for skip connections: y[..., coff:coff+C] of a
+ * (N,Hy,Wy,Ctot) map = x, nearest-upsampled 2x when up = 1 (x is then
+ * (N,Hy/2,Wy/2,C)); and the gradient of that slice back into gx (N,Hx,Wx,C),
+ * summed over each 2x2 block when up = 1. */
+ss_status ss_nn_to_slice(const void* x, int32_t N, int32_t Hy, int32_t Wy, int32_t C, int32_t up, void* y,
+                         int32_t Ctot, int32_t coff, void* stream);
+ss_status ss_nn_from_slice(const float* gy, int32_t N, int32_t Hx, int32_t Wx, int32_t C, int32_t up,
+                           int32_t Ctot, int32_t coff, float* gx, int32_t accumulate, void* stream);
+
+/* out = x + r; with target: g = 2 (out - target) / n (g may be NULL) and
+ * *loss += mean squared error (FP64). */
+ss_status ss_nn_residual_mse(const float* r, const float* x, const float* target, int64_t n, float* out,
+                             float* g, double* loss, void* stream);
+
+ss_status ss_nn_to_bf16(const float* x, int64_t n, void* y, void* stream);
+
+/* Adam step (bias-corrected) on FP32 weights; step counts from 1. */
+ss_status ss_nn_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                     float eps, int32_t step, void* stream);
+
+/* Vertical-snake vectors (nimg images of nx*nz voxels) to images (N,nz,nx,1)
+ * in FP32 and/or BF16 (to_image = 1), or images (FP32) back to snake order
+ * (to_image = 0, dst32). */
+ss_status ss_nn_snake_image(const float* src, int64_t nimg, int32_t nx, int32_t nz, int32_t to_image,
+                            float* dst32, void* dst16, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,13 @@ __global__ void k_image_fold(const float* __restrict__ f, int64_t n, float2* __r
   f12[j] = make_float2(a - b, a + b);
 }
 
+__global__ void k_fold_rhs(const float* __restrict__ p, int64_t m, float2* __restrict__ p12) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const float a = p[i], b = p[2 * m - 1 - i];
+  p12[i] = make_float2(a - b, a + b);
+}
+
 constexpr int kProjWaves = 4;
 
 // q[i] = sum_j A[i,j] f[j]; one wavefront per row, FP32 accumulation.
@@ -72,6 +79,17 @@ extern "C" ss_status ss_project(const ss_matrix_dev* A, const float* f, float* q
     return fail(SS_E_ARG, "ss_project: bad argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   k_project<<<static_cast<unsigned>((A->M + kProjWaves - 1) / kProjWaves), kWave * kProjWaves, 0, st>>>(*A, f, q);
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+extern "C" ss_status ss_fold_rhs(const float* p, int64_t M, float* p12, void* stream) {
+  clear_error();
+  if (!p || !p12 || M <= 0) return fail(SS_E_ARG, "ss_fold_rhs: bad argument");
+  if (M % 2) return fail(SS_E_ODD, "ss_fold_rhs: M must be even");
+  const int64_t m = M / 2;
+  k_fold_rhs<<<static_cast<unsigned>((m + 255) / 256), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      p, m, reinterpret_cast<float2*>(p12));
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;
 }

@@ -92,6 +92,29 @@ _SIGNATURES = {
     "ss_recombine": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ss_image_fold": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ss_project": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ss_fold_rhs": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_nn_prep_weights": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
+    "ss_nn_conv3x3": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                  C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+    "ss_nn_conv3x3_wgrad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                        C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ss_nn_relu_mask": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_nn_pool2": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                C.c_void_p]),
+    "ss_nn_pool2_grad": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                     C.c_int32, C.c_void_p]),
+    "ss_nn_to_slice": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "ss_nn_from_slice": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+    "ss_nn_residual_mse": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ss_nn_to_bf16": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_nn_adam": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
+                               C.c_float, C.c_float, C.c_float, C.c_int32, C.c_void_p]),
+    "ss_nn_snake_image": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]),
 }
 
 _lib = None
@@ -422,3 +445,68 @@ def project(A: DeviceMatrix, f, out=None):
     mc = A.c()
     _check(lib().ss_project(C.byref(mc), _ptr(f), _ptr(out), _stream(f.device)))
     return out
+
+
+def fold_rhs(p, out=None):
+    """ss_fold_rhs: (p1, p2) interleaved, for systems sharing a folded matrix."""
+    import torch
+    M = p.shape[0]
+    if out is None:
+        out = torch.empty(M, dtype=torch.float32, device=p.device)
+    _check(lib().ss_fold_rhs(_ptr(p), M, _ptr(out), _stream(p.device)))
+    return out
+
+
+# -------------------------------------------------- learned initialiser ops
+def nn_prep_weights(w32, O, C, w_fwd, w_bwd):
+    _check(lib().ss_nn_prep_weights(_ptr(w32), O, C, _ptr(w_fwd), _ptr(w_bwd), _stream(w32.device)))
+
+
+def nn_conv3x3(x, N, H, W, C, w, bias, O, relu, y, y_f32=False):
+    _check(lib().ss_nn_conv3x3(_ptr(x), N, H, W, C, _ptr(w), _ptr(bias), O, int(relu), _ptr(y),
+                               int(y_f32), _stream(x.device)))
+
+
+def nn_conv3x3_wgrad(x, gy, N, H, W, C, O, gw, gb):
+    _check(lib().ss_nn_conv3x3_wgrad(_ptr(x), _ptr(gy), N, H, W, C, O, _ptr(gw), _ptr(gb),
+                                     _stream(x.device)))
+
+
+def nn_relu_mask(g, y, out):
+    _check(lib().ss_nn_relu_mask(_ptr(g), _ptr(y), g.numel(), _ptr(out), _stream(g.device)))
+
+
+def nn_pool2(x, N, H, W, C, y):
+    _check(lib().ss_nn_pool2(_ptr(x), N, H, W, C, _ptr(y), _stream(x.device)))
+
+
+def nn_pool2_grad(gy, N, H, W, C, gx, accumulate=False):
+    _check(lib().ss_nn_pool2_grad(_ptr(gy), N, H, W, C, _ptr(gx), int(accumulate), _stream(gy.device)))
+
+
+def nn_to_slice(x, N, Hy, Wy, C, up, y, Ctot, coff):
+    _check(lib().ss_nn_to_slice(_ptr(x), N, Hy, Wy, C, int(up), _ptr(y), Ctot, coff, _stream(x.device)))
+
+
+def nn_from_slice(gy, N, Hx, Wx, C, up, Ctot, coff, gx, accumulate=False):
+    _check(lib().ss_nn_from_slice(_ptr(gy), N, Hx, Wx, C, int(up), Ctot, coff, _ptr(gx),
+                                  int(accumulate), _stream(gy.device)))
+
+
+def nn_residual_mse(r, x, target, out, g=None, loss=None):
+    _check(lib().ss_nn_residual_mse(_ptr(r), _ptr(x), _ptr(target), r.numel(), _ptr(out), _ptr(g),
+                                    _ptr(loss), _stream(r.device)))
+
+
+def nn_to_bf16(x, y):
+    _check(lib().ss_nn_to_bf16(_ptr(x), x.numel(), _ptr(y), _stream(x.device)))
+
+
+def nn_adam(w, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+    _check(lib().ss_nn_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), lr, b1, b2, eps, step,
+                            _stream(w.device)))
+
+
+def nn_snake_image(src, nimg, nx, nz, to_image, dst32=None, dst16=None):
+    _check(lib().ss_nn_snake_image(_ptr(src), nimg, nx, nz, int(to_image), _ptr(dst32), _ptr(dst16),
+                                   _stream(src.device)))
