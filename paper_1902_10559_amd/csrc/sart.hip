@@ -161,7 +161,10 @@ __device__ inline int32_t ld_stream(const int32_t* p) { return *gl(p); }
 
 // Sum over one line (row or column) of A(s)^T-free form: acc += sum_k val[k] *
 // x[idx[k]] for k in [lo, hi), by the L lanes of a group, U entries per lane
-// in flight per pass.
+// in flight per pass.  Slots past the end of the line re-read the line's last
+// entry (same cache line, no extra DRAM traffic) and are masked out of the
+// sum: with no branch around them, all 2U stream loads of a pass are issued
+// before the first wait, then all U gathers.
 template <int NV, int WT, int L, int U>
 __device__ inline void line_dot(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
                                 int glane, float* acc) {
@@ -171,18 +174,19 @@ __device__ inline void line_dot(const int32_t* idx, const void* val, const float
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t k = base + u * L;
-      c[u] = 0;
-      v[u] = Vec<NV>{};
-      if (k < hi) {
-        c[u] = ld_stream(idx + k);
-        v[u] = load_vals<NV, WT>(val, k);
-      }
+      const int64_t kk = k < hi ? k : hi - 1;
+      c[u] = ld_stream(idx + kk);
+      v[u] = load_vals<NV, WT>(val, kk);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const Vec<NV> xv = load_vec<NV>(x, c[u]);
+      const bool in = base + u * L < hi;
 #pragma unroll
-      for (int h = 0; h < NV; ++h) acc[h] = fmaf(v[u].v[h], xv.v[h], acc[h]);
+      for (int h = 0; h < NV; ++h) {
+        const float s = fmaf(v[u].v[h], xv.v[h], acc[h]);
+        acc[h] = in ? s : acc[h];
+      }
     }
   }
 }
@@ -207,13 +211,11 @@ __device__ inline TileCtx tile_ctx(const SysDesc* table, int nsys, uint32_t t, u
   c.stop = *gl(&S.st->stop);
   c.local = static_cast<int64_t>(b) - (BP ? S.bp_block0 : S.fp_block0);
   c.line = c.local * (PW * kWPB) + wave_id() * PW + lane_id() / (kWave / PW);
-  c.lo = c.hi = 0;
+  // lines past the end read ptr[lines] twice: an empty line, with no branch
   const int64_t lines = BP ? S.n : S.m;
   const int64_t* ptr = BP ? S.col_ptr : S.row_ptr;
-  if (c.line < lines) {
-    c.lo = gl(ptr)[c.line];
-    c.hi = gl(ptr)[c.line + 1];
-  }
+  c.lo = gl(ptr)[c.line < lines ? c.line : lines];
+  c.hi = gl(ptr)[c.line + 1 < lines ? c.line + 1 : lines];
   return c;
 }
 
@@ -236,13 +238,12 @@ __global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* __restrict_
     TileCtx nxt{};
     if (!cur.stop) {
       const SysDesc& S = table[cur.s];
+      // every lane requests its line's p and 1/W (one request per group),
+      // so no branch separates these loads from the row's stream loads
       const bool owner = glane == 0 && cur.line < S.m;
-      Vec<NV> pv{};
-      float w = 0.0f;
-      if (owner) {
-        pv = load_vec<NV>(S.p, cur.line);
-        w = gl(S.inv_row)[cur.line];
-      }
+      const int64_t li = cur.line < S.m ? cur.line : S.m - 1;
+      const Vec<NV> pv = load_vec<NV>(S.p, li);
+      const float w = gl(S.inv_row)[li];
       float acc[NV];
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
@@ -327,12 +328,9 @@ __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* __restrict__
       // f^k with k = max_iter is final: its residual is all that was wanted
       if (*gl(&S.st->k) < prm->max_iter) {
         const bool owner = glane == 0 && cur.line < S.n;
-        Vec<NV> fv{};
-        float tl = 0.0f;
-        if (owner) {
-          fv = load_vec<NV>(S.f[parity], cur.line);
-          tl = prm->lambda * gl(S.inv_col)[cur.line];
-        }
+        const int64_t li = cur.line < S.n ? cur.line : S.n - 1;
+        Vec<NV> fv = load_vec<NV>(S.f[parity], li);
+        const float tl = prm->lambda * gl(S.inv_col)[li];
         float acc[NV];
 #pragma unroll
         for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
