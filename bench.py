@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
-    ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT",
+    ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT,CHUNKED",
                     help="fixed launch shape instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB, so that "
@@ -131,7 +131,7 @@ def main():
     scratch = [S.new_image() for S in systems]
     if args.shape:
         (opts.rows_per_wave, opts.cols_per_wave, opts.xcd_remap, opts.unroll,
-         opts.persistent) = map(int, args.shape.split(","))
+         opts.persistent, opts.chunked) = map(int, args.shape.split(","))
     else:
         sol.autotune(scratch)
     f12 = [S.new_image() for S in systems]
@@ -173,7 +173,7 @@ def main():
                    "slices": len(slices), "nnz": int(nnz_full), "nnz_half": int(nnz_half),
                    "iterations": iters, "rows_per_wave": opts.rows_per_wave,
                    "cols_per_wave": opts.cols_per_wave, "xcd_remap": opts.xcd_remap,
-                   "unroll": opts.unroll, "persistent": opts.persistent},
+                   "unroll": opts.unroll, "persistent": opts.persistent, "chunked": opts.chunked},
     }
     if args.no_extras:
         print(json.dumps(out), flush=True)
@@ -220,7 +220,7 @@ def main():
                       "fp_ms": ufp, "bp_ms": ubp, "bytes_per_iteration": ub,
                       "kernel_gbs_per_iteration": ub / ((ufp + ubp) * 1e-3) / 1e9,
                       "shape": [uopts.rows_per_wave, uopts.cols_per_wave, uopts.xcd_remap,
-                                uopts.unroll, uopts.persistent]}
+                                uopts.unroll, uopts.persistent, uopts.chunked]}
     out["split_vs_unsplit"] = ums / ms
     log(f"unsplit step {ums:.3f} ms; split/unsplit speedup {ums / ms:.2f}")
 

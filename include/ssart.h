@@ -151,7 +151,13 @@ typedef struct {
  * p (nvals*m): right-hand side.
  * inv_row (m), inv_col (n): FP32 reciprocals of the FP64 row and column sums
  *   of A (which equal those of A(2)), 0 where a sum is 0; SART normalises
- *   both halves with them. */
+ *   both halves with them.
+ * Stream layout: the solver reads col_idx/val and row_idx/val_t in aligned
+ * chunks of SS_CHUNK entries, so each of these four arrays must start on a
+ * 16-byte boundary and have room for ss_stream_len(nnz) entries (nnz rounded
+ * up to a multiple of SS_CHUNK); entries past nnz are read and ignored, never
+ * written.  The same holds for A's arrays when a system aliases them
+ * (ss_unsplit). */
 typedef struct {
   int64_t m, n, nnz;
   int32_t nvals;
@@ -166,6 +172,14 @@ typedef struct {
   float* inv_row;
   float* inv_col;
 } ss_system;
+
+/* Entries per aligned chunk of the solver's index and value streams. */
+#define SS_CHUNK 4
+
+/* Capacity, in entries, that the index and value arrays of a system with nnz
+ * stored entries must have: nnz rounded up to a multiple of SS_CHUNK (0 for
+ * nnz <= 0). */
+int64_t ss_stream_len(int64_t nnz);
 
 /* Bytes of workspace ss_fold_size and ss_fold need for an M x N matrix. */
 ss_status ss_fold_workspace_bytes(int64_t M, int64_t N, size_t* bytes);
@@ -222,6 +236,10 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *   zero_start   1: start from f^0 = 0 (the solver clears f itself);
  *                0: start from the image the caller passes
  *   unroll       entries each lane has in flight per pass: 4 or 8 (0 = 4)
+ *   chunked      stream form per kernel, bit 0 forward, bit 1 back
+ *                projection: 0 = entry-wise (lanes of a group hold adjacent
+ *                entries), 1 = aligned chunks of SS_CHUNK entries per lane
+ *                (fewer, wider loads; gathers spread over more cache lines)
  *   persistent   1: size the grid to the resident capacity and let each block
  *                loop over tiles (prefetching the next one); 0: one block
  *                per tile
@@ -239,6 +257,7 @@ typedef struct {
   int32_t zero_start;
   int32_t unroll;
   int32_t persistent;
+  int32_t chunked;
 } ss_sart_opts;
 
 /* Workspace bytes for solving `nsys` systems together with these options. */
@@ -271,7 +290,7 @@ ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys,
                                void* workspace, size_t workspace_bytes,
                                void* stream);
 
-/* Picks rows_per_wave, cols_per_wave, unroll, persistent and xcd_remap by
+/* Picks rows_per_wave, cols_per_wave, unroll, persistent, chunked and xcd_remap by
  * timing every candidate (ss_sart_time_kernels) and writes them into
  * *opts.  Results are cached per (nvals, wdtype, shape statistics).
  * The images f are used as scratch.  Synchronises. */

@@ -163,9 +163,60 @@ __device__ inline Vec<NV> load_vals(const void* base, int64_t k) {
   return r;
 }
 
+// Entries are streamed in aligned chunks of SS_CHUNK = 4 (one 16-byte load of
+// indices, one or two of values): a quarter of the load instructions that
+// entry-wise loads need, which is what bounds the solver kernels.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <int WT>
+__device__ inline float widen16(uint32_t bits) {
+  if constexpr (WT == SS_BF16) return __uint_as_float(bits << 16);
+  else return __half2float(__ushort_as_half(static_cast<unsigned short>(bits)));
+}
+
+// Indices of entries k0 .. k0+3 (k0 a multiple of 4).
+__device__ inline u32x4 load_idx_chunk(const int32_t* idx, int64_t k0) {
+  return gl(reinterpret_cast<const u32x4*>(idx))[k0 >> 2];
+}
+
+// Values of entries k0 .. k0+3 (k0 a multiple of 4) widened to FP32.
+template <int NV, int WT>
+__device__ inline void load_val_chunk(const void* base, int64_t k0, Vec<NV>* v) {
+  if constexpr (NV == 2 && WT == SS_F32) {  // 8 bytes per entry: two loads
+    const SS_GLOBAL u32x4* p = gl(reinterpret_cast<const u32x4*>(base)) + (k0 >> 1);
+    const u32x4 a = p[0], b = p[1];
+    v[0].v[0] = __uint_as_float(a.x);
+    v[0].v[1] = __uint_as_float(a.y);
+    v[1].v[0] = __uint_as_float(a.z);
+    v[1].v[1] = __uint_as_float(a.w);
+    v[2].v[0] = __uint_as_float(b.x);
+    v[2].v[1] = __uint_as_float(b.y);
+    v[3].v[0] = __uint_as_float(b.z);
+    v[3].v[1] = __uint_as_float(b.w);
+  } else if constexpr (NV == 2) {  // a 16-bit pair per entry
+    const u32x4 a = gl(reinterpret_cast<const u32x4*>(base))[k0 >> 2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[j].v[0] = widen16<WT>(a[j] & 0xffffu);
+      v[j].v[1] = widen16<WT>(a[j] >> 16);
+    }
+  } else if constexpr (WT == SS_F32) {
+    const u32x4 a = gl(reinterpret_cast<const u32x4*>(base))[k0 >> 2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j].v[0] = __uint_as_float(a[j]);
+  } else {  // one 16-bit value per entry: 8 bytes per chunk
+    const u32x2 a = gl(reinterpret_cast<const u32x2*>(base))[k0 >> 2];
+    v[0].v[0] = widen16<WT>(a.x & 0xffffu);
+    v[1].v[0] = widen16<WT>(a.x >> 16);
+    v[2].v[0] = widen16<WT>(a.y & 0xffffu);
+    v[3].v[0] = widen16<WT>(a.y >> 16);
+  }
+}
+
 }  // namespace ss
 
-#define SS_HIP_TRY(expr)                                                            \
+#define SS_HIP_TRY(expr)                                                          \
   do {                                                                              \
     hipError_t e_ = (expr);                                                         \
     if (e_ != hipSuccess)                                                           \

@@ -159,14 +159,15 @@ __device__ inline void store_flag(int32_t* p, int v) {
 // one box, same shapes: 1.58 -> 1.40 ms forward, 1.78 -> 1.41 ms back).
 __device__ inline int32_t ld_stream(const int32_t* p) { return *gl(p); }
 
-// Sum over one line (row or column) of A(s)^T-free form: acc += sum_k val[k] *
-// x[idx[k]] for k in [lo, hi), by the L lanes of a group, U entries per lane
-// in flight per pass.  Slots past the end of the line re-read the line's last
-// entry (same cache line, no extra DRAM traffic) and are masked out of the
-// sum: with no branch around them, all 2U stream loads of a pass are issued
-// before the first wait, then all U gathers.
+// Entry-wise form of line_dot: lane g of a group takes entries lo + g,
+// lo + g + L, ...: U entries per lane in flight per pass.  Adjacent lanes
+// hold adjacent entries, so where a line's entries touch nearby positions of
+// x (a ray crossing consecutive voxels) one gather instruction touches few
+// cache lines.  Slots past the end of the line re-read its last entry (same
+// cache line) and are masked out of the sum: with no branch around them, all
+// 2U stream loads of a pass are issued before the first wait.
 template <int NV, int WT, int L, int U>
-__device__ inline void line_dot(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
+__device__ inline void line_dot_e(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
                                 int glane, float* acc) {
   for (int64_t base = lo + glane; base < hi; base += U * L) {
     int32_t c[U];
@@ -189,6 +190,56 @@ __device__ inline void line_dot(const int32_t* idx, const void* val, const float
       }
     }
   }
+}
+
+// Sum over one line (row or column): acc += sum_k val[k] * x[idx[k]] for k in
+// [lo, hi), by the L lanes of a group.  Chunked form: lanes take aligned
+// chunks of SS_CHUNK entries (U chunks per lane per pass), a quarter of the
+// stream load instructions of the entry-wise form, at the price of gathers
+// that each touch more cache lines; entries of a chunk outside
+// [lo, hi) are masked out.  Slots past the line's last chunk re-read that
+// chunk, so every pass issues all its loads without a branch and never
+// leaves the line's chunks: the arrays' capacity of ss_stream_len(nnz)
+// entries covers the last chunk of the last line.
+template <int NV, int WT, int L, int U>
+__device__ inline void line_dot_c(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
+                                int glane, float* acc) {
+  constexpr int64_t C = SS_CHUNK;
+  const int64_t first = lo & ~(C - 1);
+  const int64_t last = (hi - 1) & ~(C - 1);
+  for (int64_t base = first + C * glane; base < hi; base += C * U * L) {
+    u32x4 c[U];
+    Vec<NV> v[U][SS_CHUNK];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k0 = base + C * u * L;
+      const int64_t kk = k0 <= last ? k0 : last;
+      c[u] = load_idx_chunk(idx, kk);
+      load_val_chunk<NV, WT>(val, kk, v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int j = 0; j < SS_CHUNK; ++j) {
+        const int64_t k = base + C * u * L + j;
+        const bool in = k >= lo && k < hi;
+        const Vec<NV> xv = load_vec<NV>(x, in ? static_cast<int32_t>(c[u][j]) : 0);
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+          const float sum = fmaf(v[u][j].v[h], xv.v[h], acc[h]);
+          acc[h] = in ? sum : acc[h];
+        }
+      }
+    }
+  }
+}
+
+// U entries per lane in flight per pass, entry-wise or in chunks (CH).
+template <int NV, int WT, int L, int U, bool CH>
+__device__ inline void line_dot(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
+                                int glane, float* acc) {
+  if constexpr (CH) line_dot_c<NV, WT, L, U / SS_CHUNK>(idx, val, x, lo, hi, glane, acc);
+  else line_dot_e<NV, WT, L, U>(idx, val, x, lo, hi, glane, acc);
 }
 
 // What a tile needs before its main loads: the system, the tile's index in
@@ -223,7 +274,7 @@ __device__ inline TileCtx tile_ctx(const SysDesc* table, int nsys, uint32_t t, u
 // RPW*kWPB rows.  Per tile: p and 1/W are requested first, then the row
 // sums, then the next tile's context (so its loads overlap this tile's
 // reduction), then the residual, z and the block's FP64 partial.
-template <int NV, int WT, int RPW, int U>
+template <int NV, int WT, int RPW, int U, bool CH>
 __global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* __restrict__ table, int nsys,
                                                       uint32_t ntiles, int xcd, int parity) {
   constexpr int L = kWave / RPW;
@@ -247,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* __restrict_
       float acc[NV];
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-      line_dot<NV, WT, L, U>(S.col_idx, S.val, S.f[parity], cur.lo, cur.hi, glane, acc);
+      line_dot<NV, WT, L, U, CH>(S.col_idx, S.val, S.f[parity], cur.lo, cur.hi, glane, acc);
       if (more) nxt = tile_ctx<false, RPW>(table, nsys, tn, ntiles, xcd);
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
@@ -304,7 +355,7 @@ __device__ void finalize_residual(const Params* prm, const SysDesc& S, double* r
 // Back projection and update, with the residual finalisation in the first
 // tile of each system.  Grid-stride over tiles of CPW*kWPB columns, with the
 // same ordering as the forward kernel.
-template <int NV, int WT, int CPW, int U>
+template <int NV, int WT, int CPW, int U, bool CH>
 __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* __restrict__ prm,
                                                       const SysDesc* __restrict__ table, int nsys,
                                                       uint32_t ntiles, int xcd, int parity) {
@@ -334,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* __restrict__
         float acc[NV];
 #pragma unroll
         for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-        line_dot<NV, WT, L, U>(S.row_idx, S.val_t, S.z, cur.lo, cur.hi, glane, acc);
+        line_dot<NV, WT, L, U, CH>(S.row_idx, S.val_t, S.z, cur.lo, cur.hi, glane, acc);
         if (more) nxt = tile_ctx<true, CPW>(table, nsys, tn, ntiles, xcd);
         prefetched = true;
 #pragma unroll
@@ -401,7 +452,7 @@ Layout make_layout(const ss_system* sys, int nsys) {
 }
 
 struct Cfg {
-  int nv, wt, rpw, cpw, xcd, u, pers;
+  int nv, wt, rpw, cpw, xcd, u, pers, ch;
 };
 
 ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const char* fn) {
@@ -417,6 +468,9 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
     if (!S.row_ptr || !S.col_ptr || !S.p || !S.inv_row || !S.inv_col ||
         (S.nnz > 0 && (!S.col_idx || !S.val || !S.row_idx || !S.val_t)))
       return fail(SS_E_ARG, "%s: system %d has a NULL array", fn, s);
+    auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (S.nnz > 0 && !(aligned(S.col_idx) && aligned(S.val) && aligned(S.row_idx) && aligned(S.val_t)))
+      return fail(SS_E_ARG, "%s: system %d: index and value arrays must be 16-byte aligned", fn, s);
     if (S.m > INT32_MAX || S.n > INT32_MAX) return fail(SS_E_ARG, "%s: system %d too large", fn, s);
   }
   if (!(o->lambda > 0.0f && o->lambda < 2.0f)) return fail(SS_E_ARG, "%s: lambda must be in (0, 2)", fn);
@@ -426,6 +480,7 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
   if (!ok_pw(o->rows_per_wave, 8)) return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8", fn);
   if (!ok_pw(o->cols_per_wave, 16)) return fail(SS_E_ARG, "%s: cols_per_wave must be 0,1,2,4,8,16", fn);
   if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
+  if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
   return SS_OK;
 }
 
@@ -449,6 +504,7 @@ Cfg choose_cfg(const ss_system* sys, int nsys, const ss_sart_opts* o) {
   c.cpw = o->cols_per_wave ? o->cols_per_wave : pick_per_wave(nnz / n, 16);
   c.xcd = o->xcd_remap ? 1 : 0;
   c.u = o->unroll ? o->unroll : 4;
+  c.ch = o->chunked;
   c.pers = o->persistent ? 1 : 0;
   return c;
 }
@@ -546,26 +602,26 @@ void go(K kern, uint32_t ntiles, int persistent, hipStream_t st, Stamp e, Args..
   hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, e.start, e.stop, 0, args...);
 }
 
-template <int NV, int WT, int U>
+template <int NV, int WT, int U, bool CH>
 void launch_fp_u(int rpw, int pers, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st,
                  Stamp e) {
   switch (rpw) {
-    case 1: go(k_sart_fp<NV, WT, 1, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
-    case 2: go(k_sart_fp<NV, WT, 2, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
-    case 4: go(k_sart_fp<NV, WT, 4, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
-    default: go(k_sart_fp<NV, WT, 8, U>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_fp<NV, WT, 1, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_fp<NV, WT, 2, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_fp<NV, WT, 4, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_fp<NV, WT, 8, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
   }
 }
 
-template <int NV, int WT, int U>
+template <int NV, int WT, int U, bool CH>
 void launch_bp_u(int cpw, int pers, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
                  hipStream_t st, Stamp e) {
   switch (cpw) {
-    case 1: go(k_sart_bp<NV, WT, 1, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 2: go(k_sart_bp<NV, WT, 2, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 4: go(k_sart_bp<NV, WT, 4, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 8: go(k_sart_bp<NV, WT, 8, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    default: go(k_sart_bp<NV, WT, 16, U>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_bp<NV, WT, 1, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_bp<NV, WT, 2, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_bp<NV, WT, 4, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 8: go(k_sart_bp<NV, WT, 8, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_bp<NV, WT, 16, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
   }
 }
 
@@ -574,11 +630,16 @@ void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, cons
                    hipStream_t st, Stamp e = {}) {
   const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
-#define SS_DISPATCH(NV, WT, U)                                                              \
-  if (c.nv == NV && c.wt == WT && c.u == U) {                                               \
-    if (BP) launch_bp_u<NV, WT, U>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e); \
-    else launch_fp_u<NV, WT, U>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e);         \
-    return;                                                                                 \
+#define SS_DISPATCH(NV, WT, U)                                                                      \
+  if (c.nv == NV && c.wt == WT && c.u == U) {                                                       \
+    if (BP) {                                                                                       \
+      if (c.ch & 2) launch_bp_u<NV, WT, U, true>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e); \
+      else launch_bp_u<NV, WT, U, false>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e);        \
+    } else {                                                                                        \
+      if (c.ch & 1) launch_fp_u<NV, WT, U, true>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e);      \
+      else launch_fp_u<NV, WT, U, false>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e);             \
+    }                                                                                               \
+    return;                                                                                         \
   }
   SS_DISPATCH(2, SS_F32, 4)
   SS_DISPATCH(2, SS_BF16, 4)
@@ -617,10 +678,11 @@ struct GraphKey {
   const void* ws;
   int nsys;
   uint32_t fpb, bpb;
-  int nv, wt, rpw, cpw, xcd, u, pers, count;
+  int nv, wt, rpw, cpw, xcd, u, pers, ch, count;
   bool operator<(const GraphKey& o) const {
-    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, pers, count) <
-           std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.u, o.pers, o.count);
+    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, pers, ch, count) <
+           std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.u, o.pers, o.ch,
+                    o.count);
   }
 };
 
@@ -717,7 +779,7 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   if (opts->use_graph) {
     int dev = 0;
     SS_HIP_TRY(hipGetDevice(&dev));
-    const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, c.pers,
+    const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, c.pers, c.ch,
                        chunk};
     if (ss_status s = get_graph(key, c, ws, L, g, &exec)) return s;
   }
@@ -801,7 +863,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::tuple<int, int, int, int, int>> g_tune;
+std::map<TuneKey, std::tuple<int, int, int, int, int, int>> g_tune;
 }  // namespace
 
 extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f, ss_sart_opts* opts,
@@ -820,8 +882,8 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      std::tie(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll, opts->persistent) =
-          it->second;
+      std::tie(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll, opts->persistent,
+               opts->chunked) = it->second;
       return SS_OK;
     }
   }
@@ -832,27 +894,32 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
   const Cfg dflt = choose_cfg(sys, nsys, opts);
   struct Best {
     double t = 1e30;
-    int pw = 1, u = 4, xcd = 0, pers = 0;
+    int pw = 1, u = 4, xcd = 0, pers = 0, ch = 0;
   } bf, bb, df, db;
   for (int pers = 0; pers <= 1; ++pers) {
     for (int xcd = 0; xcd <= 1; ++xcd) {
       for (int u = 4; u <= 8; u += 4) {
-        for (int pw = 1; pw <= 16; pw <<= 1) {
-          ss_sart_opts o = *opts;
-          o.persistent = pers;
-          o.xcd_remap = xcd;
-          o.unroll = u;
-          o.rows_per_wave = pw <= 8 ? pw : 8;
-          o.cols_per_wave = pw;
-          double tf = 0, tb = 0;
-          if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes,
-                                                 stream))
-            return s;
-          const bool base = xcd == 0 && u == 4 && pers == 0;
-          if (base && o.rows_per_wave == dflt.rpw && tf < df.t) df = {tf, dflt.rpw, 4, 0, 0};
-          if (base && o.cols_per_wave == dflt.cpw && tb < db.t) db = {tb, dflt.cpw, 4, 0, 0};
-          if (pw <= 8 && tf < bf.t) bf = {tf, pw, u, xcd, pers};
-          if (tb < bb.t) bb = {tb, pw, u, xcd, pers};
+        for (int ch = 0; ch <= 3; ch += 3) {
+          for (int pw = 1; pw <= 16; pw <<= 1) {
+            ss_sart_opts o = *opts;
+            o.persistent = pers;
+            o.xcd_remap = xcd;
+            o.unroll = u;
+            o.chunked = ch;
+            o.rows_per_wave = pw <= 8 ? pw : 8;
+            o.cols_per_wave = pw;
+            double tf = 0, tb = 0;
+            if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes,
+                                                   stream))
+              return s;
+            const bool base = xcd == dflt.xcd && u == dflt.u && pers == dflt.pers;
+            if (base && (ch & 1) == (dflt.ch & 1) && o.rows_per_wave == dflt.rpw && tf < df.t)
+              df = {tf, dflt.rpw, u, xcd, pers, ch};
+            if (base && (ch & 2) == (dflt.ch & 2) && o.cols_per_wave == dflt.cpw && tb < db.t)
+              db = {tb, dflt.cpw, u, xcd, pers, ch};
+            if (pw <= 8 && tf < bf.t) bf = {tf, pw, u, xcd, pers, ch};
+            if (tb < bb.t) bb = {tb, pw, u, xcd, pers, ch};
+          }
         }
       }
     }
@@ -860,15 +927,16 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
   if (df.t <= 1.03 * bf.t) bf = df;
   if (db.t <= 1.03 * bb.t) bb = db;
   // one remap flag, unroll depth and grid mode serve both kernels: take
-  // those of the slower kernel
+  // those of the slower kernel; each kernel keeps its own stream form
   const Best& slow = bf.t >= bb.t ? bf : bb;
   opts->rows_per_wave = bf.pw;
   opts->cols_per_wave = bb.pw;
   opts->xcd_remap = slow.xcd;
   opts->unroll = slow.u;
   opts->persistent = slow.pers;
+  opts->chunked = (bf.ch & 1) | (bb.ch & 2);
   std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tune[key] = std::make_tuple(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll,
-                                opts->persistent);
+                                opts->persistent, opts->chunked);
   return SS_OK;
 }

@@ -62,7 +62,7 @@ class SartOptsC(C.Structure):
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("rows_per_wave", C.c_int32), ("cols_per_wave", C.c_int32),
                 ("xcd_remap", C.c_int32), ("zero_start", C.c_int32),
-                ("unroll", C.c_int32), ("persistent", C.c_int32)]
+                ("unroll", C.c_int32), ("persistent", C.c_int32), ("chunked", C.c_int32)]
 
 
 _SIGNATURES = {
@@ -72,6 +72,7 @@ _SIGNATURES = {
                                     C.POINTER(MatrixC)]),
     "ss_matrix_free": (None, [C.POINTER(MatrixC)]),
     "ss_snake_order": (C.c_int32, [C.POINTER(Grid), C.POINTER(C.c_int64)]),
+    "ss_stream_len": (C.c_int64, [C.c_int64]),
     "ss_fold_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "ss_fold_size": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_int64), C.c_void_p]),
@@ -228,9 +229,29 @@ def to_device(hm, device="cuda") -> DeviceMatrix:
 
     def t(a, dt):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+
+    def stream(a, dt):   # room for the solver's chunked reads (ss_stream_len)
+        a = np.ascontiguousarray(a, dtype=dt)
+        buf = stream_tensor(a.size, 1, {np.int32: torch.int32, np.float32: torch.float32}[dt], device)
+        buf.copy_(torch.from_numpy(a))
+        return buf
     return DeviceMatrix(int(hm.M), int(hm.N), int(hm.nnz), t(hm.row_ptr, np.int64),
-                        t(hm.col_idx, np.int32), t(hm.val, np.float32), t(hm.col_ptr, np.int64),
-                        t(hm.row_idx, np.int32), t(hm.val_t, np.float32))
+                        stream(hm.col_idx, np.int32), stream(hm.val, np.float32), t(hm.col_ptr, np.int64),
+                        stream(hm.row_idx, np.int32), stream(hm.val_t, np.float32))
+
+
+def stream_len(nnz: int) -> int:
+    """ss_stream_len: entries the index/value arrays of a system must hold."""
+    return int(lib().ss_stream_len(nnz))
+
+
+def stream_tensor(nnz: int, per_entry: int, dtype, device):
+    """A view of `nnz * per_entry` elements on a buffer with room for
+    ss_stream_len(nnz) entries (torch allocations are 512-byte aligned)."""
+    import torch
+    cap = stream_len(nnz) if nnz > 0 else 0
+    buf = torch.empty(max(cap, 1) * per_entry, dtype=dtype, device=device)
+    return buf[: nnz * per_entry]
 
 
 @dataclasses.dataclass
@@ -273,11 +294,10 @@ def fold_size(A: DeviceMatrix, p=None) -> int:
     return int(out.value)
 
 
-def _value_tensor(count: int, wdtype: str, device):
+def _value_tensor(nnz: int, nvals: int, wdtype: str, device):
     import torch
-    if wdtype == "f32":
-        return torch.empty(count, dtype=torch.float32, device=device)
-    return torch.empty(count, dtype=torch.int16, device=device)  # raw 16-bit storage
+    dt = torch.float32 if wdtype == "f32" else torch.int16   # int16: raw 16-bit storage
+    return stream_tensor(nnz, nvals, dt, device)
 
 
 def fold(A: DeviceMatrix, p, wdtype: str = "f32", nnz_half: int | None = None) -> System:
@@ -289,11 +309,11 @@ def fold(A: DeviceMatrix, p, wdtype: str = "f32", nnz_half: int | None = None) -
     m, n = A.M // 2, A.N // 2
     S = System(m, n, nnz_half, 2, wdtype,
                torch.empty(m + 1, dtype=torch.int64, device=dev),
-               torch.empty(nnz_half, dtype=torch.int32, device=dev),
-               _value_tensor(2 * nnz_half, wdtype, dev),
+               stream_tensor(nnz_half, 1, torch.int32, dev),
+               _value_tensor(nnz_half, 2, wdtype, dev),
                torch.empty(n + 1, dtype=torch.int64, device=dev),
-               torch.empty(nnz_half, dtype=torch.int32, device=dev),
-               _value_tensor(2 * nnz_half, wdtype, dev),
+               stream_tensor(nnz_half, 1, torch.int32, dev),
+               _value_tensor(nnz_half, 2, wdtype, dev),
                torch.empty(2 * m, dtype=torch.float32, device=dev),
                torch.empty(m, dtype=torch.float32, device=dev),
                torch.empty(n, dtype=torch.float32, device=dev))
@@ -330,7 +350,7 @@ def unsplit(A: DeviceMatrix, p, wdtype: str = "f32") -> System:
     if wdtype == "f32":
         val, val_t = A.val, A.val_t
     else:
-        val, val_t = _value_tensor(A.nnz, wdtype, dev), _value_tensor(A.nnz, wdtype, dev)
+        val, val_t = _value_tensor(A.nnz, 1, wdtype, dev), _value_tensor(A.nnz, 1, wdtype, dev)
     S = System(A.M, A.N, A.nnz, 1, wdtype, A.row_ptr, A.col_idx, val, A.col_ptr, A.row_idx,
                val_t, torch.empty(A.M, dtype=torch.float32, device=dev),
                torch.empty(A.M, dtype=torch.float32, device=dev),
@@ -353,11 +373,12 @@ class SartOptions:
     zero_start: bool = False
     unroll: int = 0
     persistent: int = 0
+    chunked: int = 0
 
     def c(self) -> SartOptsC:
         return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
                          int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
-                         self.xcd_remap, int(self.zero_start), self.unroll, self.persistent)
+                         self.xcd_remap, int(self.zero_start), self.unroll, self.persistent, self.chunked)
 
 
 class Solver:
@@ -414,6 +435,7 @@ class Solver:
         self.opts.xcd_remap = oc.xcd_remap
         self.opts.unroll = oc.unroll
         self.opts.persistent = oc.persistent
+        self.opts.chunked = oc.chunked
         return self.opts
 
 

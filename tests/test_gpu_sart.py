@@ -145,14 +145,57 @@ def test_early_exit_at_tolerance(kstar):
     assert status == 1 and it == [12]
 
 
-@pytest.mark.parametrize("rpw,cpw,xcd", [(1, 1, 0), (2, 4, 1), (4, 8, 0), (8, 16, 1)])
-def test_launch_shapes_agree_with_oracle(rpw, cpw, xcd):
-    banner(f"launch shape rpw={rpw} cpw={cpw} xcd={xcd}")
+SHAPES = [(1, 1, 0, 4, 0, 0), (2, 4, 1, 8, 0, 3), (4, 8, 0, 4, 1, 1), (8, 16, 1, 8, 1, 2),
+          (1, 2, 1, 8, 0, 3), (8, 1, 0, 4, 1, 3)]
+
+
+@pytest.mark.parametrize("rpw,cpw,xcd,u,pers,ch", SHAPES)
+def test_launch_shapes_agree_with_oracle(rpw, cpw, xcd, u, pers, ch):
+    """Every launch shape, unroll depth, grid mode and stream form (entry-wise
+    or chunked, per kernel) on cfg1 and on ragged random systems (lines that
+    start mid-chunk, empty lines, a 2 x 2 system)."""
+    banner(f"launch shape rpw={rpw} cpw={cpw} xcd={xcd} u={u} pers={pers} chunked={ch}")
+    shape = dict(rows_per_wave=rpw, cols_per_wave=cpw, xcd_remap=xcd, unroll=u, persistent=pers, chunked=ch)
     pr = problem(1)
     _, _, S = _split_system(pr)
-    f, h, _, _ = _solve([S], 20, rows_per_wave=rpw, cols_per_wave=cpw, xcd_remap=xcd)
+    f, h, _, _ = _solve([S], 20, **shape)
     f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20)
     assert rel_l2(to_np(native.recombine(f[0])), f_ref) <= 1e-5
+    assert_res_close(to_np(h[0]), res_ref)
+    for seed, M, N in [(11, 1002, 514), (13, 2, 2)]:
+        pr = random_problem(seed, M, N, 0.05 if M > 100 else 0.3)
+        _, _, S = _split_system(pr)
+        f, h, _, _ = _solve([S], 20, **shape)
+        f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20)
+        if np.linalg.norm(f_ref) > 0:
+            assert rel_l2(to_np(native.recombine(f[0])), f_ref) <= 1e-5
+        assert_res_close(to_np(h[0]), res_ref)
+
+
+def test_stream_forms_agree():
+    """Entry-wise and chunked streams visit the same entries in a different
+    per-lane order: the images agree to FP32 rounding."""
+    banner("stream forms")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    f0, _, _, _ = _solve([S], 20, chunked=0)
+    f3, _, _, _ = _solve([S], 20, chunked=3)
+    a, b = to_np(f0[0]), to_np(f3[0])
+    assert rel_l2(b, a) <= 1e-6
+
+
+def test_misaligned_stream_arrays_are_rejected():
+    import torch
+    banner("alignment check")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    buf = torch.empty(S.col_idx.numel() + 8, dtype=torch.int32, device="cuda")
+    buf[1:1 + S.col_idx.numel()].copy_(S.col_idx)
+    import dataclasses
+    bad = dataclasses.replace(S, col_idx=buf[1:1 + S.col_idx.numel()])
+    with pytest.raises(native.SSError) as e:
+        _solve([bad], 2)
+    assert e.value.code == -1 and "aligned" in str(e.value)
 
 
 def test_autotune_and_kernel_timing_run():
