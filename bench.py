@@ -139,12 +139,20 @@ def main():
     log(f"slices={len(slices)} nnz={nnz_full} nnz_half={nnz_half} shape rpw={opts.rows_per_wave} "
         f"cpw={opts.cols_per_wave} xcd={opts.xcd_remap}")
 
+    if len(slices) > 1:   # all slices fold in one launch per phase
+        fold_all = native.FoldBatch([x.A for x in slices], [x.p for x in slices], systems)
+        recombine_all = native.RecombineBatch(f12, f_out)
+    else:
+        def fold_all():
+            native.fold_into(slices[0].A, slices[0].p, systems[0])
+
+        def recombine_all():
+            native.recombine(f12[0], f_out[0])
+
     def split_step():
-        for x in slices:
-            native.fold_into(x.A, x.p, x.S)
+        fold_all()
         sol.solve(f12, want_iters=False)
-        for f, o in zip(f12, f_out):
-            native.recombine(f, o)
+        recombine_all()
 
     def timed(step, k, w):
         for _ in range(w):

@@ -204,6 +204,19 @@ ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* workspace,
 ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out,
                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* ss_fold for `count` matrices at once (Section 2 applied to each): every
+ * phase (union sizes, offsets, fill; rows, then columns) is one launch over
+ * the lines of all matrices.  A[k] (host array of descriptors of device
+ * matrices) must have passed ss_fold_size; p[k] (host array of device
+ * pointers); out[k] as for ss_fold, all with the same wdtype.  The results
+ * equal `count` calls of ss_fold bit for bit.  `workspace`: device scratch
+ * of ss_fold_batch_workspace_bytes(A, count) bytes.  Asynchronous. */
+ss_status ss_fold_batch_workspace_bytes(const ss_matrix_dev* A, int32_t count,
+                                        size_t* bytes);
+ss_status ss_fold_batch(const ss_matrix_dev* A, const float* const* p,
+                        ss_system* out, int32_t count, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
 /* The unsplit baseline: fills a single system (nvals = 1, m = M, n = N) for
  * A itself.  The caller sets out->m, n, nnz, nvals = 1, wdtype and every
  * pointer; row_ptr/col_idx/col_ptr/row_idx may alias A's arrays, and val/
@@ -306,6 +319,11 @@ ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f,
  * pairs): f[j] = (f2[j] + f1[j]) / 2, f[N-1-j] = (f2[j] - f1[j]) / 2, FP32.
  * Asynchronous. */
 ss_status ss_recombine(const float* f12, int64_t n, float* f, void* stream);
+
+/* ss_recombine for `count` images: f12[k], f[k] device pointers (host
+ * arrays), n[k] pairs each (host array).  Asynchronous. */
+ss_status ss_recombine_batch(const float* const* f12, const int64_t* n,
+                             float* const* f, int32_t count, void* stream);
 
 /* Inverse of eq. (5) (the transform in the proof of Theorem 1): f12 from f,
  * f1[j] = f[j] - f[N-1-j], f2[j] = f[j] + f[N-1-j], FP32.  Asynchronous. */

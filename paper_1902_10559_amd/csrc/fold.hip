@@ -17,6 +17,7 @@
 // the common ones counted twice).  The union size is |X| + |Y| - #common.
 
 #include <algorithm>
+#include <vector>
 
 #include "device.h"
 #include "internal.h"
@@ -73,13 +74,72 @@ __device__ inline int64_t lower_bound_idx(const int32_t* idx, int64_t len, int32
   return lo;
 }
 
+// The same list held in shared memory (address space 3, so that searches
+// compile to LDS reads).
+#define SS_LDS __attribute__((address_space(3)))
+template <bool FLIP>
+struct LSeq {
+  const SS_LDS int32_t* idx;
+  const SS_LDS float* val;
+  int64_t len;
+  int32_t base;
+  __device__ int32_t key(int64_t l) const {
+    if constexpr (FLIP) return base - idx[len - 1 - l];
+    else return idx[l];
+  }
+  __device__ float value(int64_t l) const {
+    if constexpr (FLIP) return val[len - 1 - l];
+    else return val[l];
+  }
+  __device__ int64_t lower_bound(int32_t k) const {
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (key(mid) < k) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  }
+};
+
+// Lines of up to kStage entries per list are staged in shared memory by one
+// coalesced pass, so that the per-element binary searches of the merge hit
+// LDS instead of making dependent global loads; longer lines are merged from
+// global memory.
+constexpr int kStage = 512;
+
+// Copies a sorted list of len (<= capacity) entries into shared memory and
+// returns how many of its indices are below `limit` (a prefix).
+__device__ inline int64_t stage_list(const int32_t* gi, const float* gv, int64_t len, SS_LDS int32_t* si,
+                                     SS_LDS float* sv, int32_t limit) {
+  int64_t below = 0;
+  for (int64_t b = 0; b < len; b += kWave) {
+    const int64_t k = b + lane_id();
+    int32_t c = INT32_MAX;
+    if (k < len) {
+      c = gi[k];
+      si[k] = c;
+      sv[k] = gv[k];
+    }
+    below += __popcll(__ballot(c < limit));
+  }
+  return below;
+}
+
+// Makes one wavefront's shared-memory writes visible to all its lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Merges X and Y as described at the top of the file.  FILL writes every
 // union entry at out_base + position: its index and the pair (a - b, a + b)
 // in storage type WT.  Returns the union size (in every lane) and adds each
 // entry's FP64 a + b to the lane's `sum`.
-template <bool FILL, int WT, bool FLIPY>
-__device__ int64_t wave_merge(const Seq<false>& X, const Seq<FLIPY>& Y,
-                              int64_t out_base, int32_t* out_idx, void* out_val,
+template <bool FILL, int WT, class SX, class SY>
+__device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_t* out_idx, void* out_val,
                               double& sum) {
   const int lane = lane_id();
   int64_t common = 0;
@@ -165,6 +225,55 @@ __device__ inline ColLists col_lists(const ss_matrix_dev& A, int64_t j) {
   return L;
 }
 
+// Per-wavefront staging buffers: two lists of kStage entries (the rows i and
+// M-1-i), or one column of up to 2 kStage entries.
+struct StageBuf {
+  SS_LDS int32_t* idx;
+  SS_LDS float* val;
+};
+
+// Merges output line t (a row, or a column when COLS) into the union: its
+// size, and with FILL the entries written at out_base.
+template <bool COLS, bool FILL, int WT>
+__device__ int64_t fold_line(const ss_matrix_dev& A, int64_t t, int64_t out_base, int32_t* out_idx,
+                             void* out_val, double& sum, StageBuf sb) {
+  if constexpr (COLS) {
+    const int64_t cs = A.col_ptr[t], ce = A.col_ptr[t + 1];
+    const int64_t len = ce - cs;
+    if (len <= 2 * kStage) {
+      const int64_t split = stage_list(A.row_idx + cs, A.val_t + cs, len, sb.idx, sb.val,
+                                       static_cast<int32_t>(A.M / 2));
+      wave_lds_sync();
+      const LSeq<false> X{sb.idx, sb.val, split, 0};
+      const LSeq<true> Y{sb.idx + split, sb.val + split, len - split, static_cast<int32_t>(A.M - 1)};
+      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum);
+    }
+    const ColLists L = col_lists(A, t);
+    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum);
+  } else {
+    const int64_t rs = A.row_ptr[t], re = A.row_ptr[t + 1];
+    const int64_t t2 = A.M - 1 - t;
+    const int64_t ys = A.row_ptr[t2], ye = A.row_ptr[t2 + 1];
+    if (re - rs <= kStage && ye - ys <= kStage) {
+      const int32_t n = static_cast<int32_t>(A.N / 2);
+      const int64_t xl = stage_list(A.col_idx + rs, A.val + rs, re - rs, sb.idx, sb.val, n);
+      const int64_t yl = stage_list(A.col_idx + ys, A.val + ys, ye - ys, sb.idx + kStage, sb.val + kStage, n);
+      wave_lds_sync();
+      const LSeq<false> X{sb.idx, sb.val, xl, 0};
+      const LSeq<false> Y{sb.idx + kStage, sb.val + kStage, yl, 0};
+      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum);
+    }
+    const RowLists L = row_lists(A, t);
+    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum);
+  }
+}
+
+// This wavefront's staging buffers in the block's shared memory.
+#define SS_STAGE_BUF(name)                                                        \
+  __shared__ int32_t name##_idx[kFoldWaves][2 * kStage];                          \
+  __shared__ float name##_val[kFoldWaves][2 * kStage];                            \
+  const StageBuf name{(SS_LDS int32_t*)(&name##_idx[wave_id()][0]), (SS_LDS float*)(&name##_val[wave_id()][0])}
+
 __device__ inline unsigned long long mix64(unsigned long long z) {
   z += 0x9e3779b97f4a7c15ull;
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -197,6 +306,7 @@ __global__ void k_zero_check(FoldCheck* c) {
 template <bool COLS>
 __global__ __launch_bounds__(kWave* kFoldWaves) void k_check_pairs(ss_matrix_dev A, const float* p,
                                                                    FoldCheck* chk) {
+  SS_STAGE_BUF(sb);
   const int64_t lines = COLS ? A.N : A.M;
   const int64_t other = COLS ? A.M : A.N;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
@@ -244,13 +354,7 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_check_pairs(ss_matrix_dev
   int64_t cnt = 0;
   if (sane) {
     double unused = 0.0;
-    if constexpr (COLS) {
-      const ColLists L = col_lists(A, t);
-      cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
-    } else {
-      const RowLists L = row_lists(A, t);
-      cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
-    }
+    cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb);
   }
   h = wave_sum_u64(h);
   unsigned f = flags;
@@ -263,21 +367,60 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_check_pairs(ss_matrix_dev
   }
 }
 
+// One matrix of a fold and where its lines and scan tiles sit in the grids
+// of the launches (a batch of matrices folds in one launch per phase).
+struct FoldJob {
+  ss_matrix_dev A;
+  const float* p;
+  ss_system out;
+  int64_t rblk0, cblk0;    // first block of its rows / columns (kFoldWaves lines per block)
+  int64_t rtile0, ctile0;  // first scan tile of its row / column offsets
+};
+
+// B = false: the job travels in the kernel arguments; B = true: a device
+// table of `count` jobs ordered by their first blocks.
+struct JobArg {
+  const FoldJob* table;
+  int32_t count;
+  FoldJob one;
+};
+
+// The job owning grid block b of the row (COLS false) or column lines, or of
+// the scan tiles (TILES), and b's index within that job.
+template <bool B, bool COLS, bool TILES>
+__device__ inline const FoldJob& find_job(const JobArg& J, int64_t b, int64_t* local) {
+  if constexpr (!B) {
+    *local = b;
+    return J.one;
+  } else {
+    auto first = [](const FoldJob& q) {
+      return TILES ? (COLS ? q.ctile0 : q.rtile0) : (COLS ? q.cblk0 : q.rblk0);
+    };
+    int lo = 0, hi = J.count - 1;
+    while (lo < hi) {
+      const int mid = __builtin_amdgcn_readfirstlane((lo + hi + 1) >> 1);
+      if (first(J.table[mid]) <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    *local = b - first(J.table[lo]);
+    return J.table[lo];
+  }
+}
+
 // Union size of every output line into ptr[t + 1]; ptr[0] = 0.
-template <bool COLS>
-__global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(ss_matrix_dev A, int64_t* ptr) {
+template <bool COLS, bool B>
+__global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(JobArg J) {
+  SS_STAGE_BUF(sb);
+  int64_t lb;
+  const FoldJob& jb = find_job<B, COLS, false>(J, blockIdx.x, &lb);
+  const ss_matrix_dev& A = jb.A;
   const int64_t lines = COLS ? A.N / 2 : A.M / 2;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
+  const int64_t t = lb * kFoldWaves + wave_id();
   if (t >= lines) return;
   double unused = 0.0;
-  int64_t cnt;
-  if constexpr (COLS) {
-    const ColLists L = col_lists(A, t);
-    cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
-  } else {
-    const RowLists L = row_lists(A, t);
-    cnt = wave_merge<false, SS_F32>(L.X, L.Y, 0, nullptr, nullptr, unused);
-  }
+  const int64_t cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb);
+  int64_t* ptr = COLS ? jb.out.col_ptr : jb.out.row_ptr;
   if (lane_id() == 0) {
     ptr[t + 1] = cnt;
     if (t == 0) ptr[0] = 0;
@@ -293,8 +436,21 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 16;
 constexpr int kScanTile = kScanThreads * kScanPer;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int64_t* ptr, int64_t len, int64_t* tile_sum) {
-  const int64_t base = 1 + static_cast<int64_t>(blockIdx.x) * kScanTile;
+// Tiles of a job's offsets array: ptr[1..len], len = m (rows) or n (columns).
+template <bool COLS>
+__device__ inline void job_offsets(const FoldJob& jb, int64_t** ptr, int64_t* len) {
+  *ptr = COLS ? jb.out.col_ptr : jb.out.row_ptr;
+  *len = COLS ? jb.out.n : jb.out.m;
+}
+
+template <bool COLS, bool B>
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(JobArg J, int64_t* tile_sum) {
+  int64_t lt;
+  const FoldJob& jb = find_job<B, COLS, true>(J, blockIdx.x, &lt);
+  int64_t* ptr;
+  int64_t len;
+  job_offsets<COLS>(jb, &ptr, &len);
+  const int64_t base = 1 + lt * kScanTile;
   int64_t acc = 0;
 #pragma unroll
   for (int j = 0; j < kScanPer; ++j) {
@@ -313,11 +469,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int64_t* ptr,
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t* ptr, int64_t len, const int64_t* tile_sum) {
+// Each block adds the totals of its job's earlier tiles (few: len /
+// kScanTile) and scans its own tile in shared memory.
+template <bool COLS, bool B>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(JobArg J, const int64_t* tile_sum) {
   __shared__ int64_t vals[kScanTile];
   __shared__ int64_t tot[kScanThreads];
   __shared__ int64_t carry;
-  const int64_t base = 1 + static_cast<int64_t>(blockIdx.x) * kScanTile;
+  int64_t lt;
+  const FoldJob& jb = find_job<B, COLS, true>(J, blockIdx.x, &lt);
+  int64_t* ptr;
+  int64_t len;
+  job_offsets<COLS>(jb, &ptr, &len);
+  const int64_t base = 1 + lt * kScanTile;
   for (int j = 0; j < kScanPer; ++j) {
     const int t = threadIdx.x + j * kScanThreads;
     const int64_t i = base + t;
@@ -325,7 +489,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t* ptr, int64
   }
   if (threadIdx.x == 0) {
     int64_t c = 0;
-    for (unsigned b = 0; b < blockIdx.x; ++b) c += tile_sum[b];
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) - lt; b < static_cast<int64_t>(blockIdx.x); ++b) c += tile_sum[b];
     carry = c;
   }
   __syncthreads();
@@ -355,12 +519,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t* ptr, int64
 
 inline int64_t scan_tiles(int64_t len) { return (len + kScanTile - 1) / kScanTile; }
 
-void launch_scan(int64_t* ptr, int64_t len, int64_t* scratch, hipStream_t st) {
-  const unsigned nt = static_cast<unsigned>(std::max<int64_t>(1, scan_tiles(len)));
-  k_scan_tiles<<<nt, kScanThreads, 0, st>>>(ptr, len, scratch);
-  k_scan_apply<<<nt, kScanThreads, 0, st>>>(ptr, len, scratch);
-}
-
 __device__ inline float recip_or_zero(double s) {
   return s != 0.0 ? static_cast<float>(1.0 / s) : 0.0f;
 }
@@ -369,20 +527,20 @@ __device__ inline float recip_or_zero(double s) {
 // with the FP32 reciprocal of the FP64 line sum of A (rows: W_i = sum over
 // row i of A = sum of a + b over the union; columns: V_j likewise), and for
 // rows also the folded p.
-template <bool COLS, int WT>
-__global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_fill(ss_matrix_dev A, const float* p,
-                                                                 ss_system out) {
+template <bool COLS, int WT, bool B>
+__global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_fill(JobArg J) {
+  SS_STAGE_BUF(sb);
+  int64_t lb;
+  const FoldJob& jb = find_job<B, COLS, false>(J, blockIdx.x, &lb);
+  const ss_matrix_dev& A = jb.A;
+  const ss_system& out = jb.out;
+  const float* p = jb.p;
   const int64_t lines = COLS ? out.n : out.m;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
+  const int64_t t = lb * kFoldWaves + wave_id();
   if (t >= lines) return;
   double sum = 0.0;
-  if constexpr (COLS) {
-    const ColLists L = col_lists(A, t);
-    wave_merge<true, WT>(L.X, L.Y, out.col_ptr[t], out.row_idx, out.val_t, sum);
-  } else {
-    const RowLists L = row_lists(A, t);
-    wave_merge<true, WT>(L.X, L.Y, out.row_ptr[t], out.col_idx, out.val, sum);
-  }
+  if constexpr (COLS) fold_line<true, true, WT>(A, t, out.col_ptr[t], out.row_idx, out.val_t, sum, sb);
+  else fold_line<false, true, WT>(A, t, out.row_ptr[t], out.col_idx, out.val, sum, sb);
   sum = group_sum<kWave>(sum);
   if (lane_id() == 0) {
     if constexpr (COLS) {
@@ -431,13 +589,87 @@ ss_status check_dev_matrix(const ss_matrix_dev* A, const char* fn) {
   return SS_OK;
 }
 
-template <bool COLS>
-void launch_fill(int wt, const ss_matrix_dev& A, const float* p, const ss_system& out, unsigned nb,
-                 hipStream_t st) {
-  if (wt == SS_F32) k_fold_fill<COLS, SS_F32><<<nb, kWave * kFoldWaves, 0, st>>>(A, p, out);
-  else if (wt == SS_BF16) k_fold_fill<COLS, SS_BF16><<<nb, kWave * kFoldWaves, 0, st>>>(A, p, out);
-  else k_fold_fill<COLS, SS_F16><<<nb, kWave * kFoldWaves, 0, st>>>(A, p, out);
+// Jobs written into the device table from kernel arguments, kJobChunk per
+// launch (no host-to-device copy of a pageable buffer).
+constexpr int kJobChunk = 16;
+struct JobChunk {
+  FoldJob j[kJobChunk];
+  int32_t count;
+  int32_t first;
+};
+
+__global__ void k_put_jobs(JobChunk ch, FoldJob* table) {
+  if (static_cast<int>(threadIdx.x) < ch.count) table[ch.first + threadIdx.x] = ch.j[threadIdx.x];
 }
+
+// Grid sizes of one fold call: blocks of row and column lines, scan tiles.
+struct FoldGrid {
+  int64_t rblk = 0, cblk = 0, rtile = 0, ctile = 0;
+};
+
+inline int64_t tiles_for(int64_t len) { return std::max<int64_t>(1, scan_tiles(len)); }
+
+// count, scan and fill for rows, then for columns; tiles: scan scratch.
+template <bool B>
+void run_fold(const JobArg& J, const FoldGrid& g, int wt, int64_t* tiles, hipStream_t st) {
+  const dim3 lb(kWave * kFoldWaves), sb(kScanThreads);
+  const auto R = static_cast<unsigned>(g.rblk), Cb = static_cast<unsigned>(g.cblk);
+  const auto RT = static_cast<unsigned>(g.rtile), CT = static_cast<unsigned>(g.ctile);
+  if (R > 0) {
+    k_fold_count<false, B><<<R, lb, 0, st>>>(J);
+    k_scan_tiles<false, B><<<RT, sb, 0, st>>>(J, tiles);
+    k_scan_apply<false, B><<<RT, sb, 0, st>>>(J, tiles);
+    if (wt == SS_F32) k_fold_fill<false, SS_F32, B><<<R, lb, 0, st>>>(J);
+    else if (wt == SS_BF16) k_fold_fill<false, SS_BF16, B><<<R, lb, 0, st>>>(J);
+    else k_fold_fill<false, SS_F16, B><<<R, lb, 0, st>>>(J);
+  }
+  if (Cb > 0) {
+    k_fold_count<true, B><<<Cb, lb, 0, st>>>(J);
+    k_scan_tiles<true, B><<<CT, sb, 0, st>>>(J, tiles);
+    k_scan_apply<true, B><<<CT, sb, 0, st>>>(J, tiles);
+    if (wt == SS_F32) k_fold_fill<true, SS_F32, B><<<Cb, lb, 0, st>>>(J);
+    else if (wt == SS_BF16) k_fold_fill<true, SS_BF16, B><<<Cb, lb, 0, st>>>(J);
+    else k_fold_fill<true, SS_F16, B><<<Cb, lb, 0, st>>>(J);
+  }
+}
+
+ss_status check_fold_out(const ss_matrix_dev* A, const float* p, const ss_system* out, const char* fn) {
+  if (ss_status s = check_dev_matrix(A, fn)) return s;
+  if (!p || !out) return fail(SS_E_ARG, "%s: NULL argument", fn);
+  if (A->M % 2 || A->N % 2) return fail(SS_E_ODD, "%s: M and N must be even", fn);
+  if (out->m != A->M / 2 || out->n != A->N / 2 || out->nvals != 2)
+    return fail(SS_E_ARG, "%s: out must be m = M/2, n = N/2, nvals = 2", fn);
+  if (out->wdtype != SS_F32 && out->wdtype != SS_BF16 && out->wdtype != SS_F16)
+    return fail(SS_E_ARG, "%s: unknown wdtype %d", fn, out->wdtype);
+  if (!out->row_ptr || !out->col_ptr || !out->p || !out->inv_row || !out->inv_col ||
+      (out->nnz > 0 && (!out->col_idx || !out->val || !out->row_idx || !out->val_t)))
+    return fail(SS_E_ARG, "%s: NULL output array", fn);
+  return SS_OK;
+}
+
+// Offsets of each job in the batched grids; returns the totals.
+FoldGrid layout_jobs(const ss_matrix_dev* A, const float* const* p, const ss_system* out, int32_t count,
+                     std::vector<FoldJob>* jobs) {
+  FoldGrid g;
+  for (int32_t k = 0; k < count; ++k) {
+    FoldJob j{};
+    j.A = A[k];
+    j.p = p ? p[k] : nullptr;
+    if (out) j.out = out[k];
+    j.rblk0 = g.rblk;
+    j.cblk0 = g.cblk;
+    j.rtile0 = g.rtile;
+    j.ctile0 = g.ctile;
+    g.rblk += blocks_for(A[k].M / 2);
+    g.cblk += blocks_for(A[k].N / 2);
+    g.rtile += tiles_for(A[k].M / 2);
+    g.ctile += tiles_for(A[k].N / 2);
+    if (jobs) jobs->push_back(j);
+  }
+  return g;
+}
+
+size_t batch_table_bytes(int32_t count) { return (sizeof(FoldJob) * static_cast<size_t>(count) + 255) & ~size_t{255}; }
 
 }  // namespace
 }  // namespace ss
@@ -483,28 +715,60 @@ extern "C" ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* 
 extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out, void* workspace,
                              size_t workspace_bytes, void* stream) {
   clear_error();
-  if (ss_status s = check_dev_matrix(A, "ss_fold")) return s;
-  if (!p || !out) return fail(SS_E_ARG, "ss_fold: NULL argument");
-  if (A->M % 2 || A->N % 2) return fail(SS_E_ODD, "ss_fold: M and N must be even");
-  if (out->m != A->M / 2 || out->n != A->N / 2 || out->nvals != 2)
-    return fail(SS_E_ARG, "ss_fold: out must be m = M/2, n = N/2, nvals = 2");
-  if (out->wdtype != SS_F32 && out->wdtype != SS_BF16 && out->wdtype != SS_F16)
-    return fail(SS_E_ARG, "ss_fold: unknown wdtype %d", out->wdtype);
-  if (!out->row_ptr || !out->col_ptr || !out->p || !out->inv_row || !out->inv_col ||
-      (out->nnz > 0 && (!out->col_idx || !out->val || !out->row_idx || !out->val_t)))
-    return fail(SS_E_ARG, "ss_fold: NULL output array");
+  if (ss_status s = check_fold_out(A, p, out, "ss_fold")) return s;
   size_t need = 0;
   ss_fold_workspace_bytes(A->M, A->N, &need);
   if (!workspace || workspace_bytes < need) return fail(SS_E_WORKSPACE, "ss_fold: workspace needs %zu bytes", need);
   int64_t* tiles = reinterpret_cast<int64_t*>(static_cast<char*>(workspace) + 512);
+  JobArg J{};
+  J.count = 1;
+  J.one.A = *A;
+  J.one.p = p;
+  J.one.out = *out;
+  const FoldGrid g = layout_jobs(A, nullptr, nullptr, 1, nullptr);
+  run_fold<false>(J, g, out->wdtype, tiles, static_cast<hipStream_t>(stream));
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+extern "C" ss_status ss_fold_batch_workspace_bytes(const ss_matrix_dev* A, int32_t count, size_t* bytes) {
+  clear_error();
+  if (!A || count <= 0 || !bytes) return fail(SS_E_ARG, "ss_fold_batch_workspace_bytes: bad argument");
+  for (int32_t k = 0; k < count; ++k)
+    if (A[k].M <= 0 || A[k].N <= 0) return fail(SS_E_ARG, "ss_fold_batch_workspace_bytes: bad matrix %d", k);
+  const FoldGrid g = layout_jobs(A, nullptr, nullptr, count, nullptr);
+  *bytes = batch_table_bytes(count) + sizeof(int64_t) * static_cast<size_t>(std::max(g.rtile, g.ctile));
+  return SS_OK;
+}
+
+extern "C" ss_status ss_fold_batch(const ss_matrix_dev* A, const float* const* p, ss_system* out, int32_t count,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (!A || !p || !out || count <= 0) return fail(SS_E_ARG, "ss_fold_batch: bad argument");
+  for (int32_t k = 0; k < count; ++k) {
+    if (ss_status s = check_fold_out(&A[k], p[k], &out[k], "ss_fold_batch")) return s;
+    if (out[k].wdtype != out[0].wdtype) return fail(SS_E_ARG, "ss_fold_batch: all outputs must share wdtype");
+  }
+  size_t need = 0;
+  if (ss_status s = ss_fold_batch_workspace_bytes(A, count, &need)) return s;
+  if (!workspace || workspace_bytes < need)
+    return fail(SS_E_WORKSPACE, "ss_fold_batch: workspace needs %zu bytes", need);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const unsigned nbr = blocks_for(out->m), nbc = blocks_for(out->n);
-  k_fold_count<false><<<nbr, kWave * kFoldWaves, 0, st>>>(*A, out->row_ptr);
-  launch_scan(out->row_ptr, out->m, tiles, st);
-  launch_fill<false>(out->wdtype, *A, p, *out, nbr, st);
-  k_fold_count<true><<<nbc, kWave * kFoldWaves, 0, st>>>(*A, out->col_ptr);
-  launch_scan(out->col_ptr, out->n, tiles, st);
-  launch_fill<true>(out->wdtype, *A, p, *out, nbc, st);
+  std::vector<FoldJob> jobs;
+  const FoldGrid g = layout_jobs(A, p, out, count, &jobs);
+  FoldJob* table = static_cast<FoldJob*>(workspace);
+  int64_t* tiles = reinterpret_cast<int64_t*>(static_cast<char*>(workspace) + batch_table_bytes(count));
+  for (int32_t k0 = 0; k0 < count; k0 += kJobChunk) {
+    JobChunk ch{};
+    ch.first = k0;
+    ch.count = std::min(kJobChunk, count - k0);
+    for (int i = 0; i < ch.count; ++i) ch.j[i] = jobs[k0 + i];
+    k_put_jobs<<<1, kWave, 0, st>>>(ch, table);
+  }
+  JobArg J{};
+  J.table = table;
+  J.count = count;
+  run_fold<true>(J, g, out[0].wdtype, tiles, st);
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;
 }

@@ -61,6 +61,20 @@ extern "C" ss_status ss_recombine(const float* f12, int64_t n, float* f, void* s
   return SS_OK;
 }
 
+extern "C" ss_status ss_recombine_batch(const float* const* f12, const int64_t* n, float* const* f, int32_t count,
+                                       void* stream) {
+  clear_error();
+  if (!f12 || !n || !f || count < 0) return fail(SS_E_ARG, "ss_recombine_batch: bad argument");
+  for (int32_t k = 0; k < count; ++k)
+    if (!f12[k] || !f[k] || n[k] <= 0) return fail(SS_E_ARG, "ss_recombine_batch: bad image %d", k);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int32_t k = 0; k < count; ++k)
+    k_recombine<<<static_cast<unsigned>((n[k] + 255) / 256), 256, 0, st>>>(reinterpret_cast<const float2*>(f12[k]),
+                                                                           n[k], f[k]);
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
 extern "C" ss_status ss_image_fold(const float* f, int64_t N, float* f12, void* stream) {
   clear_error();
   if (!f || !f12 || N <= 0) return fail(SS_E_ARG, "ss_image_fold: bad argument");

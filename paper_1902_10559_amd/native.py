@@ -74,6 +74,11 @@ _SIGNATURES = {
     "ss_snake_order": (C.c_int32, [C.POINTER(Grid), C.POINTER(C.c_int64)]),
     "ss_stream_len": (C.c_int64, [C.c_int64]),
     "ss_fold_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "ss_recombine_batch": (C.c_int32, [C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                                       C.c_int32, C.c_void_p]),
+    "ss_fold_batch_workspace_bytes": (C.c_int32, [C.POINTER(MatrixDevC), C.c_int32, C.POINTER(C.c_size_t)]),
+    "ss_fold_batch": (C.c_int32, [C.POINTER(MatrixDevC), C.POINTER(C.c_void_p), C.POINTER(SystemC), C.c_int32,
+                                  C.c_void_p, C.c_size_t, C.c_void_p]),
     "ss_fold_size": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_int64), C.c_void_p]),
     "ss_fold": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p,
@@ -343,6 +348,28 @@ def fold_into(A: DeviceMatrix, p, S: System) -> None:
                          _stream(A.val.device)))
 
 
+class FoldBatch:
+    """ss_fold_batch over fixed lists of matrices, right-hand sides and
+    systems (the descriptor arrays are built once)."""
+
+    def __init__(self, As, ps, systems):
+        import torch
+        assert len(As) == len(ps) == len(systems) > 0
+        self.count = len(As)
+        self._keep = (list(As), list(ps), list(systems))
+        self._A = (MatrixDevC * self.count)(*[A.c() for A in As])
+        self._p = (C.c_void_p * self.count)(*[_ptr(p) for p in ps])
+        self._S = (SystemC * self.count)(*[S.c() for S in systems])
+        nb = C.c_size_t()
+        _check(lib().ss_fold_batch_workspace_bytes(self._A, self.count, C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=ps[0].device)
+
+    def __call__(self):
+        _check(lib().ss_fold_batch(self._A, self._p, self._S, self.count, _ptr(self.ws), self.ws_bytes,
+                                   _stream(self.ws.device)))
+
+
 def unsplit(A: DeviceMatrix, p, wdtype: str = "f32") -> System:
     """ss_unsplit: A itself as a single system (the unsplit baseline)."""
     import torch
@@ -447,6 +474,22 @@ def recombine(f12, out=None):
         out = torch.empty(2 * n, dtype=torch.float32, device=f12.device)
     _check(lib().ss_recombine(_ptr(f12), n, _ptr(out), _stream(f12.device)))
     return out
+
+
+class RecombineBatch:
+    """ss_recombine_batch over fixed lists of half-image pairs and outputs."""
+
+    def __init__(self, f12s, outs):
+        assert len(f12s) == len(outs) > 0
+        self.count = len(f12s)
+        self._keep = (list(f12s), list(outs))
+        self._f12 = (C.c_void_p * self.count)(*[_ptr(f) for f in f12s])
+        self._n = (C.c_int64 * self.count)(*[f.shape[0] for f in f12s])
+        self._out = (C.c_void_p * self.count)(*[_ptr(o) for o in outs])
+        self._dev = f12s[0].device
+
+    def __call__(self):
+        _check(lib().ss_recombine_batch(self._f12, self._n, self._out, self.count, _stream(self._dev)))
 
 
 def image_fold(f, out=None):

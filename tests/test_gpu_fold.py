@@ -194,3 +194,46 @@ def test_empty_matrix_folds_and_solves():
     h = [torch.zeros(6, dtype=torch.float64, device="cuda")]
     status, it = native.Solver([S], native.SartOptions(max_iter=5)).solve(f, h)
     assert it == [5] and np.all(to_np(f[0]) == 0) and np.allclose(to_np(h[0]), 1.0)
+
+
+def _poison(S):
+    """Fills every output array with a pattern the fold never writes."""
+    for t in (S.row_ptr, S.col_ptr, S.col_idx, S.row_idx):
+        t.fill_(-7)
+    for t in (S.val, S.val_t):
+        t.fill_(float("nan") if t.dtype.is_floating_point else 0x7fc1)
+    for t in (S.p, S.inv_row, S.inv_col):
+        t.fill_(float("nan"))
+
+
+@pytest.mark.parametrize("wdtype", ["f32", "bf16"])
+def test_batch_fold_equals_single_folds_bitwise(wdtype):
+    """ss_fold_batch over matrices of different sizes (cfg1, ragged random
+    ones, a 2 x 2) writes exactly what one ss_fold per matrix writes."""
+    import torch
+    banner(f"batch fold {wdtype}")
+    probs = [problem(1), random_problem(21, 1002, 514, 0.05), random_problem(22, 66, 130, 0.3),
+             random_problem(23, 2, 2, 0.3), problem(1, 3)]
+    As = [device(pr.A) for pr in probs]
+    ps = [torch.from_numpy(np.ascontiguousarray(pr.p, dtype=np.float32)).cuda() for pr in probs]
+    singles = [native.fold(A, p, wdtype) for A, p in zip(As, ps)]
+    batch = [native.fold(A, p, wdtype) for A, p in zip(As, ps)]
+    for S in batch:
+        _poison(S)
+    native.FoldBatch(As, ps, batch)()
+    for a, b in zip(singles, batch):
+        for name in ("row_ptr", "col_idx", "val", "col_ptr", "row_idx", "val_t", "p", "inv_row", "inv_col"):
+            x, y = to_np(getattr(a, name)), to_np(getattr(b, name))
+            assert x.shape == y.shape and np.array_equal(x.view(np.uint8), y.view(np.uint8)), name
+
+
+def test_batch_recombine_equals_single():
+    import torch
+    banner("batch recombine")
+    g = torch.Generator().manual_seed(3)
+    f12 = [torch.randn(n, 2, generator=g).cuda() for n in (1, 7, 2048)]
+    want = [native.recombine(f) for f in f12]
+    outs = [torch.full((2 * f.shape[0],), float("nan"), device="cuda") for f in f12]
+    native.RecombineBatch(f12, outs)()
+    for w, o in zip(want, outs):
+        assert np.array_equal(to_np(w), to_np(o))
