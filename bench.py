@@ -6,13 +6,16 @@ HBM: fold A and p into the split pair (systems (3), (4) of the paper), run
 A (host Siddon) and synthesising p happen before the timed region.
 
 Workloads:
-  slice (default)  a 512 x 128 voxel slice (N = 65536), 24 sources over +-20
-                   degrees, 1024-bin detector (M = 24576), 40 random ellipses,
-                   1 % noise, 100 iterations, FP32 weights.
-  batched          256 slices of 1024 x nz voxels, nz in {32, 48, ..., 128},
+  batched (default)  256 slices of 1024 x nz voxels, nz in {32, 48, ..., 128},
                    each with its own geometry, 24 sources, 2048 bins,
                    noise-free, 100 iterations; all slices and both halves in
-                   the same launches.
+                   the same launches.  Its 11 GB per iteration stream from
+                   HBM: the workload the HBM roofline is taken on.
+  slice            a 512 x 128 voxel slice (N = 65536), 24 sources over +-20
+                   degrees, 1024-bin detector (M = 24576), 40 random ellipses,
+                   1 % noise, 100 iterations, FP32 weights.  Its 32 MB per
+                   iteration stay in the 256 MB Infinity Cache, so its kernels
+                   are bound by latency, not by HBM.
 The same step on the unsplit A is timed beside it.
 
 Output: one JSON line on stdout (progress on stderr).  ``value`` is
@@ -44,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--iters", type=int, default=100, help="SART iterations per step")
-    ap.add_argument("--workload", choices=["slice", "batched"], default="slice")
+    ap.add_argument("--workload", choices=["slice", "batched"], default="batched")
     ap.add_argument("--wdtype", choices=["f32", "bf16", "f16"], default="f32",
                     help="storage type of the split pair's weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -233,28 +236,58 @@ def main():
     log(f"unsplit step {ums:.3f} ms; split/unsplit speedup {ums / ms:.2f}")
 
     # time to relative residual 1e-3 (capped at 20000 iterations)
+    ttr = {}
     if args.workload == "slice":
-        ttr = {}
-        for name, slv, img in (("split", sol, f12), ("unsplit", usol, fu)):
-            o = slv.opts
-            saved = (o.max_iter, o.tol, o.check_every)
-            o.max_iter, o.tol, o.check_every = 20000, 1e-3, 100
-            hist = [torch.empty(20001, dtype=torch.float64, device=dev)]
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, it = slv.solve(img, hist)
-            torch.cuda.synchronize()
-            secs = time.perf_counter() - t0
-            ttr[name] = {"iterations": it[0], "seconds": secs, "reached": bool(st == 0),
-                         "final_rel_res": float(hist[0][it[0]].item()), "cap": 20000}
-            o.max_iter, o.tol, o.check_every = saved
-        out["time_to_1e-3"] = ttr
-        log(f"time to 1e-3: {ttr}")
+        ttr["bench_workload"] = {"split": time_to_tol(sol, f12, dev), "unsplit": time_to_tol(usol, fu, dev)}
+    ttr["64x64_slice_0.5pct_noise"] = small_slice_time_to_tol(dev, lam)
+    out["time_to_1e-3"] = ttr
+    log(f"time to 1e-3: {ttr}")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, slices, iters, lam)
         log(f"cpu baseline {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
+
+
+def time_to_tol(slv, img, dev, tol=1e-3, cap=20000):
+    """Iterations to rel_res <= tol from f0 = 0, then the time of exactly
+    that many iterations (a second run with max_iter = k*, so that the graph
+    chunks of the first run do not overshoot), by events on the stream."""
+    import torch
+    o = slv.opts
+    saved = (o.max_iter, o.tol, o.check_every, o.zero_start)
+    o.max_iter, o.tol, o.check_every, o.zero_start = cap, tol, 50, True
+    hist = [torch.empty(cap + 1, dtype=torch.float64, device=dev) for _ in img]
+    st, it = slv.solve(img, hist)
+    k = it[0]
+    rec = {"iterations": k, "reached": bool(st == 0), "final_rel_res": float(hist[0][k].item()), "cap": cap}
+    o.max_iter, o.tol = k, 0.0
+    slv.solve(img, want_iters=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    slv.solve(img, want_iters=False)
+    e1.record()
+    torch.cuda.synchronize()
+    rec["seconds"] = e0.elapsed_time(e1) * 1e-3
+    rec["us_per_iteration"] = rec["seconds"] * 1e6 / max(k, 1)
+    o.max_iter, o.tol, o.check_every, o.zero_start = saved
+    return rec
+
+
+def small_slice_time_to_tol(dev, lam):
+    """The 64 x 64 slice (K=10, 128 bins, 0.5% noise), which reaches 1e-3:
+    split vs unsplit SART in FP32, and split SART with BF16 and FP16 weights."""
+    from paper_1902_10559_amd import native, workloads
+    res = {}
+    for name, wdtype, split in (("split_f32", "f32", True), ("unsplit_f32", "f32", False),
+                                ("split_bf16", "bf16", True), ("split_f16", "f16", True)):
+        sl = workloads.single_slice(1, dev, wdtype)
+        S = sl.S if split else native.unsplit(sl.A, sl.p, wdtype)
+        slv = native.Solver([S], native.SartOptions(lam=lam, use_graph=True))
+        slv.autotune([S.new_image()])
+        res[name] = time_to_tol(slv, [S.new_image()], dev)
+    return res
 
 
 def cpu_baseline(args, slices, iters, lam):
