@@ -20,6 +20,10 @@ method's standard published definition:
 * ``sart``      -- simultaneous SART (Andersen & Kak, the paper's ref. [001];
   convergence for lambda in (0, 2) per ref. [003]) on the full system and on
   the split pair, with relative-residual histories.
+* ``ossart``    -- ordered-subset SART (ordered subsets per the paper's ref.
+  [004]) with subsets of mirror-paired views, full and split.
+* ``nn``        -- the learned initialiser's layers (3x3 convolution and its
+  gradients, pooling, upsampling, ReLU, squared error, Adam).
 
 Pins: every function here is checked by ``tests/test_oracle_*.py`` against
 values the paper prints (Example 1), closed forms, invariants and brute force.

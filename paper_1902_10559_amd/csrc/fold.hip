@@ -102,11 +102,15 @@ struct LSeq {
   }
 };
 
-// Lines of up to kStage entries per list are staged in shared memory by one
-// coalesced pass, so that the per-element binary searches of the merge hit
-// LDS instead of making dependent global loads; longer lines are merged from
-// global memory.
-constexpr int kStage = 512;
+// Lines are staged in shared memory by one coalesced pass, so that the
+// per-element binary searches of the merge hit LDS instead of making
+// dependent global loads: rows of up to kStageRow entries (two lists), columns
+// of up to kStageCol entries; longer lines are merged from global memory.
+// The buffers are sized for the lines of the workloads (rows up to ~400,
+// columns up to ~80 entries) and small enough to keep 6 (rows) or 8
+// (columns) blocks per CU.
+constexpr int kStageRow = 384;
+constexpr int kStageCol = 256;
 
 // Copies a sorted list of len (<= capacity) entries into shared memory and
 // returns how many of its indices are below `limit` (a prefix).
@@ -225,8 +229,8 @@ __device__ inline ColLists col_lists(const ss_matrix_dev& A, int64_t j) {
   return L;
 }
 
-// Per-wavefront staging buffers: two lists of kStage entries (the rows i and
-// M-1-i), or one column of up to 2 kStage entries.
+// Per-wavefront staging buffers: two lists of kStageRow entries (the rows i
+// and M-1-i), or one column of up to kStageCol entries.
 struct StageBuf {
   SS_LDS int32_t* idx;
   SS_LDS float* val;
@@ -240,7 +244,7 @@ __device__ int64_t fold_line(const ss_matrix_dev& A, int64_t t, int64_t out_base
   if constexpr (COLS) {
     const int64_t cs = A.col_ptr[t], ce = A.col_ptr[t + 1];
     const int64_t len = ce - cs;
-    if (len <= 2 * kStage) {
+    if (len <= kStageCol) {
       const int64_t split = stage_list(A.row_idx + cs, A.val_t + cs, len, sb.idx, sb.val,
                                        static_cast<int32_t>(A.M / 2));
       wave_lds_sync();
@@ -254,13 +258,13 @@ __device__ int64_t fold_line(const ss_matrix_dev& A, int64_t t, int64_t out_base
     const int64_t rs = A.row_ptr[t], re = A.row_ptr[t + 1];
     const int64_t t2 = A.M - 1 - t;
     const int64_t ys = A.row_ptr[t2], ye = A.row_ptr[t2 + 1];
-    if (re - rs <= kStage && ye - ys <= kStage) {
+    if (re - rs <= kStageRow && ye - ys <= kStageRow) {
       const int32_t n = static_cast<int32_t>(A.N / 2);
       const int64_t xl = stage_list(A.col_idx + rs, A.val + rs, re - rs, sb.idx, sb.val, n);
-      const int64_t yl = stage_list(A.col_idx + ys, A.val + ys, ye - ys, sb.idx + kStage, sb.val + kStage, n);
+      const int64_t yl = stage_list(A.col_idx + ys, A.val + ys, ye - ys, sb.idx + kStageRow, sb.val + kStageRow, n);
       wave_lds_sync();
       const LSeq<false> X{sb.idx, sb.val, xl, 0};
-      const LSeq<false> Y{sb.idx + kStage, sb.val + kStage, yl, 0};
+      const LSeq<false> Y{sb.idx + kStageRow, sb.val + kStageRow, yl, 0};
       return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum);
     }
     const RowLists L = row_lists(A, t);
@@ -270,8 +274,9 @@ __device__ int64_t fold_line(const ss_matrix_dev& A, int64_t t, int64_t out_base
 
 // This wavefront's staging buffers in the block's shared memory.
 #define SS_STAGE_BUF(name)                                                        \
-  __shared__ int32_t name##_idx[kFoldWaves][2 * kStage];                          \
-  __shared__ float name##_val[kFoldWaves][2 * kStage];                            \
+  constexpr int name##_cap = COLS ? kStageCol : 2 * kStageRow;                    \
+  __shared__ int32_t name##_idx[kFoldWaves][name##_cap];                          \
+  __shared__ float name##_val[kFoldWaves][name##_cap];                            \
   const StageBuf name{(SS_LDS int32_t*)(&name##_idx[wave_id()][0]), (SS_LDS float*)(&name##_val[wave_id()][0])}
 
 __device__ inline unsigned long long mix64(unsigned long long z) {
