@@ -76,10 +76,12 @@ def bytes_per_iteration(nnz, m, n, nv, sv):
 
 
 def source_hash():
-    """Hash of the solver's device code (device.h and the kernel section of
-    sart.hip): traffic counted for other kernel code is not reported."""
+    """Hash of the solver's device code (device.h, lines.h and the kernel
+    section of sart.hip): traffic counted for other kernel code is not
+    reported."""
     csrc = os.path.join(ROOT, "paper_1902_10559_amd", "csrc")
     h = hashlib.sha256(open(os.path.join(csrc, "device.h"), "rb").read())
+    h.update(open(os.path.join(csrc, "lines.h"), "rb").read())
     text = open(os.path.join(csrc, "sart.hip")).read()
     a, b = text.index("// ---- device code begin"), text.index("// ---- device code end")
     h.update(text[a:b].encode())

@@ -312,6 +312,54 @@ ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f,
                            size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Ordered-subset SART (the paper's ref. [004] applied to SART, ref. [001])
+ * with subsets that the fold preserves
+ * ---------------------------------------------------------------------- */
+
+/* The subsets of one folded pair.  A subset of rays closed under the ray
+ * mirror i -> M-1-i (the rays of sources k and K-1-k of the symmetric scan)
+ * folds onto a block of rows; with rays ordered source-major, subset s of S
+ * is the folded rows [s m/S, (s+1) m/S), and S must divide m.
+ *   col_sub      device, n*(S+1) ints: column j's entries in subset s are
+ *                col_ptr[j] + col_sub[j*(S+1)+s] .. col_ptr[j] +
+ *                col_sub[j*(S+1)+s+1] - 1 (rows ascend, so they are
+ *                contiguous)
+ *   inv_col_sub  device, S*n floats: FP32 reciprocal of the FP64 sum of
+ *                A(2) over column j's entries in subset s (0 for a zero
+ *                sum); it equals A's column sum over the mirror-closed
+ *                subset. */
+typedef struct {
+  int32_t S;
+  int32_t* col_sub;
+  float* inv_col_sub;
+} ss_subsets;
+
+/* Fills col_sub and inv_col_sub (caller-allocated) for a folded FP32 pair
+ * (nvals = 2, wdtype = SS_F32).  Asynchronous. */
+ss_status ss_subsets_build(const ss_system* sys, ss_subsets* sub, void* stream);
+
+/* Workspace bytes for ss_ossart_solve on these systems. */
+ss_status ss_ossart_workspace_bytes(const ss_system* sys, const ss_subsets* sub,
+                                    int32_t nsys, const ss_sart_opts* opts,
+                                    size_t* bytes);
+
+/* Ordered-subset SART on nsys folded pairs (all with the same S): one pass
+ * applies, for s = 0 .. S-1, f <- f + lambda V_s^-1 A_s^T W^-1 (p_s - A_s f)
+ * to both halves, V_s the subset column sums; recombined by eq. (5) the
+ * iterates are ordered-subset SART on A with the mirror-closed subsets.
+ * Options as for ss_sart_solve, with max_iter counting passes; `persistent`
+ * is ignored.  res_hist[s][k] = rel_res of the image after k passes, for
+ * k = 0 .. passes[s] (max_iter + 1 doubles); passes (host, or NULL)
+ * receives the passes applied.  Every pass evaluates the residual of its
+ * starting image (one extra forward projection of every row).  Returns
+ * SS_NOT_CONVERGED as ss_sart_solve does. */
+ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub,
+                          int32_t nsys, float* const* f,
+                          double* const* res_hist, const ss_sart_opts* opts,
+                          int32_t* passes, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Images
  * ---------------------------------------------------------------------- */
 

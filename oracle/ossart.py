@@ -24,6 +24,15 @@ have no split counterpart.
 
 ``res[k]`` is ||p - A f^k|| / ||p|| for f^k the image after k passes,
 k = 0 .. passes.
+
+Behaviour (observed with this oracle, not a claim of the paper): every
+subset step uses its own column weights V_s, so the pass map is not a
+projection in one common metric.  For a consistent overdetermined system of
+full rank the passes converge to the solution, but on underdetermined
+systems they can settle at a fixed point of the pass map with a nonzero
+residual (0.019 for a random 40 x 100 system; the noise-free 64 x 64 scan is
+still at 2.5e-3 after 3000 passes, where SART reaches 3e-4), while the first
+passes lower the residual several times faster than SART iterations do.
 """
 from __future__ import annotations
 

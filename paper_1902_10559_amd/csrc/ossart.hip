@@ -1,0 +1,563 @@
+// Ordered-subset SART on the folded pair: the paper's ref. [004] (ordered
+// subsets of projection data) applied to SART (ref. [001]), with subsets
+// that the fold of Section 2 preserves.
+//
+// A subset is closed under the ray mirror i -> M-1-i (the rays of sources k
+// and K-1-k of the symmetric scan); the fold maps it onto a block of rows of
+// the folded system.  With rays ordered source-major, subset s of S is the
+// folded rows [s R, (s+1) R), R = m / S.  One pass applies, for s = 0 .. S-1,
+//     f <- f + lambda * V_s^-1 A_s^T W_s^-1 (p_s - A_s f)
+// to both halves, with W the row sums of A(2) and V_s the column sums of
+// A(2) over the rows of subset s (equal to A's over the mirror-closed
+// subset), so that the recombined iterates are those of ordered-subset SART
+// on A itself.
+//
+// Launches per pass: the residual of the current image (forward projection
+// of every row, FP64 partials per block), its finalisation (history entry,
+// stop decision, pass counter), then for each subset a forward kernel over
+// its rows (z = W^-1 (p - A f)) and a back projection over every column,
+// reading only the column's entries in that subset (a contiguous range of
+// the CSC, located by `col_sub`) and updating f in place: each column
+// belongs to one lane group, and the next subset's kernel starts after this
+// one has ended.  A stop decided by the finalisation is read by every later
+// kernel of the pass, so a stopped system's image is f^k exactly.
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+#include "lines.h"
+
+namespace ss {
+namespace {
+
+constexpr int kOsWPB = 4;  // wavefronts per block
+constexpr int kOsThreads = kWave * kOsWPB;
+
+struct OsState {
+  double pnorm2;
+  double last_res;
+  int32_t k;     // passes applied to the image
+  int32_t stop;  // 1: the image is final
+};
+
+struct OsDesc {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const void* val;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const void* val_t;
+  const int32_t* col_sub;
+  const float* inv_col_sub;
+  const float* p;
+  const float* inv_row;
+  float* f;
+  float* z;
+  double* res_hist;
+  double* partials;
+  OsState* st;
+  int64_t m, n;
+  int32_t S, R;
+  int64_t blk0[3];    // first block of this system in the subset-row, all-row and column grids
+  int32_t nblk[3];
+};
+
+enum { kSubRows = 0, kAllRows = 1, kCols = 2 };
+
+struct OsParams {
+  float lambda;
+  int32_t max_iter;
+  double tol;
+};
+
+constexpr int kOsChunk = 16;
+struct OsChunk {
+  OsDesc d[kOsChunk];
+  OsParams prm;
+  int32_t count;
+  int32_t first;
+  int32_t zero_start;
+};
+
+template <int G>
+__device__ inline int os_find(const OsDesc* t, int nsys, int64_t b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = __builtin_amdgcn_readfirstlane((lo + hi + 1) >> 1);
+    if (t[mid].blk0[G] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// The system and block-local index of grid block b (uniform per block).
+template <int G>
+__device__ inline int os_block(const OsDesc* t, int nsys, uint32_t ntiles, int xcd, int64_t* local) {
+  const uint32_t b = __builtin_amdgcn_readfirstlane(xcd ? xcd_remap(blockIdx.x, ntiles) : blockIdx.x);
+  const int s = nsys == 1 ? 0 : os_find<G>(t, nsys, b);
+  *local = static_cast<int64_t>(b) - t[s].blk0[G];
+  return s;
+}
+
+__global__ __launch_bounds__(kOsThreads) void k_os_setup(OsChunk ch, OsDesc* table, OsParams* prm) {
+  const OsDesc& d = ch.d[blockIdx.x];
+  if (ch.zero_start)
+    for (int64_t i = threadIdx.x; i < 2 * d.n; i += kOsThreads) d.f[i] = 0.0f;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < 2 * d.m; i += kOsThreads) {
+    const double v = d.p[i];
+    s += v * v;
+  }
+  __shared__ double red[kOsWPB];
+  s = block_sum<kOsWPB>(s, red);
+  if (threadIdx.x == 0) {
+    table[ch.first + blockIdx.x] = d;
+    d.st->pnorm2 = s;
+    d.st->last_res = 0.0;
+    d.st->k = 0;
+    d.st->stop = 0;
+    if (ch.first == 0 && blockIdx.x == 0) *prm = ch.prm;
+  }
+}
+
+// Forward projection of rows [r0, r0 + rows) in tiles of RPW*kOsWPB rows.
+// RES: FP64 partial of |p - A f|^2 per block into `partials`; otherwise
+// z = W^-1 (p - A f).
+template <int WT, int RPW, int U, bool CH, bool RES>
+__global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsDesc* __restrict__ table, int nsys, uint32_t ntiles,
+                                                      int xcd, int sub) {
+  constexpr int L = kWave / RPW;
+  __shared__ double red[kOsWPB];
+  if (blockIdx.x >= ntiles) return;
+  int64_t local;
+  const int si = os_block<RES ? kAllRows : kSubRows>(table, nsys, ntiles, xcd, &local);
+  const OsDesc& S = table[si];
+  if (*gl(&S.st->stop)) return;
+  const int64_t r0 = RES ? 0 : static_cast<int64_t>(sub) * S.R;
+  const int64_t r1 = RES ? S.m : r0 + S.R;
+  const int glane = lane_id() % L;
+  const int64_t row = r0 + local * (RPW * kOsWPB) + wave_id() * RPW + lane_id() / L;
+  const bool in = row < r1;
+  const int64_t li = in ? row : r1 - 1;
+  const Vec<2> pv = load_vec<2>(S.p, li);
+  const float w = gl(S.inv_row)[li];
+  const int64_t lo = gl(S.row_ptr)[li];
+  const int64_t hi = in ? gl(S.row_ptr)[li + 1] : lo;
+  float acc[2] = {0.0f, 0.0f};
+  line_dot<2, WT, L, U, CH>(S.col_idx, S.val, S.f, lo, hi, glane, acc);
+  acc[0] = group_sum<L>(acc[0]);
+  acc[1] = group_sum<L>(acc[1]);
+  const bool owner = glane == 0 && in;
+  const float ra = pv.v[0] - acc[0], rb = pv.v[1] - acc[1];
+  if constexpr (RES) {
+    const double d = owner ? static_cast<double>(ra) * ra + static_cast<double>(rb) * rb : 0.0;
+    const double tot = block_sum<kOsWPB>(d, red);
+    if (threadIdx.x == 0) glw(S.partials)[local] = tot;
+  } else {
+    if (owner) store_vec<2>(S.z, row, Vec<2>{{ra * w, rb * w}});
+  }
+}
+
+// One block per system: rel_res of the current image from the partials in
+// index order, the history entry, the stop decision and the pass counter.
+__global__ __launch_bounds__(kOsThreads) void k_os_fin(const OsDesc* __restrict__ table, const OsParams* prm) {
+  const OsDesc& S = table[blockIdx.x];
+  if (*gl(&S.st->stop)) return;
+  __shared__ double red[kOsWPB];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < S.nblk[kAllRows]; t += kOsThreads) acc += gl(S.partials)[t];
+  const double rsum = block_sum<kOsWPB>(acc, red);
+  if (threadIdx.x == 0) {
+    OsState* st = S.st;
+    const double pn = st->pnorm2;
+    const double rel = pn > 0.0 ? sqrt(rsum / pn) : sqrt(rsum);
+    const int k = st->k;
+    if (S.res_hist) glw(S.res_hist)[k] = rel;
+    st->last_res = rel;
+    if (rel <= prm->tol || k >= prm->max_iter) st->stop = 1;
+    else st->k = k + 1;
+  }
+}
+
+// Back projection of subset `sub` and the in-place update, column by column.
+template <int WT, int CPW, int U, bool CH>
+__global__ __launch_bounds__(kOsThreads) void k_os_bp(const OsParams* __restrict__ prm,
+                                                      const OsDesc* __restrict__ table, int nsys, uint32_t ntiles,
+                                                      int xcd, int sub) {
+  constexpr int L = kWave / CPW;
+  if (blockIdx.x >= ntiles) return;
+  int64_t local;
+  const int si = os_block<kCols>(table, nsys, ntiles, xcd, &local);
+  const OsDesc& S = table[si];
+  if (*gl(&S.st->stop)) return;
+  const int glane = lane_id() % L;
+  const int64_t col = local * (CPW * kOsWPB) + wave_id() * CPW + lane_id() / L;
+  const bool in = col < S.n;
+  const int64_t ci = in ? col : S.n - 1;
+  const int32_t* cs = S.col_sub + ci * (S.S + 1) + sub;
+  const int64_t base = gl(S.col_ptr)[ci];
+  const int64_t lo = base + gl(cs)[0];
+  const int64_t hi = in ? base + gl(cs)[1] : lo;
+  Vec<2> fv = load_vec<2>(S.f, ci);
+  const float tl = prm->lambda * gl(S.inv_col_sub)[static_cast<int64_t>(sub) * S.n + ci];
+  float acc[2] = {0.0f, 0.0f};
+  line_dot<2, WT, L, U, CH>(S.row_idx, S.val_t, S.z, lo, hi, glane, acc);
+  acc[0] = group_sum<L>(acc[0]);
+  acc[1] = group_sum<L>(acc[1]);
+  if (glane == 0 && in) {
+    fv.v[0] = fmaf(tl, acc[0], fv.v[0]);
+    fv.v[1] = fmaf(tl, acc[1], fv.v[1]);
+    store_vec<2>(S.f, col, fv);
+  }
+}
+
+// Subset ranges of each column and the FP32 reciprocals of the FP64 subset
+// column sums of A(2) (the second value of each FP32 pair): one thread per
+// column walks its ascending rows.
+__global__ void k_subsets_build(ss_system sys, int32_t S, int32_t R, int32_t* col_sub, float* inv_col_sub) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= sys.n) return;
+  const float* v = static_cast<const float*>(sys.val_t);
+  const int64_t base = sys.col_ptr[j], end = sys.col_ptr[j + 1];
+  int64_t e = base;
+  for (int s = 0; s < S; ++s) {
+    col_sub[j * (S + 1) + s] = static_cast<int32_t>(e - base);
+    const int64_t lim = static_cast<int64_t>(s + 1) * R;
+    double sum = 0.0;
+    for (; e < end && sys.row_idx[e] < lim; ++e) sum += static_cast<double>(v[2 * e + 1]);
+    inv_col_sub[static_cast<int64_t>(s) * sys.n + j] = sum != 0.0 ? static_cast<float>(1.0 / sum) : 0.0f;
+  }
+  col_sub[j * (S + 1) + S] = static_cast<int32_t>(e - base);
+}
+
+// ------------------------------------------------------------------ host
+struct OsCfg {
+  int rpw, cpw, xcd, u, ch;
+};
+
+struct OsLayout {
+  size_t params, table, states, total;
+  std::vector<size_t> z_off, part_off;
+};
+
+inline size_t al256(size_t v) { return (v + 255) & ~size_t{255}; }
+
+OsLayout os_layout(const ss_system* sys, int nsys) {
+  OsLayout L;
+  size_t o = 0;
+  L.params = o;
+  o += al256(sizeof(OsParams));
+  L.table = o;
+  o += al256(sizeof(OsDesc) * nsys);
+  L.states = o;
+  o += al256(sizeof(OsState) * nsys);
+  for (int s = 0; s < nsys; ++s) {
+    L.z_off.push_back(o);
+    o += al256(sizeof(float) * 2 * static_cast<size_t>(sys[s].m));
+  }
+  for (int s = 0; s < nsys; ++s) {
+    L.part_off.push_back(o);
+    o += al256(sizeof(double) * static_cast<size_t>((sys[s].m + kOsWPB - 1) / kOsWPB));  // 1 row per wave
+  }
+  L.total = o;
+  return L;
+}
+
+ss_status os_validate(const ss_system* sys, const ss_subsets* sub, int nsys, const ss_sart_opts* o, const char* fn) {
+  if (!sys || !sub || nsys <= 0 || !o) return fail(SS_E_ARG, "%s: NULL systems, subsets or options", fn);
+  for (int s = 0; s < nsys; ++s) {
+    const ss_system& Y = sys[s];
+    if (Y.nvals != 2 || Y.wdtype != SS_F32)
+      return fail(SS_E_ARG, "%s: system %d: ordered subsets need a folded FP32 pair", fn, s);
+    if (Y.m <= 0 || Y.n <= 0 || Y.nnz < 0 || Y.m > INT32_MAX || Y.n > INT32_MAX)
+      return fail(SS_E_ARG, "%s: system %d has a bad size", fn, s);
+    if (!Y.row_ptr || !Y.col_ptr || !Y.p || !Y.inv_row ||
+        (Y.nnz > 0 && (!Y.col_idx || !Y.val || !Y.row_idx || !Y.val_t)))
+      return fail(SS_E_ARG, "%s: system %d has a NULL array", fn, s);
+    auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (Y.nnz > 0 && !(aligned(Y.col_idx) && aligned(Y.val) && aligned(Y.row_idx) && aligned(Y.val_t)))
+      return fail(SS_E_ARG, "%s: system %d: index and value arrays must be 16-byte aligned", fn, s);
+    const ss_subsets& B = sub[s];
+    if (B.S <= 0 || B.S > Y.m || Y.m % B.S != 0 || !B.col_sub || !B.inv_col_sub)
+      return fail(SS_E_ARG, "%s: system %d: S must divide m and the subset arrays be set", fn, s);
+  }
+  if (!(o->lambda > 0.0f && o->lambda < 2.0f)) return fail(SS_E_ARG, "%s: lambda must be in (0, 2)", fn);
+  if (o->max_iter < 0 || o->max_iter > (1 << 30)) return fail(SS_E_ARG, "%s: bad max_iter", fn);
+  if (o->tol > 0.0 && o->check_every <= 0) return fail(SS_E_ARG, "%s: check_every must be > 0", fn);
+  auto ok_pw = [](int v, int maxv) { return v == 0 || (v > 0 && v <= maxv && (v & (v - 1)) == 0); };
+  if (!ok_pw(o->rows_per_wave, 8) || !ok_pw(o->cols_per_wave, 16))
+    return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8 and cols_per_wave 0,1,..,16", fn);
+  if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
+  if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
+  return SS_OK;
+}
+
+OsCfg os_cfg(const ss_sart_opts* o) {
+  OsCfg c;
+  c.rpw = o->rows_per_wave ? o->rows_per_wave : 4;
+  c.cpw = o->cols_per_wave ? o->cols_per_wave : 8;
+  c.xcd = o->xcd_remap ? 1 : 0;
+  c.u = o->unroll ? o->unroll : 4;
+  c.ch = o->chunked;
+  return c;
+}
+
+struct OsGrid {
+  uint32_t nb[3] = {0, 0, 0};
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <int WT, int U, bool CH, bool RES>
+void os_fp_rpw(int rpw, const OsDesc* t, int nsys, uint32_t nb, int xcd, int sub, hipStream_t st) {
+  const dim3 g(nb), b(kOsThreads);
+  switch (rpw) {
+    case 1: k_os_fp<WT, 1, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
+    case 2: k_os_fp<WT, 2, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
+    case 4: k_os_fp<WT, 4, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
+    default: k_os_fp<WT, 8, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
+  }
+}
+
+template <int WT, int U, bool CH>
+void os_bp_cpw(int cpw, const OsParams* prm, const OsDesc* t, int nsys, uint32_t nb, int xcd, int sub,
+               hipStream_t st) {
+  const dim3 g(nb), b(kOsThreads);
+  switch (cpw) {
+    case 1: k_os_bp<WT, 1, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
+    case 2: k_os_bp<WT, 2, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
+    case 4: k_os_bp<WT, 4, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
+    case 8: k_os_bp<WT, 8, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
+    default: k_os_bp<WT, 16, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
+  }
+}
+
+// One pass group: residual, finalisation, then the S subset updates.
+template <int U>
+void os_pass(const OsCfg& c, const OsParams* prm, const OsDesc* t, int nsys, int S, const OsGrid& g,
+             hipStream_t st) {
+  const bool fch = c.ch & 1, bch = c.ch & 2;
+  if (fch) os_fp_rpw<SS_F32, U, true, true>(c.rpw, t, nsys, g.nb[kAllRows], c.xcd, 0, st);
+  else os_fp_rpw<SS_F32, U, false, true>(c.rpw, t, nsys, g.nb[kAllRows], c.xcd, 0, st);
+  k_os_fin<<<nsys, kOsThreads, 0, st>>>(t, prm);
+  for (int s = 0; s < S; ++s) {
+    if (fch) os_fp_rpw<SS_F32, U, true, false>(c.rpw, t, nsys, g.nb[kSubRows], c.xcd, s, st);
+    else os_fp_rpw<SS_F32, U, false, false>(c.rpw, t, nsys, g.nb[kSubRows], c.xcd, s, st);
+    if (bch) os_bp_cpw<SS_F32, U, true>(c.cpw, prm, t, nsys, g.nb[kCols], c.xcd, s, st);
+    else os_bp_cpw<SS_F32, U, false>(c.cpw, prm, t, nsys, g.nb[kCols], c.xcd, s, st);
+  }
+}
+
+void os_passes(const OsCfg& c, const char* ws, const OsLayout& L, int nsys, int S, const OsGrid& g, int count,
+               hipStream_t st) {
+  const OsParams* prm = reinterpret_cast<const OsParams*>(ws + L.params);
+  const OsDesc* t = reinterpret_cast<const OsDesc*>(ws + L.table);
+  for (int i = 0; i < count; ++i) {
+    if (c.u == 8) os_pass<8>(c, prm, t, nsys, S, g, st);
+    else os_pass<4>(c, prm, t, nsys, S, g, st);
+  }
+}
+
+struct OsKey {
+  int device;
+  const void* ws;
+  int nsys, S;
+  uint32_t nb0, nb1, nb2;
+  int rpw, cpw, xcd, u, ch, count;
+  bool operator<(const OsKey& o) const {
+    return std::tie(device, ws, nsys, S, nb0, nb1, nb2, rpw, cpw, xcd, u, ch, count) <
+           std::tie(o.device, o.ws, o.nsys, o.S, o.nb0, o.nb1, o.nb2, o.rpw, o.cpw, o.xcd, o.u, o.ch, o.count);
+  }
+};
+
+struct OsGraphs {
+  std::mutex mu;
+  std::map<OsKey, hipGraphExec_t> execs;
+  std::map<int, hipStream_t> capture;
+};
+
+OsGraphs& os_graphs() {
+  static OsGraphs* g = new OsGraphs();  // lives until process exit
+  return *g;
+}
+
+ss_status os_graph(const OsKey& key, const OsCfg& c, const char* ws, const OsLayout& L, const OsGrid& g,
+                   hipGraphExec_t* out) {
+  OsGraphs& G = os_graphs();
+  std::lock_guard<std::mutex> lock(G.mu);
+  auto it = G.execs.find(key);
+  if (it != G.execs.end()) {
+    *out = it->second;
+    return SS_OK;
+  }
+  if (G.execs.size() >= 16) {
+    for (auto& kv : G.execs) (void)hipGraphExecDestroy(kv.second);
+    G.execs.clear();
+  }
+  hipStream_t cs;
+  auto sit = G.capture.find(key.device);
+  if (sit == G.capture.end()) {
+    SS_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    G.capture[key.device] = cs;
+  } else {
+    cs = sit->second;
+  }
+  SS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  os_passes(c, ws, L, key.nsys, key.S, g, key.count, cs);
+  hipGraph_t graph;
+  const hipError_t ce = hipStreamEndCapture(cs, &graph);
+  if (ce != hipSuccess) return fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+  hipGraphExec_t exec;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(SS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+  G.execs[key] = exec;
+  *out = exec;
+  return SS_OK;
+}
+
+}  // namespace
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" ss_status ss_subsets_build(const ss_system* sys, ss_subsets* sub, void* stream) {
+  clear_error();
+  if (!sys || !sub) return fail(SS_E_ARG, "ss_subsets_build: NULL argument");
+  if (sys->nvals != 2 || sys->wdtype != SS_F32)
+    return fail(SS_E_ARG, "ss_subsets_build: ordered subsets need a folded FP32 pair");
+  if (sys->m <= 0 || sys->n <= 0 || !sys->col_ptr || (sys->nnz > 0 && (!sys->row_idx || !sys->val_t)))
+    return fail(SS_E_ARG, "ss_subsets_build: bad system");
+  if (sub->S <= 0 || sub->S > sys->m || sys->m % sub->S != 0)
+    return fail(SS_E_ARG, "ss_subsets_build: S = %d must divide m = %lld", sub->S, (long long)sys->m);
+  if (!sub->col_sub || !sub->inv_col_sub) return fail(SS_E_ARG, "ss_subsets_build: NULL subset arrays");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned nb = static_cast<unsigned>(cdiv(sys->n, 256));
+  k_subsets_build<<<nb, 256, 0, st>>>(*sys, sub->S, static_cast<int32_t>(sys->m / sub->S), sub->col_sub,
+                                             sub->inv_col_sub);
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+extern "C" ss_status ss_ossart_workspace_bytes(const ss_system* sys, const ss_subsets* sub, int32_t nsys,
+                                               const ss_sart_opts* opts, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(SS_E_ARG, "ss_ossart_workspace_bytes: NULL bytes");
+  if (ss_status s = os_validate(sys, sub, nsys, opts, "ss_ossart_workspace_bytes")) return s;
+  *bytes = os_layout(sys, nsys).total;
+  return SS_OK;
+}
+
+extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub, int32_t nsys, float* const* f,
+                                     double* const* res_hist, const ss_sart_opts* opts, int32_t* passes,
+                                     void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (ss_status s = os_validate(sys, sub, nsys, opts, "ss_ossart_solve")) return s;
+  if (!f || !workspace) return fail(SS_E_ARG, "ss_ossart_solve: NULL images or workspace");
+  const int S = sub[0].S;
+  for (int s = 0; s < nsys; ++s) {
+    if (!f[s] || (res_hist && !res_hist[s])) return fail(SS_E_ARG, "ss_ossart_solve: NULL image %d", s);
+    if (sub[s].S != S) return fail(SS_E_ARG, "ss_ossart_solve: all systems must have the same S");
+  }
+  const OsLayout L = os_layout(sys, nsys);
+  if (workspace_bytes < L.total)
+    return fail(SS_E_WORKSPACE, "ss_ossart_solve: workspace needs %zu bytes", L.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const OsCfg c = os_cfg(opts);
+  // descriptors, grids and states
+  OsGrid g;
+  std::vector<OsDesc> ds(nsys);
+  const int64_t rows_blk = static_cast<int64_t>(c.rpw) * kOsWPB, cols_blk = static_cast<int64_t>(c.cpw) * kOsWPB;
+  int64_t acc[3] = {0, 0, 0};
+  for (int s = 0; s < nsys; ++s) {
+    const ss_system& Y = sys[s];
+    OsDesc& d = ds[s];
+    d = OsDesc{};
+    d.row_ptr = Y.row_ptr;
+    d.col_idx = Y.col_idx;
+    d.val = Y.val;
+    d.col_ptr = Y.col_ptr;
+    d.row_idx = Y.row_idx;
+    d.val_t = Y.val_t;
+    d.col_sub = sub[s].col_sub;
+    d.inv_col_sub = sub[s].inv_col_sub;
+    d.p = Y.p;
+    d.inv_row = Y.inv_row;
+    d.f = f[s];
+    d.z = reinterpret_cast<float*>(ws + L.z_off[s]);
+    d.res_hist = res_hist ? res_hist[s] : nullptr;
+    d.partials = reinterpret_cast<double*>(ws + L.part_off[s]);
+    d.st = reinterpret_cast<OsState*>(ws + L.states) + s;
+    d.m = Y.m;
+    d.n = Y.n;
+    d.S = S;
+    d.R = static_cast<int32_t>(Y.m / S);
+    const int64_t nb[3] = {cdiv(d.R, rows_blk), cdiv(Y.m, rows_blk), cdiv(Y.n, cols_blk)};
+    for (int k = 0; k < 3; ++k) {
+      d.blk0[k] = acc[k];
+      d.nblk[k] = static_cast<int32_t>(nb[k]);
+      acc[k] += nb[k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (acc[k] > static_cast<int64_t>(UINT32_MAX)) return fail(SS_E_ARG, "ss_ossart_solve: grid too large");
+    g.nb[k] = static_cast<uint32_t>(acc[k]);
+  }
+  for (int s0 = 0; s0 < nsys; s0 += kOsChunk) {
+    OsChunk ch{};
+    ch.first = s0;
+    ch.count = std::min(kOsChunk, nsys - s0);
+    ch.zero_start = opts->zero_start;
+    ch.prm = OsParams{opts->lambda, opts->max_iter, opts->tol};
+    for (int i = 0; i < ch.count; ++i) ch.d[i] = ds[s0 + i];
+    k_os_setup<<<ch.count, kOsThreads, 0, st>>>(ch, reinterpret_cast<OsDesc*>(ws + L.table),
+                                                  reinterpret_cast<OsParams*>(ws + L.params));
+  }
+  SS_HIP_TRY(hipGetLastError());
+  // max_iter passes and the residual of the final image: max_iter + 1 groups
+  const int64_t total = static_cast<int64_t>(opts->max_iter) + 1;
+  const int chunk = opts->tol > 0.0 ? static_cast<int>(std::min<int64_t>(opts->check_every, total))
+                                    : static_cast<int>(std::min<int64_t>(total, 32));
+  hipGraphExec_t exec = nullptr;
+  if (opts->use_graph) {
+    int dev = 0;
+    SS_HIP_TRY(hipGetDevice(&dev));
+    const OsKey key{dev, workspace, nsys, S, g.nb[0], g.nb[1], g.nb[2], c.rpw, c.cpw, c.xcd, c.u, c.ch, chunk};
+    if (ss_status s = os_graph(key, c, ws, L, g, &exec)) return s;
+  }
+  std::vector<OsState> hs(nsys);
+  auto read_states = [&]() -> ss_status {
+    SS_HIP_TRY(hipMemcpyAsync(hs.data(), ws + L.states, sizeof(OsState) * nsys, hipMemcpyDeviceToHost, st));
+    SS_HIP_TRY(hipStreamSynchronize(st));
+    return SS_OK;
+  };
+  for (int64_t done = 0; done < total; done += chunk) {
+    if (exec) {
+      SS_HIP_TRY(hipGraphLaunch(exec, st));
+    } else {
+      os_passes(c, ws, L, nsys, S, g, static_cast<int>(std::min<int64_t>(chunk, total - done)), st);
+      SS_HIP_TRY(hipGetLastError());
+    }
+    if (opts->tol > 0.0 && done + chunk < total) {
+      if (ss_status s = read_states()) return s;
+      bool all = true;
+      for (const auto& x : hs) all = all && x.stop;
+      if (all) break;
+    }
+  }
+  if (!passes && opts->tol <= 0.0) return SS_OK;
+  if (ss_status s = read_states()) return s;
+  ss_status result = SS_OK;
+  for (int s = 0; s < nsys; ++s) {
+    if (passes) passes[s] = hs[s].k;
+    if (opts->tol > 0.0 && !(hs[s].last_res <= opts->tol)) result = SS_NOT_CONVERGED;
+  }
+  return result;
+}

@@ -65,6 +65,10 @@ class SartOptsC(C.Structure):
                 ("unroll", C.c_int32), ("persistent", C.c_int32), ("chunked", C.c_int32)]
 
 
+class SubsetsC(C.Structure):
+    _fields_ = [("S", C.c_int32), ("col_sub", C.c_void_p), ("inv_col_sub", C.c_void_p)]
+
+
 _SIGNATURES = {
     "ss_last_error": (C.c_char_p, []),
     "ss_version": (C.c_char_p, []),
@@ -73,6 +77,12 @@ _SIGNATURES = {
     "ss_matrix_free": (None, [C.POINTER(MatrixC)]),
     "ss_snake_order": (C.c_int32, [C.POINTER(Grid), C.POINTER(C.c_int64)]),
     "ss_stream_len": (C.c_int64, [C.c_int64]),
+    "ss_subsets_build": (C.c_int32, [C.POINTER(SystemC), C.POINTER(SubsetsC), C.c_void_p]),
+    "ss_ossart_workspace_bytes": (C.c_int32, [C.POINTER(SystemC), C.POINTER(SubsetsC), C.c_int32,
+                                              C.POINTER(SartOptsC), C.POINTER(C.c_size_t)]),
+    "ss_ossart_solve": (C.c_int32, [C.POINTER(SystemC), C.POINTER(SubsetsC), C.c_int32, C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_void_p), C.POINTER(SartOptsC), C.POINTER(C.c_int32),
+                                    C.c_void_p, C.c_size_t, C.c_void_p]),
     "ss_fold_workspace_bytes": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "ss_recombine_batch": (C.c_int32, [C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
                                        C.c_int32, C.c_void_p]),
@@ -464,6 +474,62 @@ class Solver:
         self.opts.persistent = oc.persistent
         self.opts.chunked = oc.chunked
         return self.opts
+
+
+class Subsets:
+    """ss_subsets of one folded FP32 pair: S blocks of m/S folded rows (for
+    the symmetric scan, S = K/2 mirror-paired views)."""
+
+    def __init__(self, S: System, n_subsets: int):
+        import torch
+        self.S = int(n_subsets)
+        dev = S.p.device
+        self.col_sub = torch.empty(S.n * (self.S + 1), dtype=torch.int32, device=dev)
+        self.inv_col_sub = torch.empty(self.S * S.n, dtype=torch.float32, device=dev)
+        sc, bc = S.c(), self.c()
+        _check(lib().ss_subsets_build(C.byref(sc), C.byref(bc), _stream(dev)))
+
+    def c(self) -> SubsetsC:
+        return SubsetsC(self.S, _ptr(self.col_sub), _ptr(self.inv_col_sub))
+
+
+class OsSolver:
+    """Marshals ss_ossart_solve for fixed lists of systems and subsets,
+    owning the workspace.  Options as SartOptions, max_iter counting passes."""
+
+    def __init__(self, systems, subsets, opts: SartOptions | None = None):
+        import torch
+        self.systems = list(systems)
+        self.subsets = list(subsets)
+        assert len(self.systems) == len(self.subsets)
+        self.opts = opts or SartOptions()
+        self._arr = (SystemC * len(self.systems))(*[s.c() for s in self.systems])
+        self._sub = (SubsetsC * len(self.subsets))(*[b.c() for b in self.subsets])
+        nb = C.c_size_t()
+        oc = self.opts.c()
+        _check(lib().ss_ossart_workspace_bytes(self._arr, self._sub, len(self.systems), C.byref(oc), C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.systems[0].p.device)
+
+    def solve(self, f, res_hist=None, want_passes: bool = True):
+        """Runs ordered-subset SART in place on ``f``; returns (status, passes)."""
+        o = self.opts
+        oc = o.c()
+        assert len(f) == len(self.systems)
+        for s, t in zip(self.systems, f):
+            assert t.is_contiguous() and t.numel() == 2 * s.n and t.dtype.itemsize == 4
+        imgs = (C.c_void_p * len(f))(*[t.data_ptr() for t in f])
+        if res_hist is not None:
+            for h in res_hist:
+                assert h.numel() >= o.max_iter + 1 and h.dtype.itemsize == 8
+            rh = (C.c_void_p * len(res_hist))(*[h.data_ptr() for h in res_hist])
+        else:
+            rh = None
+        it = (C.c_int32 * len(self.systems))() if want_passes else None
+        st = lib().ss_ossart_solve(self._arr, self._sub, len(self.systems), imgs, rh, C.byref(oc), it,
+                                   _ptr(self.ws), self.ws_bytes, _stream(self.ws.device))
+        _check(st, allow_warning=True)
+        return st, (list(it) if it is not None else None)
 
 
 def recombine(f12, out=None):

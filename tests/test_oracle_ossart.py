@@ -101,3 +101,18 @@ def test_split_os_sart_equals_full_on_the_64x64_scan():
     # informative: ordered subsets lower the residual faster per pass than SART
     _, rr = sart.sart_full(A, p, 0.5, 6)
     assert res[6] < rr[6]
+
+
+def test_underdetermined_passes_settle_above_zero_residual():
+    """Documents the limit of ordered subsets with subset column weights: on a
+    consistent underdetermined system SART converges to a solution, the
+    two-subset passes settle at a fixed point of the pass map instead."""
+    rng = np.random.default_rng(0)
+    A = sp.csr_matrix(rng.uniform(0, 1, (40, 100)) * (rng.uniform(0, 1, (40, 100)) < 0.3))
+    p = A @ rng.uniform(0, 1, 100)
+    f, res = ossart.os_sart_full(A, p, 0.5, 3000, [np.arange(0, 20), np.arange(20, 40)])
+    _, rs = sart.sart_full(A, p, 0.5, 3000)
+    assert rs[-1] < 1e-12 and 1e-3 < res[-1] and abs(res[-1] - res[-500]) < 1e-12
+    # a fixed point of the pass map: one more pass leaves the image unchanged
+    f2, _ = ossart.os_sart_full(A, p, 0.5, 1, [np.arange(0, 20), np.arange(20, 40)], f0=f)
+    assert np.max(np.abs(f2 - f)) < 1e-10 * np.abs(f).max()
