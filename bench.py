@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--wdtype", choices=["f32", "bf16", "f16"], default="f32",
                     help="storage type of the split pair's weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-subsets", action="store_true", help="skip the ordered-subset comparison")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
     ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT,CHUNKED",
@@ -237,6 +238,11 @@ def main():
     out["split_vs_unsplit"] = ums / ms
     log(f"unsplit step {ums:.3f} ms; split/unsplit speedup {ums / ms:.2f}")
 
+    # ordered subsets (mirror-paired views) against SART, to rel_res 1e-2
+    if not args.no_subsets:
+        out["ordered_subsets"] = subsets_report(slices, systems, opts, dev, lam)
+        log(f"ordered subsets: {out['ordered_subsets']}")
+
     # time to relative residual 1e-3 (capped at 20000 iterations)
     ttr = {}
     if args.workload == "slice":
@@ -275,6 +281,38 @@ def time_to_tol(slv, img, dev, tol=1e-3, cap=20000):
     rec["us_per_iteration"] = rec["seconds"] * 1e6 / max(k, 1)
     o.max_iter, o.tol, o.check_every, o.zero_start = saved
     return rec
+
+
+def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
+    """Whole-batch time to rel_res <= tol from f0 = 0: SART iterations
+    against ordered-subset SART passes with S = K/2 mirror-paired views
+    (every system stops on its own; the solve ends when all have)."""
+    import numpy as np
+    import torch
+    from paper_1902_10559_amd import native
+    S_count = slices[0].geom.K // 2
+    subsets = [native.Subsets(S, S_count) for S in systems]
+    rep = {"subsets": S_count, "tol": tol, "cap": cap}
+    for name in ("sart", "os_sart"):
+        # the subset back projection picks its own lanes per column (1/S of
+        # each column per launch); the rest of the shape is the autotuned one
+        o = native.SartOptions(lam=lam, max_iter=cap, tol=tol, check_every=25, zero_start=True,
+                               rows_per_wave=opts.rows_per_wave,
+                               cols_per_wave=opts.cols_per_wave if name == "sart" else 0,
+                               xcd_remap=opts.xcd_remap, unroll=opts.unroll, chunked=opts.chunked)
+        slv = native.Solver(systems, o) if name == "sart" else native.OsSolver(systems, subsets, o)
+        imgs = [S.new_image() for S in systems]
+        slv.solve(imgs)                     # warm-up (graph capture)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        st, it = slv.solve(imgs)
+        e1.record()
+        torch.cuda.synchronize()
+        rep[name] = {"median_steps": float(np.median(it)), "max_steps": int(max(it)), "reached": bool(st == 0),
+                     "seconds": e0.elapsed_time(e1) * 1e-3}
+    rep["speedup"] = rep["sart"]["seconds"] / rep["os_sart"]["seconds"]
+    return rep
 
 
 def small_slice_time_to_tol(dev, lam):

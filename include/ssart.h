@@ -320,22 +320,33 @@ ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f,
  * mirror i -> M-1-i (the rays of sources k and K-1-k of the symmetric scan)
  * folds onto a block of rows; with rays ordered source-major, subset s of S
  * is the folded rows [s m/S, (s+1) m/S), and S must divide m.
- *   col_sub      device, n*(S+1) ints: column j's entries in subset s are
- *                col_ptr[j] + col_sub[j*(S+1)+s] .. col_ptr[j] +
- *                col_sub[j*(S+1)+s+1] - 1 (rows ascend, so they are
+ *   col_sub      device, (S+1)*n ints, subset-major: column j's entries
+ *                in subset s are col_ptr[j] + col_sub[s*n+j] .. col_ptr[j] +
+ *                col_sub[(s+1)*n+j] - 1 (rows ascend, so they are
  *                contiguous)
  *   inv_col_sub  device, S*n floats: FP32 reciprocal of the FP64 sum of
  *                A(2) over column j's entries in subset s (0 for a zero
  *                sum); it equals A's column sum over the mirror-closed
- *                subset. */
+ *                subset.
+ *   col_ptr_os, row_idx_os, val_t_os  a subset-major copy of the CSC: the
+ *                entries of column j in subset s are positions
+ *                col_ptr_os[s*n+j] .. col_ptr_os[s*n+j+1]-1 (device,
+ *                S*n+1 int64); row_idx_os (int32) and val_t_os (FP32
+ *                pairs) have room for ss_stream_len(nnz) entries and are
+ *                16-byte aligned.  A subset's back projection then streams
+ *                1/S of the entries. */
 typedef struct {
   int32_t S;
   int32_t* col_sub;
   float* inv_col_sub;
+  int64_t* col_ptr_os;
+  int32_t* row_idx_os;
+  void* val_t_os;
 } ss_subsets;
 
-/* Fills col_sub and inv_col_sub (caller-allocated) for a folded FP32 pair
- * (nvals = 2, wdtype = SS_F32).  Asynchronous. */
+/* Fills every array of `sub` (caller-allocated) for a folded FP32 pair
+ * (nvals = 2, wdtype = SS_F32).  SYNCHRONISES the stream once (the
+ * subset-major offsets are scanned on the host). */
 ss_status ss_subsets_build(const ss_system* sys, ss_subsets* sub, void* stream);
 
 /* Workspace bytes for ss_ossart_solve on these systems. */
@@ -347,7 +358,8 @@ ss_status ss_ossart_workspace_bytes(const ss_system* sys, const ss_subsets* sub,
  * applies, for s = 0 .. S-1, f <- f + lambda V_s^-1 A_s^T W^-1 (p_s - A_s f)
  * to both halves, V_s the subset column sums; recombined by eq. (5) the
  * iterates are ordered-subset SART on A with the mirror-closed subsets.
- * Options as for ss_sart_solve, with max_iter counting passes; `persistent`
+ * Options as for ss_sart_solve, with max_iter counting passes and
+ * cols_per_wave up to 64 (a subset sees 1/S of each column); `persistent`
  * is ignored.  res_hist[s][k] = rel_res of the image after k passes, for
  * k = 0 .. passes[s] (max_iter + 1 doubles); passes (host, or NULL)
  * receives the passes applied.  Every pass evaluates the residual of its

@@ -16,8 +16,10 @@
 // of every row, FP64 partials per block), its finalisation (history entry,
 // stop decision, pass counter), then for each subset a forward kernel over
 // its rows (z = W^-1 (p - A f)) and a back projection over every column,
-// reading only the column's entries in that subset (a contiguous range of
-// the CSC, located by `col_sub`) and updating f in place: each column
+// reading only the column's entries in that subset from a subset-major copy
+// of the CSC (all columns' entries of subset s are contiguous, so a launch
+// streams 1/S of the entries instead of touching every column's cache lines
+// S times per pass), and updating f in place: each column
 // belongs to one lane group, and the next subset's kernel starts after this
 // one has ended.  A stop decided by the finalisation is read by every later
 // kernel of the pass, so a stopped system's image is f^k exactly.
@@ -53,7 +55,9 @@ struct OsDesc {
   const int64_t* col_ptr;
   const int32_t* row_idx;
   const void* val_t;
-  const int32_t* col_sub;
+  const int64_t* col_ptr_os;   // subset-major CSC: subset s, column j at s*n + j
+  const int32_t* row_idx_os;
+  const void* val_t_os;
   const float* inv_col_sub;
   const float* p;
   const float* inv_row;
@@ -85,24 +89,23 @@ struct OsChunk {
   int32_t zero_start;
 };
 
+// The system and block-local index of grid block b (uniform per block),
+// from a block -> system table filled at set-up: the blocks of these
+// kernels carry little work, so one lookup load beats a binary search.
 template <int G>
-__device__ inline int os_find(const OsDesc* t, int nsys, int64_t b) {
-  int lo = 0, hi = nsys - 1;
-  while (lo < hi) {
-    const int mid = __builtin_amdgcn_readfirstlane((lo + hi + 1) >> 1);
-    if (t[mid].blk0[G] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return __builtin_amdgcn_readfirstlane(lo);
-}
-
-// The system and block-local index of grid block b (uniform per block).
-template <int G>
-__device__ inline int os_block(const OsDesc* t, int nsys, uint32_t ntiles, int xcd, int64_t* local) {
+__device__ inline int os_block(const OsDesc* t, const int32_t* b2s, int nsys, uint32_t ntiles, int xcd,
+                               int64_t* local) {
   const uint32_t b = __builtin_amdgcn_readfirstlane(xcd ? xcd_remap(blockIdx.x, ntiles) : blockIdx.x);
-  const int s = nsys == 1 ? 0 : os_find<G>(t, nsys, b);
+  const int s = nsys == 1 ? 0 : __builtin_amdgcn_readfirstlane(gl(b2s)[b]);
   *local = static_cast<int64_t>(b) - t[s].blk0[G];
   return s;
+}
+
+__global__ void k_os_blk2sys(const OsDesc* t, int32_t* b0, int32_t* b1, int32_t* b2) {
+  const OsDesc& d = t[blockIdx.x];
+  int32_t* out[3] = {b0, b1, b2};
+  for (int k = 0; k < 3; ++k)
+    for (int64_t i = threadIdx.x; i < d.nblk[k]; i += blockDim.x) out[k][d.blk0[k] + i] = blockIdx.x;
 }
 
 __global__ __launch_bounds__(kOsThreads) void k_os_setup(OsChunk ch, OsDesc* table, OsParams* prm) {
@@ -130,13 +133,14 @@ __global__ __launch_bounds__(kOsThreads) void k_os_setup(OsChunk ch, OsDesc* tab
 // RES: FP64 partial of |p - A f|^2 per block into `partials`; otherwise
 // z = W^-1 (p - A f).
 template <int WT, int RPW, int U, bool CH, bool RES>
-__global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsDesc* __restrict__ table, int nsys, uint32_t ntiles,
+__global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsDesc* __restrict__ table,
+                                                      const int32_t* __restrict__ b2s, int nsys, uint32_t ntiles,
                                                       int xcd, int sub) {
   constexpr int L = kWave / RPW;
   __shared__ double red[kOsWPB];
   if (blockIdx.x >= ntiles) return;
   int64_t local;
-  const int si = os_block<RES ? kAllRows : kSubRows>(table, nsys, ntiles, xcd, &local);
+  const int si = os_block<RES ? kAllRows : kSubRows>(table, b2s, nsys, ntiles, xcd, &local);
   const OsDesc& S = table[si];
   if (*gl(&S.st->stop)) return;
   const int64_t r0 = RES ? 0 : static_cast<int64_t>(sub) * S.R;
@@ -188,26 +192,26 @@ __global__ __launch_bounds__(kOsThreads) void k_os_fin(const OsDesc* __restrict_
 // Back projection of subset `sub` and the in-place update, column by column.
 template <int WT, int CPW, int U, bool CH>
 __global__ __launch_bounds__(kOsThreads) void k_os_bp(const OsParams* __restrict__ prm,
-                                                      const OsDesc* __restrict__ table, int nsys, uint32_t ntiles,
+                                                      const OsDesc* __restrict__ table,
+                                                      const int32_t* __restrict__ b2s, int nsys, uint32_t ntiles,
                                                       int xcd, int sub) {
   constexpr int L = kWave / CPW;
   if (blockIdx.x >= ntiles) return;
   int64_t local;
-  const int si = os_block<kCols>(table, nsys, ntiles, xcd, &local);
+  const int si = os_block<kCols>(table, b2s, nsys, ntiles, xcd, &local);
   const OsDesc& S = table[si];
   if (*gl(&S.st->stop)) return;
   const int glane = lane_id() % L;
   const int64_t col = local * (CPW * kOsWPB) + wave_id() * CPW + lane_id() / L;
   const bool in = col < S.n;
   const int64_t ci = in ? col : S.n - 1;
-  const int32_t* cs = S.col_sub + ci * (S.S + 1) + sub;
-  const int64_t base = gl(S.col_ptr)[ci];
-  const int64_t lo = base + gl(cs)[0];
-  const int64_t hi = in ? base + gl(cs)[1] : lo;
+  const int64_t* cp = S.col_ptr_os + static_cast<int64_t>(sub) * S.n + ci;
+  const int64_t lo = gl(cp)[0];
+  const int64_t hi = in ? gl(cp)[1] : lo;
   Vec<2> fv = load_vec<2>(S.f, ci);
   const float tl = prm->lambda * gl(S.inv_col_sub)[static_cast<int64_t>(sub) * S.n + ci];
   float acc[2] = {0.0f, 0.0f};
-  line_dot<2, WT, L, U, CH>(S.row_idx, S.val_t, S.z, lo, hi, glane, acc);
+  line_dot<2, WT, L, U, CH>(S.row_idx_os, S.val_t_os, S.z, lo, hi, glane, acc);
   acc[0] = group_sum<L>(acc[0]);
   acc[1] = group_sum<L>(acc[1]);
   if (glane == 0 && in) {
@@ -227,13 +231,32 @@ __global__ void k_subsets_build(ss_system sys, int32_t S, int32_t R, int32_t* co
   const int64_t base = sys.col_ptr[j], end = sys.col_ptr[j + 1];
   int64_t e = base;
   for (int s = 0; s < S; ++s) {
-    col_sub[j * (S + 1) + s] = static_cast<int32_t>(e - base);
+    col_sub[static_cast<int64_t>(s) * sys.n + j] = static_cast<int32_t>(e - base);
     const int64_t lim = static_cast<int64_t>(s + 1) * R;
     double sum = 0.0;
     for (; e < end && sys.row_idx[e] < lim; ++e) sum += static_cast<double>(v[2 * e + 1]);
     inv_col_sub[static_cast<int64_t>(s) * sys.n + j] = sum != 0.0 ? static_cast<float>(1.0 / sum) : 0.0f;
   }
-  col_sub[j * (S + 1) + S] = static_cast<int32_t>(e - base);
+  col_sub[static_cast<int64_t>(S) * sys.n + j] = static_cast<int32_t>(e - base);
+}
+
+// Copies each column's subset ranges into the subset-major CSC.
+__global__ void k_subsets_scatter(ss_system sys, int32_t S, const int32_t* col_sub, const int64_t* col_ptr_os,
+                                  int32_t* row_idx_os, float* val_t_os) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= sys.n) return;
+  const int64_t base = sys.col_ptr[j];
+  const float* v = static_cast<const float*>(sys.val_t);
+  for (int s = 0; s < S; ++s) {
+    const int64_t a = base + col_sub[static_cast<int64_t>(s) * sys.n + j];
+    const int64_t b = base + col_sub[static_cast<int64_t>(s + 1) * sys.n + j];
+    int64_t o = col_ptr_os[static_cast<int64_t>(s) * sys.n + j];
+    for (int64_t e = a; e < b; ++e, ++o) {
+      row_idx_os[o] = sys.row_idx[e];
+      val_t_os[2 * o] = v[2 * e];
+      val_t_os[2 * o + 1] = v[2 * e + 1];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ host
@@ -242,7 +265,7 @@ struct OsCfg {
 };
 
 struct OsLayout {
-  size_t params, table, states, total;
+  size_t params, table, states, b2s[3], total;
   std::vector<size_t> z_off, part_off;
 };
 
@@ -257,6 +280,17 @@ OsLayout os_layout(const ss_system* sys, int nsys) {
   o += al256(sizeof(OsDesc) * nsys);
   L.states = o;
   o += al256(sizeof(OsState) * nsys);
+  // block -> system tables, sized for the smallest tiles (one line per wave)
+  int64_t nb[3] = {0, 0, 0};
+  for (int s = 0; s < nsys; ++s) {
+    nb[0] += (sys[s].m + kOsWPB - 1) / kOsWPB;  // a subset has at most m rows
+    nb[1] += (sys[s].m + kOsWPB - 1) / kOsWPB;
+    nb[2] += (sys[s].n + kOsWPB - 1) / kOsWPB;
+  }
+  for (int k = 0; k < 3; ++k) {
+    L.b2s[k] = o;
+    o += al256(sizeof(int32_t) * static_cast<size_t>(nb[k]));
+  }
   for (int s = 0; s < nsys; ++s) {
     L.z_off.push_back(o);
     o += al256(sizeof(float) * 2 * static_cast<size_t>(sys[s].m));
@@ -284,24 +318,50 @@ ss_status os_validate(const ss_system* sys, const ss_subsets* sub, int nsys, con
     if (Y.nnz > 0 && !(aligned(Y.col_idx) && aligned(Y.val) && aligned(Y.row_idx) && aligned(Y.val_t)))
       return fail(SS_E_ARG, "%s: system %d: index and value arrays must be 16-byte aligned", fn, s);
     const ss_subsets& B = sub[s];
-    if (B.S <= 0 || B.S > Y.m || Y.m % B.S != 0 || !B.col_sub || !B.inv_col_sub)
+    if (B.S <= 0 || B.S > Y.m || Y.m % B.S != 0 || !B.col_sub || !B.inv_col_sub || !B.col_ptr_os ||
+        (Y.nnz > 0 && (!B.row_idx_os || !B.val_t_os)))
       return fail(SS_E_ARG, "%s: system %d: S must divide m and the subset arrays be set", fn, s);
+    if (Y.nnz > 0 && !(aligned(B.row_idx_os) && aligned(B.val_t_os)))
+      return fail(SS_E_ARG, "%s: system %d: subset CSC arrays must be 16-byte aligned", fn, s);
   }
   if (!(o->lambda > 0.0f && o->lambda < 2.0f)) return fail(SS_E_ARG, "%s: lambda must be in (0, 2)", fn);
   if (o->max_iter < 0 || o->max_iter > (1 << 30)) return fail(SS_E_ARG, "%s: bad max_iter", fn);
   if (o->tol > 0.0 && o->check_every <= 0) return fail(SS_E_ARG, "%s: check_every must be > 0", fn);
   auto ok_pw = [](int v, int maxv) { return v == 0 || (v > 0 && v <= maxv && (v & (v - 1)) == 0); };
-  if (!ok_pw(o->rows_per_wave, 8) || !ok_pw(o->cols_per_wave, 16))
-    return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8 and cols_per_wave 0,1,..,16", fn);
+  if (!ok_pw(o->rows_per_wave, 8) || !ok_pw(o->cols_per_wave, 64))
+    return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8 and cols_per_wave 0,1,..,64", fn);
   if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
   if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
   return SS_OK;
 }
 
-OsCfg os_cfg(const ss_sart_opts* o) {
+// Lanes per line from the mean line length: the smallest power of two of
+// lines per wavefront whose lanes still cover ~48 entries.
+int os_per_wave(double mean_len, int maxv) {
+  int v = 1;
+  while (v < maxv && mean_len * v < 48.0) v <<= 1;
+  return v;
+}
+
+// Defaults from the statistics of the systems: a subset back projection sees
+// only 1/S of each column, so it packs more columns into a wavefront than
+// the full back projection does.
+OsCfg os_cfg(const ss_system* sys, int nsys, int S, const ss_sart_opts* o) {
+  double nnz = 0, m = 0, n = 0;
+  for (int s = 0; s < nsys; ++s) {
+    nnz += static_cast<double>(sys[s].nnz);
+    m += static_cast<double>(sys[s].m);
+    n += static_cast<double>(sys[s].n);
+  }
   OsCfg c;
-  c.rpw = o->rows_per_wave ? o->rows_per_wave : 4;
-  c.cpw = o->cols_per_wave ? o->cols_per_wave : 8;
+  c.rpw = o->rows_per_wave ? o->rows_per_wave : os_per_wave(nnz / m, 8);
+  // a subset holds ~1/S of each column: few entries, so few lanes per column
+  // (measured on the 256-slice batch, S = 12, ~3 entries: one lane per
+  // column, 5.2 ms per pass, against 8.1 ms with four)
+  const double sub_len = nnz / (n * S);
+  int lanes = 1;
+  while (lanes < kWave && lanes * 4 < sub_len) lanes <<= 1;
+  c.cpw = o->cols_per_wave ? o->cols_per_wave : kWave / lanes;
   c.xcd = o->xcd_remap ? 1 : 0;
   c.u = o->unroll ? o->unroll : 4;
   c.ch = o->chunked;
@@ -315,42 +375,45 @@ struct OsGrid {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <int WT, int U, bool CH, bool RES>
-void os_fp_rpw(int rpw, const OsDesc* t, int nsys, uint32_t nb, int xcd, int sub, hipStream_t st) {
+void os_fp_rpw(int rpw, const OsDesc* t, const int32_t* b2s, int nsys, uint32_t nb, int xcd, int sub,
+               hipStream_t st) {
   const dim3 g(nb), b(kOsThreads);
   switch (rpw) {
-    case 1: k_os_fp<WT, 1, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
-    case 2: k_os_fp<WT, 2, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
-    case 4: k_os_fp<WT, 4, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
-    default: k_os_fp<WT, 8, U, CH, RES><<<g, b, 0, st>>>(t, nsys, nb, xcd, sub); break;
+    case 1: k_os_fp<WT, 1, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
+    case 2: k_os_fp<WT, 2, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
+    case 4: k_os_fp<WT, 4, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
+    default: k_os_fp<WT, 8, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
   }
 }
 
 template <int WT, int U, bool CH>
-void os_bp_cpw(int cpw, const OsParams* prm, const OsDesc* t, int nsys, uint32_t nb, int xcd, int sub,
-               hipStream_t st) {
+void os_bp_cpw(int cpw, const OsParams* prm, const OsDesc* t, const int32_t* b2s, int nsys, uint32_t nb, int xcd,
+               int sub, hipStream_t st) {
   const dim3 g(nb), b(kOsThreads);
   switch (cpw) {
-    case 1: k_os_bp<WT, 1, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
-    case 2: k_os_bp<WT, 2, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
-    case 4: k_os_bp<WT, 4, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
-    case 8: k_os_bp<WT, 8, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
-    default: k_os_bp<WT, 16, U, CH><<<g, b, 0, st>>>(prm, t, nsys, nb, xcd, sub); break;
+    case 1: k_os_bp<WT, 1, U, CH><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 2: k_os_bp<WT, 2, U, CH><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 4: k_os_bp<WT, 4, U, CH><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 8: k_os_bp<WT, 8, U, CH><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 16: k_os_bp<WT, 16, U, CH><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 32: k_os_bp<WT, 32, U, CH><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    default: k_os_bp<WT, 64, U, CH><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
   }
 }
 
 // One pass group: residual, finalisation, then the S subset updates.
 template <int U>
-void os_pass(const OsCfg& c, const OsParams* prm, const OsDesc* t, int nsys, int S, const OsGrid& g,
-             hipStream_t st) {
+void os_pass(const OsCfg& c, const OsParams* prm, const OsDesc* t, const int32_t* const* b2s, int nsys, int S,
+             const OsGrid& g, hipStream_t st) {
   const bool fch = c.ch & 1, bch = c.ch & 2;
-  if (fch) os_fp_rpw<SS_F32, U, true, true>(c.rpw, t, nsys, g.nb[kAllRows], c.xcd, 0, st);
-  else os_fp_rpw<SS_F32, U, false, true>(c.rpw, t, nsys, g.nb[kAllRows], c.xcd, 0, st);
+  if (fch) os_fp_rpw<SS_F32, U, true, true>(c.rpw, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
+  else os_fp_rpw<SS_F32, U, false, true>(c.rpw, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
   k_os_fin<<<nsys, kOsThreads, 0, st>>>(t, prm);
   for (int s = 0; s < S; ++s) {
-    if (fch) os_fp_rpw<SS_F32, U, true, false>(c.rpw, t, nsys, g.nb[kSubRows], c.xcd, s, st);
-    else os_fp_rpw<SS_F32, U, false, false>(c.rpw, t, nsys, g.nb[kSubRows], c.xcd, s, st);
-    if (bch) os_bp_cpw<SS_F32, U, true>(c.cpw, prm, t, nsys, g.nb[kCols], c.xcd, s, st);
-    else os_bp_cpw<SS_F32, U, false>(c.cpw, prm, t, nsys, g.nb[kCols], c.xcd, s, st);
+    if (fch) os_fp_rpw<SS_F32, U, true, false>(c.rpw, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
+    else os_fp_rpw<SS_F32, U, false, false>(c.rpw, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
+    if (bch) os_bp_cpw<SS_F32, U, true>(c.cpw, prm, t, b2s[kCols], nsys, g.nb[kCols], c.xcd, s, st);
+    else os_bp_cpw<SS_F32, U, false>(c.cpw, prm, t, b2s[kCols], nsys, g.nb[kCols], c.xcd, s, st);
   }
 }
 
@@ -358,9 +421,12 @@ void os_passes(const OsCfg& c, const char* ws, const OsLayout& L, int nsys, int 
                hipStream_t st) {
   const OsParams* prm = reinterpret_cast<const OsParams*>(ws + L.params);
   const OsDesc* t = reinterpret_cast<const OsDesc*>(ws + L.table);
+  const int32_t* b2s[3] = {reinterpret_cast<const int32_t*>(ws + L.b2s[0]),
+                           reinterpret_cast<const int32_t*>(ws + L.b2s[1]),
+                           reinterpret_cast<const int32_t*>(ws + L.b2s[2])};
   for (int i = 0; i < count; ++i) {
-    if (c.u == 8) os_pass<8>(c, prm, t, nsys, S, g, st);
-    else os_pass<4>(c, prm, t, nsys, S, g, st);
+    if (c.u == 8) os_pass<8>(c, prm, t, b2s, nsys, S, g, st);
+    else os_pass<4>(c, prm, t, b2s, nsys, S, g, st);
   }
 }
 
@@ -436,12 +502,34 @@ extern "C" ss_status ss_subsets_build(const ss_system* sys, ss_subsets* sub, voi
     return fail(SS_E_ARG, "ss_subsets_build: bad system");
   if (sub->S <= 0 || sub->S > sys->m || sys->m % sub->S != 0)
     return fail(SS_E_ARG, "ss_subsets_build: S = %d must divide m = %lld", sub->S, (long long)sys->m);
-  if (!sub->col_sub || !sub->inv_col_sub) return fail(SS_E_ARG, "ss_subsets_build: NULL subset arrays");
+  if (!sub->col_sub || !sub->inv_col_sub || !sub->col_ptr_os || (sys->nnz > 0 && (!sub->row_idx_os || !sub->val_t_os)))
+    return fail(SS_E_ARG, "ss_subsets_build: NULL subset arrays");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const int S = sub->S;
   const unsigned nb = static_cast<unsigned>(cdiv(sys->n, 256));
-  k_subsets_build<<<nb, 256, 0, st>>>(*sys, sub->S, static_cast<int32_t>(sys->m / sub->S), sub->col_sub,
-                                             sub->inv_col_sub);
+  k_subsets_build<<<nb, 256, 0, st>>>(*sys, S, static_cast<int32_t>(sys->m / S), sub->col_sub, sub->inv_col_sub);
   SS_HIP_TRY(hipGetLastError());
+  // offsets of the subset-major CSC: an exclusive scan, subset by subset,
+  // of the per-column counts (on the host: set-up work, done once)
+  const size_t cells = static_cast<size_t>(S + 1) * static_cast<size_t>(sys->n);
+  std::vector<int32_t> cs(cells);
+  SS_HIP_TRY(hipMemcpyAsync(cs.data(), sub->col_sub, sizeof(int32_t) * cells, hipMemcpyDeviceToHost, st));
+  SS_HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int64_t> cp(static_cast<size_t>(S) * sys->n + 1);
+  int64_t acc = 0;
+  for (int s = 0; s < S; ++s)
+    for (int64_t j = 0; j < sys->n; ++j) {
+      cp[static_cast<size_t>(s) * sys->n + j] = acc;
+      acc += cs[static_cast<size_t>(s + 1) * sys->n + j] - cs[static_cast<size_t>(s) * sys->n + j];
+    }
+  cp.back() = acc;
+  if (acc != sys->nnz) return fail(SS_E_SHAPE, "ss_subsets_build: subset counts do not add up to nnz");
+  SS_HIP_TRY(hipMemcpy(sub->col_ptr_os, cp.data(), sizeof(int64_t) * cp.size(), hipMemcpyHostToDevice));
+  if (sys->nnz > 0) {
+    k_subsets_scatter<<<nb, 256, 0, st>>>(*sys, S, sub->col_sub, sub->col_ptr_os, sub->row_idx_os,
+                                          static_cast<float*>(sub->val_t_os));
+    SS_HIP_TRY(hipGetLastError());
+  }
   return SS_OK;
 }
 
@@ -470,7 +558,7 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     return fail(SS_E_WORKSPACE, "ss_ossart_solve: workspace needs %zu bytes", L.total);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  const OsCfg c = os_cfg(opts);
+  const OsCfg c = os_cfg(sys, nsys, S, opts);
   // descriptors, grids and states
   OsGrid g;
   std::vector<OsDesc> ds(nsys);
@@ -486,7 +574,9 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     d.col_ptr = Y.col_ptr;
     d.row_idx = Y.row_idx;
     d.val_t = Y.val_t;
-    d.col_sub = sub[s].col_sub;
+    d.col_ptr_os = sub[s].col_ptr_os;
+    d.row_idx_os = sub[s].row_idx_os;
+    d.val_t_os = sub[s].val_t_os;
     d.inv_col_sub = sub[s].inv_col_sub;
     d.p = Y.p;
     d.inv_row = Y.inv_row;
@@ -520,6 +610,11 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     k_os_setup<<<ch.count, kOsThreads, 0, st>>>(ch, reinterpret_cast<OsDesc*>(ws + L.table),
                                                   reinterpret_cast<OsParams*>(ws + L.params));
   }
+  if (nsys > 1)
+    k_os_blk2sys<<<nsys, 256, 0, st>>>(reinterpret_cast<const OsDesc*>(ws + L.table),
+                                       reinterpret_cast<int32_t*>(ws + L.b2s[0]),
+                                       reinterpret_cast<int32_t*>(ws + L.b2s[1]),
+                                       reinterpret_cast<int32_t*>(ws + L.b2s[2]));
   SS_HIP_TRY(hipGetLastError());
   // max_iter passes and the residual of the final image: max_iter + 1 groups
   const int64_t total = static_cast<int64_t>(opts->max_iter) + 1;

@@ -66,7 +66,8 @@ class SartOptsC(C.Structure):
 
 
 class SubsetsC(C.Structure):
-    _fields_ = [("S", C.c_int32), ("col_sub", C.c_void_p), ("inv_col_sub", C.c_void_p)]
+    _fields_ = [("S", C.c_int32), ("col_sub", C.c_void_p), ("inv_col_sub", C.c_void_p),
+                ("col_ptr_os", C.c_void_p), ("row_idx_os", C.c_void_p), ("val_t_os", C.c_void_p)]
 
 
 _SIGNATURES = {
@@ -486,11 +487,15 @@ class Subsets:
         dev = S.p.device
         self.col_sub = torch.empty(S.n * (self.S + 1), dtype=torch.int32, device=dev)
         self.inv_col_sub = torch.empty(self.S * S.n, dtype=torch.float32, device=dev)
+        self.col_ptr_os = torch.empty(self.S * S.n + 1, dtype=torch.int64, device=dev)
+        self.row_idx_os = stream_tensor(S.nnz, 1, torch.int32, dev)
+        self.val_t_os = stream_tensor(S.nnz, 2, torch.float32, dev)
         sc, bc = S.c(), self.c()
         _check(lib().ss_subsets_build(C.byref(sc), C.byref(bc), _stream(dev)))
 
     def c(self) -> SubsetsC:
-        return SubsetsC(self.S, _ptr(self.col_sub), _ptr(self.inv_col_sub))
+        return SubsetsC(self.S, _ptr(self.col_sub), _ptr(self.inv_col_sub), _ptr(self.col_ptr_os),
+                        _ptr(self.row_idx_os), _ptr(self.val_t_os))
 
 
 class OsSolver:

@@ -52,13 +52,28 @@ def test_subset_ranges_and_sums_match_the_oracle():
     B = native.Subsets(S, nsub)
     Sp = OSp.fold(pr.A)
     R = Sp.m // nsub
-    cs = to_np(B.col_sub).reshape(S.n, nsub + 1)
+    cs = to_np(B.col_sub).reshape(nsub + 1, S.n).T
     inv = to_np(B.inv_col_sub).reshape(nsub, S.n)
     A2 = Sp.v2.astype(np.float64)
     for j in range(S.n):
         rows = Sp.cindices[Sp.cindptr[j]:Sp.cindptr[j + 1]]
         want = np.searchsorted(rows, np.arange(nsub + 1) * R)
         assert np.array_equal(cs[j], want)
+    # the subset-major CSC holds, for subset s and column j, exactly the
+    # column's entries with rows in subset s, in ascending row order
+    cp = to_np(B.col_ptr_os)
+    ri = to_np(B.row_idx_os)
+    vt = to_np(B.val_t_os).reshape(-1, 2)
+    assert cp[0] == 0 and cp[-1] == Sp.nnz
+    for s_ in range(nsub):
+        for j in range(0, S.n, 7):
+            a, b = Sp.cindptr[j], Sp.cindptr[j + 1]
+            rows = Sp.cindices[a:b]
+            keep = (rows >= s_ * R) & (rows < (s_ + 1) * R)
+            lo, hi = cp[s_ * S.n + j], cp[s_ * S.n + j + 1]
+            assert np.array_equal(ri[lo:hi], rows[keep])
+            assert np.array_equal(vt[lo:hi, 0].astype(np.float32), Sp.cv1[a:b][keep].astype(np.float32))
+            assert np.array_equal(vt[lo:hi, 1].astype(np.float32), Sp.cv2[a:b][keep].astype(np.float32))
     import scipy.sparse as sp
     A2m = sp.csr_matrix((A2, Sp.indices, Sp.indptr), shape=(Sp.m, Sp.n))
     for s in range(nsub):
