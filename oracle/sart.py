@@ -26,6 +26,14 @@ so the relative residual of the full system can be tracked on the halves.
 
 ``res[k]`` is ||p - A f^k|| / ||p|| for k = 0..iters (f^k before the k-th
 update; res[iters] belongs to the returned image).
+
+Non-negativity (``nonneg``): after every update the image is projected onto
+f >= 0, i.e. every voxel is clamped at 0 (the Euclidean projection onto the
+non-negative orthant).  On the split pair, voxels j and N-1-j are
+f_j = (f2_j + f1_j) / 2 and f_{N-1-j} = (f2_j - f1_j) / 2 by eq. (5), so the
+same projection is: clamp both at 0 and map back, f1 = a - b, f2 = a + b.  It
+couples the two halves voxel pair by voxel pair only (f2_j >= |f1_j|), and
+the split iterates stay exactly the full ones.
 """
 from __future__ import annotations
 
@@ -35,7 +43,14 @@ import scipy.sparse as sp
 from .split import Split, reciprocal
 
 
-def sart_full(A: sp.csr_matrix, p, lam: float, iters: int, f0=None, sums=None):
+def nonneg_pair(f1, f2):
+    """The projection onto f >= 0 in split coordinates (see the header)."""
+    a = np.maximum(0.5 * (f2 + f1), 0.0)
+    b = np.maximum(0.5 * (f2 - f1), 0.0)
+    return a - b, a + b
+
+
+def sart_full(A: sp.csr_matrix, p, lam: float, iters: int, f0=None, sums=None, nonneg=False):
     """``sums`` = (W, V) overrides the row and column sums of A; the 16-bit
     storage variant keeps the sums of the FP32 weights while iterating with
     the rounded ones."""
@@ -53,11 +68,13 @@ def sart_full(A: sp.csr_matrix, p, lam: float, iters: int, f0=None, sums=None):
         r = p - A @ f
         res[k] = np.linalg.norm(r) / pn
         f = f + lam * invV * (At @ (invW * r))
+        if nonneg:
+            f = np.maximum(f, 0.0)
     res[iters] = np.linalg.norm(p - A @ f) / pn
     return f, res
 
 
-def sart_split(S: Split, p1, p2, lam: float, iters: int, f10=None, f20=None):
+def sart_split(S: Split, p1, p2, lam: float, iters: int, f10=None, f20=None, nonneg=False):
     A1 = sp.csr_matrix((S.v1.astype(np.float64), S.indices, S.indptr),
                        shape=(S.m, S.n))
     A2 = sp.csr_matrix((S.v2.astype(np.float64), S.indices, S.indptr),
@@ -77,6 +94,8 @@ def sart_split(S: Split, p1, p2, lam: float, iters: int, f10=None, f20=None):
         res[k] = np.sqrt(0.5 * (r1 @ r1 + r2 @ r2)) / pn
         f1 = f1 + lam * invV * (A1t @ (invW * r1))
         f2 = f2 + lam * invV * (A2t @ (invW * r2))
+        if nonneg:
+            f1, f2 = nonneg_pair(f1, f2)
     r1 = p1 - A1 @ f1
     r2 = p2 - A2 @ f2
     res[iters] = np.sqrt(0.5 * (r1 @ r1 + r2 @ r2)) / pn

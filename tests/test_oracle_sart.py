@@ -130,3 +130,37 @@ def test_explicit_sums_equal_default_sums_when_they_are_the_matrix_sums():
     # and they matter: scaled sums give a different iterate
     h, _ = sart.sart_full(A, p, 0.5, 15, sums=(2 * W, V))
     assert np.max(np.abs(h - f)) > 1e-3 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("lam", [0.5, 1.2])
+def test_nonnegative_identity_system_closed_form(lam):
+    """A = I: a voxel with p_j < 0 stays at 0 (every step would go
+    negative), the others follow the unconstrained closed form."""
+    p = np.array([0.7, -0.4, 1.3, -2.0, 0.0, 0.25])
+    A = sp.identity(6, format="csr")
+    for k in (1, 2, 9):
+        f, _ = sart.sart_full(A, p, lam, k, nonneg=True)
+        want = np.where(p > 0, (1 - (1 - lam) ** k) * p, 0.0)
+        assert np.allclose(f, want, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_nonnegative_split_sart_equals_clamped_full_sart(seed):
+    A, p = _random_problem(seed)            # inconsistent data: the clamp is active
+    S = split.fold(A)
+    p1, p2 = split.fold_p(p)
+    f, res = sart.sart_full(A, p, 0.5, 40, nonneg=True)
+    f_free, _ = sart.sart_full(A, p, 0.5, 40)
+    assert f.min() >= 0.0 and f_free.min() < -1e-3      # the constraint binds
+    f1, f2, res_s = sart.sart_split(S, p1, p2, 0.5, 40, nonneg=True)
+    assert np.max(np.abs(res - res_s)) < 1e-13
+    assert np.max(np.abs(split.recombine(f1, f2) - f)) < 1e-12 * np.abs(f).max()
+    assert np.all(f2 >= np.abs(f1) - 1e-15)
+
+
+def test_nonneg_pair_is_the_clamp_of_the_recombined_image():
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal(20)
+    f1, f2 = split.image_fold(f)
+    g1, g2 = sart.nonneg_pair(f1, f2)
+    assert np.allclose(split.recombine(g1, g2), np.maximum(f, 0.0), atol=1e-15)
