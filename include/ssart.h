@@ -249,6 +249,10 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *   zero_start   1: start from f^0 = 0 (the solver clears f itself);
  *                0: start from the image the caller passes
  *   unroll       entries each lane has in flight per pass: 4 or 8 (0 = 4)
+ *   nonneg       1: project every updated image onto f >= 0 (each voxel
+ *                of the full image clamped at 0; on the folded pair the
+ *                equivalent map of each pair (f1, f2) with eq. (5), which
+ *                keeps f2 >= |f1|)
  *   chunked      stream form per kernel, bit 0 forward, bit 1 back
  *                projection: 0 = entry-wise (lanes of a group hold adjacent
  *                entries), 1 = aligned chunks of SS_CHUNK entries per lane
@@ -271,6 +275,7 @@ typedef struct {
   int32_t unroll;
   int32_t persistent;
   int32_t chunked;
+  int32_t nonneg;
 } ss_sart_opts;
 
 /* Workspace bytes for solving `nsys` systems together with these options. */

@@ -39,6 +39,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
+from .sart import nonneg_pair
 from .split import Split, reciprocal
 
 
@@ -62,7 +63,8 @@ def _subset_sums(A: sp.csr_matrix, rows):
     return sub, sub.T.tocsr(), reciprocal(np.asarray(sub.sum(axis=0)).ravel())
 
 
-def os_sart_full(A: sp.csr_matrix, p, lam: float, passes: int, subsets, f0=None):
+def os_sart_full(A: sp.csr_matrix, p, lam: float, passes: int, subsets, f0=None, nonneg=False):
+    """``nonneg``: clamp the image at 0 after every subset step."""
     A = sp.csr_matrix(A, dtype=np.float64)
     p = np.asarray(p, dtype=np.float64)
     invW = reciprocal(np.asarray(A.sum(axis=1)).ravel())
@@ -75,11 +77,14 @@ def os_sart_full(A: sp.csr_matrix, p, lam: float, passes: int, subsets, f0=None)
         for rows, As, Ast, invVs in parts:
             r = p[rows] - As @ f
             f = f + lam * invVs * (Ast @ (invW[rows] * r))
+            if nonneg:
+                f = np.maximum(f, 0.0)
     res[passes] = np.linalg.norm(p - A @ f) / pn
     return f, res
 
 
-def os_sart_split(S: Split, p1, p2, lam: float, passes: int, folded_subsets, f10=None, f20=None):
+def os_sart_split(S: Split, p1, p2, lam: float, passes: int, folded_subsets, f10=None, f20=None,
+                  nonneg=False):
     """Both halves of the folded pair, normalised by A(2)'s row sums and
     A(2)'s column sums over each folded subset."""
     A1 = sp.csr_matrix((S.v1.astype(np.float64), S.indices, S.indptr), shape=(S.m, S.n))
@@ -107,5 +112,7 @@ def os_sart_split(S: Split, p1, p2, lam: float, passes: int, folded_subsets, f10
             z2 = invW[rows] * (p2[rows] - A2s @ f2)
             f1 = f1 + lam * invVs * (A1st @ z1)
             f2 = f2 + lam * invVs * (A2st @ z2)
+            if nonneg:
+                f1, f2 = nonneg_pair(f1, f2)
     res[passes] = rel()
     return f1, f2, res

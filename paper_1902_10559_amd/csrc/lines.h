@@ -103,4 +103,21 @@ __device__ inline void line_dot(const int32_t* idx, const void* val, const float
   else line_dot_e<NV, WT, L, U>(idx, val, x, lo, hi, glane, acc);
 }
 
+// Projection of the updated image onto f >= 0.  One system: clamp.  The
+// folded pair: voxels j and N-1-j are (f2 + f1) / 2 and (f2 - f1) / 2 by
+// eq. (5); clamp both and map back, which keeps f2 >= |f1| (halving and
+// doubling are exact in FP32).
+template <int NV>
+__device__ inline Vec<NV> project_nonneg(Vec<NV> f) {
+  if constexpr (NV == 1) {
+    f.v[0] = fmaxf(f.v[0], 0.0f);
+  } else {
+    const float a = fmaxf(0.5f * (f.v[1] + f.v[0]), 0.0f);
+    const float b = fmaxf(0.5f * (f.v[1] - f.v[0]), 0.0f);
+    f.v[0] = a - b;
+    f.v[1] = a + b;
+  }
+  return f;
+}
+
 }  // namespace ss

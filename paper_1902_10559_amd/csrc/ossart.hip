@@ -78,6 +78,7 @@ struct OsParams {
   float lambda;
   int32_t max_iter;
   double tol;
+  int32_t nonneg;
 };
 
 constexpr int kOsChunk = 16;
@@ -217,6 +218,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_bp(const OsParams* __restrict
   if (glane == 0 && in) {
     fv.v[0] = fmaf(tl, acc[0], fv.v[0]);
     fv.v[1] = fmaf(tl, acc[1], fv.v[1]);
+    if (prm->nonneg) fv = project_nonneg<2>(fv);
     store_vec<2>(S.f, col, fv);
   }
 }
@@ -332,6 +334,7 @@ ss_status os_validate(const ss_system* sys, const ss_subsets* sub, int nsys, con
     return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8 and cols_per_wave 0,1,..,64", fn);
   if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
   if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
+  if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
   return SS_OK;
 }
 
@@ -605,7 +608,7 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     ch.first = s0;
     ch.count = std::min(kOsChunk, nsys - s0);
     ch.zero_start = opts->zero_start;
-    ch.prm = OsParams{opts->lambda, opts->max_iter, opts->tol};
+    ch.prm = OsParams{opts->lambda, opts->max_iter, opts->tol, opts->nonneg};
     for (int i = 0; i < ch.count; ++i) ch.d[i] = ds[s0 + i];
     k_os_setup<<<ch.count, kOsThreads, 0, st>>>(ch, reinterpret_cast<OsDesc*>(ws + L.table),
                                                   reinterpret_cast<OsParams*>(ws + L.params));

@@ -87,6 +87,7 @@ struct Params {
   float lambda;
   int32_t max_iter;
   double tol;
+  int32_t nonneg;
 };
 
 struct SetupFlags {
@@ -298,6 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* __restrict__
         if (owner) {
 #pragma unroll
           for (int h = 0; h < NV; ++h) fv.v[h] = fmaf(tl, acc[h], fv.v[h]);
+          if (prm->nonneg) fv = project_nonneg<NV>(fv);
           store_vec<NV>(S.f[parity ^ 1], cur.line, fv);
         }
       }
@@ -386,6 +388,7 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
   if (!ok_pw(o->cols_per_wave, 16)) return fail(SS_E_ARG, "%s: cols_per_wave must be 0,1,2,4,8,16", fn);
   if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
   if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
+  if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
   return SS_OK;
 }
 
@@ -672,7 +675,7 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   const Cfg c = choose_cfg(sys, nsys, opts);
-  Params prm{opts->lambda, opts->max_iter, opts->tol};
+  Params prm{opts->lambda, opts->max_iter, opts->tol, opts->nonneg};
   Grids g{};
   if (ss_status s = setup(sys, nsys, f, res_hist, prm, c, L, ws, &g, opts->zero_start, st)) return s;
   const int64_t total = static_cast<int64_t>(opts->max_iter) + 1;  // forward passes incl. the final residual
@@ -727,7 +730,7 @@ extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, fl
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   const Cfg c = choose_cfg(sys, nsys, opts);
-  Params prm{opts->lambda, (1 << 30), -1.0};
+  Params prm{opts->lambda, (1 << 30), -1.0, opts->nonneg};
   Grids g{};
   if (ss_status s = setup(sys, nsys, f, nullptr, prm, c, L, ws, &g, 0, st)) return s;
   // the kernels are timed where they run in a solve, forward and back

@@ -62,7 +62,8 @@ class SartOptsC(C.Structure):
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("rows_per_wave", C.c_int32), ("cols_per_wave", C.c_int32),
                 ("xcd_remap", C.c_int32), ("zero_start", C.c_int32),
-                ("unroll", C.c_int32), ("persistent", C.c_int32), ("chunked", C.c_int32)]
+                ("unroll", C.c_int32), ("persistent", C.c_int32), ("chunked", C.c_int32),
+                ("nonneg", C.c_int32)]
 
 
 class SubsetsC(C.Structure):
@@ -412,11 +413,13 @@ class SartOptions:
     unroll: int = 0
     persistent: int = 0
     chunked: int = 0
+    nonneg: bool = False
 
     def c(self) -> SartOptsC:
         return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
                          int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
-                         self.xcd_remap, int(self.zero_start), self.unroll, self.persistent, self.chunked)
+                         self.xcd_remap, int(self.zero_start), self.unroll, self.persistent, self.chunked,
+                         int(self.nonneg))
 
 
 class Solver:

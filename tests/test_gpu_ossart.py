@@ -154,3 +154,17 @@ def test_subsets_reject_bad_arguments():
     Sb = native.fold(device(pr.A), S.p.new_tensor(pr.p), "bf16")
     with pytest.raises(native.SSError):
         native.Subsets(Sb, 5)         # FP32 pairs only
+
+
+def test_nonnegative_os_sart_matches_the_oracle():
+    banner("os-sart nonneg")
+    pr = problem(1)
+    S = _system(pr)
+    nsub = inputs.geometry_for(1).K // 2
+    f, h, _, _ = _solve([S], [native.Subsets(S, nsub)], 10, nonneg=True)
+    Sp = OSp.fold(pr.A.astype(np.float64))
+    p1, p2 = OSp.fold_p(pr.p.astype(np.float64))
+    f1, f2, res = OO.os_sart_split(Sp, p1, p2, 0.5, 10, _folded_blocks(Sp.m, nsub), nonneg=True)
+    img = to_np(native.recombine(f[0]))
+    assert img.min() >= 0.0 and rel_l2(img, OSp.recombine(f1, f2)) <= 1e-5
+    assert_res_close(to_np(h[0]), res)

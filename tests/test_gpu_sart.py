@@ -227,3 +227,23 @@ def test_iterations_to_1e3_match_the_oracle():
     assert res_ref[k_ref] <= 1e-3 and k_ref > 1000
     f, h, status, it = _solve([S], 5000, tol=1e-3, check_every=50)
     assert status == 0 and abs(it[0] - k_ref) <= 2
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_nonnegative_sart_matches_the_oracle(cfg):
+    """The fused projection onto f >= 0 (the pair map of eq. (5) on the
+    split, a clamp on the unsplit A) against the clamped FP64 oracle."""
+    banner(f"nonneg SART cfg{cfg}")
+    pr = problem(cfg)
+    Ad, pd, S = _split_system(pr)
+    f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 20, nonneg=True)
+    f_free, _ = OS.sart_full(pr.A, pr.p, 0.5, 20)
+    assert f_free.min() < 0.0                      # the constraint binds
+    f, h, _, _ = _solve([S], 20, nonneg=True)
+    img = to_np(native.recombine(f[0]))
+    assert img.min() >= 0.0 and rel_l2(img, f_ref) <= 1e-5
+    assert_res_close(to_np(h[0]), res_ref)
+    U = native.unsplit(Ad, pd)
+    fu, hu, _, _ = _solve([U], 20, nonneg=True)
+    assert rel_l2(to_np(fu[0]), f_ref) <= 1e-5
+    assert_res_close(to_np(hu[0]), res_ref)

@@ -116,3 +116,17 @@ def test_underdetermined_passes_settle_above_zero_residual():
     # a fixed point of the pass map: one more pass leaves the image unchanged
     f2, _ = ossart.os_sart_full(A, p, 0.5, 1, [np.arange(0, 20), np.arange(20, 40)], f0=f)
     assert np.max(np.abs(f2 - f)) < 1e-10 * np.abs(f).max()
+
+
+def test_nonnegative_split_os_sart_equals_clamped_full():
+    rng = np.random.default_rng(3)
+    A = random_symmetric_sparse(rng, 40, 30, 0.25)
+    p = rng.standard_normal(40)
+    full, folded = ossart.mirror_paired_views(8, 5)
+    S = split.fold(A)
+    p1, p2 = split.fold_p(p)
+    f, res = ossart.os_sart_full(A, p, 0.5, 12, full, nonneg=True)
+    f1, f2, rs = ossart.os_sart_split(S, p1, p2, 0.5, 12, folded, nonneg=True)
+    assert f.min() >= 0.0
+    assert np.max(np.abs(res - rs)) < 1e-13
+    assert np.max(np.abs(split.recombine(f1, f2) - f)) < 1e-12 * np.abs(f).max()
