@@ -22,6 +22,8 @@ method's standard published definition:
   the split pair, with relative-residual histories.
 * ``ossart``    -- ordered-subset SART (ordered subsets per the paper's ref.
   [004]) with subsets of mirror-paired views, full and split.
+* ``normal``    -- the direct path: normal equations of the full system and
+  of the split pair (Theorem 2), solved by Cholesky.
 * ``nn``        -- the learned initialiser's layers (3x3 convolution and its
   gradients, pooling, upsampling, ReLU, squared error, Adam).
 

@@ -128,6 +128,20 @@ def geometry_cfg5() -> Geometry:
                     bin_x=detector_bins(512), det_z=-50.0)
 
 
+def geometry_normal(n: int) -> Geometry:
+    """The shape of the paper's Table 1 experiment (Example 2): an n x n
+    slice (n = 32, 64, 128) seen from K = 24 n/32 sources over +-30 degrees
+    and B = 96 n/32 bins, so that A has M = 2304 (n/32)^2 rays for
+    N = n^2 voxels (the paper: 2280, 9120, 36480) and full column rank;
+    sources 100 n/32 mm above a detector plane 50 n/32 mm below the slice,
+    0.7 mm bins."""
+    s = n // 32
+    assert n == 32 * s and s >= 1
+    src_x, src_z = angular_sources(24 * s, 30.0, 100.0 * s, -50.0 * s)
+    return Geometry(nx=n, nz=n, pitch=1.0, src_x=src_x, src_z=src_z,
+                    bin_x=detector_bins(96 * s, 0.7), det_z=-50.0 * s)
+
+
 @dataclasses.dataclass(frozen=True)
 class Workload:
     name: str
@@ -144,6 +158,7 @@ WORKLOADS = {
     3: Workload("cfg3: cfg1 geometry, bf16/fp16 weights", 3, 10, 0.005, 100),
     4: Workload("cfg4: 256 slices 1024 x nz, K=24, 2048 bins", 4, 10, 0.0, 100),
     5: Workload("cfg5: 256x256 slice, K=16, 512 bins", 5, 10, 0.0, 200),
+    6: Workload("cfg6: Table 1 shapes, n x n slices, normal equations", 6, 10, 0.0, 0),
 }
 
 
