@@ -377,6 +377,25 @@ ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub,
                           size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The direct path: normal equations (Theorem 2)
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for ss_normal_solve: n*m + n*n + 2n doubles (dense A^T and
+ * B of one half at a time). */
+ss_status ss_normal_workspace_bytes(const ss_system* sys, size_t* bytes);
+
+/* Solves the normal equations A(k)^T A(k) f(k) = A(k)^T p(k) of each half of
+ * a folded FP32 pair (nvals = 2) by Cholesky factorisation in FP64 and
+ * writes their recombination by eq. (5), which by Theorem 2 is the normal
+ * pseudo-solution of (1) (the least-squares solution when A has full column
+ * rank); for nvals = 1 the same solve on A itself.  f: device, 2n doubles
+ * (nvals = 2) or n doubles.  Only the CSC and p of `sys` are read.  Returns
+ * SS_E_SHAPE if a normal matrix is not positive definite.  SYNCHRONISES
+ * the stream once. */
+ss_status ss_normal_solve(const ss_system* sys, double* f, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Images
  * ---------------------------------------------------------------------- */
 

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libssart.so")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["capi.cpp", "build_system.cpp"]
-HIP_SOURCES = ["fold.hip", "sart.hip", "ossart.hip", "images.hip", "nn.hip"]
+HIP_SOURCES = ["fold.hip", "sart.hip", "ossart.hip", "normal.hip", "images.hip", "nn.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -79,6 +79,8 @@ _SIGNATURES = {
     "ss_matrix_free": (None, [C.POINTER(MatrixC)]),
     "ss_snake_order": (C.c_int32, [C.POINTER(Grid), C.POINTER(C.c_int64)]),
     "ss_stream_len": (C.c_int64, [C.c_int64]),
+    "ss_normal_workspace_bytes": (C.c_int32, [C.POINTER(SystemC), C.POINTER(C.c_size_t)]),
+    "ss_normal_solve": (C.c_int32, [C.POINTER(SystemC), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "ss_subsets_build": (C.c_int32, [C.POINTER(SystemC), C.POINTER(SubsetsC), C.c_void_p]),
     "ss_ossart_workspace_bytes": (C.c_int32, [C.POINTER(SystemC), C.POINTER(SubsetsC), C.c_int32,
                                               C.POINTER(SartOptsC), C.POINTER(C.c_size_t)]),
@@ -538,6 +540,21 @@ class OsSolver:
                                    _ptr(self.ws), self.ws_bytes, _stream(self.ws.device))
         _check(st, allow_warning=True)
         return st, (list(it) if it is not None else None)
+
+
+def normal_solve(S: System, out=None):
+    """ss_normal_solve: the normal-equation solution (FP64), recombined by
+    eq. (5) for a folded pair."""
+    import torch
+    sc = S.c()
+    nb = C.c_size_t()
+    _check(lib().ss_normal_workspace_bytes(C.byref(sc), C.byref(nb)))
+    dev = S.p.device
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty(S.n * S.nvals, dtype=torch.float64, device=dev)
+    _check(lib().ss_normal_solve(C.byref(sc), _ptr(out), _ptr(ws), nb.value, _stream(dev)))
+    return out
 
 
 def recombine(f12, out=None):
