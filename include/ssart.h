@@ -380,8 +380,11 @@ ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub,
  * The direct path: normal equations (Theorem 2)
  * ---------------------------------------------------------------------- */
 
-/* Workspace bytes for ss_normal_solve: n*m + n*n + 2n doubles (dense A^T and
- * B of one half at a time). */
+/* Workspace bytes for ss_normal_solve: about nvals*n*n doubles (the dense
+ * normal matrices, lower triangles used; both halves are factored together:
+ * 2 (N/2)^2 = N^2/2 for the split pair against N^2 for A), plus O(n).  Errors:
+ * SS_E_ARG for a NULL argument, a system that is not FP32 with nvals 1 or
+ * 2, or n > 2^17. */
 ss_status ss_normal_workspace_bytes(const ss_system* sys, size_t* bytes);
 
 /* Solves the normal equations A(k)^T A(k) f(k) = A(k)^T p(k) of each half of
@@ -389,8 +392,13 @@ ss_status ss_normal_workspace_bytes(const ss_system* sys, size_t* bytes);
  * writes their recombination by eq. (5), which by Theorem 2 is the normal
  * pseudo-solution of (1) (the least-squares solution when A has full column
  * rank); for nvals = 1 the same solve on A itself.  f: device, 2n doubles
- * (nvals = 2) or n doubles.  Only the CSC and p of `sys` are read.  Returns
- * SS_E_SHAPE if a normal matrix is not positive definite.  SYNCHRONISES
+ * (nvals = 2) or n doubles; workspace: device, at least the bytes
+ * ss_normal_workspace_bytes returns, owned by the caller and overwritten.
+ * B is formed from both the CSR and the CSC of `sys`, and p; inv_row and
+ * inv_col are not read.  Errors: those of ss_normal_workspace_bytes;
+ * SS_E_WORKSPACE if the workspace is too small; SS_E_SHAPE if a normal
+ * matrix is not positive definite (A, or A(1) or A(2), lacks full column
+ * rank: a zero or negative pivot; f then holds no solution).  SYNCHRONISES
  * the stream once. */
 ss_status ss_normal_solve(const ss_system* sys, double* f, void* workspace,
                           size_t workspace_bytes, void* stream);

@@ -2,15 +2,17 @@
 // A(k)^T p(k) of each half of the folded pair, solved by a Cholesky
 // factorisation in FP64, and the halves recombined by eq. (5); for a single
 // system (nvals = 1) the same solve on A itself.  The split turns one
-// N x N factorisation of an N x N matrix formed from M rays into two of
-// (N/2)^2 from M/2 rays: 1/4 of the flops of forming B and 1/4 of the
-// factorisation's (the paper's 2^(alpha+beta) argument after Theorem 1).
+// N x N factorisation into two of N/2 x N/2: 1/4 of the flops (the paper's
+// 2^(alpha+beta) argument after Theorem 1, alpha + beta = 3 here), while
+// forming B from the sparse rows costs about the same either way.
 //
-// Steps per half: A^T densified (n rows of m FP64, row j = column j of A,
-// from the CSC); c = A^T p; B = A^T A, lower triangle, by an FP64 matrix-core
-// GEMM (v_mfma_f64_16x16x4f64); right-looking blocked Cholesky of B in place
-// (64 x 64 diagonal blocks factored in shared memory, panel solves, trailing
-// updates by the same GEMM); forward and back substitution, block by block.
+// Both halves go through the same launches (blockIdx.z selects the half).
+// Steps per half: B = A^T A, lower triangle, and c = A^T p from the sparse
+// rows (row-wise sums over the rays through each voxel, in shared memory);
+// right-looking blocked Cholesky of B in place (64 x 64 diagonal blocks
+// factored in shared memory, panel solves, trailing updates by an FP64
+// matrix-core GEMM, v_mfma_f64_16x16x4f64); forward and back substitution,
+// block by block.
 
 #include <algorithm>
 #include <cmath>
@@ -22,195 +24,346 @@
 namespace ss {
 namespace {
 
-constexpr int kNb = 64;  // Cholesky block and GEMM tile
+constexpr int kNb = 64;      // Cholesky block and GEMM tile
+constexpr int kPanel = 256;  // columns per trailing update
+constexpr int kTrail = 64;   // tile of the trailing update
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__global__ void k_zero_f64(double* p, int64_t count) {
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    p[i] = 0.0;
-}
+// Row j of B(h) = A(h)^T A(h) on and below the diagonal, and c[j] =
+// (A(h)^T p(h))[j].  One block per row: B[j, c] is the sum over the rays i
+// that cross voxel j (column j of the CSC, ascending i) of a_ij a_ic, from
+// ray i's CSR row.  The columns 0..j are accumulated in shared memory,
+// kFormCols at a time; within one ray a column occurs once, and a barrier
+// separates rays, so every sum runs in ascending ray order (the result is
+// the same from run to run).  The rays' row ranges and a_ij are staged in
+// shared memory kFormRays at a time, and each thread loads its first entry
+// of the next ray before adding those of the current one.  Products of FP32
+// values are exact in FP64.
+constexpr int kFormCols = 8192;
+constexpr int kFormRays = 256;
+constexpr int kFormThreads = 256;
 
-// At[j * m + i] = A(h)[i, j]; c[j] = sum_i A(h)[i, j] p(h)[i].  One thread
-// per column j of the half's CSC; value h of each entry's nv values.
-__global__ void k_densify(ss_system sys, int h, double* At, double* c) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= sys.n) return;
-  const float* v = static_cast<const float*>(sys.val_t);
+__global__ __launch_bounds__(kFormThreads) void k_form_b(ss_system sys, double* B, int64_t bs, double* c, int64_t vs) {
+  __shared__ double acc[kFormCols];
+  __shared__ int64_t rs[kFormRays];
+  __shared__ int32_t rl[kFormRays];
+  __shared__ double ra[kFormRays], rp[kFormRays];
+  const int tid = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  const int h = blockIdx.z;  // the half: A(1) or A(2)
+  B += h * bs;
+  c += h * vs;
+  const int64_t n = sys.n;
   const int nv = sys.nvals;
-  double acc = 0.0;
-  for (int64_t e = sys.col_ptr[j]; e < sys.col_ptr[j + 1]; ++e) {
-    const int64_t i = sys.row_idx[e];
-    const double a = v[nv * e + h];
-    At[j * sys.m + i] = a;
-    acc += a * static_cast<double>(sys.p[nv * i + h]);
+  const float* vt = static_cast<const float*>(sys.val_t);
+  const float* v = static_cast<const float*>(sys.val);
+  const int64_t e0 = sys.col_ptr[j], e1 = sys.col_ptr[j + 1];
+  double cj = 0.0;  // thread 0
+  for (int64_t c0 = 0; c0 <= j; c0 += kFormCols) {
+    const int w = static_cast<int>(std::min<int64_t>(kFormCols, j + 1 - c0));
+    for (int t = tid; t < w; t += kFormThreads) acc[t] = 0.0;
+    for (int64_t eb = e0; eb < e1; eb += kFormRays) {
+      const int nr = static_cast<int>(std::min<int64_t>(kFormRays, e1 - eb));
+      __syncthreads();
+      for (int t = tid; t < nr; t += kFormThreads) {
+        const int64_t i = sys.row_idx[eb + t];
+        const int64_t b0 = sys.row_ptr[i];
+        rs[t] = b0;
+        rl[t] = static_cast<int32_t>(sys.row_ptr[i + 1] - b0);
+        ra[t] = static_cast<double>(vt[nv * (eb + t) + h]);
+        rp[t] = static_cast<double>(sys.p[nv * i + h]);
+      }
+      __syncthreads();
+      if (c0 == 0 && tid == 0)
+        for (int t = 0; t < nr; ++t) cj += ra[t] * rp[t];
+      // entry tid of ray r, loaded one ray ahead
+      int64_t col = -1;
+      double val = 0.0;
+      if (tid < rl[0]) {
+        col = sys.col_idx[rs[0] + tid];
+        val = static_cast<double>(v[nv * (rs[0] + tid) + h]);
+      }
+      for (int r = 0; r < nr; ++r) {
+        const double a = ra[r];
+        const int64_t b0 = rs[r];
+        const int len = rl[r];
+        const int64_t cur_col = col;
+        const double cur_val = val;
+        col = -1;
+        if (r + 1 < nr && tid < rl[r + 1]) {
+          col = sys.col_idx[rs[r + 1] + tid];
+          val = static_cast<double>(v[nv * (rs[r + 1] + tid) + h]);
+        }
+        if (cur_col >= c0 && cur_col < c0 + w) acc[cur_col - c0] += a * cur_val;
+        for (int k = tid + kFormThreads; k < len; k += kFormThreads) {
+          const int64_t cc = sys.col_idx[b0 + k];
+          if (cc >= c0 && cc < c0 + w) acc[cc - c0] += a * static_cast<double>(v[nv * (b0 + k) + h]);
+        }
+        __syncthreads();
+      }
+    }
+    for (int t = tid; t < w; t += kFormThreads) B[j * n + c0 + t] = acc[t];
   }
-  c[j] = acc;
+  if (tid == 0) c[j] = cj;
 }
 
-// C[i, j] = beta * C[i, j] + alpha * sum_k X[i, k] Y[j, k] for the tiles of C
-// on or below the diagonal (i-tile >= j-tile), 64 x 64 per block of 4
-// wavefronts (2 x 2, 32 x 32 each as 2 x 2 matrix-core tiles).  X, Y, C
-// row-major with leading dimensions ldx, ldy, ldc; n x n output, K terms.
+// C[i, j] = beta * C[i, j] + alpha * sum_k X[i, k] Y[j, k] over an nr x nc
+// region of C, one TM x TM tile per block of 4 wavefronts (2 x 2, each
+// TM/2 x TM/2 as matrix-core tiles of 16 x 16); blockIdx.x is the tile row,
+// blockIdx.y the tile column.  With `lower`, tiles above the diagonal of the
+// region are skipped and elements above it are left alone.  X (nr rows), Y
+// (nc rows) and C are row-major with leading dimensions ldx, ldy, ldc; K
+// terms.  C may be X itself when nc <= TM (one tile column): a block reads
+// all of its X rows before it writes them.  K is staged through shared
+// memory kKc columns at a time, k-major, in two buffers: the next chunk's
+// global loads are in flight while the current one is multiplied.
 // Operand layouts of v_mfma_f64_16x16x4f64 for lane l (g = l / 16):
 //   A[m][k]: m = l % 16, k = g;  B[k][n]: n = l % 16, k = g;
 //   D[m][n]: m = g + 4 r (r = 0..3, the accumulator's element), n = l % 16
 // (rows interleaved by 4, unlike the 4 consecutive rows of the FP32 forms).
 constexpr int kKc = 16;
-__global__ __launch_bounds__(256) void k_gemm_nt_lower(const double* __restrict__ X, int64_t ldx,
-                                                       const double* __restrict__ Y, int64_t ldy, double* C,
-                                                       int64_t ldc, int64_t n, int64_t K, double alpha,
-                                                       double beta) {
-  // triangular block index -> (ti, tj), ti >= tj
-  const int64_t b = blockIdx.x;
-  int64_t ti = static_cast<int64_t>((std::sqrt(8.0 * static_cast<double>(b) + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-  while (ti * (ti + 1) / 2 > b) --ti;
-  const int64_t tj = b - ti * (ti + 1) / 2;
-  const int64_t r0 = ti * kNb, c0 = tj * kNb;
-  __shared__ double xs[kNb][kKc + 1];
-  __shared__ double ys[kNb][kKc + 1];
+template <int TM>
+__global__ __launch_bounds__(256) void k_gemm_nt(const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                                                 double* C, int64_t ldc, int64_t nr, int64_t nc, int64_t K,
+                                                 double alpha, double beta, int lower, int64_t xs_, int64_t ys_,
+                                                 int64_t cs_) {
+  constexpr int MT = TM / 32;                // 16 x 16 tiles per wave along each side
+  constexpr int PER = TM * kKc / 256 / 2;    // double pairs staged per thread per operand
+  constexpr int LDS_LD = TM + 1;
+  const int64_t ti = blockIdx.x, tj = blockIdx.y;
+  if (lower && tj > ti) return;
+  X += blockIdx.z * xs_;  // the half
+  Y += blockIdx.z * ys_;
+  C += blockIdx.z * cs_;
+  const int64_t r0 = ti * TM, c0 = tj * TM;
+  __shared__ double xs[2][kKc][LDS_LD];
+  __shared__ double ys[2][kKc][LDS_LD];
   const int lane = lane_id(), w = wave_id();
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;  // this wave's 32 x 32 quadrant
+  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
   const int g = lane / 16, l16 = lane % 16;
-  f64x4 acc[2][2];
+  f64x4 acc[MT][MT];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) acc[a][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = 0; k0 < K; k0 += kKc) {
-    // stage 64 x 16 of X (rows r0..) and of Y (rows c0..), zero outside
-    for (int t = threadIdx.x; t < kNb * kKc; t += 256) {
-      const int rr = t / kKc, kk = t % kKc;
+    for (int q = 0; q < MT; ++q) acc[a][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // staging: pair p of thread tid is row (tid + 256 p) / (kKc/2), columns 2 ((tid + 256 p) % (kKc/2)) + {0, 1}
+  double2 xr[PER], yr[PER];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + 256 * p;
+      const int rr = e / (kKc / 2), kk = 2 * (e % (kKc / 2));
       const int64_t k = k0 + kk;
-      const int64_t xr = r0 + rr, yr = c0 + rr;
-      xs[rr][kk] = (xr < n && k < K) ? X[xr * ldx + k] : 0.0;
-      ys[rr][kk] = (yr < n && k < K) ? Y[yr * ldy + k] : 0.0;
+      const int64_t xi = r0 + rr, yi = c0 + rr;
+      // two 8-byte loads: a row start need not be 16-byte aligned
+      double2 vx = {0.0, 0.0}, vy = {0.0, 0.0};
+      if (xi < nr) {
+        if (k < K) vx.x = X[xi * ldx + k];
+        if (k + 1 < K) vx.y = X[xi * ldx + k + 1];
+      }
+      if (yi < nc) {
+        if (k < K) vy.x = Y[yi * ldy + k];
+        if (k + 1 < K) vy.y = Y[yi * ldy + k + 1];
+      }
+      xr[p] = vx;
+      yr[p] = vy;
     }
-    __syncthreads();
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + 256 * p;
+      const int rr = e / (kKc / 2), kk = 2 * (e % (kKc / 2));
+      xs[b][kk][rr] = xr[p].x;
+      xs[b][kk + 1][rr] = xr[p].y;
+      ys[b][kk][rr] = yr[p].x;
+      ys[b][kk + 1][rr] = yr[p].y;
+    }
+  };
+  const int64_t nch = (K + kKc - 1) / kKc;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int b = static_cast<int>(ch & 1);
+    if (ch + 1 < nch) load((ch + 1) * kKc);
 #pragma unroll
     for (int kk = 0; kk < kKc; kk += 4) {
+      double av[MT], bv[MT];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const double av = xs[wr + 16 * a + l16][kk + g];
+      for (int a = 0; a < MT; ++a) av[a] = xs[b][kk + g][wr + 16 * a + l16];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const double bv = ys[wc + 16 * q + l16][kk + g];
-          acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][q], 0, 0, 0);
-        }
-      }
+      for (int q = 0; q < MT; ++q) bv[q] = ys[b][kk + g][wc + 16 * q + l16];
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int q = 0; q < MT; ++q) acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[q], acc[a][q], 0, 0, 0);
     }
+    if (ch + 1 < nch) store(b ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < MT; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t i = r0 + wr + 16 * a + g + 4 * r;
         const int64_t j = c0 + wc + 16 * q + l16;
-        if (i < n && j < n && j <= i) {
+        if (i < nr && j < nc && (!lower || j <= i)) {
           double* cp = C + i * ldc + j;
           *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[a][q][r];
         }
       }
 }
 
-// Cholesky of the diagonal block B[k0.., k0..] (size nb <= 64) in shared
-// memory, lower factor written back; thread t owns row t.  A non-positive
-// pivot sets *flag and is replaced by 1 so that the rest stays finite.
-__global__ __launch_bounds__(64) void k_potrf_diag(double* B, int64_t ld, int64_t k0, int nb, int32_t* flag) {
-  __shared__ double s[kNb][kNb + 1];
-  const int t = threadIdx.x;
-  if (t < nb)
-    for (int c = 0; c <= t; ++c) s[t][c] = B[(k0 + t) * ld + k0 + c];
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (t == 0) {
-      double d = s[j][j];
+// Cholesky of the diagonal block B[k0.., k0..] (size nb <= 64), padded to
+// 64 with the identity, and the inverse of its factor, by 4 wavefronts:
+// thread (t, q) (q = wavefront) holds columns 16q .. 16q+15 of row t of the
+// block (`row`) and of the identity (`r`), in registers.  Step j, one
+// barrier: the owners of column j put it in shared memory, and lane j of
+// every wavefront its part of row j of r (two buffers); then every thread
+// reads the pivot d and forms 1/sqrt(d) itself (the hardware estimate and
+// one Newton step: within an ulp or so), with L[c][j] = B[c][j] / sqrt(d)
+// subtracts L[t][j] L[c][j] from its entries c > j, and eliminates with row
+// j of L^{-1} (r_j / sqrt(d)) likewise, which turns r into L^{-1}.  The
+// inner loops are unrolled, so every register index is a constant.  L goes
+// back to B (lower part, nb x nb), L^{-1} to Linv (64 x 64 row-major, zero
+// above the diagonal).  A non-positive pivot sets *flag and is replaced by
+// 1 so that the rest stays finite.
+constexpr int kSeg = 16;
+__global__ __launch_bounds__(256) void k_potrf_diag(double* B, int64_t ld, int64_t k0, int nb, double* Linv,
+                                                    int32_t* flag, int64_t bs, int64_t ls) {
+  __shared__ double colj[2][kNb], xj[2][kNb];
+  const int t = lane_id(), q = wave_id();
+  B += blockIdx.z * bs;  // the half
+  Linv += blockIdx.z * ls;
+  double row[kSeg], r[kSeg];
+#pragma unroll
+  for (int cc = 0; cc < kSeg; ++cc) {
+    const int c = kSeg * q + cc;
+    row[cc] = (t < nb && c <= t) ? B[(k0 + t) * ld + k0 + c] : (c == t ? 1.0 : 0.0);
+    r[cc] = (c == t) ? 1.0 : 0.0;
+  }
+  bool bad = false;
+  for (int s = 0; s < kNb / kSeg; ++s) {
+#pragma unroll
+    for (int jj = 0; jj < kSeg; ++jj) {
+      const int j = kSeg * s + jj, b = jj & 1;
+      if (q == s) colj[b][t] = row[jj];
+      if (t == j) {
+#pragma unroll
+        for (int cc = 0; cc < kSeg; ++cc) xj[b][kSeg * q + cc] = r[cc];
+      }
+      __syncthreads();
+      double d = colj[b][j];
       if (!(d > 0.0)) {
-        *flag = 1;
+        bad = true;
         d = 1.0;
       }
-      s[j][j] = std::sqrt(d);
+      double ip = __builtin_amdgcn_rsq(d);
+      ip = ip * (1.5 - 0.5 * d * ip * ip);
+      const double lt = colj[b][t] * ip;  // L[t][j] for t > j
+      if (q == s) row[jj] = (t > j) ? lt : (t == j ? d * ip : 0.0);
+      // Branch-free: a zero multiplier leaves what must not change (rows
+      // t <= j, entries c <= j), so the shared-memory reads are not
+      // serialised behind per-entry branches.
+      const double sc = (t > j) ? lt * ip : 0.0;
+      const double rs = (t == j) ? ip : 1.0;
+#pragma unroll
+      for (int cc = 0; cc < kSeg; ++cc) {
+        const int c = kSeg * q + cc;
+        row[cc] -= (c > j ? sc : 0.0) * colj[b][c];
+        r[cc] = r[cc] * rs - sc * xj[b][c];
+      }
     }
-    __syncthreads();
-    if (t > j && t < nb) s[t][j] /= s[j][j];
-    __syncthreads();
-    if (t > j && t < nb)
-      for (int c = j + 1; c <= t; ++c) s[t][c] -= s[t][j] * s[c][j];
-    __syncthreads();
   }
-  if (t < nb)
-    for (int c = 0; c <= t; ++c) B[(k0 + t) * ld + k0 + c] = s[t][c];
+  if (bad && t == 0 && q == 0) *flag = 1;
+#pragma unroll
+  for (int cc = 0; cc < kSeg; ++cc) {
+    const int c = kSeg * q + cc;
+    if (t < nb && c <= t) B[(k0 + t) * ld + k0 + c] = row[cc];
+    Linv[t * kNb + c] = r[cc];
+  }
 }
 
-// Panel below the diagonal block: rows k0+nb .. n-1 of columns k0 ..
-// k0+nb-1 become X with X L^T = B (L the factored diagonal block, read from
-// global memory: every thread reads the same entry).  One thread per row,
-// its row kept in its own column of a shared array.
-__global__ __launch_bounds__(64) void k_trsm_panel(double* B, int64_t ld, int64_t n, int64_t k0, int nb) {
-  __shared__ double xt[kNb][kNb];
-  const int t = threadIdx.x;
-  const int64_t row = k0 + nb + static_cast<int64_t>(blockIdx.x) * kNb + t;
-  if (row >= n) return;
-  for (int c = 0; c < nb; ++c) xt[c][t] = B[row * ld + k0 + c];
-  for (int c = 0; c < nb; ++c) {
-    const double x = xt[c][t] / B[(k0 + c) * ld + k0 + c];
-    xt[c][t] = x;
-    for (int c2 = c + 1; c2 < nb; ++c2) xt[c2][t] -= x * B[(k0 + c2) * ld + k0 + c];
-  }
-  for (int c = 0; c < nb; ++c) B[row * ld + k0 + c] = xt[c][t];
-}
-
-// Forward substitution on block k: y[k0..k0+nb) = L_kk^{-1} c[k0..);
-// then every later row: c[i] -= sum_t L[i, k0+t] y[k0+t].
-__global__ __launch_bounds__(64) void k_trsv_fwd_diag(const double* L, int64_t ld, int64_t k0, int nb, double* c) {
-  __shared__ double y[kNb];
-  const int t = threadIdx.x;
-  if (t < nb) y[t] = c[k0 + t];
+// Forward substitution, block k of L y = c: y_k = L_kk^{-1} c_k, then
+// c[i] -= sum_t L[i, k0+t] y_k[t] for the 64 rows i >= k0 + nb of this
+// block (thread (row, quarter) takes 16 consecutive t, the quarters summed
+// across adjacent lanes in a fixed order).  Every block forms y_k (c_k is
+// not written here); block 0 stores it.
+__global__ __launch_bounds__(256) void k_fwd_step(const double* L, int64_t ld, int64_t n, int64_t k0, int nb,
+                                                  const double* Linv, double* c, double* y, int64_t bs, int64_t ls,
+                                                  int64_t vs) {
+  __shared__ double li[kNb][kNb + 1];
+  __shared__ double ck[kNb], yk[kNb];
+  const int tid = threadIdx.x;
+  L += blockIdx.z * bs;  // the half
+  Linv += blockIdx.z * ls;
+  c += blockIdx.z * vs;
+  y += blockIdx.z * vs;
+  for (int e = tid; e < kNb * kNb; e += 256) li[e / kNb][e % kNb] = Linv[e];
+  if (tid < kNb) ck[tid] = (tid < nb) ? c[k0 + tid] : 0.0;
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (t == 0) y[j] /= L[(k0 + j) * ld + k0 + j];
-    __syncthreads();
-    if (t > j && t < nb) y[t] -= L[(k0 + t) * ld + k0 + j] * y[j];
-    __syncthreads();
+  if (tid < kNb) {
+    double a = 0.0;
+    for (int q = 0; q <= tid; ++q) a += li[tid][q] * ck[q];
+    yk[tid] = a;
+    if (blockIdx.x == 0 && tid < nb) y[k0 + tid] = a;
   }
-  if (t < nb) c[k0 + t] = y[t];
-}
-
-__global__ void k_trsv_fwd_update(const double* L, int64_t ld, int64_t n, int64_t k0, int nb, double* c) {
-  const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double acc = 0.0;
-  for (int t = 0; t < nb; ++t) acc += L[i * ld + k0 + t] * c[k0 + t];
-  c[i] -= acc;
-}
-
-// Back substitution with L^T on block k (from the last): f[k0..) =
-// L_kk^{-T} y[k0..); then every earlier row: y[i] -= sum_t L[k0+t, i] f[k0+t].
-__global__ __launch_bounds__(64) void k_trsv_bwd_diag(const double* L, int64_t ld, int64_t k0, int nb, double* y) {
-  __shared__ double f[kNb];
-  const int t = threadIdx.x;
-  if (t < nb) f[t] = y[k0 + t];
   __syncthreads();
-  for (int j = nb - 1; j >= 0; --j) {
-    if (t == 0) f[j] /= L[(k0 + j) * ld + k0 + j];
-    __syncthreads();
-    if (t < j) f[t] -= L[(k0 + j) * ld + k0 + t] * f[j];
-    __syncthreads();
+  const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * kNb + tid / 4;
+  const int qp = (tid % 4) * 16;
+  double a = 0.0;
+  if (i < n) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (qp + u < nb) a += L[i * ld + k0 + qp + u] * yk[qp + u];
   }
-  if (t < nb) y[k0 + t] = f[t];
+  a += __shfl_xor(a, 1, kWave);
+  a += __shfl_xor(a, 2, kWave);
+  if (i < n && tid % 4 == 0) c[i] -= a;
 }
 
-__global__ void k_trsv_bwd_update(const double* L, int64_t ld, int64_t k0, int nb, double* y) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= k0) return;
-  double acc = 0.0;
-  for (int t = 0; t < nb; ++t) acc += L[(k0 + t) * ld + i] * y[k0 + t];
-  y[i] -= acc;
+// Back substitution, block k of L^T x = y (from the last block): x_k =
+// L_kk^{-T} y_k, then y[i] -= sum_t L[k0+t, i] x_k[t] for the 64 rows i < k0
+// of this block (wavefront w takes t = 16w .. 16w+15, lanes run along i;
+// the four partial sums are added in wavefront order).
+__global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, int64_t k0, int nb,
+                                                  const double* Linv, double* y, double* x, int64_t bs, int64_t ls,
+                                                  int64_t vs) {
+  __shared__ double li[kNb][kNb + 1];
+  __shared__ double yk[kNb], xk[kNb];
+  __shared__ double part[4][kNb];
+  const int tid = threadIdx.x;
+  L += blockIdx.z * bs;  // the half
+  Linv += blockIdx.z * ls;
+  y += blockIdx.z * vs;
+  x += blockIdx.z * vs;
+  for (int e = tid; e < kNb * kNb; e += 256) li[e / kNb][e % kNb] = Linv[e];
+  if (tid < kNb) yk[tid] = (tid < nb) ? y[k0 + tid] : 0.0;
+  __syncthreads();
+  if (tid < kNb) {
+    double a = 0.0;
+    for (int q = tid; q < kNb; ++q) a += li[q][tid] * yk[q];
+    xk[tid] = a;
+    if (blockIdx.x == 0 && tid < nb) x[k0 + tid] = a;
+  }
+  __syncthreads();
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNb + lane_id();
+  const int w = wave_id();
+  double a = 0.0;
+  if (i < k0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = 16 * w + u;
+      if (q < nb) a += L[(k0 + q) * ld + i] * xk[q];
+    }
+  }
+  part[w][lane_id()] = a;
+  __syncthreads();
+  if (tid < kNb && i < k0) y[i] -= ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
 }
 
 // f[j] = (f2 + f1) / 2, f[N-1-j] = (f2 - f1) / 2 (eq. (5)), or a copy for
@@ -226,23 +379,33 @@ __global__ void k_recombine_f64(const double* h1, const double* h2, int64_t n, i
   }
 }
 
+// Per half h (blockIdx.z of every launch): B at b + h*bs, c, y, x at
+// c/y/x + h*vs, the inverted diagonal blocks at linv + h*ls (in doubles).
 struct NormalLayout {
-  size_t at, b, c[2], flag, total;
+  size_t b, c, y, x, linv, flag, total;
+  int64_t bs, vs, ls;
 };
 
 inline size_t al(size_t v) { return (v + 255) & ~size_t{255}; }
 
 NormalLayout normal_layout(const ss_system* sys) {
+  const size_t n = static_cast<size_t>(sys->n), nv = static_cast<size_t>(sys->nvals);
+  const size_t nt = (n + kNb - 1) / kNb;
   NormalLayout L;
+  L.bs = static_cast<int64_t>(al(sizeof(double) * n * n) / sizeof(double));
+  L.vs = static_cast<int64_t>(al(sizeof(double) * n) / sizeof(double));
+  L.ls = static_cast<int64_t>(nt * kNb * kNb);
   size_t o = 0;
-  L.at = o;
-  o += al(sizeof(double) * static_cast<size_t>(sys->n) * static_cast<size_t>(sys->m));
   L.b = o;
-  o += al(sizeof(double) * static_cast<size_t>(sys->n) * static_cast<size_t>(sys->n));
-  for (int h = 0; h < 2; ++h) {
-    L.c[h] = o;
-    o += al(sizeof(double) * static_cast<size_t>(sys->n));
-  }
+  o += sizeof(double) * static_cast<size_t>(L.bs) * nv;
+  L.c = o;
+  o += sizeof(double) * static_cast<size_t>(L.vs) * nv;
+  L.y = o;
+  o += sizeof(double) * static_cast<size_t>(L.vs) * nv;
+  L.x = o;
+  o += sizeof(double) * static_cast<size_t>(L.vs) * 2;  // two halves even for nvals = 1 (the second unused)
+  L.linv = o;
+  o += al(sizeof(double) * static_cast<size_t>(L.ls) * nv);
   L.flag = o;
   o += 256;
   L.total = o;
@@ -256,7 +419,7 @@ ss_status check_normal(const ss_system* sys, const char* fn) {
   if (sys->m <= 0 || sys->n <= 0 || sys->nnz < 0 || !sys->col_ptr || !sys->p ||
       (sys->nnz > 0 && (!sys->row_idx || !sys->val_t)))
     return fail(SS_E_ARG, "%s: bad system", fn);
-  if (sys->n > (int64_t{1} << 20) || sys->m > (int64_t{1} << 24))
+  if (sys->n > (int64_t{1} << 17) || sys->m > (int64_t{1} << 30))
     return fail(SS_E_ARG, "%s: system too large for the dense path", fn);
   return SS_OK;
 }
@@ -285,50 +448,63 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
   if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_normal_solve: workspace needs %zu bytes", L.total);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  double* At = reinterpret_cast<double*>(ws + L.at);
   double* B = reinterpret_cast<double*>(ws + L.b);
   int32_t* flag = reinterpret_cast<int32_t*>(ws + L.flag);
-  const int64_t n = sys->n, m = sys->m;
+  const int64_t n = sys->n;
   const int64_t nt = (n + kNb - 1) / kNb;
+  const unsigned nv = static_cast<unsigned>(sys->nvals);
+  double* c = reinterpret_cast<double*>(ws + L.c);
+  double* y = reinterpret_cast<double*>(ws + L.y);
+  double* x = reinterpret_cast<double*>(ws + L.x);
+  double* Linv = reinterpret_cast<double*>(ws + L.linv);
+  const int64_t bs = L.bs, vs = L.vs, ls = L.ls;
+  auto tiles = [](int64_t v, int t) { return static_cast<unsigned>((v + t - 1) / t); };
   SS_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
-  for (int h = 0; h < sys->nvals; ++h) {
-    double* c = reinterpret_cast<double*>(ws + L.c[h]);
-    k_zero_f64<<<4096, 256, 0, st>>>(At, n * m);
-    k_densify<<<blocks(n, 256), 256, 0, st>>>(*sys, h, At, c);
-    // B = At At^T (lower tiles)
-    k_gemm_nt_lower<<<static_cast<unsigned>(nt * (nt + 1) / 2), 256, 0, st>>>(At, m, At, m, B, n, n, m, 1.0, 0.0);
-    // blocked Cholesky, lower, in place
-    for (int64_t k = 0; k < nt; ++k) {
-      const int64_t k0 = k * kNb;
-      const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
-      k_potrf_diag<<<1, 64, 0, st>>>(B, n, k0, nb, flag);
-      const int64_t rest = n - k0 - nb;
-      if (rest > 0) {
-        k_trsm_panel<<<blocks(rest, kNb), 64, 0, st>>>(B, n, n, k0, nb);
-        const int64_t rt = (rest + kNb - 1) / kNb;
-        // trailing B[k0+nb.., k0+nb..] -= P P^T with P the panel (K = nb)
-        double* T = B + (k0 + nb) * n + (k0 + nb);
-        const double* P = B + (k0 + nb) * n + k0;
-        k_gemm_nt_lower<<<static_cast<unsigned>(rt * (rt + 1) / 2), 256, 0, st>>>(P, n, P, n, T, n, rest, nb, -1.0,
-                                                                                 1.0);
-      }
+  // Both halves go through every launch together (blockIdx.z = half): they
+  // are independent systems, so the latency-bound steps of the
+  // factorisation are shared between them.
+  k_form_b<<<dim3(static_cast<unsigned>(n), 1, nv), kFormThreads, 0, st>>>(*sys, B, bs, c, vs);
+  // Blocked right-looking Cholesky, lower, in place: panels of kPanel
+  // columns factored 64 columns at a time (diagonal block, panel solve as a
+  // product with L_kk^{-T}, update of the panel's remaining columns); then
+  // one trailing update of the rest with K = kPanel.
+  for (int64_t K0 = 0; K0 < n; K0 += kPanel) {
+    const int64_t W = std::min<int64_t>(kPanel, n - K0);
+    for (int64_t k0 = K0; k0 < K0 + W; k0 += kNb) {
+      const int nb = static_cast<int>(std::min<int64_t>(kNb, K0 + W - k0));
+      double* Lk = Linv + (k0 / kNb) * kNb * kNb;
+      k_potrf_diag<<<dim3(1, 1, nv), 256, 0, st>>>(B, n, k0, nb, Lk, flag, bs, ls);
+      const int64_t below = n - k0 - nb;
+      if (below <= 0) continue;  // nb < 64 only for the last block
+      double* P = B + (k0 + nb) * n + k0;
+      k_gemm_nt<kNb><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
+                                                                      bs, ls, bs);
+      const int64_t pw = K0 + W - (k0 + nb);
+      if (pw > 0)
+        k_gemm_nt<kNb><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
+            P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
     }
-    // L y = c, then L^T x = y (in place in c)
-    for (int64_t k = 0; k < nt; ++k) {
-      const int64_t k0 = k * kNb;
-      const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
-      k_trsv_fwd_diag<<<1, 64, 0, st>>>(B, n, k0, nb, c);
-      if (n - k0 - nb > 0) k_trsv_fwd_update<<<blocks(n - k0 - nb, 256), 256, 0, st>>>(B, n, n, k0, nb, c);
-    }
-    for (int64_t k = nt - 1; k >= 0; --k) {
-      const int64_t k0 = k * kNb;
-      const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
-      k_trsv_bwd_diag<<<1, 64, 0, st>>>(B, n, k0, nb, c);
-      if (k0 > 0) k_trsv_bwd_update<<<blocks(k0, 256), 256, 0, st>>>(B, n, k0, nb, c);
+    const int64_t rest = n - K0 - W;
+    if (rest > 0) {
+      double* Q = B + (K0 + W) * n + K0;
+      k_gemm_nt<kTrail><<<dim3(tiles(rest, kTrail), tiles(rest, kTrail), nv), 256, 0, st>>>(
+          Q, n, Q, n, Q + W, n, rest, rest, W, -1.0, 1.0, 1, bs, bs, bs);
     }
   }
-  k_recombine_f64<<<blocks(n, 256), 256, 0, st>>>(reinterpret_cast<double*>(ws + L.c[0]),
-                                                  reinterpret_cast<double*>(ws + L.c[1]), n, sys->nvals, f);
+  // L y = c, then L^T x = y
+  for (int64_t k = 0; k < nt; ++k) {
+    const int64_t k0 = k * kNb;
+    const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
+    k_fwd_step<<<dim3(std::max(1u, blocks(n - k0 - nb, kNb)), 1, nv), 256, 0, st>>>(
+        B, n, n, k0, nb, Linv + k * kNb * kNb, c, y, bs, ls, vs);
+  }
+  for (int64_t k = nt - 1; k >= 0; --k) {
+    const int64_t k0 = k * kNb;
+    const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
+    k_bwd_step<<<dim3(std::max(1u, blocks(k0, kNb)), 1, nv), 256, 0, st>>>(B, n, k0, nb, Linv + k * kNb * kNb, y, x,
+                                                                            bs, ls, vs);
+  }
+  k_recombine_f64<<<blocks(n, 256), 256, 0, st>>>(x, x + vs, n, sys->nvals, f);
   SS_HIP_TRY(hipGetLastError());
   int32_t hflag = 0;
   SS_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st));
