@@ -16,7 +16,11 @@ Workloads:
                    1 % noise, 100 iterations, FP32 weights.  Its 32 MB per
                    iteration stay in the 256 MB Infinity Cache, so its kernels
                    are bound by latency, not by HBM.
-The same step on the unsplit A is timed beside it.
+The same step on the unsplit A is timed beside it.  Extras: ordered-subset
+SART against SART to a residual of 1e-2, the direct path (normal equations by
+Cholesky, Theorem 2) on Table 1's three sizes, time to a residual of 1e-3,
+and the CPU oracle's rate.  ``--direct-only`` prints just the direct path's
+report.
 
 Output: one JSON line on stdout (progress on stderr).  ``value`` is
 original-system nonzeros processed per second: iterations x nnz(A) / time.
@@ -52,6 +56,10 @@ def parse():
                     help="storage type of the split pair's weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-subsets", action="store_true", help="skip the ordered-subset comparison")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the direct (normal-equation) path at Table 1's sizes")
+    ap.add_argument("--direct-only", action="store_true",
+                    help="only the direct path's report (one JSON line), for profiling it")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
     ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT,CHUNKED",
@@ -126,6 +134,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.direct_only:
+        print(json.dumps({"direct_normal_equations": direct_report(dev)}), flush=True)
+        return
     log(f"setting up workload {args.workload}")
     slices, desc, lam = setup(args, dev)
     systems = [x.S for x in slices]
@@ -243,6 +254,11 @@ def main():
         out["ordered_subsets"] = subsets_report(slices, systems, opts, dev, lam)
         log(f"ordered subsets: {out['ordered_subsets']}")
 
+    # the direct path (Theorem 2) at Table 1's sizes: full system vs split pair
+    if not args.no_direct:
+        out["direct_normal_equations"] = direct_report(dev)
+        log(f"direct path: {out['direct_normal_equations']}")
+
     # time to relative residual 1e-3 (capped at 20000 iterations)
     ttr = {}
     if args.workload == "slice":
@@ -312,6 +328,44 @@ def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
         rep[name] = {"median_steps": float(np.median(it)), "max_steps": int(max(it)), "reached": bool(st == 0),
                      "seconds": e0.elapsed_time(e1) * 1e-3}
     rep["speedup"] = rep["sart"]["seconds"] / rep["os_sart"]["seconds"]
+    return rep
+
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix cores and vector units alike)
+
+
+def direct_report(dev, sizes=(32, 64, 128), reps=3):
+    """ss_normal_solve on the n x n slices of Table 1's shapes (M = 2304
+    (n/32)^2 rays, N = n^2 voxels): the unsplit system against the split pair
+    (both halves factored together), best of `reps` after a warm-up.  The
+    Cholesky flop count is N^3/3 unsplit and 2 (N/2)^3/3 split; `tflops` is
+    that count over the whole solve's time (formation and substitutions
+    included), against the FP64 peak."""
+    import numpy as np
+    import torch
+    from paper_1902_10559_amd import native, workloads
+    rep = {}
+    for n in sizes:
+        case = workloads.table1_case(n, dev)
+        N = case.A.N
+        f_true = torch.from_numpy(workloads.phantom_snake(case.geom, 6, 0)).to(dev).double()
+        row = {"M": case.A.M, "N": N, "nnz": case.A.nnz}
+        for name, S, flops in (("unsplit", native.unsplit(case.A, case.p), N ** 3 / 3),
+                               ("split", case.S, 2 * (N // 2) ** 3 / 3)):
+            f = native.normal_solve(S)
+            best = 1e30
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                native.normal_solve(S, f)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            err = float(torch.linalg.norm(f - f_true) / torch.linalg.norm(f_true))
+            row[name] = {"ms": best * 1e3, "rel_err_vs_phantom": err,
+                         "tflops": flops / best / 1e12, "frac_fp64_peak": flops / best / 1e12 / FP64_PEAK_TFLOPS}
+        row["speedup"] = row["unsplit"]["ms"] / row["split"]["ms"]
+        rep[f"{n}x{n}"] = row
+        del case
     return rep
 
 

@@ -26,7 +26,8 @@ namespace {
 
 constexpr int kNb = 64;      // Cholesky block and GEMM tile
 constexpr int kPanel = 256;  // columns per trailing update
-constexpr int kTrail = 64;   // tile of the trailing update
+constexpr int kTrail = 128;      // tile of the trailing update
+constexpr int kTrailWaves = 8;   // wavefronts per trailing-update block
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -109,9 +110,9 @@ __global__ __launch_bounds__(kFormThreads) void k_form_b(ss_system sys, double* 
 }
 
 // C[i, j] = beta * C[i, j] + alpha * sum_k X[i, k] Y[j, k] over an nr x nc
-// region of C, one TM x TM tile per block of 4 wavefronts (2 x 2, each
-// TM/2 x TM/2 as matrix-core tiles of 16 x 16); blockIdx.x is the tile row,
-// blockIdx.y the tile column.  With `lower`, tiles above the diagonal of the
+// region of C, one TM x TM tile per block of NW wavefronts (2 x NW/2, each
+// TM/2 x 2TM/NW as matrix-core tiles of 16 x 16); blockIdx.x is the tile
+// row, blockIdx.y the tile column.  With `lower`, tiles above the diagonal of the
 // region are skipped and elements above it are left alone.  X (nr rows), Y
 // (nc rows) and C are row-major with leading dimensions ldx, ldy, ldc; K
 // terms.  C may be X itself when nc <= TM (one tile column): a block reads
@@ -123,14 +124,17 @@ __global__ __launch_bounds__(kFormThreads) void k_form_b(ss_system sys, double* 
 //   D[m][n]: m = g + 4 r (r = 0..3, the accumulator's element), n = l % 16
 // (rows interleaved by 4, unlike the 4 consecutive rows of the FP32 forms).
 constexpr int kKc = 16;
-template <int TM>
-__global__ __launch_bounds__(256) void k_gemm_nt(const double* X, int64_t ldx, const double* Y, int64_t ldy,
+template <int TM, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_nt(const double* X, int64_t ldx, const double* Y, int64_t ldy,
                                                  double* C, int64_t ldc, int64_t nr, int64_t nc, int64_t K,
                                                  double alpha, double beta, int lower, int64_t xs_, int64_t ys_,
                                                  int64_t cs_) {
-  constexpr int MT = TM / 32;                // 16 x 16 tiles per wave along each side
-  constexpr int PER = TM * kKc / 256 / 2;    // double pairs staged per thread per operand
+  constexpr int NT = NW * 64;                 // threads
+  constexpr int WM = TM / 2, WN = 2 * TM / NW;  // this wave's sub-tile
+  constexpr int MR = WM / 16, MC = WN / 16;   // 16 x 16 tiles per wave
+  constexpr int PER = TM * kKc / NT / 2;      // double pairs staged per thread per operand
   constexpr int LDS_LD = TM + 1;
+  static_assert(PER >= 1 && MR >= 1 && MC >= 1, "tile shape");
   const int64_t ti = blockIdx.x, tj = blockIdx.y;
   if (lower && tj > ti) return;
   X += blockIdx.z * xs_;  // the half
@@ -140,19 +144,19 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const double* X, int64_t ldx, c
   __shared__ double xs[2][kKc][LDS_LD];
   __shared__ double ys[2][kKc][LDS_LD];
   const int lane = lane_id(), w = wave_id();
-  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+  const int wr = (w / (NW / 2)) * WM, wc = (w % (NW / 2)) * WN;
   const int g = lane / 16, l16 = lane % 16;
-  f64x4 acc[MT][MT];
+  f64x4 acc[MR][MC];
 #pragma unroll
-  for (int a = 0; a < MT; ++a)
+  for (int a = 0; a < MR; ++a)
 #pragma unroll
-    for (int q = 0; q < MT; ++q) acc[a][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // staging: pair p of thread tid is row (tid + 256 p) / (kKc/2), columns 2 ((tid + 256 p) % (kKc/2)) + {0, 1}
+    for (int q = 0; q < MC; ++q) acc[a][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // staging: pair p of thread tid is row (tid + NT p) / (kKc/2), columns 2 ((tid + NT p) % (kKc/2)) + {0, 1}
   double2 xr[PER], yr[PER];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-      const int e = threadIdx.x + 256 * p;
+      const int e = threadIdx.x + NT * p;
       const int rr = e / (kKc / 2), kk = 2 * (e % (kKc / 2));
       const int64_t k = k0 + kk;
       const int64_t xi = r0 + rr, yi = c0 + rr;
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const double* X, int64_t ldx, c
   auto store = [&](int b) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-      const int e = threadIdx.x + 256 * p;
+      const int e = threadIdx.x + NT * p;
       const int rr = e / (kKc / 2), kk = 2 * (e % (kKc / 2));
       xs[b][kk][rr] = xr[p].x;
       xs[b][kk + 1][rr] = xr[p].y;
@@ -190,23 +194,23 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const double* X, int64_t ldx, c
     if (ch + 1 < nch) load((ch + 1) * kKc);
 #pragma unroll
     for (int kk = 0; kk < kKc; kk += 4) {
-      double av[MT], bv[MT];
+      double av[MR], bv[MC];
 #pragma unroll
-      for (int a = 0; a < MT; ++a) av[a] = xs[b][kk + g][wr + 16 * a + l16];
+      for (int a = 0; a < MR; ++a) av[a] = xs[b][kk + g][wr + 16 * a + l16];
 #pragma unroll
-      for (int q = 0; q < MT; ++q) bv[q] = ys[b][kk + g][wc + 16 * q + l16];
+      for (int q = 0; q < MC; ++q) bv[q] = ys[b][kk + g][wc + 16 * q + l16];
 #pragma unroll
-      for (int a = 0; a < MT; ++a)
+      for (int a = 0; a < MR; ++a)
 #pragma unroll
-        for (int q = 0; q < MT; ++q) acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[q], acc[a][q], 0, 0, 0);
+        for (int q = 0; q < MC; ++q) acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[q], acc[a][q], 0, 0, 0);
     }
     if (ch + 1 < nch) store(b ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < MT; ++a)
+  for (int a = 0; a < MR; ++a)
 #pragma unroll
-    for (int q = 0; q < MT; ++q)
+    for (int q = 0; q < MC; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t i = r0 + wr + 16 * a + g + 4 * r;
@@ -477,17 +481,17 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
       const int64_t below = n - k0 - nb;
       if (below <= 0) continue;  // nb < 64 only for the last block
       double* P = B + (k0 + nb) * n + k0;
-      k_gemm_nt<kNb><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
+      k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
                                                                       bs, ls, bs);
       const int64_t pw = K0 + W - (k0 + nb);
       if (pw > 0)
-        k_gemm_nt<kNb><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
+        k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
             P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
     }
     const int64_t rest = n - K0 - W;
     if (rest > 0) {
       double* Q = B + (K0 + W) * n + K0;
-      k_gemm_nt<kTrail><<<dim3(tiles(rest, kTrail), tiles(rest, kTrail), nv), 256, 0, st>>>(
+      k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(rest, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
           Q, n, Q, n, Q + W, n, rest, rest, W, -1.0, 1.0, 1, bs, bs, bs);
     }
   }

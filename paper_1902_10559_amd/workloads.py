@@ -87,3 +87,15 @@ def batched_slices(n_slices: int = 256, device="cuda", wdtype: str = "f32",
             if progress and (s + 1) % 32 == 0:
                 progress(f"built {s + 1}/{n_slices} slices")
     return out
+
+
+def table1_case(n: int, device="cuda") -> Slice:
+    """The direct path's workload at one of Table 1's sizes (n = 32, 64,
+    128): the n x n slice of ``geometry_normal``, its seeded phantom and
+    noise-free projections, and the fold."""
+    g = inputs.geometry_normal(n)
+    hm = native.build_system(g)
+    A = native.to_device(hm, device)
+    f = phantom_snake(g, 6, 0)
+    p = projections(A, g, f, 6, 0, 0.0, device)
+    return Slice(g, None, A, p, native.fold(A, p))
