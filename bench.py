@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-subsets", action="store_true", help="skip the ordered-subset comparison")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the direct (normal-equation) path at Table 1's sizes")
+    ap.add_argument("--no-polar", action="store_true",
+                    help="skip the polar-grid SART comparison")
     ap.add_argument("--direct-only", action="store_true",
                     help="only the direct path's report (one JSON line), for profiling it")
     ap.add_argument("--no-extras", action="store_true",
@@ -259,6 +261,11 @@ def main():
         out["direct_normal_equations"] = direct_report(dev)
         log(f"direct path: {out['direct_normal_equations']}")
 
+    # the polar grid of the closing example (Fig. 4) at 32768 voxels
+    if not args.no_polar:
+        out["polar_grid"] = polar_report(dev, lam)
+        log(f"polar grid: {out['polar_grid']}")
+
     # time to relative residual 1e-3 (capped at 20000 iterations)
     ttr = {}
     if args.workload == "slice":
@@ -328,6 +335,44 @@ def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
         rep[name] = {"median_steps": float(np.median(it)), "max_steps": int(max(it)), "reached": bool(st == 0),
                      "seconds": e0.elapsed_time(e1) * 1e-3}
     rep["speedup"] = rep["sart"]["seconds"] / rep["os_sart"]["seconds"]
+    return rep
+
+
+def polar_report(dev, lam, iters=100, reps=5):
+    """The polar grid (128 rings x 256 sectors, N = 32768; 256 parallel views
+    x 256 offsets, M = 65536; noise-free): 100 split-SART iterations against
+    100 on the unsplit A, each autotuned and graph-replayed (best of `reps`),
+    their kernels' algorithmic GB/s, and the fold."""
+    import torch
+    from paper_1902_10559_amd import native, workloads
+    case = workloads.polar_case(8, dev)
+    rep = {"M": case.A.M, "N": case.A.N, "nnz": case.A.nnz, "nnz_half": case.S.nnz, "iterations": iters}
+
+    def best_of(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    for name, S in (("split", case.S), ("unsplit", native.unsplit(case.A, case.p))):
+        sol = native.Solver([S], native.SartOptions(lam=lam, max_iter=iters, use_graph=True))
+        scratch = [S.new_image()]
+        sol.autotune(scratch)
+        f = [S.new_image()]
+        ms = best_of(lambda: sol.solve(f, want_iters=False))
+        fp, bp = sol.time_kernels(scratch, reps=50)
+        a, b = bytes_per_iteration(S.nnz, S.m, S.n, S.nvals, 4)
+        rep[name] = {"ms_per_iteration": ms / iters, "nnz_per_s": iters * case.A.nnz / (ms * 1e-3),
+                     "fp_ms": fp, "bp_ms": bp, "kernel_gbs": (a + b) / ((fp + bp) * 1e-3) / 1e9}
+    rep["split_vs_unsplit"] = rep["unsplit"]["ms_per_iteration"] / rep["split"]["ms_per_iteration"]
+    rep["fold_ms"] = best_of(lambda: native.fold_into(case.A, case.p, case.S))
     return rep
 
 

@@ -120,6 +120,42 @@ void ss_matrix_free(ss_matrix* A);
  * voxels (host array of nx*nz entries, caller-owned).  Section 2, Fig. 1. */
 ss_status ss_snake_order(const ss_grid* grid, int64_t* snake);
 
+/* A polar grid (the closing example's tomographic gamma scanning of a
+ * cylindrical container, Fig. 4): a disk of radius `radius` (mm) centred on
+ * the origin of the slice plane, cut into `rings` rings of equal width and
+ * `sectors` (even) sectors of equal angle whose boundaries include the
+ * symmetry axis OZ.  On either side of OZ a voxel is (ring r from the
+ * centre, sector h counted from +z by the angle atan2(|x|, z)); on the side
+ * x < 0 it has index j = r*(sectors/2) + h and its mirror (x > 0) has N-1-j,
+ * N = rings*sectors: the renumbering that makes eq. (2) hold (Fig. 4b). */
+typedef struct {
+  int32_t rings, sectors;
+  double radius;
+} ss_polar_grid;
+
+/* A parallel-beam scan: K view angles phi (radians, ascending inside
+ * (-pi/2, pi/2), phi[K-1-k] == -phi[k] bitwise; 0 = rays along -z) and B
+ * lateral offsets (mm, ascending, offset[B-1-b] == -offset[b] bitwise).  Ray
+ * i = k*B + b is the line {offset[b] (cos phi, sin phi) + u (sin phi,
+ * -cos phi)}, so ray M-1-i is the mirror of ray i. */
+typedef struct {
+  int32_t K;
+  const double* phi;
+  int32_t B;
+  const double* offset;
+} ss_parallel_scan;
+
+/* Builds A for a polar grid and a parallel scan: w[i,j] = length (mm) of ray
+ * i inside voxel j, from the ray's crossings with the ring circles and the
+ * sector-boundary lines (FP64; segments <= 1e-9 mm dropped; a voxel crossed
+ * twice gets the sum, in order along the ray), rounded to FP32.  A
+ * satisfies eq. (2) bitwise.  `nthreads` <= 0 uses all hardware threads.
+ * Errors: SS_E_ARG (NULL, non-positive sizes or radius, views or offsets not
+ * ascending, a view outside (-pi/2, pi/2)), SS_E_ODD (sectors, K or B odd),
+ * SS_E_ASYM (views or offsets not mirror-exact), SS_E_NOMEM. */
+ss_status ss_build_polar_system(const ss_polar_grid* grid, const ss_parallel_scan* scan,
+                                int32_t nthreads, ss_matrix* out);
+
 /* ------------------------------------------------------------------------
  * Device-side A, the fold into systems (3)-(4), and the solver's system
  * ---------------------------------------------------------------------- */

@@ -19,7 +19,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libssart.so")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["capi.cpp", "build_system.cpp"]
+HOST_SOURCES = ["capi.cpp", "build_system.cpp", "build_polar.cpp"]
 HIP_SOURCES = ["fold.hip", "sart.hip", "ossart.hip", "normal.hip", "images.hip", "nn.hip"]
 
 HIPCC_FLAGS = [

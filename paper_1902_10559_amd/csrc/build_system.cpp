@@ -14,18 +14,16 @@
 // This file is compiled without floating-point contraction so that the same
 // expressions give the same bits on every ray.
 //
-// Rays are traced twice (count, then fill) on a pool of host threads; the
-// CSC copy is a counting sort of the CSR entries by column, stable in rows.
+// Rays are traced twice (count, then fill) on a pool of host threads
+// (host_build.h), which also forms the CSC copy.
 
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
-#include <new>
-#include <thread>
 #include <vector>
 
+#include "host_build.h"
 #include "internal.h"
 
 namespace {
@@ -123,33 +121,6 @@ struct Tracer {
   }
 };
 
-template <class F>
-void parallel_rows(int64_t M, int nthreads, F&& body) {
-  std::atomic<int64_t> next{0};
-  const int64_t chunk = 256;
-  auto worker = [&]() {
-    std::vector<double> alphas;
-    std::vector<std::pair<int32_t, double>> seg;
-    alphas.reserve(4096);
-    seg.reserve(4096);
-    for (;;) {
-      const int64_t s = next.fetch_add(chunk);
-      if (s >= M) break;
-      const int64_t e = std::min(M, s + chunk);
-      for (int64_t i = s; i < e; ++i) body(i, alphas, seg);
-    }
-  };
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nthreads; ++t) pool.emplace_back(worker);
-  worker();
-  for (auto& th : pool) th.join();
-}
-
-template <class T>
-T* alloc(int64_t count) {
-  return static_cast<T*>(std::malloc(sizeof(T) * static_cast<size_t>(std::max<int64_t>(count, 1))));
-}
-
 }  // namespace
 
 extern "C" ss_status ss_snake_order(const ss_grid* grid, int64_t* snake) {
@@ -201,58 +172,11 @@ extern "C" ss_status ss_build_system(const ss_grid* grid, const ss_geometry* geo
   const int64_t N = static_cast<int64_t>(grid->nx) * grid->nz;
   if (N > INT32_MAX || M > INT32_MAX)
     return ss::fail(SS_E_ARG, "ss_build_system: M and N must fit in int32");
-  int nt = nthreads > 0 ? nthreads : static_cast<int>(std::thread::hardware_concurrency());
-  nt = std::max(1, std::min(nt, 256));
-
+  const int nt = ss::host::threads(nthreads);
   const Tracer tr(*grid);
-  auto ray = [&](int64_t i, std::vector<double>& al, std::vector<std::pair<int32_t, double>>& seg) {
+  auto ray = [&](int64_t i, std::vector<double>& al, ss::host::Segments& seg) {
     const int64_t k = i / B, b = i % B;
     tr.trace(geom->src_x[k], geom->src_z[k], geom->bin_x[b], geom->det_z, al, seg);
   };
-
-  ss_matrix A{};
-  A.M = M;
-  A.N = N;
-  A.row_ptr = alloc<int64_t>(M + 1);
-  if (!A.row_ptr) return ss::fail(SS_E_NOMEM, "ss_build_system: out of host memory");
-  A.row_ptr[0] = 0;
-  parallel_rows(M, nt, [&](int64_t i, std::vector<double>& al, std::vector<std::pair<int32_t, double>>& seg) {
-    ray(i, al, seg);
-    A.row_ptr[i + 1] = static_cast<int64_t>(seg.size());
-  });
-  for (int64_t i = 0; i < M; ++i) A.row_ptr[i + 1] += A.row_ptr[i];
-  const int64_t nnz = A.row_ptr[M];
-  A.nnz = nnz;
-  A.col_idx = alloc<int32_t>(nnz);
-  A.val = alloc<float>(nnz);
-  A.col_ptr = alloc<int64_t>(N + 1);
-  A.row_idx = alloc<int32_t>(nnz);
-  A.val_t = alloc<float>(nnz);
-  if (!A.col_idx || !A.val || !A.col_ptr || !A.row_idx || !A.val_t) {
-    ss_matrix_free(&A);
-    return ss::fail(SS_E_NOMEM, "ss_build_system: out of host memory (nnz=%lld)", (long long)nnz);
-  }
-  parallel_rows(M, nt, [&](int64_t i, std::vector<double>& al, std::vector<std::pair<int32_t, double>>& seg) {
-    ray(i, al, seg);
-    int64_t o = A.row_ptr[i];
-    for (const auto& s : seg) {
-      A.col_idx[o] = s.first;
-      A.val[o] = static_cast<float>(s.second);
-      ++o;
-    }
-  });
-  // CSC: counting sort by column, stable in row order
-  std::memset(A.col_ptr, 0, sizeof(int64_t) * static_cast<size_t>(N + 1));
-  for (int64_t e = 0; e < nnz; ++e) A.col_ptr[A.col_idx[e] + 1]++;
-  for (int64_t j = 0; j < N; ++j) A.col_ptr[j + 1] += A.col_ptr[j];
-  std::vector<int64_t> fill(A.col_ptr, A.col_ptr + N);
-  for (int64_t i = 0; i < M; ++i) {
-    for (int64_t e = A.row_ptr[i]; e < A.row_ptr[i + 1]; ++e) {
-      const int64_t o = fill[A.col_idx[e]]++;
-      A.row_idx[o] = static_cast<int32_t>(i);
-      A.val_t[o] = A.val[e];
-    }
-  }
-  *out = A;
-  return SS_OK;
+  return ss::host::assemble(M, N, nt, ray, "ss_build_system", out);
 }

@@ -159,6 +159,8 @@ WORKLOADS = {
     4: Workload("cfg4: 256 slices 1024 x nz, K=24, 2048 bins", 4, 10, 0.0, 100),
     5: Workload("cfg5: 256x256 slice, K=16, 512 bins", 5, 10, 0.0, 200),
     6: Workload("cfg6: Table 1 shapes, n x n slices, normal equations", 6, 10, 0.0, 0),
+    7: Workload("cfg7: polar grid 3 rings x 24 sectors (72 voxels), 12 views x 24 offsets", 7, 4, 0.0, 20),
+    8: Workload("cfg8: polar grid 128 rings x 256 sectors, 256 views x 256 offsets", 8, 10, 0.0, 100),
 }
 
 
@@ -170,6 +172,91 @@ def geometry_for(cfg: int) -> Geometry:
     if cfg == 5:
         return geometry_cfg5()
     raise ValueError("cfg4 has one geometry per slice: use geometry_cfg4_slice")
+
+
+# ------------------------------------------------------- polar geometry
+@dataclasses.dataclass(frozen=True)
+class PolarGeometry:
+    """A polar voxel grid (``rings`` x ``sectors`` voxels of a disk of
+    ``radius`` mm, sector boundaries including OZ) and a parallel-beam scan
+    (view angles ``phi`` in (-pi/2, pi/2), lateral offsets ``offset`` mm,
+    both mirror-exact); ray i = k*B + b."""
+    rings: int
+    sectors: int
+    radius: float
+    phi: np.ndarray
+    offset: np.ndarray
+
+    @property
+    def K(self) -> int:
+        return int(self.phi.shape[0])
+
+    @property
+    def B(self) -> int:
+        return int(self.offset.shape[0])
+
+    @property
+    def M(self) -> int:
+        return self.K * self.B
+
+    @property
+    def N(self) -> int:
+        return self.rings * self.sectors
+
+
+def parallel_views(K: int) -> np.ndarray:
+    """K view angles evenly spread over the half-turn (-pi/2, pi/2), mirror
+    exact: (k + 1/2) pi / K - pi/2."""
+    assert K % 2 == 0
+    return mirrored((np.arange(K // 2) + 0.5) * (math.pi / K))
+
+
+def geometry_tgs() -> PolarGeometry:
+    """The closing example's size: 72 voxels (3 rings x 24 sectors) of a
+    300 mm-radius container, 12 views x 24 offsets 25 mm apart (288 rays)."""
+    return PolarGeometry(3, 24, 300.0, parallel_views(12), detector_bins(24, 25.0))
+
+
+def geometry_polar_large() -> PolarGeometry:
+    """128 rings x 256 sectors (N = 32768) of a 300 mm disk, 256 views x
+    256 offsets 2.34375 mm apart (M = 65536)."""
+    return PolarGeometry(128, 256, 300.0, parallel_views(256), detector_bins(256, 600.0 / 256))
+
+
+def polar_voxel_centres(g: PolarGeometry) -> tuple[np.ndarray, np.ndarray]:
+    """(x, z) of every voxel's centre (mid radius, mid angle) in index order
+    j = r*(S/2) + h on the side x < 0, N-1-j for its mirror."""
+    S2 = g.sectors // 2
+    r = np.repeat(np.arange(g.rings), S2)
+    h = np.tile(np.arange(S2), g.rings)
+    rho = (r + 0.5) * g.radius / g.rings
+    ang = (h + 0.5) * (2.0 * math.pi / g.sectors)
+    x_left, z = -rho * np.sin(ang), rho * np.cos(ang)
+    x = np.concatenate([x_left, -x_left[::-1]])
+    zz = np.concatenate([z, z[::-1]])
+    return x, zz
+
+
+def polar_phantom(cfg: int, item: int, g: PolarGeometry) -> np.ndarray:
+    """Seeded ellipses inside the disk (centres within 0.6 R, semi-axes in
+    [0.1, 0.4] R, densities in [0.1, 1]) sampled at the voxel centres, as a
+    vector in the polar numbering."""
+    rng = rng_for(cfg, item, STREAM_PHANTOM)
+    n = WORKLOADS[cfg].n_ellipses
+    R = g.radius
+    rad = 0.6 * R * np.sqrt(rng.uniform(0.0, 1.0, n))
+    th = rng.uniform(0.0, 2.0 * math.pi, n)
+    e = Ellipses(rad * np.sin(th), rad * np.cos(th), rng.uniform(0.1, 0.4, n) * R,
+                 rng.uniform(0.1, 0.4, n) * R, rng.uniform(0.0, math.pi, n), rng.uniform(0.1, 1.0, n))
+    x, z = polar_voxel_centres(g)
+    f = np.zeros(g.N)
+    for k in range(n):
+        dx, dz = x - e.cx[k], z - e.cz[k]
+        cs, sn = math.cos(e.phi[k]), math.sin(e.phi[k])
+        u = (dx * cs + dz * sn) / e.a[k]
+        v = (-dx * sn + dz * cs) / e.b[k]
+        f += np.where(u * u + v * v <= 1.0, e.rho[k], 0.0)
+    return f
 
 
 # ----------------------------------------------------------------- phantoms

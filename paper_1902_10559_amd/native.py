@@ -36,6 +36,15 @@ class GeometryC(C.Structure):
                 ("bin_x", C.POINTER(C.c_double)), ("det_z", C.c_double)]
 
 
+class PolarGridC(C.Structure):
+    _fields_ = [("rings", C.c_int32), ("sectors", C.c_int32), ("radius", C.c_double)]
+
+
+class ParallelScanC(C.Structure):
+    _fields_ = [("K", C.c_int32), ("phi", C.POINTER(C.c_double)), ("B", C.c_int32),
+                ("offset", C.POINTER(C.c_double))]
+
+
 class MatrixC(C.Structure):
     _fields_ = [("M", C.c_int64), ("N", C.c_int64), ("nnz", C.c_int64),
                 ("row_ptr", C.POINTER(C.c_int64)), ("col_idx", C.POINTER(C.c_int32)),
@@ -74,6 +83,8 @@ class SubsetsC(C.Structure):
 _SIGNATURES = {
     "ss_last_error": (C.c_char_p, []),
     "ss_version": (C.c_char_p, []),
+    "ss_build_polar_system": (C.c_int32, [C.POINTER(PolarGridC), C.POINTER(ParallelScanC), C.c_int32,
+                               C.POINTER(MatrixC)]),
     "ss_build_system": (C.c_int32, [C.POINTER(Grid), C.POINTER(GeometryC), C.c_int32,
                                     C.POINTER(MatrixC)]),
     "ss_matrix_free": (None, [C.POINTER(MatrixC)]),
@@ -201,6 +212,24 @@ def build_system(geom, nthreads: int = 0) -> HostMatrix:
                    bx.ctypes.data_as(dp), float(geom.det_z))
     m = MatrixC()
     _check(lib().ss_build_system(C.byref(g), C.byref(gc), int(nthreads), C.byref(m)))
+    return _take_host(m)
+
+
+def build_polar_system(geom, nthreads: int = 0) -> HostMatrix:
+    """ss_build_polar_system for a polar grid and parallel scan described by
+    ``inputs.PolarGeometry``."""
+    g = PolarGridC(int(geom.rings), int(geom.sectors), float(geom.radius))
+    phi = np.ascontiguousarray(geom.phi, dtype=np.float64)
+    off = np.ascontiguousarray(geom.offset, dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    sc = ParallelScanC(len(phi), phi.ctypes.data_as(dp), len(off), off.ctypes.data_as(dp))
+    m = MatrixC()
+    _check(lib().ss_build_polar_system(C.byref(g), C.byref(sc), int(nthreads), C.byref(m)))
+    return _take_host(m)
+
+
+def _take_host(m: MatrixC) -> HostMatrix:
+    """Copies a library-owned host matrix into numpy arrays and frees it."""
     try:
         M, N, nnz = m.M, m.N, m.nnz
         out = HostMatrix(M, N, nnz,

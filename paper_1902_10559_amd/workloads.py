@@ -99,3 +99,15 @@ def table1_case(n: int, device="cuda") -> Slice:
     f = phantom_snake(g, 6, 0)
     p = projections(A, g, f, 6, 0, 0.0, device)
     return Slice(g, None, A, p, native.fold(A, p))
+
+
+def polar_case(cfg: int, device="cuda") -> Slice:
+    """A polar-grid workload (cfg 7: the closing example's 72 voxels; cfg 8:
+    128 rings x 256 sectors): the library's polar matrix, noise-free
+    projections of the seeded polar phantom, and the fold."""
+    g = inputs.geometry_tgs() if cfg == 7 else inputs.geometry_polar_large()
+    hm = native.build_polar_system(g)
+    A = native.to_device(hm, device)
+    f = inputs.polar_phantom(cfg, 0, g).astype(np.float32)
+    p = projections(A, g, f, cfg, 0, inputs.WORKLOADS[cfg].noise, device)
+    return Slice(g, None, A, p, native.fold(A, p))

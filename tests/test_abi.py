@@ -122,3 +122,37 @@ def test_fold_rejects_odd_sizes_before_device_work():
     assert st == -2
     assert "even" in L.ss_last_error().decode()
     assert L.ss_image_fold(one, 7, one, None) == -2
+
+
+@pytest.mark.parametrize("which", ["tgs", "medium"])
+def test_host_build_polar_system_matches_oracle_bitwise(which):
+    from oracle import polar as P
+    if which == "tgs":
+        g = inputs.geometry_tgs()
+    else:
+        g = inputs.PolarGeometry(12, 32, 150.0, inputs.parallel_views(20), inputs.detector_bins(40, 7.3))
+    hm = native.build_polar_system(g, nthreads=3)
+    A = G.to_fp32(P.system_matrix(g))
+    assert (hm.M, hm.N, hm.nnz) == (A.shape[0], A.shape[1], A.nnz)
+    assert np.array_equal(hm.row_ptr, A.indptr)
+    assert np.array_equal(hm.col_idx, A.indices)
+    assert np.array_equal(hm.val.view(np.uint32), A.data.view(np.uint32))
+    Ac = A.tocsc()
+    Ac.sort_indices()
+    assert np.array_equal(hm.col_ptr, Ac.indptr)
+    assert np.array_equal(hm.row_idx, Ac.indices)
+    assert np.array_equal(hm.val_t.view(np.uint32), Ac.data.view(np.uint32))
+    assert G.is_symmetric(hm.to_scipy())
+
+
+def test_build_polar_system_rejects_bad_scans():
+    g = inputs.geometry_tgs()
+    bad = [(dict(sectors=23), -2), (dict(phi=np.concatenate([g.phi[:-1], [-g.phi[0] + 1e-12]])), -3),
+           (dict(offset=np.concatenate([g.offset[:-1], [-g.offset[0] * (1 + 1e-15)]])), -3),
+           (dict(phi=inputs.mirrored([0.3, 1.6])), -1), (dict(radius=0.0), -1)]
+    for change, code in bad:
+        d = dict(rings=g.rings, sectors=g.sectors, radius=g.radius, phi=g.phi, offset=g.offset)
+        d.update(change)
+        with pytest.raises(native.SSError) as e:
+            native.build_polar_system(inputs.PolarGeometry(**d))
+        assert e.value.code == code, change
