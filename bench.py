@@ -19,8 +19,8 @@ Workloads:
 The same step on the unsplit A is timed beside it.  Extras: ordered-subset
 SART against SART to a residual of 1e-2, the direct path (normal equations by
 Cholesky, Theorem 2) on Table 1's three sizes, time to a residual of 1e-3,
-and the CPU oracle's rate.  ``--direct-only`` prints just the direct path's
-report.
+and the CPU oracle's rate.  ``--direct-only``, ``--polar-only`` and
+``--subsets-only`` print just that report.
 
 Output: one JSON line on stdout (progress on stderr).  ``value`` is
 original-system nonzeros processed per second: iterations x nnz(A) / time.
@@ -62,6 +62,10 @@ def parse():
                     help="skip the polar-grid SART comparison")
     ap.add_argument("--direct-only", action="store_true",
                     help="only the direct path's report (one JSON line), for profiling it")
+    ap.add_argument("--polar-only", action="store_true",
+                    help="only the polar-grid report (one JSON line), for profiling it")
+    ap.add_argument("--subsets-only", action="store_true",
+                    help="only the ordered-subset comparison on the workload (one JSON line)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
     ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT,CHUNKED",
@@ -139,6 +143,9 @@ def main():
     if args.direct_only:
         print(json.dumps({"direct_normal_equations": direct_report(dev)}), flush=True)
         return
+    if args.polar_only:
+        print(json.dumps({"polar_grid": polar_report(dev, 0.5)}), flush=True)
+        return
     log(f"setting up workload {args.workload}")
     slices, desc, lam = setup(args, dev)
     systems = [x.S for x in slices]
@@ -185,6 +192,10 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k, time.perf_counter() - t0
+
+    if args.subsets_only:
+        print(json.dumps({"ordered_subsets": subsets_report(slices, systems, opts, dev, lam)}), flush=True)
+        return
 
     ms, wall = timed(split_step, args.steps, args.warmup)
     value = iters * nnz_full / (ms * 1e-3)
