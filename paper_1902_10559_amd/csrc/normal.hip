@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "device.h"
@@ -430,6 +431,28 @@ ss_status check_normal(const ss_system* sys, const char* fn) {
 
 inline unsigned blocks(int64_t count, int per) { return static_cast<unsigned>((count + per - 1) / per); }
 
+// The factorisation's second stream and its events, one set per device,
+// created on first use and kept for the process.  A call holds its
+// device's lock from start to end, so calls that overlap on one device run
+// one after the other.
+struct Lookahead {
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::mutex mu;
+};
+constexpr int kMaxDevices = 64;
+Lookahead g_lookahead[kMaxDevices];
+
+ss_status lookahead_resources(Lookahead& la, size_t events) {
+  if (!la.side) SS_HIP_TRY(hipStreamCreateWithFlags(&la.side, hipStreamNonBlocking));
+  while (la.ev.size() < events) {
+    hipEvent_t e;
+    SS_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    la.ev.push_back(e);
+  }
+  return SS_OK;
+}
+
 }  // namespace
 }  // namespace ss
 
@@ -463,17 +486,40 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
   double* Linv = reinterpret_cast<double*>(ws + L.linv);
   const int64_t bs = L.bs, vs = L.vs, ls = L.ls;
   auto tiles = [](int64_t v, int t) { return static_cast<unsigned>((v + t - 1) / t); };
+  int dev = 0;
+  SS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SS_E_ARG, "ss_normal_solve: device %d out of range", dev);
+  Lookahead& la = g_lookahead[dev];
+  std::lock_guard<std::mutex> lock(la.mu);
+  const int64_t npanel = (n + kPanel - 1) / kPanel;
+  if (ss_status s = lookahead_resources(la, static_cast<size_t>(2 * npanel + 1))) return s;
+  hipEvent_t* evF = la.ev.data();              // panel p factored
+  hipEvent_t* evU = la.ev.data() + npanel;     // panel p's far trailing update done
+  hipEvent_t evFork = la.ev[static_cast<size_t>(2 * npanel)];
+  hipStream_t sb = la.side;
+
   SS_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
   // Both halves go through every launch together (blockIdx.z = half): they
   // are independent systems, so the latency-bound steps of the
   // factorisation are shared between them.
   k_form_b<<<dim3(static_cast<unsigned>(n), 1, nv), kFormThreads, 0, st>>>(*sys, B, bs, c, vs);
-  // Blocked right-looking Cholesky, lower, in place: panels of kPanel
-  // columns factored 64 columns at a time (diagonal block, panel solve as a
-  // product with L_kk^{-T}, update of the panel's remaining columns); then
-  // one trailing update of the rest with K = kPanel.
-  for (int64_t K0 = 0; K0 < n; K0 += kPanel) {
+  SS_HIP_TRY(hipEventRecord(evFork, st));
+  SS_HIP_TRY(hipStreamWaitEvent(sb, evFork, 0));
+  // Blocked right-looking Cholesky, lower, in place, with a look-ahead of
+  // one panel.  Panel p (kPanel columns) is factored on the caller's stream
+  // 64 columns at a time (diagonal block, panel solve as a product with
+  // L_kk^{-T}, update of the panel's remaining columns).  Its trailing update
+  // is cut in two: the next panel's columns (near), on the caller's stream,
+  // and everything to their right (far), on the second stream, where it
+  // runs while the next panel is factored.  Ordering: panel p waits for the
+  // far update of panel p-2 (the last one that touches its columns and has
+  // not been waited for); the near update of panel p waits for the far
+  // update of panel p-1 (both write panel p+1's columns); the far update of
+  // panel p waits for panel p's factor.
+  for (int64_t p = 0; p < npanel; ++p) {
+    const int64_t K0 = p * kPanel;
     const int64_t W = std::min<int64_t>(kPanel, n - K0);
+    if (p >= 2) SS_HIP_TRY(hipStreamWaitEvent(st, evU[p - 2], 0));
     for (int64_t k0 = K0; k0 < K0 + W; k0 += kNb) {
       const int nb = static_cast<int>(std::min<int64_t>(kNb, K0 + W - k0));
       double* Lk = Linv + (k0 / kNb) * kNb * kNb;
@@ -488,13 +534,25 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
         k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
             P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
     }
+    SS_HIP_TRY(hipEventRecord(evF[p], st));
     const int64_t rest = n - K0 - W;
     if (rest > 0) {
       double* Q = B + (K0 + W) * n + K0;
-      k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(rest, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
-          Q, n, Q, n, Q + W, n, rest, rest, W, -1.0, 1.0, 1, bs, bs, bs);
+      const int64_t W1 = std::min<int64_t>(kPanel, rest);
+      if (p >= 1) SS_HIP_TRY(hipStreamWaitEvent(st, evU[p - 1], 0));
+      k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(W1, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
+          Q, n, Q, n, Q + W, n, rest, W1, W, -1.0, 1.0, 1, bs, bs, bs);
+      const int64_t far = rest - W1;
+      if (far > 0) {
+        SS_HIP_TRY(hipStreamWaitEvent(sb, evF[p], 0));
+        double* Qf = Q + W1 * n;
+        k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(far, kTrail), tiles(far, kTrail), nv), 64 * kTrailWaves, 0, sb>>>(
+            Qf, n, Qf, n, Qf + W + W1, n, far, far, W, -1.0, 1.0, 1, bs, bs, bs);
+      }
     }
+    SS_HIP_TRY(hipEventRecord(evU[p], sb));
   }
+  SS_HIP_TRY(hipStreamWaitEvent(st, evU[npanel - 1], 0));
   // L y = c, then L^T x = y
   for (int64_t k = 0; k < nt; ++k) {
     const int64_t k0 = k * kNb;
