@@ -293,82 +293,133 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* B, int64_t ld, int64
   }
 }
 
-// Forward substitution, block k of L y = c: y_k = L_kk^{-1} c_k, then
-// c[i] -= sum_t L[i, k0+t] y_k[t] for the 64 rows i >= k0 + nb of this
-// block (thread (row, quarter) takes 16 consecutive t, the quarters summed
-// across adjacent lanes in a fixed order).  Every block forms y_k (c_k is
-// not written here); block 0 stores it.
-__global__ __launch_bounds__(256) void k_fwd_step(const double* L, int64_t ld, int64_t n, int64_t k0, int nb,
-                                                  const double* Linv, double* c, double* y, int64_t bs, int64_t ls,
-                                                  int64_t vs) {
-  __shared__ double li[kNb][kNb + 1];
-  __shared__ double ck[kNb], yk[kNb];
-  const int tid = threadIdx.x;
-  L += blockIdx.z * bs;  // the half
-  Linv += blockIdx.z * ls;
+// Substitutions.  y_k = L_kk^{-1} c_k for the first block, and x_k =
+// L_kk^{-T} y_k for the last, by one block each (thread (t, quarter) sums
+// 16 terms, the quarters added across adjacent lanes in a fixed order).
+__global__ __launch_bounds__(256) void k_diag_fwd(const double* Linv, const double* c, double* y, int64_t k0, int nb,
+                                                  int64_t ls, int64_t vs) {
+  Linv += blockIdx.z * ls;  // the half
   c += blockIdx.z * vs;
   y += blockIdx.z * vs;
-  for (int e = tid; e < kNb * kNb; e += 256) li[e / kNb][e % kNb] = Linv[e];
-  if (tid < kNb) ck[tid] = (tid < nb) ? c[k0 + tid] : 0.0;
-  __syncthreads();
-  if (tid < kNb) {
-    double a = 0.0;
-    for (int q = 0; q <= tid; ++q) a += li[tid][q] * ck[q];
-    yk[tid] = a;
-    if (blockIdx.x == 0 && tid < nb) y[k0 + tid] = a;
-  }
-  __syncthreads();
-  const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * kNb + tid / 4;
-  const int qp = (tid % 4) * 16;
+  const int t = threadIdx.x / 4, qp = (threadIdx.x % 4) * 16;
   double a = 0.0;
-  if (i < n) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (qp + u < nb) a += L[i * ld + k0 + qp + u] * yk[qp + u];
+  for (int u = 0; u < 16; ++u) {
+    const int q = qp + u;
+    a += Linv[t * kNb + q] * (q < nb ? c[k0 + q] : 0.0);
   }
   a += __shfl_xor(a, 1, kWave);
   a += __shfl_xor(a, 2, kWave);
-  if (i < n && tid % 4 == 0) c[i] -= a;
+  if (threadIdx.x % 4 == 0 && t < nb) y[k0 + t] = a;
 }
 
-// Back substitution, block k of L^T x = y (from the last block): x_k =
-// L_kk^{-T} y_k, then y[i] -= sum_t L[k0+t, i] x_k[t] for the 64 rows i < k0
-// of this block (wavefront w takes t = 16w .. 16w+15, lanes run along i;
-// the four partial sums are added in wavefront order).
-__global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, int64_t k0, int nb,
-                                                  const double* Linv, double* y, double* x, int64_t bs, int64_t ls,
-                                                  int64_t vs) {
-  __shared__ double li[kNb][kNb + 1];
-  __shared__ double yk[kNb], xk[kNb];
+__global__ __launch_bounds__(256) void k_diag_bwd(const double* Linv, const double* y, double* x, int64_t k0, int nb,
+                                                  int64_t ls, int64_t vs) {
+  __shared__ double part[4][kNb];
+  Linv += blockIdx.z * ls;  // the half
+  y += blockIdx.z * vs;
+  x += blockIdx.z * vs;
+  const int t = lane_id(), w = wave_id();
+  double a = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = 16 * w + u;
+    a += Linv[q * kNb + t] * (q < nb ? y[k0 + q] : 0.0);
+  }
+  part[w][t] = a;
+  __syncthreads();
+  if (threadIdx.x < kNb && t < nb) x[k0 + t] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+}
+
+// Forward substitution, block k of L y = c (k0 = 64 k, a full block with
+// rows below): with y_k already formed, c[i] -= sum_t L[i, k0+t] y_k[t] for
+// this block's 64 rows i >= k0 + 64 (thread (row, quarter) takes 16
+// consecutive t; quarters added across adjacent lanes in a fixed order).
+// Block 0's rows are block k+1's, which no later step touches: block 0 then
+// forms y_{k+1} = L^{-1}_{k+1,k+1} c_{k+1} for the next step, so no block
+// has to stage an inverse.
+__global__ __launch_bounds__(256) void k_fwd_step(const double* L, int64_t ld, int64_t n, int64_t k0,
+                                                  const double* Linv_next, double* c, double* y, int64_t bs,
+                                                  int64_t ls, int64_t vs) {
+  __shared__ double yk[kNb], cn[kNb];
+  const int tid = threadIdx.x;
+  L += blockIdx.z * bs;  // the half
+  Linv_next += blockIdx.z * ls;
+  c += blockIdx.z * vs;
+  y += blockIdx.z * vs;
+  if (tid < kNb) yk[tid] = y[k0 + tid];
+  __syncthreads();
+  const int r = tid / 4, qp = (tid % 4) * 16;
+  const int64_t i = k0 + kNb + static_cast<int64_t>(blockIdx.x) * kNb + r;
+  const int64_t ic = i < n ? i : n - 1;  // rows past n read a valid row; their result is dropped
+  double a = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) a += L[ic * ld + k0 + qp + u] * yk[qp + u];
+  a += __shfl_xor(a, 1, kWave);
+  a += __shfl_xor(a, 2, kWave);
+  double cnew = 0.0;
+  if (i < n) {
+    cnew = c[i] - a;
+    if (tid % 4 == 0) c[i] = cnew;
+  }
+  if (blockIdx.x != 0) return;
+  if (tid % 4 == 0) cn[r] = cnew;  // zero past n: the padded part of block k+1
+  __syncthreads();
+  const int nb_next = static_cast<int>(std::min<int64_t>(kNb, n - k0 - kNb));
+  double b = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) b += Linv_next[r * kNb + qp + u] * cn[qp + u];
+  b += __shfl_xor(b, 1, kWave);
+  b += __shfl_xor(b, 2, kWave);
+  if (tid % 4 == 0 && r < nb_next) y[k0 + kNb + r] = b;
+}
+
+// Back substitution, block k of L^T x = y (from the last block; k >= 1):
+// with x_k already formed, y[i] -= sum_t L[k0+t, i] x_k[t] for this block's
+// 64 rows i < k0 (wavefront w takes t = 16w .. 16w+15, lanes run along i;
+// the four partial sums added in wavefront order).  The last block's rows
+// are block k-1's: it then forms x_{k-1} = L^{-T}_{k-1,k-1} y_{k-1}.
+__global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, int64_t n, int64_t k0, int nb,
+                                                  const double* Linv_prev, double* y, double* x, int64_t bs,
+                                                  int64_t ls, int64_t vs) {
+  __shared__ double xk[kNb], yn[kNb];
   __shared__ double part[4][kNb];
   const int tid = threadIdx.x;
   L += blockIdx.z * bs;  // the half
-  Linv += blockIdx.z * ls;
+  Linv_prev += blockIdx.z * ls;
   y += blockIdx.z * vs;
   x += blockIdx.z * vs;
-  for (int e = tid; e < kNb * kNb; e += 256) li[e / kNb][e % kNb] = Linv[e];
-  if (tid < kNb) yk[tid] = (tid < nb) ? y[k0 + tid] : 0.0;
+  if (tid < kNb) xk[tid] = tid < nb ? x[k0 + tid] : 0.0;
   __syncthreads();
-  if (tid < kNb) {
-    double a = 0.0;
-    for (int q = tid; q < kNb; ++q) a += li[q][tid] * yk[q];
-    xk[tid] = a;
-    if (blockIdx.x == 0 && tid < nb) x[k0 + tid] = a;
-  }
-  __syncthreads();
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNb + lane_id();
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNb + lane_id();  // < k0: the grid covers k0 rows
   const int w = wave_id();
   double a = 0.0;
-  if (i < k0) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int q = 16 * w + u;
-      if (q < nb) a += L[(k0 + q) * ld + i] * xk[q];
-    }
+  for (int u = 0; u < 16; ++u) {
+    const int q = 16 * w + u;
+    const int64_t row = std::min<int64_t>(k0 + q, n - 1);  // past n: x_k is 0 there
+    a += L[row * ld + i] * xk[q];
   }
   part[w][lane_id()] = a;
   __syncthreads();
-  if (tid < kNb && i < k0) y[i] -= ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+  double ynew = 0.0;
+  if (tid < kNb) {
+    ynew = y[i] - (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]);
+    y[i] = ynew;
+  }
+  if (blockIdx.x + 1 != gridDim.x) return;
+  if (tid < kNb) yn[tid] = ynew;
+  __syncthreads();
+  const int t = lane_id();
+  double b = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = 16 * w + u;
+    b += Linv_prev[q * kNb + t] * yn[q];
+  }
+  part[w][t] = b;
+  __syncthreads();
+  if (tid < kNb) x[k0 - kNb + t] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
 }
 
 // f[j] = (f2 + f1) / 2, f[N-1-j] = (f2 - f1) / 2 (eq. (5)), or a copy for
@@ -553,18 +604,24 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
     SS_HIP_TRY(hipEventRecord(evU[p], sb));
   }
   SS_HIP_TRY(hipStreamWaitEvent(st, evU[npanel - 1], 0));
-  // L y = c, then L^T x = y
-  for (int64_t k = 0; k < nt; ++k) {
+  // L y = c, then L^T x = y, 64 rows a step
+  k_diag_fwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv, c, y, 0, static_cast<int>(std::min<int64_t>(kNb, n)), ls, vs);
+  for (int64_t k = 0; k + 1 < nt; ++k) {
     const int64_t k0 = k * kNb;
-    const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
-    k_fwd_step<<<dim3(std::max(1u, blocks(n - k0 - nb, kNb)), 1, nv), 256, 0, st>>>(
-        B, n, n, k0, nb, Linv + k * kNb * kNb, c, y, bs, ls, vs);
+    k_fwd_step<<<dim3(blocks(n - k0 - kNb, kNb), 1, nv), 256, 0, st>>>(B, n, n, k0, Linv + (k + 1) * kNb * kNb, c, y,
+                                                                      bs, ls, vs);
   }
-  for (int64_t k = nt - 1; k >= 0; --k) {
+  {
+    const int64_t k0 = (nt - 1) * kNb;
+    k_diag_bwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv + (nt - 1) * kNb * kNb, y, x, k0,
+                                               static_cast<int>(n - k0), ls, vs);
+  }
+  for (int64_t k = nt - 1; k >= 1; --k) {
     const int64_t k0 = k * kNb;
     const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
-    k_bwd_step<<<dim3(std::max(1u, blocks(k0, kNb)), 1, nv), 256, 0, st>>>(B, n, k0, nb, Linv + k * kNb * kNb, y, x,
-                                                                            bs, ls, vs);
+    k_bwd_step<<<dim3(static_cast<unsigned>(k0 / kNb), 1, nv), 256, 0, st>>>(B, n, n, k0, nb,
+                                                                              Linv + (k - 1) * kNb * kNb, y, x, bs,
+                                                                              ls, vs);
   }
   k_recombine_f64<<<blocks(n, 256), 256, 0, st>>>(x, x + vs, n, sys->nvals, f);
   SS_HIP_TRY(hipGetLastError());
