@@ -434,8 +434,11 @@ ss_status ss_normal_workspace_bytes(const ss_system* sys, size_t* bytes);
  * inv_col are not read.  Errors: those of ss_normal_workspace_bytes;
  * SS_E_WORKSPACE if the workspace is too small; SS_E_SHAPE if a normal
  * matrix is not positive definite (A, or A(1) or A(2), lacks full column
- * rank: a zero or negative pivot; f then holds no solution).  SYNCHRONISES
- * the stream once. */
+ * rank: a zero or negative pivot; f then holds no solution).  Part of the
+ * factorisation runs on a second stream that the library creates once per
+ * device (default priority), ordered against `stream` by events; calls on
+ * one device are serialised by a lock held for the whole call.
+ * SYNCHRONISES the stream once. */
 ss_status ss_normal_solve(const ss_system* sys, double* f, void* workspace,
                           size_t workspace_bytes, void* stream);
 
