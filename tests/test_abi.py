@@ -156,3 +156,43 @@ def test_build_polar_system_rejects_bad_scans():
         with pytest.raises(native.SSError) as e:
             native.build_polar_system(inputs.PolarGeometry(**d))
         assert e.value.code == code, change
+
+
+def test_normal_equations_are_validated_on_the_host():
+    """ss_normal_workspace_bytes sizes the dense path (nvals * n^2 doubles
+    and O(n)) and rejects, before any device work, what it cannot solve."""
+    L = native.lib()
+    nb = C.c_size_t()
+    s = _fake_system(m=40, n=6, nvals=2)
+    assert L.ss_normal_workspace_bytes(C.byref(s), C.byref(nb)) == 0
+    assert nb.value >= 2 * 6 * 6 * 8
+    one = _fake_system(m=40, n=6, nvals=1)
+    nb1 = C.c_size_t()
+    assert L.ss_normal_workspace_bytes(C.byref(one), C.byref(nb1)) == 0
+    assert nb1.value < nb.value
+    for bad in [_fake_system(n=(1 << 17) + 1), _fake_system(nvals=3), _fake_system(m=0)]:
+        assert L.ss_normal_workspace_bytes(C.byref(bad), C.byref(nb)) == -1
+    bf16 = _fake_system()
+    bf16.wdtype = 1
+    assert L.ss_normal_workspace_bytes(C.byref(bf16), C.byref(nb)) == -1
+    assert L.ss_normal_solve(C.byref(s), None, C.c_void_p(16), 1 << 20, None) == -1
+    assert L.ss_normal_solve(C.byref(s), C.c_void_p(16), C.c_void_p(16), 8, None) == -8
+
+
+def test_polar_voxel_centres_follow_the_numbering():
+    """The seeded polar phantom samples voxel j at its centre: the centre of
+    j and of N-1-j are mirrors, and each lies in the ring and sector that
+    the numbering gives j."""
+    import math
+    from oracle import polar as P
+    g = inputs.PolarGeometry(3, 8, 30.0, inputs.parallel_views(4), inputs.detector_bins(4, 5.0))
+    x, z = inputs.polar_voxel_centres(g)
+    assert np.array_equal(x[::-1], -x) and np.array_equal(z[::-1], z)
+    for r in range(3):
+        for h in range(4):
+            for left in (True, False):
+                j = P.voxel_index(r, h, left, 3, 8)
+                rho = math.hypot(x[j], z[j])
+                assert int(rho * 3 / 30.0) == r
+                assert int(math.atan2(abs(x[j]), z[j]) / (2 * math.pi / 8)) == h
+                assert (x[j] < 0) == left
