@@ -9,7 +9,6 @@ import pytest
 from gpu_util import banner, rel_l2, to_np
 from oracle import geometry as G
 from oracle import sart as OS
-from oracle import split as OSp
 from paper_1902_10559_amd import inputs, learned, unet
 
 pytestmark = pytest.mark.gpu

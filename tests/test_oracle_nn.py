@@ -1,7 +1,6 @@
 """Pins for the network reference: finite differences for every gradient,
 library cross-correlation for the convolution, closed forms for the rest."""
 import numpy as np
-import pytest
 
 from oracle import nn
 
