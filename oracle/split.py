@@ -186,7 +186,8 @@ def round_storage(v32: np.ndarray, dtype: str) -> np.ndarray:
     rounds to nearest-even."""
     v32 = np.asarray(v32, dtype=np.float32)
     if dtype == "f16":
-        return v32.astype(np.float16).astype(np.float64)
+        with np.errstate(over="ignore"):  # beyond the binary16 range: +-inf, as intended
+            return v32.astype(np.float16).astype(np.float64)
     assert dtype == "bf16"
     bits = v32.view(np.uint32).astype(np.uint64)
     lo_bits = (bits & 0xFFFF0000).astype(np.uint32)

@@ -153,7 +153,8 @@ def test_bf16_and_f16_rounding_match_library_conversions():
     v = np.concatenate([v, ties, np.float32([0.0, -0.0, 1.0, 3.0e38, -1.5e-40])])
     want = torch.from_numpy(v).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     assert np.array_equal(split.storage_bits(v, "bf16"), want)
-    assert np.array_equal(split.storage_bits(v, "f16"), v.astype(np.float16).view(np.uint16))
+    with np.errstate(over="ignore"):  # 3e38 rounds to inf in binary16
+        assert np.array_equal(split.storage_bits(v, "f16"), v.astype(np.float16).view(np.uint16))
     # rounding is to nearest: error at most half an ulp of 8 (bf16) bits
     r = split.round_storage(v[:100000], "bf16")
     nz = v[:100000] != 0
