@@ -3,7 +3,8 @@ FP32 matrices: the solution within 1e-7 relative L2 (both sides solve the
 same FP64 normal equations; Cholesky rounding grows with cond(B) ~ 1e7),
 for the split pair (recombined) and for A itself; and Theorem 2 on the GPU:
 the split and unsplit solutions, and the phantom for consistent data, agree
-up to the FP32 rounding of the folded values."""
+up to the FP32 rounding of the folded values.  Repeated and interleaved
+calls (the look-ahead stream and events are reused) are bitwise reproducible."""
 import numpy as np
 import pytest
 
@@ -89,3 +90,27 @@ def test_singular_normal_matrix_is_reported():
         with pytest.raises(native.SSError) as e:
             native.normal_solve(S)
         assert e.value.code == -4
+
+
+def test_repeated_and_interleaved_solves_are_reproducible():
+    """The factorisation's second stream and its events are reused from call
+    to call: solves of different sizes and forms, interleaved, give bitwise
+    the same results as the first time."""
+    import torch
+    banner("normal equations repeated")
+    A32, p32, _ = _table1_problem(32)
+    rng = np.random.default_rng(7)
+    from symm import random_symmetric_sparse
+    Ar = random_symmetric_sparse(rng, 600, 266, 0.3)
+    pr = (Ar.astype(np.float64) @ rng.uniform(0, 1, 266)).astype(np.float32)
+    cases = [(A32, p32, True), (Ar, pr, False), (A32, p32, False), (Ar, pr, True)]
+    first = [_solve(A, p, split) for A, p, split in cases]
+    for (A, p, split), want in zip(cases[::-1], first[::-1]):
+        got = _solve(A, p, split)
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    # on a side stream of the caller's
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got = _solve(A32, p32, True)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.view(np.uint64), first[0].view(np.uint64))
