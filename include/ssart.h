@@ -188,12 +188,24 @@ typedef struct {
  * inv_row (m), inv_col (n): FP32 reciprocals of the FP64 row and column sums
  *   of A (which equal those of A(2)), 0 where a sum is 0; SART normalises
  *   both halves with them.
- * Stream layout: the solver reads col_idx/val and row_idx/val_t in aligned
- * chunks of SS_CHUNK entries, so each of these four arrays must start on a
- * 16-byte boundary and have room for ss_stream_len(nnz) entries (nnz rounded
- * up to a multiple of SS_CHUNK); entries past nnz are read and ignored, never
- * written.  The same holds for A's arrays when a system aliases them
- * (ss_unsplit). */
+ * Stream layout: the solver reads col_idx/val and row_idx/val_t in chunks
+ * of SS_CHUNK entries, so each of these four arrays must start on a 16-byte
+ * boundary and have room for ss_stream_len(nnz) entries (nnz rounded up to
+ * a multiple of SS_CHUNK, plus SS_CHUNK: the interleaved order's last loads
+ * reach up to SS_CHUNK - 1 entries past the last line); entries past nnz are
+ * read and ignored, never written.  The same holds for A's arrays when a system aliases them
+ * (ss_unsplit).
+ * row_lanes, col_lanes: order of the entries within each row (column).
+ *   0: ascending, the CSR/CSC convention.  L > 0: the interleaved order of
+ *   the solver's stream form for groups of L lanes: a line of n entries is
+ *   cut into blocks of SS_CHUNK*L entries (the last one r < SS_CHUNK*L
+ *   long), and entry e of a block, with lane g = e mod L and q = r / L,
+ *   sits at g*q + min(g, r mod L) + e / L within it.  ss_fold writes that
+ *   order when the caller sets these fields; ss_sart_* then read the lines
+ *   in place with rows_per_wave = 64/row_lanes (cols_per_wave =
+ *   64/col_lanes).  row_lanes is 0, 8, 16, 32 or 64, col_lanes 0, 4, 8, 16,
+ *   32 or 64 (else SS_E_ARG).  ss_unsplit, ss_subsets_build, ss_ossart_*
+ *   and ss_normal_* need 0 (else SS_E_ARG). */
 typedef struct {
   int64_t m, n, nnz;
   int32_t nvals;
@@ -207,14 +219,16 @@ typedef struct {
   float* p;
   float* inv_row;
   float* inv_col;
+  int32_t row_lanes;
+  int32_t col_lanes;
 } ss_system;
 
 /* Entries per aligned chunk of the solver's index and value streams. */
 #define SS_CHUNK 4
 
 /* Capacity, in entries, that the index and value arrays of a system with nnz
- * stored entries must have: nnz rounded up to a multiple of SS_CHUNK (0 for
- * nnz <= 0). */
+ * stored entries must have: nnz rounded up to a multiple of SS_CHUNK, plus
+ * SS_CHUNK (0 for nnz <= 0). */
 int64_t ss_stream_len(int64_t nnz);
 
 /* Bytes of workspace ss_fold_size and ss_fold need for an M x N matrix. */
@@ -235,6 +249,8 @@ ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* workspace,
  * one correctly rounded FP32 subtraction/addition per entry, then rounded to
  * nearest-even for BF16/FP16 storage; p1/p2 likewise in FP32; inv_row/inv_col
  * from FP64 sums of A's FP32 entries.  A must have passed ss_fold_size.
+ * Each output line is written in the order out->row_lanes (rows) and
+ * out->col_lanes (columns) select (see ss_system; 0: ascending).
  * `workspace`: device scratch of ss_fold_workspace_bytes(M, N) bytes (its
  * contents on entry do not matter).  Asynchronous. */
 ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out,
@@ -292,7 +308,17 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *   chunked      stream form per kernel, bit 0 forward, bit 1 back
  *                projection: 0 = entry-wise (lanes of a group hold adjacent
  *                entries), 1 = aligned chunks of SS_CHUNK entries per lane
- *                (fewer, wider loads; gathers spread over more cache lines)
+ *                (fewer, wider loads; gathers spread over more cache lines);
+ *                bit 2 forward, bit 3 back projection (taking precedence
+ *                over bits 0 and 1): interleaved, i.e. the solver first
+ *                copies the line lists into its workspace in an order where
+ *                each lane reads SS_CHUNK entries with one load and a gather
+ *                still has adjacent lanes on adjacent entries; the sums run
+ *                in the entry-wise order, so results equal the entry-wise
+ *                form's bitwise.  Needs entries of at least 4 bytes (not a
+ *                single system with 16-bit values: SS_E_ARG) and workspace
+ *                for the copies (ss_sart_workspace_bytes counts it); the copy
+ *                is made on every solve
  *   persistent   1: size the grid to the resident capacity and let each block
  *                loop over tiles (prefetching the next one); 0: one block
  *                per tile
@@ -346,7 +372,9 @@ ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys,
 
 /* Picks rows_per_wave, cols_per_wave, unroll, persistent, chunked and xcd_remap by
  * timing every candidate (ss_sart_time_kernels) and writes them into
- * *opts.  Results are cached per (nvals, wdtype, shape statistics).
+ * *opts.  The interleaved forms are candidates only when workspace_bytes
+ * holds their copies; their per-solve copy time, spread over opts->max_iter
+ * iterations, is added to their kernel times.  Results are cached per (nvals, wdtype, shape statistics).
  * The images f are used as scratch.  Synchronises. */
 ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float* const* f,
                            ss_sart_opts* opts, void* workspace,

@@ -27,5 +27,5 @@ extern "C" const char* ss_last_error(void) { return g_last_error; }
 extern "C" const char* ss_version(void) { return "ssart 0.1 gfx950"; }
 
 extern "C" int64_t ss_stream_len(int64_t nnz) {
-  return nnz <= 0 ? 0 : (nnz + SS_CHUNK - 1) / SS_CHUNK * SS_CHUNK;
+  return nnz <= 0 ? 0 : (nnz + SS_CHUNK - 1) / SS_CHUNK * SS_CHUNK + SS_CHUNK;
 }

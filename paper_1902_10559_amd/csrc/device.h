@@ -214,6 +214,47 @@ __device__ inline void load_val_chunk(const void* base, int64_t k0, Vec<NV>* v) 
   }
 }
 
+// Loads of SS_CHUNK consecutive entries starting at any entry k (the
+// interleaved stream form): 4-byte alignment is all the vector loads need.
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+// (the address-space cast is written out: template deduction would drop the
+// typedef's alignment)
+__device__ inline u32x4 load_idx_at(const int32_t* idx, int64_t k) {
+  return *(const SS_GLOBAL u32x4_a4*)(idx + k);
+}
+
+// Values of entries k .. k+3 widened to FP32; entries of at least 4 bytes
+// (a pair, or one FP32 value).
+template <int NV, int WT>
+__device__ inline void load_val_at(const void* base, int64_t k, Vec<NV>* v) {
+  static_assert(NV == 2 || WT == SS_F32, "entries of at least 4 bytes");
+  if constexpr (NV == 2 && WT == SS_F32) {
+    const SS_GLOBAL u32x4_a8* p = (const SS_GLOBAL u32x4_a8*)(reinterpret_cast<const uint64_t*>(base) + k);
+    const u32x4 a = p[0], b = p[1];
+    v[0].v[0] = __uint_as_float(a.x);
+    v[0].v[1] = __uint_as_float(a.y);
+    v[1].v[0] = __uint_as_float(a.z);
+    v[1].v[1] = __uint_as_float(a.w);
+    v[2].v[0] = __uint_as_float(b.x);
+    v[2].v[1] = __uint_as_float(b.y);
+    v[3].v[0] = __uint_as_float(b.z);
+    v[3].v[1] = __uint_as_float(b.w);
+  } else {
+    const u32x4 a = *(const SS_GLOBAL u32x4_a4*)(reinterpret_cast<const uint32_t*>(base) + k);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (NV == 2) {
+        v[j].v[0] = widen16<WT>(a[j] & 0xffffu);
+        v[j].v[1] = widen16<WT>(a[j] >> 16);
+      } else {
+        v[j].v[0] = __uint_as_float(a[j]);
+      }
+    }
+  }
+}
+
 }  // namespace ss
 
 #define SS_HIP_TRY(expr)                                                          \

@@ -21,6 +21,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "lines.h"
 
 namespace ss {
 namespace {
@@ -112,20 +113,43 @@ struct LSeq {
 constexpr int kStageRow = 384;
 constexpr int kStageCol = 256;
 
-// Copies a sorted list of len (<= capacity) entries into shared memory and
-// returns how many of its indices are below `limit` (a prefix).
-__device__ inline int64_t stage_list(const int32_t* gi, const float* gv, int64_t len, SS_LDS int32_t* si,
-                                     SS_LDS float* sv, int32_t limit) {
-  int64_t below = 0;
-  for (int64_t b = 0; b < len; b += kWave) {
-    const int64_t k = b + lane_id();
-    int32_t c = INT32_MAX;
+// A sorted list of len (<= R * 64) entries in registers, R per lane: all
+// its loads are issued before the first is waited for, so a line pair costs
+// one memory latency, not one per 64 entries.  VALS: also the values (the
+// counting pass needs only the indices).
+template <int R, bool VALS>
+struct Staged {
+  int32_t c[R];
+  float v[R];
+};
+
+template <int R, bool VALS>
+__device__ inline void stage_load(const int32_t* gi, const float* gv, int64_t len, Staged<R, VALS>& s) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t k = static_cast<int64_t>(r) * kWave + lane_id();
+    s.c[r] = INT32_MAX;
     if (k < len) {
-      c = gi[k];
-      si[k] = c;
-      sv[k] = gv[k];
+      s.c[r] = gl(gi)[k];
+      if constexpr (VALS) s.v[r] = gl(gv)[k];
     }
-    below += __popcll(__ballot(c < limit));
+  }
+}
+
+// Writes the staged list to shared memory and returns how many of its
+// indices are below `limit` (a prefix).
+template <int R, bool VALS>
+__device__ inline int64_t stage_store(const Staged<R, VALS>& s, int64_t len, SS_LDS int32_t* si, SS_LDS float* sv,
+                                      int32_t limit) {
+  int64_t below = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t k = static_cast<int64_t>(r) * kWave + lane_id();
+    if (k < len) {
+      si[k] = s.c[r];
+      if constexpr (VALS) sv[k] = s.v[r];
+    }
+    below += __popcll(__ballot(s.c[r] < limit));
   }
   return below;
 }
@@ -140,11 +164,13 @@ __device__ inline void wave_lds_sync() {
 
 // Merges X and Y as described at the top of the file.  FILL writes every
 // union entry at out_base + position: its index and the pair (a - b, a + b)
-// in storage type WT.  Returns the union size (in every lane) and adds each
+// in storage type WT.  With lanes > 0 the position within the line (of
+// n_out entries) is permuted into the solver's interleaved order for groups
+// of that many lanes.  Returns the union size (in every lane) and adds each
 // entry's FP64 a + b to the lane's `sum`.
 template <bool FILL, int WT, class SX, class SY>
 __device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_t* out_idx, void* out_val,
-                              double& sum) {
+                              double& sum, int64_t n_out, int lanes) {
   const int lane = lane_id();
   int64_t common = 0;
   for (int64_t base = 0; base < X.len; base += kWave) {
@@ -161,7 +187,8 @@ __device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_
     const uint64_t mask = __ballot(dup);
     if (FILL && valid) {
       const int64_t before = common + __popcll(mask & lanemask_lt());
-      const int64_t pos = k + r - before;
+      const int64_t pos0 = k + r - before;
+      const int64_t pos = lanes ? interleaved_pos(pos0, n_out, lanes) : pos0;
       const float a = X.value(k);
       const float b = dup ? Y.value(r) : 0.0f;
       out_idx[out_base + pos] = x;
@@ -185,7 +212,8 @@ __device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_
     const uint64_t mask = __ballot(dup);
     if (FILL && valid && !dup) {
       const int64_t before = seen + __popcll(mask & lanemask_lt());
-      const int64_t pos = s + l - before;
+      const int64_t pos0 = s + l - before;
+      const int64_t pos = lanes ? interleaved_pos(pos0, n_out, lanes) : pos0;
       const float b = Y.value(l);
       out_idx[out_base + pos] = y;
       store_pair<WT>(out_val, out_base + pos, 0.0f - b, 0.0f + b);
@@ -240,35 +268,39 @@ struct StageBuf {
 // size, and with FILL the entries written at out_base.
 template <bool COLS, bool FILL, int WT>
 __device__ int64_t fold_line(const ss_matrix_dev& A, int64_t t, int64_t out_base, int32_t* out_idx,
-                             void* out_val, double& sum, StageBuf sb) {
+                             void* out_val, double& sum, StageBuf sb, int64_t n_out, int lanes) {
   if constexpr (COLS) {
-    const int64_t cs = A.col_ptr[t], ce = A.col_ptr[t + 1];
+    const int64_t cs = gl(A.col_ptr)[t], ce = gl(A.col_ptr)[t + 1];
     const int64_t len = ce - cs;
     if (len <= kStageCol) {
-      const int64_t split = stage_list(A.row_idx + cs, A.val_t + cs, len, sb.idx, sb.val,
-                                       static_cast<int32_t>(A.M / 2));
+      Staged<kStageCol / kWave, FILL> sl;
+      stage_load(A.row_idx + cs, A.val_t + cs, len, sl);
+      const int64_t split = stage_store(sl, len, sb.idx, sb.val, static_cast<int32_t>(A.M / 2));
       wave_lds_sync();
       const LSeq<false> X{sb.idx, sb.val, split, 0};
       const LSeq<true> Y{sb.idx + split, sb.val + split, len - split, static_cast<int32_t>(A.M - 1)};
-      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum);
+      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum, n_out, lanes);
     }
     const ColLists L = col_lists(A, t);
-    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum);
+    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum, n_out, lanes);
   } else {
-    const int64_t rs = A.row_ptr[t], re = A.row_ptr[t + 1];
     const int64_t t2 = A.M - 1 - t;
-    const int64_t ys = A.row_ptr[t2], ye = A.row_ptr[t2 + 1];
+    const int64_t rs = gl(A.row_ptr)[t], re = gl(A.row_ptr)[t + 1];
+    const int64_t ys = gl(A.row_ptr)[t2], ye = gl(A.row_ptr)[t2 + 1];
     if (re - rs <= kStageRow && ye - ys <= kStageRow) {
       const int32_t n = static_cast<int32_t>(A.N / 2);
-      const int64_t xl = stage_list(A.col_idx + rs, A.val + rs, re - rs, sb.idx, sb.val, n);
-      const int64_t yl = stage_list(A.col_idx + ys, A.val + ys, ye - ys, sb.idx + kStageRow, sb.val + kStageRow, n);
+      Staged<kStageRow / kWave, FILL> sx, sy;
+      stage_load(A.col_idx + rs, A.val + rs, re - rs, sx);
+      stage_load(A.col_idx + ys, A.val + ys, ye - ys, sy);
+      const int64_t xl = stage_store(sx, re - rs, sb.idx, sb.val, n);
+      const int64_t yl = stage_store(sy, ye - ys, sb.idx + kStageRow, sb.val + kStageRow, n);
       wave_lds_sync();
       const LSeq<false> X{sb.idx, sb.val, xl, 0};
       const LSeq<false> Y{sb.idx + kStageRow, sb.val + kStageRow, yl, 0};
-      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum);
+      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum, n_out, lanes);
     }
     const RowLists L = row_lists(A, t);
-    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum);
+    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum, n_out, lanes);
   }
 }
 
@@ -359,7 +391,7 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_check_pairs(ss_matrix_dev
   int64_t cnt = 0;
   if (sane) {
     double unused = 0.0;
-    cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb);
+    cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb, 0, 0);
   }
   h = wave_sum_u64(h);
   unsigned f = flags;
@@ -424,7 +456,7 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(JobArg J) {
   const int64_t t = lb * kFoldWaves + wave_id();
   if (t >= lines) return;
   double unused = 0.0;
-  const int64_t cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb);
+  const int64_t cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb, 0, 0);
   int64_t* ptr = COLS ? jb.out.col_ptr : jb.out.row_ptr;
   if (lane_id() == 0) {
     ptr[t + 1] = cnt;
@@ -544,8 +576,13 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_fill(JobArg J) {
   const int64_t t = lb * kFoldWaves + wave_id();
   if (t >= lines) return;
   double sum = 0.0;
-  if constexpr (COLS) fold_line<true, true, WT>(A, t, out.col_ptr[t], out.row_idx, out.val_t, sum, sb);
-  else fold_line<false, true, WT>(A, t, out.row_ptr[t], out.col_idx, out.val, sum, sb);
+  if constexpr (COLS) {
+    const int64_t o = out.col_ptr[t];
+    fold_line<true, true, WT>(A, t, o, out.row_idx, out.val_t, sum, sb, out.col_ptr[t + 1] - o, out.col_lanes);
+  } else {
+    const int64_t o = out.row_ptr[t];
+    fold_line<false, true, WT>(A, t, o, out.col_idx, out.val, sum, sb, out.row_ptr[t + 1] - o, out.row_lanes);
+  }
   sum = group_sum<kWave>(sum);
   if (lane_id() == 0) {
     if constexpr (COLS) {
@@ -649,6 +686,7 @@ ss_status check_fold_out(const ss_matrix_dev* A, const float* p, const ss_system
   if (!out->row_ptr || !out->col_ptr || !out->p || !out->inv_row || !out->inv_col ||
       (out->nnz > 0 && (!out->col_idx || !out->val || !out->row_idx || !out->val_t)))
     return fail(SS_E_ARG, "%s: NULL output array", fn);
+  if (ss_status s = check_lanes(out, fn)) return s;
   return SS_OK;
 }
 
@@ -791,6 +829,7 @@ extern "C" ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_syste
     return fail(SS_E_ARG, "ss_unsplit: NULL output array");
   if (out->wdtype == SS_F32 && (out->val != A->val || out->val_t != A->val_t))
     return fail(SS_E_ARG, "ss_unsplit: FP32 values must alias A's arrays");
+  if (ss_status s = check_ascending(out, "ss_unsplit")) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   k_line_recip<false><<<blocks_for(A->M), kWave * kFoldWaves, 0, st>>>(A->row_ptr, A->val, A->M, out->inv_row);
   k_line_recip<true><<<blocks_for(A->N), kWave * kFoldWaves, 0, st>>>(A->col_ptr, A->val_t, A->N, out->inv_col);

@@ -95,6 +95,66 @@ __device__ inline void line_dot_c(const int32_t* idx, const void* val, const flo
   }
 }
 
+// Interleaved stream form.  A line of n entries is cut into blocks of
+// SS_CHUNK * L entries (the last one shorter, r entries).  Within a block,
+// lane g of the group takes the entries g, g + L, g + 2L, ... of the block
+// (q = r / L of them, one more if g < r mod L), and they are stored
+// consecutively, lane after lane: entry e of the block (lane e mod L, slot
+// e / L) sits at position g*q + min(g, r mod L) + e / L.  One load of
+// SS_CHUNK entries per lane then streams a block, as in the chunked form,
+// while a gather instruction still has adjacent lanes on adjacent entries of
+// the line, as in the entry-wise form.  The permutation stays inside each
+// line, so the line offsets do not change.
+__host__ __device__ inline int64_t interleaved_pos(int64_t e, int64_t n, int L) {
+  const int64_t B = static_cast<int64_t>(SS_CHUNK) * L;
+  const int64_t b = e / B, s = e - b * B;
+  const int64_t r = n - b * B < B ? n - b * B : B;
+  const int64_t q = r / L, rem = r - q * L;
+  const int64_t g = s % L;
+  return b * B + g * q + (g < rem ? g : rem) + s / L;
+}
+
+// P blocks per pass.  Idle slots (past a lane's share of a block, or blocks
+// past the line's last) are masked out.  A lane's load of SS_CHUNK entries
+// starts at most at the end of its block, so the loads reach at most
+// SS_CHUNK entries past the line's end: the interleaved copy of a stream
+// has room for nnz + SS_CHUNK entries.
+template <int NV, int WT, int L, int P>
+__device__ inline void line_dot_i(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
+                                  int glane, float* acc) {
+  constexpr int B = SS_CHUNK * L;
+  const int n = static_cast<int>(hi - lo);
+  const int nb = (n + B - 1) / B;
+  for (int b0 = 0; b0 < nb; b0 += P) {
+    u32x4 c[P];
+    Vec<NV> v[P][SS_CHUNK];
+    int cnt[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int b = b0 + u < nb ? b0 + u : nb - 1;
+      const int r = n - b * B < B ? n - b * B : B;
+      const int q = r / L, rem = r % L;
+      cnt[u] = b0 + u < nb ? q + (glane < rem ? 1 : 0) : 0;
+      const int64_t k = lo + b * B + glane * q + (glane < rem ? glane : rem);
+      c[u] = load_idx_at(idx, k);
+      load_val_at<NV, WT>(val, k, v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+#pragma unroll
+      for (int j = 0; j < SS_CHUNK; ++j) {
+        const bool in = j < cnt[u];
+        const Vec<NV> xv = load_vec<NV>(x, in ? static_cast<int32_t>(c[u][j]) : 0);
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+          const float sum = fmaf(v[u][j].v[h], xv.v[h], acc[h]);
+          acc[h] = in ? sum : acc[h];
+        }
+      }
+    }
+  }
+}
+
 // U entries per lane in flight per pass, entry-wise or in chunks (CH).
 template <int NV, int WT, int L, int U, bool CH>
 __device__ inline void line_dot(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,

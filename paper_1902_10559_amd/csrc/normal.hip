@@ -472,6 +472,7 @@ ss_status check_normal(const ss_system* sys, const char* fn) {
   if (!sys) return fail(SS_E_ARG, "%s: NULL system", fn);
   if (sys->wdtype != SS_F32 || (sys->nvals != 1 && sys->nvals != 2))
     return fail(SS_E_ARG, "%s: an FP32 system with nvals 1 or 2 is required", fn);
+  if (ss_status e = check_ascending(sys, fn)) return e;
   if (sys->m <= 0 || sys->n <= 0 || sys->nnz < 0 || !sys->col_ptr || !sys->p ||
       (sys->nnz > 0 && (!sys->row_idx || !sys->val_t)))
     return fail(SS_E_ARG, "%s: bad system", fn);

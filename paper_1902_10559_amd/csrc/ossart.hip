@@ -311,6 +311,7 @@ ss_status os_validate(const ss_system* sys, const ss_subsets* sub, int nsys, con
     const ss_system& Y = sys[s];
     if (Y.nvals != 2 || Y.wdtype != SS_F32)
       return fail(SS_E_ARG, "%s: system %d: ordered subsets need a folded FP32 pair", fn, s);
+    if (ss_status e = check_ascending(&Y, fn)) return e;
     if (Y.m <= 0 || Y.n <= 0 || Y.nnz < 0 || Y.m > INT32_MAX || Y.n > INT32_MAX)
       return fail(SS_E_ARG, "%s: system %d has a bad size", fn, s);
     if (!Y.row_ptr || !Y.col_ptr || !Y.p || !Y.inv_row ||
@@ -501,6 +502,7 @@ extern "C" ss_status ss_subsets_build(const ss_system* sys, ss_subsets* sub, voi
   if (!sys || !sub) return fail(SS_E_ARG, "ss_subsets_build: NULL argument");
   if (sys->nvals != 2 || sys->wdtype != SS_F32)
     return fail(SS_E_ARG, "ss_subsets_build: ordered subsets need a folded FP32 pair");
+  if (ss_status e = check_ascending(sys, "ss_subsets_build")) return e;
   if (sys->m <= 0 || sys->n <= 0 || !sys->col_ptr || (sys->nnz > 0 && (!sys->row_idx || !sys->val_t)))
     return fail(SS_E_ARG, "ss_subsets_build: bad system");
   if (sub->S <= 0 || sub->S > sys->m || sys->m % sub->S != 0)

@@ -180,7 +180,36 @@ __device__ inline TileCtx tile_ctx(const SysDesc* table, int nsys, uint32_t t, u
 // RPW*kWPB rows.  Per tile: p and 1/W are requested first, then the row
 // sums, then the next tile's context (so its loads overlap this tile's
 // reduction), then the residual, z and the block's FP64 partial.
-template <int NV, int WT, int RPW, int U, bool CH>
+// Stream forms: 0 entry-wise, 1 aligned chunks, 2 interleaved (the line's
+// entries read from the workspace copy that k_interleave writes).
+template <int NV, int WT, int L, int U, int SF>
+__device__ inline void line_sum(const int32_t* idx, const void* val, const float* x, int64_t lo, int64_t hi,
+                                int glane, float* acc) {
+  if constexpr (SF == 2) line_dot_i<NV, WT, L, U / SS_CHUNK>(idx, val, x, lo, hi, glane, acc);
+  else line_dot<NV, WT, L, U, SF == 1>(idx, val, x, lo, hi, glane, acc);
+}
+
+// Copies one line list (CSR rows or CSC columns) into the interleaved order
+// of line_dot_i, one wavefront per line.  VB: value bytes per entry (4 or 8).
+template <int VB>
+__global__ __launch_bounds__(kThreads) void k_interleave(const int64_t* __restrict__ ptr, int64_t lines,
+                                                         const int32_t* __restrict__ idx,
+                                                         const void* __restrict__ val, int32_t* __restrict__ idx_out,
+                                                         void* __restrict__ val_out, int L) {
+  const int64_t line = static_cast<int64_t>(blockIdx.x) * kWPB + wave_id();
+  if (line >= lines) return;
+  const int64_t lo = gl(ptr)[line], n = gl(ptr)[line + 1] - lo;
+  for (int64_t e = lane_id(); e < n; e += kWave) {
+    const int64_t d = lo + interleaved_pos(e, n, L);
+    glw(idx_out)[d] = gl(idx)[lo + e];
+    if constexpr (VB == 8)
+      glw(static_cast<uint64_t*>(val_out))[d] = gl(static_cast<const uint64_t*>(val))[lo + e];
+    else
+      glw(static_cast<uint32_t*>(val_out))[d] = gl(static_cast<const uint32_t*>(val))[lo + e];
+  }
+}
+
+template <int NV, int WT, int RPW, int U, int SF>
 __global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* __restrict__ table, int nsys,
                                                       uint32_t ntiles, int xcd, int parity) {
   constexpr int L = kWave / RPW;
@@ -204,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_sart_fp(const SysDesc* __restrict_
       float acc[NV];
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-      line_dot<NV, WT, L, U, CH>(S.col_idx, S.val, S.f[parity], cur.lo, cur.hi, glane, acc);
+      line_sum<NV, WT, L, U, SF>(S.col_idx, S.val, S.f[parity], cur.lo, cur.hi, glane, acc);
       if (more) nxt = tile_ctx<false, RPW>(table, nsys, tn, ntiles, xcd);
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
@@ -261,7 +290,7 @@ __device__ void finalize_residual(const Params* prm, const SysDesc& S, double* r
 // Back projection and update, with the residual finalisation in the first
 // tile of each system.  Grid-stride over tiles of CPW*kWPB columns, with the
 // same ordering as the forward kernel.
-template <int NV, int WT, int CPW, int U, bool CH>
+template <int NV, int WT, int CPW, int U, int SF>
 __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* __restrict__ prm,
                                                       const SysDesc* __restrict__ table, int nsys,
                                                       uint32_t ntiles, int xcd, int parity) {
@@ -291,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void k_sart_bp(const Params* __restrict__
         float acc[NV];
 #pragma unroll
         for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-        line_dot<NV, WT, L, U, CH>(S.row_idx, S.val_t, S.z, cur.lo, cur.hi, glane, acc);
+        line_sum<NV, WT, L, U, SF>(S.row_idx, S.val_t, S.z, cur.lo, cur.hi, glane, acc);
         if (more) nxt = tile_ctx<true, CPW>(table, nsys, tn, ntiles, xcd);
         prefetched = true;
 #pragma unroll
@@ -326,11 +355,28 @@ __global__ __launch_bounds__(kThreads) void k_finish(const SysDesc* table) {
 struct Layout {
   size_t params, table, states, z, partials, total;
   std::vector<size_t> z_off, part_off, f_off;
+  // interleaved copies of the row (forward) and column (back) streams
+  std::vector<size_t> fi_idx, fi_val, bi_idx, bi_val;
 };
+
+// Stream form of each kernel from the chunked option: bit 2 (bit 3) selects
+// the interleaved form for the forward (back) projection, else bit 0 (bit 1)
+// the chunked one.
+inline int fp_form(int ch) { return (ch & 4) ? 2 : (ch & 1); }
+inline int bp_form(int ch) { return (ch & 8) ? 2 : ((ch >> 1) & 1); }
+
+// Systems whose lines are stored interleaved (row_lanes / col_lanes) are
+// read in place with the interleaved form; others get workspace copies.
+inline int effective_chunked(const ss_system* sys, int ch) {
+  return ch | (sys[0].row_lanes ? 4 : 0) | (sys[0].col_lanes ? 8 : 0);
+}
+
+inline size_t value_bytes(const ss_system& S) { return static_cast<size_t>(S.nvals) * (S.wdtype == SS_F32 ? 4 : 2); }
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
 
-Layout make_layout(const ss_system* sys, int nsys) {
+Layout make_layout(const ss_system* sys, int nsys, int ch_opt) {
+  const int ch = effective_chunked(sys, ch_opt);
   Layout L;
   size_t o = 0;
   L.params = o;
@@ -353,6 +399,16 @@ Layout make_layout(const ss_system* sys, int nsys) {
     L.part_off.push_back(o);
     // the most forward-projection blocks any configuration uses: 1 row per wave
     o += align256(sizeof(double) * static_cast<size_t>((sys[s].m + kWPB - 1) / kWPB));
+  }
+  for (int s = 0; s < nsys; ++s) {
+    const size_t cap = static_cast<size_t>(sys[s].nnz) + SS_CHUNK;
+    for (int which = 0; which < 2; ++which) {
+      if (!(which ? bp_form(ch) == 2 && !sys[s].col_lanes : fp_form(ch) == 2 && !sys[s].row_lanes)) continue;
+      (which ? L.bi_idx : L.fi_idx).push_back(o);
+      o += align256(sizeof(int32_t) * cap);
+      (which ? L.bi_val : L.fi_val).push_back(o);
+      o += align256(value_bytes(sys[s]) * cap);
+    }
   }
   L.total = o;
   return L;
@@ -379,7 +435,16 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
     if (S.nnz > 0 && !(aligned(S.col_idx) && aligned(S.val) && aligned(S.row_idx) && aligned(S.val_t)))
       return fail(SS_E_ARG, "%s: system %d: index and value arrays must be 16-byte aligned", fn, s);
     if (S.m > INT32_MAX || S.n > INT32_MAX) return fail(SS_E_ARG, "%s: system %d too large", fn, s);
+    if (ss_status e = check_lanes(&S, fn)) return e;
+    if (S.row_lanes != sys[0].row_lanes || S.col_lanes != sys[0].col_lanes)
+      return fail(SS_E_ARG, "%s: all systems of one call must share row_lanes and col_lanes", fn);
   }
+  if (sys[0].row_lanes && o->rows_per_wave && o->rows_per_wave != kWave / sys[0].row_lanes)
+    return fail(SS_E_ARG, "%s: rows stored for %d lanes need rows_per_wave %d (or 0)", fn, sys[0].row_lanes,
+                kWave / sys[0].row_lanes);
+  if (sys[0].col_lanes && o->cols_per_wave && o->cols_per_wave != kWave / sys[0].col_lanes)
+    return fail(SS_E_ARG, "%s: columns stored for %d lanes need cols_per_wave %d (or 0)", fn, sys[0].col_lanes,
+                kWave / sys[0].col_lanes);
   if (!(o->lambda > 0.0f && o->lambda < 2.0f)) return fail(SS_E_ARG, "%s: lambda must be in (0, 2)", fn);
   if (o->max_iter < 0 || o->max_iter > (1 << 30)) return fail(SS_E_ARG, "%s: bad max_iter", fn);
   if (o->tol > 0.0 && o->check_every <= 0) return fail(SS_E_ARG, "%s: check_every must be > 0", fn);
@@ -387,7 +452,9 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
   if (!ok_pw(o->rows_per_wave, 8)) return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8", fn);
   if (!ok_pw(o->cols_per_wave, 16)) return fail(SS_E_ARG, "%s: cols_per_wave must be 0,1,2,4,8,16", fn);
   if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
-  if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
+  if (o->chunked < 0 || o->chunked > 15) return fail(SS_E_ARG, "%s: chunked must be 0..15", fn);
+  if ((effective_chunked(sys, o->chunked) & 12) && sys[0].nvals == 1 && sys[0].wdtype != SS_F32)
+    return fail(SS_E_ARG, "%s: the interleaved stream form needs entries of at least 4 bytes", fn);
   if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
   return SS_OK;
 }
@@ -408,11 +475,13 @@ Cfg choose_cfg(const ss_system* sys, int nsys, const ss_sart_opts* o) {
   Cfg c;
   c.nv = sys[0].nvals;
   c.wt = sys[0].wdtype;
-  c.rpw = o->rows_per_wave ? o->rows_per_wave : pick_per_wave(nnz / m, 8);
-  c.cpw = o->cols_per_wave ? o->cols_per_wave : pick_per_wave(nnz / n, 16);
+  c.rpw = sys[0].row_lanes ? kWave / sys[0].row_lanes
+         : o->rows_per_wave ? o->rows_per_wave : pick_per_wave(nnz / m, 8);
+  c.cpw = sys[0].col_lanes ? kWave / sys[0].col_lanes
+         : o->cols_per_wave ? o->cols_per_wave : pick_per_wave(nnz / n, 16);
   c.xcd = o->xcd_remap ? 1 : 0;
   c.u = o->unroll ? o->unroll : 4;
-  c.ch = o->chunked;
+  c.ch = effective_chunked(sys, o->chunked);
   c.pers = o->persistent ? 1 : 0;
   return c;
 }
@@ -421,7 +490,18 @@ struct Grids {
   uint32_t fp_blocks, bp_blocks;
 };
 
-// Writes the descriptor table and resets states (stream-ordered kernels).
+ss_status interleave(const int64_t* ptr, int64_t lines, const int32_t* idx, const void* val, int32_t* idx_out,
+                     void* val_out, size_t vb, int L, hipStream_t st) {
+  const int64_t blocks = (lines + kWPB - 1) / kWPB;
+  if (blocks > INT32_MAX) return fail(SS_E_ARG, "SART: too many lines to interleave");
+  if (vb == 8) k_interleave<8><<<static_cast<uint32_t>(blocks), kThreads, 0, st>>>(ptr, lines, idx, val, idx_out, val_out, L);
+  else k_interleave<4><<<static_cast<uint32_t>(blocks), kThreads, 0, st>>>(ptr, lines, idx, val, idx_out, val_out, L);
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+// Writes the descriptor table and resets states (stream-ordered kernels);
+// writes the interleaved stream copies where a kernel reads them.
 ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* res_hist,
                 const Params& prm, const Cfg& c, const Layout& L, char* ws, Grids* g,
                 int zero_start, hipStream_t st) {
@@ -454,6 +534,20 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
     d.bp_nblocks = static_cast<int32_t>((S.n + cpb - 1) / cpb);
     d.fp_block0 = fb;
     d.bp_block0 = bb;
+    if (S.nnz > 0 && fp_form(c.ch) == 2 && !S.row_lanes) {
+      d.col_idx = reinterpret_cast<int32_t*>(ws + L.fi_idx[s]);
+      d.val = ws + L.fi_val[s];
+      if (ss_status e = interleave(S.row_ptr, S.m, S.col_idx, S.val, const_cast<int32_t*>(d.col_idx),
+                                   const_cast<void*>(d.val), value_bytes(S), kWave / c.rpw, st))
+        return e;
+    }
+    if (S.nnz > 0 && bp_form(c.ch) == 2 && !S.col_lanes) {
+      d.row_idx = reinterpret_cast<int32_t*>(ws + L.bi_idx[s]);
+      d.val_t = ws + L.bi_val[s];
+      if (ss_status e = interleave(S.col_ptr, S.n, S.row_idx, S.val_t, const_cast<int32_t*>(d.row_idx),
+                                   const_cast<void*>(d.val_t), value_bytes(S), kWave / c.cpw, st))
+        return e;
+    }
     fb += d.fp_nblocks;
     bb += d.bp_nblocks;
     ch.d[ch.count++] = d;
@@ -510,26 +604,26 @@ void go(K kern, uint32_t ntiles, int persistent, hipStream_t st, Stamp e, Args..
   hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, e.start, e.stop, 0, args...);
 }
 
-template <int NV, int WT, int U, bool CH>
+template <int NV, int WT, int U, int SF>
 void launch_fp_u(int rpw, int pers, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par, hipStream_t st,
                  Stamp e) {
   switch (rpw) {
-    case 1: go(k_sart_fp<NV, WT, 1, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
-    case 2: go(k_sart_fp<NV, WT, 2, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
-    case 4: go(k_sart_fp<NV, WT, 4, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
-    default: go(k_sart_fp<NV, WT, 8, U, CH>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_fp<NV, WT, 1, U, SF>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_fp<NV, WT, 2, U, SF>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_fp<NV, WT, 4, U, SF>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_fp<NV, WT, 8, U, SF>, nb, pers, st, e, t, nsys, nb, xcd, par); break;
   }
 }
 
-template <int NV, int WT, int U, bool CH>
+template <int NV, int WT, int U, int SF>
 void launch_bp_u(int cpw, int pers, const Params* prm, const SysDesc* t, int nsys, uint32_t nb, int xcd, int par,
                  hipStream_t st, Stamp e) {
   switch (cpw) {
-    case 1: go(k_sart_bp<NV, WT, 1, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 2: go(k_sart_bp<NV, WT, 2, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 4: go(k_sart_bp<NV, WT, 4, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    case 8: go(k_sart_bp<NV, WT, 8, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
-    default: go(k_sart_bp<NV, WT, 16, U, CH>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 1: go(k_sart_bp<NV, WT, 1, U, SF>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 2: go(k_sart_bp<NV, WT, 2, U, SF>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 4: go(k_sart_bp<NV, WT, 4, U, SF>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    case 8: go(k_sart_bp<NV, WT, 8, U, SF>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
+    default: go(k_sart_bp<NV, WT, 16, U, SF>, nb, pers, st, e, prm, t, nsys, nb, xcd, par); break;
   }
 }
 
@@ -538,14 +632,20 @@ void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, cons
                    hipStream_t st, Stamp e = {}) {
   const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
+// single 16-bit values are rejected for the interleaved form by validate()
+#define SF2(NV, WT) ((NV) == 2 || (WT) == SS_F32 ? 2 : 0)
 #define SS_DISPATCH(NV, WT, U)                                                                      \
   if (c.nv == NV && c.wt == WT && c.u == U) {                                                       \
     if (BP) {                                                                                       \
-      if (c.ch & 2) launch_bp_u<NV, WT, U, true>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e); \
-      else launch_bp_u<NV, WT, U, false>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e);        \
+      const int sf = bp_form(c.ch);                                                                 \
+      if (sf == 2) launch_bp_u<NV, WT, U, SF2(NV, WT)>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e); \
+      else if (sf == 1) launch_bp_u<NV, WT, U, 1>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e); \
+      else launch_bp_u<NV, WT, U, 0>(c.cpw, c.pers, prm, t, nsys, g.bp_blocks, c.xcd, par, st, e);      \
     } else {                                                                                        \
-      if (c.ch & 1) launch_fp_u<NV, WT, U, true>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e);      \
-      else launch_fp_u<NV, WT, U, false>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e);             \
+      const int sf = fp_form(c.ch);                                                                 \
+      if (sf == 2) launch_fp_u<NV, WT, U, SF2(NV, WT)>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e); \
+      else if (sf == 1) launch_fp_u<NV, WT, U, 1>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e); \
+      else launch_fp_u<NV, WT, U, 0>(c.rpw, c.pers, t, nsys, g.fp_blocks, c.xcd, par, st, e);       \
     }                                                                                               \
     return;                                                                                         \
   }
@@ -562,6 +662,7 @@ void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, cons
   SS_DISPATCH(1, SS_BF16, 8)
   SS_DISPATCH(1, SS_F16, 8)
 #undef SS_DISPATCH
+#undef SF2
 }
 
 // `count` iterations; iteration i reads buffer (first + i) mod 2.
@@ -658,7 +759,7 @@ extern "C" ss_status ss_sart_workspace_bytes(const ss_system* sys, int32_t nsys,
   clear_error();
   if (!bytes) return fail(SS_E_ARG, "ss_sart_workspace_bytes: NULL bytes");
   if (ss_status s = validate(sys, nsys, opts, "ss_sart_workspace_bytes")) return s;
-  *bytes = make_layout(sys, nsys).total;
+  *bytes = make_layout(sys, nsys, opts->chunked).total;
   return SS_OK;
 }
 
@@ -670,7 +771,7 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   if (!f || !workspace) return fail(SS_E_ARG, "ss_sart_solve: NULL images or workspace");
   for (int s = 0; s < nsys; ++s)
     if (!f[s] || (res_hist && !res_hist[s])) return fail(SS_E_ARG, "ss_sart_solve: NULL image %d", s);
-  const Layout L = make_layout(sys, nsys);
+  const Layout L = make_layout(sys, nsys, opts->chunked);
   if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_solve: workspace needs %zu bytes", L.total);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
@@ -725,7 +826,7 @@ extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, fl
   if (ss_status s = validate(sys, nsys, opts, "ss_sart_time_kernels")) return s;
   if (!f || !workspace || !fp_ms || !bp_ms || reps <= 0)
     return fail(SS_E_ARG, "ss_sart_time_kernels: bad argument");
-  const Layout L = make_layout(sys, nsys);
+  const Layout L = make_layout(sys, nsys, opts->chunked);
   if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_time_kernels: workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
@@ -762,12 +863,50 @@ extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, fl
 }
 
 namespace {
+// Time of the per-solve copies of the interleaved form, rows and columns
+// (setup with the copies minus setup without them; best of 3).
+ss_status time_copies(const ss_system* sys, int nsys, float* const* f, const ss_sart_opts* opts, void* workspace,
+                      size_t workspace_bytes, hipStream_t st, double* rows_ms, double* cols_ms) {
+  hipEvent_t e0, e1;
+  SS_HIP_TRY(hipEventCreate(&e0));
+  SS_HIP_TRY(hipEventCreate(&e1));
+  double best[3] = {1e30, 1e30, 1e30};
+  const int forms[3] = {0, 4, 8};
+  ss_status result = SS_OK;
+  for (int r = 0; r < 3 && result == SS_OK; ++r) {
+    for (int k = 0; k < 3 && result == SS_OK; ++k) {
+      ss_sart_opts o = *opts;
+      o.chunked = forms[k];
+      const Layout L = make_layout(sys, nsys, o.chunked);
+      if (L.total > workspace_bytes) {
+        result = fail(SS_E_WORKSPACE, "ss_sart_autotune: workspace too small");
+        break;
+      }
+      const Cfg c = choose_cfg(sys, nsys, &o);
+      const Params prm{o.lambda, 1, -1.0, o.nonneg};
+      Grids g{};
+      (void)hipEventRecord(e0, st);
+      result = setup(sys, nsys, f, nullptr, prm, c, L, static_cast<char*>(workspace), &g, 0, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best[k] = std::min(best[k], static_cast<double>(ms));
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *rows_ms = std::max(0.0, best[1] - best[0]);
+  *cols_ms = std::max(0.0, best[2] - best[0]);
+  return result;
+}
+
 struct TuneKey {
-  int nv, wt, nsys;
+  int nv, wt, nsys, row_lanes, col_lanes;
   int64_t m_bucket, row_bucket, col_bucket;
   bool operator<(const TuneKey& o) const {
-    return std::tie(nv, wt, nsys, m_bucket, row_bucket, col_bucket) <
-           std::tie(o.nv, o.wt, o.nsys, o.m_bucket, o.row_bucket, o.col_bucket);
+    return std::tie(nv, wt, nsys, row_lanes, col_lanes, m_bucket, row_bucket, col_bucket) <
+           std::tie(o.nv, o.wt, o.nsys, o.row_lanes, o.col_lanes, o.m_bucket, o.row_bucket, o.col_bucket);
   }
 };
 std::mutex g_tune_mu;
@@ -784,7 +923,7 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
     m += static_cast<double>(sys[s].m);
     n += static_cast<double>(sys[s].n);
   }
-  const TuneKey key{sys[0].nvals, sys[0].wdtype, nsys, static_cast<int64_t>(std::log2(m)),
+  const TuneKey key{sys[0].nvals, sys[0].wdtype, nsys, sys[0].row_lanes, sys[0].col_lanes, static_cast<int64_t>(std::log2(m)),
                     static_cast<int64_t>(std::log2(1.0 + nnz / m) * 4), static_cast<int64_t>(std::log2(1.0 + nnz / n) * 4)};
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -804,29 +943,55 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
     double t = 1e30;
     int pw = 1, u = 4, xcd = 0, pers = 0, ch = 0;
   } bf, bb, df, db;
+  // stream forms: entry-wise, chunked, and interleaved where the workspace
+  // holds the interleaved copies
+  std::vector<int> forms{0, 3};
+  double copy_rows = 0.0, copy_cols = 0.0;
+  const int fixed_rows = sys[0].row_lanes ? kWave / sys[0].row_lanes : 0;
+  const int fixed_cols = sys[0].col_lanes ? kWave / sys[0].col_lanes : 0;
+  if (fixed_rows && fixed_cols) {
+    forms = {0};  // both kernels read the stored order in place
+  } else {
+    ss_sart_opts o = *opts;
+    o.chunked = 12;
+    if (validate(sys, nsys, &o, "ss_sart_autotune") == SS_OK && make_layout(sys, nsys, 12).total <= workspace_bytes) {
+      forms.push_back(12);
+      // the copies are made once per solve: spread over its iterations
+      if (ss_status s = time_copies(sys, nsys, f, opts, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
+                                    &copy_rows, &copy_cols))
+        return s;
+      const double iters = std::max(1, opts->max_iter);
+      copy_rows /= iters;
+      copy_cols /= iters;
+    }
+    clear_error();
+  }
   for (int pers = 0; pers <= 1; ++pers) {
     for (int xcd = 0; xcd <= 1; ++xcd) {
       for (int u = 4; u <= 8; u += 4) {
-        for (int ch = 0; ch <= 3; ch += 3) {
+        for (int ch : forms) {
           for (int pw = 1; pw <= 16; pw <<= 1) {
             ss_sart_opts o = *opts;
             o.persistent = pers;
             o.xcd_remap = xcd;
             o.unroll = u;
             o.chunked = ch;
-            o.rows_per_wave = pw <= 8 ? pw : 8;
-            o.cols_per_wave = pw;
+            if (fixed_rows && fixed_cols && pw > 1) continue;
+            o.rows_per_wave = fixed_rows ? fixed_rows : (pw <= 8 ? pw : 8);
+            o.cols_per_wave = fixed_cols ? fixed_cols : pw;
             double tf = 0, tb = 0;
             if (ss_status s = ss_sart_time_kernels(sys, nsys, f, &o, reps, &tf, &tb, workspace, workspace_bytes,
                                                    stream))
               return s;
+            if (fp_form(ch) == 2) tf += copy_rows;
+            if (bp_form(ch) == 2) tb += copy_cols;
             const bool base = xcd == dflt.xcd && u == dflt.u && pers == dflt.pers;
-            if (base && (ch & 1) == (dflt.ch & 1) && o.rows_per_wave == dflt.rpw && tf < df.t)
+            if (base && fp_form(ch) == fp_form(dflt.ch) && o.rows_per_wave == dflt.rpw && tf < df.t)
               df = {tf, dflt.rpw, u, xcd, pers, ch};
-            if (base && (ch & 2) == (dflt.ch & 2) && o.cols_per_wave == dflt.cpw && tb < db.t)
+            if (base && bp_form(ch) == bp_form(dflt.ch) && o.cols_per_wave == dflt.cpw && tb < db.t)
               db = {tb, dflt.cpw, u, xcd, pers, ch};
-            if (pw <= 8 && tf < bf.t) bf = {tf, pw, u, xcd, pers, ch};
-            if (tb < bb.t) bb = {tb, pw, u, xcd, pers, ch};
+            if (pw <= 8 && tf < bf.t) bf = {tf, o.rows_per_wave, u, xcd, pers, ch};
+            if (tb < bb.t) bb = {tb, o.cols_per_wave, u, xcd, pers, ch};
           }
         }
       }
@@ -842,7 +1007,7 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
   opts->xcd_remap = slow.xcd;
   opts->unroll = slow.u;
   opts->persistent = slow.pers;
-  opts->chunked = (bf.ch & 1) | (bb.ch & 2);
+  opts->chunked = (bf.ch & 5) | (bb.ch & 10);
   std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tune[key] = std::make_tuple(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll,
                                 opts->persistent, opts->chunked);

@@ -63,7 +63,8 @@ class SystemC(C.Structure):
                 ("nvals", C.c_int32), ("wdtype", C.c_int32),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
                 ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p), ("val_t", C.c_void_p),
-                ("p", C.c_void_p), ("inv_row", C.c_void_p), ("inv_col", C.c_void_p)]
+                ("p", C.c_void_p), ("inv_row", C.c_void_p), ("inv_col", C.c_void_p),
+                ("row_lanes", C.c_int32), ("col_lanes", C.c_int32)]
 
 
 class SartOptsC(C.Structure):
@@ -319,12 +320,17 @@ class System:
     p: "torch.Tensor"
     inv_row: "torch.Tensor"
     inv_col: "torch.Tensor"
+    # order of the entries within each row / column: 0 ascending, L the
+    # solver's interleaved order for groups of L lanes (what ss_fold writes)
+    row_lanes: int = 0
+    col_lanes: int = 0
 
     def c(self) -> SystemC:
         return SystemC(self.m, self.n, self.nnz, self.nvals, WDTYPES[self.wdtype],
                        _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.val),
                        _ptr(self.col_ptr), _ptr(self.row_idx), _ptr(self.val_t),
-                       _ptr(self.p), _ptr(self.inv_row), _ptr(self.inv_col))
+                       _ptr(self.p), _ptr(self.inv_row), _ptr(self.inv_col),
+                       self.row_lanes, self.col_lanes)
 
     def new_image(self):
         import torch
@@ -348,8 +354,11 @@ def _value_tensor(nnz: int, nvals: int, wdtype: str, device):
     return stream_tensor(nnz, nvals, dt, device)
 
 
-def fold(A: DeviceMatrix, p, wdtype: str = "f32", nnz_half: int | None = None) -> System:
-    """ss_fold: the split pair (A(1), A(2)), (p1, p2) and the SART sums."""
+def fold(A: DeviceMatrix, p, wdtype: str = "f32", nnz_half: int | None = None, row_lanes: int = 0,
+         col_lanes: int = 0) -> System:
+    """ss_fold: the split pair (A(1), A(2)), (p1, p2) and the SART sums;
+    rows (columns) written in the interleaved order for row_lanes
+    (col_lanes) lanes when nonzero."""
     import torch
     dev = A.val.device
     if nnz_half is None:
@@ -364,7 +373,7 @@ def fold(A: DeviceMatrix, p, wdtype: str = "f32", nnz_half: int | None = None) -
                _value_tensor(nnz_half, 2, wdtype, dev),
                torch.empty(2 * m, dtype=torch.float32, device=dev),
                torch.empty(m, dtype=torch.float32, device=dev),
-               torch.empty(n, dtype=torch.float32, device=dev))
+               torch.empty(n, dtype=torch.float32, device=dev), row_lanes, col_lanes)
     fold_into(A, p, S)
     return S
 
@@ -462,11 +471,25 @@ class Solver:
         self.systems = list(systems)
         self.opts = opts or SartOptions()
         self._arr = (SystemC * len(self.systems))(*[s.c() for s in self.systems])
+        self.ws_bytes = 0
+        self.ws = None
+        self._reserve(self.opts)
+
+    def _bytes(self, opts) -> int:
         nb = C.c_size_t()
-        oc = self.opts.c()
+        oc = opts.c()
         _check(lib().ss_sart_workspace_bytes(self._arr, len(self.systems), C.byref(oc), C.byref(nb)))
-        self.ws_bytes = nb.value
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.systems[0].p.device)
+        return nb.value
+
+    def _reserve(self, opts):
+        """Grows the workspace to what ``opts`` needs (the interleaved stream
+        form keeps copies of the streams there)."""
+        import torch
+        need = self._bytes(opts)
+        if need > self.ws_bytes:
+            self.ws = None
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.systems[0].p.device)
+            self.ws_bytes = need
 
     def _imgs(self, f):
         assert len(f) == len(self.systems)
@@ -485,6 +508,7 @@ class Solver:
         else:
             rh = None
         it = (C.c_int32 * len(self.systems))() if want_iters else None
+        self._reserve(o)
         st = lib().ss_sart_solve(self._arr, len(self.systems), self._imgs(f), rh, C.byref(oc),
                                  it, _ptr(self.ws), self.ws_bytes, _stream(self.ws.device))
         _check(st, allow_warning=True)
@@ -492,6 +516,7 @@ class Solver:
 
     def time_kernels(self, f, reps: int = 20):
         fp, bp = C.c_double(), C.c_double()
+        self._reserve(self.opts)
         oc = self.opts.c()
         _check(lib().ss_sart_time_kernels(self._arr, len(self.systems), self._imgs(f), C.byref(oc),
                                           reps, C.byref(fp), C.byref(bp), _ptr(self.ws),
@@ -499,6 +524,11 @@ class Solver:
         return fp.value, bp.value
 
     def autotune(self, f):
+        # room for the interleaved candidates, where the systems allow them
+        try:
+            self._reserve(dataclasses.replace(self.opts, chunked=12))
+        except SSError:
+            self._reserve(self.opts)
         oc = self.opts.c()
         _check(lib().ss_sart_autotune(self._arr, len(self.systems), self._imgs(f), C.byref(oc),
                                       _ptr(self.ws), self.ws_bytes, _stream(self.ws.device)))

@@ -88,11 +88,12 @@ def test_build_system_rejects_odd_and_asymmetric_geometries():
     assert e.value.code == -1
 
 
-def _fake_system(m=4, n=6, nvals=2):
+def _fake_system(m=4, n=6, nvals=2, wdtype=0, row_lanes=0, col_lanes=0):
     # host-side validation rejects these before any device work, so the
     # pointers are never dereferenced
     one = C.c_void_p(16)
-    return native.SystemC(m, n, 10, nvals, 0, one, one, one, one, one, one, one, one, one)
+    return native.SystemC(m, n, 10, nvals, wdtype, one, one, one, one, one, one, one, one, one,
+                          row_lanes, col_lanes)
 
 
 def test_sart_options_are_validated_on_the_host():
@@ -111,6 +112,48 @@ def test_sart_options_are_validated_on_the_host():
     assert nb.value > 0
     mixed = (native.SystemC * 2)(_fake_system(), _fake_system(nvals=1))
     assert L.ss_sart_workspace_bytes(mixed, 2, C.byref(o), C.byref(nb)) == -1
+
+
+def test_stream_orders_are_validated_on_the_host():
+    """Stored line orders (row_lanes / col_lanes) and the interleaved stream
+    form: allowed values, consistency with the launch shape, the workspace
+    for the solver's copies, and the consumers that need ascending lines."""
+    L = native.lib()
+    nb = C.c_size_t()
+
+    def ws(opts=None, **sys_kw):
+        arr = (native.SystemC * 1)(_fake_system(**sys_kw))
+        o = (opts or native.SartOptions()).c()
+        st = L.ss_sart_workspace_bytes(arr, 1, C.byref(o), C.byref(nb))
+        return st, nb.value
+
+    st0, plain = ws()
+    assert st0 == 0
+    st, copies = ws(native.SartOptions(chunked=12))
+    assert st == 0 and copies > plain                      # room for both copies
+    st, stored = ws(native.SartOptions(chunked=12), row_lanes=8, col_lanes=8)
+    assert st == 0 and stored == plain                     # read in place
+    st, half = ws(native.SartOptions(chunked=12), row_lanes=8)
+    assert st == 0 and plain < half < copies               # columns copied only
+    for bad in [dict(row_lanes=4), dict(row_lanes=12), dict(col_lanes=2), dict(col_lanes=128)]:
+        assert ws(**bad)[0] == -1, bad
+    assert ws(native.SartOptions(rows_per_wave=4), row_lanes=8)[0] == -1
+    assert ws(native.SartOptions(rows_per_wave=8), row_lanes=8)[0] == 0
+    assert ws(native.SartOptions(cols_per_wave=2), col_lanes=16)[0] == -1
+    assert ws(native.SartOptions(chunked=16))[0] == -1
+    # a single system of 16-bit values has 2-byte entries: no interleaved form
+    assert ws(native.SartOptions(chunked=4), nvals=1, wdtype=native.WDTYPES["bf16"])[0] == -1
+    assert ws(native.SartOptions(chunked=4), nvals=1)[0] == 0
+    mixed = (native.SystemC * 2)(_fake_system(row_lanes=8), _fake_system())
+    o = native.SartOptions().c()
+    assert L.ss_sart_workspace_bytes(mixed, 2, C.byref(o), C.byref(nb)) == -1
+    # consumers that need ascending lines
+    S = _fake_system(row_lanes=16)
+    assert L.ss_normal_workspace_bytes(C.byref(S), C.byref(nb)) == -1
+    assert "ascending" in L.ss_last_error().decode()
+    sub = native.SubsetsC(2, *([C.c_void_p(16)] * 5))
+    assert L.ss_subsets_build(C.byref(S), C.byref(sub), None) == -1
+    assert "ascending" in L.ss_last_error().decode()
 
 
 def test_fold_rejects_odd_sizes_before_device_work():

@@ -206,18 +206,20 @@ def _poison(S):
         t.fill_(float("nan"))
 
 
-@pytest.mark.parametrize("wdtype", ["f32", "bf16"])
-def test_batch_fold_equals_single_folds_bitwise(wdtype):
+@pytest.mark.parametrize("wdtype,lanes", [("f32", 0), ("bf16", 0), ("f32", 8)])
+def test_batch_fold_equals_single_folds_bitwise(wdtype, lanes):
     """ss_fold_batch over matrices of different sizes (cfg1, ragged random
-    ones, a 2 x 2) writes exactly what one ss_fold per matrix writes."""
+    ones, a 2 x 2) writes exactly what one ss_fold per matrix writes, also
+    in the interleaved line order."""
     import torch
-    banner(f"batch fold {wdtype}")
+    banner(f"batch fold {wdtype} lanes={lanes}")
     probs = [problem(1), random_problem(21, 1002, 514, 0.05), random_problem(22, 66, 130, 0.3),
              random_problem(23, 2, 2, 0.3), problem(1, 3)]
     As = [device(pr.A) for pr in probs]
     ps = [torch.from_numpy(np.ascontiguousarray(pr.p, dtype=np.float32)).cuda() for pr in probs]
-    singles = [native.fold(A, p, wdtype) for A, p in zip(As, ps)]
-    batch = [native.fold(A, p, wdtype) for A, p in zip(As, ps)]
+    kw = dict(row_lanes=lanes, col_lanes=lanes // 2)
+    singles = [native.fold(A, p, wdtype, **kw) for A, p in zip(As, ps)]
+    batch = [native.fold(A, p, wdtype, **kw) for A, p in zip(As, ps)]
     for S in batch:
         _poison(S)
     native.FoldBatch(As, ps, batch)()
@@ -237,3 +239,46 @@ def test_batch_recombine_equals_single():
     native.RecombineBatch(f12, outs)()
     for w, o in zip(want, outs):
         assert np.array_equal(to_np(w), to_np(o))
+
+
+def _interleaved_positions(ptr, L):
+    """Stored position of every entry of every line, written out from the
+    order documented with ss_system: blocks of 4L entries (the last one r
+    long); entry e of a block (lane g = e mod L, q = r // L) sits at
+    g*q + min(g, r mod L) + e // L within it."""
+    pos = np.empty(int(ptr[-1]), np.int64)
+    B = 4 * L
+    for t in range(len(ptr) - 1):
+        lo, n = int(ptr[t]), int(ptr[t + 1] - ptr[t])
+        e = np.arange(n)
+        b = e // B
+        s_ = e - b * B
+        r = np.minimum(B, n - b * B)
+        q, rem, g = r // L, r % L, s_ % L
+        pos[lo + e] = lo + b * B + g * q + np.minimum(g, rem) + s_ // L
+    return pos
+
+
+@pytest.mark.parametrize("rl,cl", [(8, 8), (16, 4), (64, 32)])
+def test_fold_writes_interleaved_lines(rl, cl):
+    """With row_lanes / col_lanes set, every line holds the entries of the
+    ascending fold at the documented interleaved positions (bitwise), and
+    the offsets, p and the sums are unchanged."""
+    import torch
+    banner(f"interleaved fold rl={rl} cl={cl}")
+    for pr in [problem(1), random_problem(21, 1002, 514, 0.05), random_problem(23, 2, 2, 0.3)]:
+        Ad = device(pr.A)
+        pd = torch.from_numpy(np.ascontiguousarray(pr.p, dtype=np.float32)).cuda()
+        S0 = native.fold(Ad, pd)
+        S1 = native.fold(Ad, pd, row_lanes=rl, col_lanes=cl)
+        for name in ("row_ptr", "col_ptr", "p", "inv_row", "inv_col"):
+            assert np.array_equal(to_np(getattr(S0, name)).view(np.uint8), to_np(getattr(S1, name)).view(np.uint8))
+        nnz = S0.nnz
+        for ptr, idx, val, L in [("row_ptr", "col_idx", "val", rl), ("col_ptr", "row_idx", "val_t", cl)]:
+            pos = _interleaved_positions(to_np(getattr(S0, ptr)), L)
+            assert np.array_equal(np.sort(pos), np.arange(nnz))
+            i0, i1 = to_np(getattr(S0, idx))[:nnz], to_np(getattr(S1, idx))[:nnz]
+            assert np.array_equal(i1[pos], i0)
+            v0 = to_np(getattr(S0, val)).reshape(-1).view(np.uint64)[:nnz]
+            v1 = to_np(getattr(S1, val)).reshape(-1).view(np.uint64)[:nnz]
+            assert np.array_equal(v1[pos], v0)

@@ -146,13 +146,14 @@ def test_early_exit_at_tolerance(kstar):
 
 
 SHAPES = [(1, 1, 0, 4, 0, 0), (2, 4, 1, 8, 0, 3), (4, 8, 0, 4, 1, 1), (8, 16, 1, 8, 1, 2),
-          (1, 2, 1, 8, 0, 3), (8, 1, 0, 4, 1, 3)]
+          (1, 2, 1, 8, 0, 3), (8, 1, 0, 4, 1, 3), (8, 8, 1, 8, 0, 12), (1, 16, 0, 4, 1, 6),
+          (4, 1, 1, 8, 1, 9), (2, 2, 0, 4, 0, 15)]
 
 
 @pytest.mark.parametrize("rpw,cpw,xcd,u,pers,ch", SHAPES)
 def test_launch_shapes_agree_with_oracle(rpw, cpw, xcd, u, pers, ch):
-    """Every launch shape, unroll depth, grid mode and stream form (entry-wise
-    or chunked, per kernel) on cfg1 and on ragged random systems (lines that
+    """Every launch shape, unroll depth, grid mode and stream form (entry-wise,
+    chunked or interleaved, per kernel) on cfg1 and on ragged random systems (lines that
     start mid-chunk, empty lines, a 2 x 2 system)."""
     banner(f"launch shape rpw={rpw} cpw={cpw} xcd={xcd} u={u} pers={pers} chunked={ch}")
     shape = dict(rows_per_wave=rpw, cols_per_wave=cpw, xcd_remap=xcd, unroll=u, persistent=pers, chunked=ch)
@@ -182,6 +183,57 @@ def test_stream_forms_agree():
     f3, _, _, _ = _solve([S], 20, chunked=3)
     a, b = to_np(f0[0]), to_np(f3[0])
     assert rel_l2(b, a) <= 1e-6
+
+
+@pytest.mark.parametrize("rpw,cpw,u", [(8, 8, 8), (1, 16, 4), (4, 2, 8)])
+def test_interleaved_streams_are_bitwise_entrywise(rpw, cpw, u):
+    """The interleaved copy gives every lane the entries g, g + L, g + 2L, ...
+    of its line in that order, as the entry-wise form does: images and
+    residual histories are bitwise equal, on the folded pair (FP32 and BF16
+    values) and on the unsplit A, ragged random systems included."""
+    banner(f"interleaved vs entry-wise rpw={rpw} cpw={cpw} u={u}")
+    shape = dict(rows_per_wave=rpw, cols_per_wave=cpw, unroll=u)
+    pr = problem(1)
+    Ad, pd, S = _split_system(pr)
+    cases = [S, native.unsplit(Ad, pd), _split_system(pr, "bf16")[2],
+             _split_system(random_problem(11, 1002, 514, 0.05))[2]]
+    for sys_ in cases:
+        f0, h0, _, _ = _solve([sys_], 20, chunked=0, **shape)
+        f1, h1, _, _ = _solve([sys_], 20, chunked=12, **shape)
+        assert np.array_equal(to_np(f0[0]).view(np.uint32), to_np(f1[0]).view(np.uint32))
+        assert np.array_equal(to_np(h0[0]), to_np(h1[0]))
+
+
+@pytest.mark.parametrize("rl,cl,u", [(8, 8, 8), (64, 4, 4), (16, 32, 8)])
+def test_stored_interleaved_lines_solve_bitwise_as_entrywise(rl, cl, u):
+    """A pair folded straight into the interleaved order is read in place
+    (no copies) and gives the entry-wise results bitwise, with the launch
+    shape its line order fixes; the autotuner keeps that shape."""
+    import torch
+    banner(f"stored interleaved lines rl={rl} cl={cl} u={u}")
+    shape = dict(rows_per_wave=64 // rl, cols_per_wave=64 // cl, unroll=u)
+    for pr in [problem(1), random_problem(11, 1002, 514, 0.05)]:
+        Ad = device(pr.A)
+        pd = torch.from_numpy(np.ascontiguousarray(pr.p, dtype=np.float32)).cuda()
+        S0 = native.fold(Ad, pd)
+        S1 = native.fold(Ad, pd, row_lanes=rl, col_lanes=cl)
+        f0, h0, _, _ = _solve([S0], 20, chunked=0, **shape)
+        f1, h1, _, _ = _solve([S1], 20, chunked=0, **shape)
+        assert np.array_equal(to_np(f0[0]).view(np.uint32), to_np(f1[0]).view(np.uint32))
+        assert np.array_equal(to_np(h0[0]), to_np(h1[0]))
+    sol = native.Solver([S1], native.SartOptions(lam=0.5, max_iter=20))
+    o = sol.autotune([S1.new_image()])
+    assert o.rows_per_wave == 64 // rl and o.cols_per_wave == 64 // cl
+
+
+def test_interleaved_form_rejects_single_16bit_values():
+    banner("interleaved form: 16-bit unsplit rejected")
+    pr = problem(1)
+    Ad, pd, _ = _split_system(pr)
+    U16 = native.unsplit(Ad, pd, "bf16")
+    with pytest.raises(native.SSError) as e:
+        _solve([U16], 2, chunked=4)
+    assert e.value.code == -1
 
 
 def test_misaligned_stream_arrays_are_rejected():
