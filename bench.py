@@ -397,7 +397,8 @@ def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
         o = native.SartOptions(lam=lam, max_iter=cap, tol=tol, check_every=25, zero_start=True,
                                rows_per_wave=opts.rows_per_wave,
                                cols_per_wave=opts.cols_per_wave if name == "sart" else 0,
-                               xcd_remap=opts.xcd_remap, unroll=opts.unroll, chunked=opts.chunked)
+                               xcd_remap=opts.xcd_remap, unroll=opts.unroll,
+                               chunked=opts.chunked if name == "sart" else opts.chunked & 3)
         slv = native.Solver(systems, o) if name == "sart" else native.OsSolver(systems, subsets, o)
         imgs = [S.new_image() for S in systems]
         slv.solve(imgs)                     # warm-up (graph capture)

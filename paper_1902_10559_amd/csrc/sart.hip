@@ -943,6 +943,7 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
     double t = 1e30;
     int pw = 1, u = 4, xcd = 0, pers = 0, ch = 0;
   } bf, bb, df, db;
+  Best bestf[2][2][2], bestb[2][2][2];  // per (persistent, xcd_remap, unroll == 8)
   // stream forms: entry-wise, chunked, and interleaved where the workspace
   // holds the interleaved copies
   std::vector<int> forms{0, 3};
@@ -990,23 +991,35 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
               df = {tf, dflt.rpw, u, xcd, pers, ch};
             if (base && bp_form(ch) == bp_form(dflt.ch) && o.cols_per_wave == dflt.cpw && tb < db.t)
               db = {tb, dflt.cpw, u, xcd, pers, ch};
-            if (pw <= 8 && tf < bf.t) bf = {tf, o.rows_per_wave, u, xcd, pers, ch};
-            if (tb < bb.t) bb = {tb, o.cols_per_wave, u, xcd, pers, ch};
+            Best& cf = bestf[pers][xcd][u / 8];
+            Best& cb = bestb[pers][xcd][u / 8];
+            if (pw <= 8 && tf < cf.t) cf = {tf, o.rows_per_wave, u, xcd, pers, ch};
+            if (tb < cb.t) cb = {tb, o.cols_per_wave, u, xcd, pers, ch};
           }
         }
       }
     }
   }
-  if (df.t <= 1.03 * bf.t) bf = df;
-  if (db.t <= 1.03 * bb.t) bb = db;
-  // one remap flag, unroll depth and grid mode serve both kernels: take
-  // those of the slower kernel; each kernel keeps its own stream form
-  const Best& slow = bf.t >= bb.t ? bf : bb;
+  // one remap flag, unroll depth and grid mode serve both kernels: the
+  // combination with the least forward + back time, each kernel with its
+  // own lanes per line and stream form under it; the default is kept unless
+  // that is more than 3 % faster
+  for (int pers = 0; pers <= 1; ++pers)
+    for (int xcd = 0; xcd <= 1; ++xcd)
+      for (int u8 = 0; u8 <= 1; ++u8)
+        if (bestf[pers][xcd][u8].t + bestb[pers][xcd][u8].t < bf.t + bb.t) {
+          bf = bestf[pers][xcd][u8];
+          bb = bestb[pers][xcd][u8];
+        }
+  if (df.t + db.t <= 1.03 * (bf.t + bb.t)) {
+    bf = df;
+    bb = db;
+  }
   opts->rows_per_wave = bf.pw;
   opts->cols_per_wave = bb.pw;
-  opts->xcd_remap = slow.xcd;
-  opts->unroll = slow.u;
-  opts->persistent = slow.pers;
+  opts->xcd_remap = bf.xcd;
+  opts->unroll = bf.u;
+  opts->persistent = bf.pers;
   opts->chunked = (bf.ch & 5) | (bb.ch & 10);
   std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tune[key] = std::make_tuple(opts->rows_per_wave, opts->cols_per_wave, opts->xcd_remap, opts->unroll,
