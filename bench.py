@@ -381,6 +381,13 @@ def pick_line_order(args, slices, systems, sol, scratch):
     return native.Solver(systems, opts)
 
 
+def os_forms(chunked):
+    """Stream forms for the ordered-subset kernels, which have no
+    interleaved form: the forward projection's interleaved order maps to the
+    entry-wise form (the same gathers), the back projection's to chunks."""
+    return (chunked & 1 if not chunked & 4 else 0) | (2 if chunked & 10 else 0)
+
+
 def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
     """Whole-batch time to rel_res <= tol from f0 = 0: SART iterations
     against ordered-subset SART passes with S = K/2 mirror-paired views
@@ -398,7 +405,7 @@ def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
                                rows_per_wave=opts.rows_per_wave,
                                cols_per_wave=opts.cols_per_wave if name == "sart" else 0,
                                xcd_remap=opts.xcd_remap, unroll=opts.unroll,
-                               chunked=opts.chunked if name == "sart" else opts.chunked & 3)
+                               chunked=opts.chunked if name == "sart" else os_forms(opts.chunked))
         slv = native.Solver(systems, o) if name == "sart" else native.OsSolver(systems, subsets, o)
         imgs = [S.new_image() for S in systems]
         slv.solve(imgs)                     # warm-up (graph capture)
