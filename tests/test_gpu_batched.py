@@ -74,3 +74,28 @@ def test_small_batch_equals_solo_solves_bitwise():
         fs = [S.new_image()]
         native.Solver([S], native.SartOptions(max_iter=7, **shape)).solve(fs)
         assert np.array_equal(to_np(fb[k]).view(np.uint32), to_np(fs[0]).view(np.uint32))
+
+
+def test_batch_in_stored_interleaved_order_equals_ascending_batch():
+    """The batch folded straight into the interleaved line order (one
+    ss_fold_batch) and solved in place gives, bitwise, what the ascending
+    batch gives with the entry-wise form at the same shape."""
+    import torch
+    banner("batched: stored interleaved order vs ascending")
+    sl = workloads.batched_slices(6)
+    systems = [x.S for x in sl]
+    shape = dict(rows_per_wave=8, cols_per_wave=16, xcd_remap=1, unroll=8)
+    f0 = [S.new_image() for S in systems]
+    h0 = [torch.full((8,), -1.0, dtype=torch.float64, device="cuda") for _ in systems]
+    native.Solver(systems, native.SartOptions(max_iter=7, chunked=0, **shape)).solve(f0, h0)
+    for S in systems:
+        S.row_lanes, S.col_lanes = 8, 4
+    native.FoldBatch([x.A for x in sl], [x.p for x in sl], systems)()
+    f1 = [S.new_image() for S in systems]
+    h1 = [torch.full((8,), -1.0, dtype=torch.float64, device="cuda") for _ in systems]
+    native.Solver(systems, native.SartOptions(max_iter=7, **shape)).solve(f1, h1)
+    for a, b, ha, hb in zip(f0, f1, h0, h1):
+        assert np.array_equal(to_np(a).view(np.uint32), to_np(b).view(np.uint32))
+        assert np.array_equal(to_np(ha), to_np(hb))
+    for S in systems:
+        S.row_lanes = S.col_lanes = 0

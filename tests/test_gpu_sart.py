@@ -226,6 +226,22 @@ def test_stored_interleaved_lines_solve_bitwise_as_entrywise(rl, cl, u):
     assert o.rows_per_wave == 64 // rl and o.cols_per_wave == 64 // cl
 
 
+def test_interleaved_form_with_nonnegativity_and_early_exit():
+    """The projection onto f >= 0 and the stop at a tolerance behave as in
+    the entry-wise form: same stop index, bitwise equal images and
+    histories."""
+    banner("interleaved: nonneg + early exit")
+    pr = problem(1)
+    _, _, S = _split_system(pr)
+    shape = dict(rows_per_wave=4, cols_per_wave=8, unroll=4)
+    f0, h0, s0, it0 = _solve([S], 60, chunked=0, nonneg=1, tol=0.08, check_every=7, **shape)
+    f1, h1, s1, it1 = _solve([S], 60, chunked=12, nonneg=1, tol=0.08, check_every=7, **shape)
+    assert s0 == s1 == 0 and it0 == it1 and it0[0] < 60
+    assert np.array_equal(to_np(f0[0]).view(np.uint32), to_np(f1[0]).view(np.uint32))
+    assert np.array_equal(to_np(h0[0]), to_np(h1[0]))
+    assert to_np(native.recombine(f1[0])).min() >= 0.0
+
+
 def test_interleaved_form_rejects_single_16bit_values():
     banner("interleaved form: 16-bit unsplit rejected")
     pr = problem(1)
