@@ -105,13 +105,18 @@ __device__ inline void line_dot_c(const int32_t* idx, const void* val, const flo
 // while a gather instruction still has adjacent lanes on adjacent entries of
 // the line, as in the entry-wise form.  The permutation stays inside each
 // line, so the line offsets do not change.
+// L is a power of two (4 .. 64): shifts and masks, not divisions.
+static_assert(SS_CHUNK == 4, "interleaved_pos takes blocks of 4 entries per lane");
 __host__ __device__ inline int64_t interleaved_pos(int64_t e, int64_t n, int L) {
-  const int64_t B = static_cast<int64_t>(SS_CHUNK) * L;
-  const int64_t b = e / B, s = e - b * B;
-  const int64_t r = n - b * B < B ? n - b * B : B;
-  const int64_t q = r / L, rem = r - q * L;
-  const int64_t g = s % L;
-  return b * B + g * q + (g < rem ? g : rem) + s / L;
+  const int lg = __builtin_ctz(static_cast<unsigned>(L));
+  const int lgB = lg + 2;  // SS_CHUNK = 4 entries per lane and block
+  const int64_t B = int64_t{1} << lgB;
+  const int64_t base = (e >> lgB) << lgB;
+  const int64_t s = e - base;
+  const int64_t r = n - base < B ? n - base : B;
+  const int64_t q = r >> lg, rem = r & (L - 1);
+  const int64_t g = s & (L - 1);
+  return base + g * q + (g < rem ? g : rem) + (s >> lg);
 }
 
 // P blocks per pass.  Idle slots (past a lane's share of a block, or blocks
