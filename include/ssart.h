@@ -318,7 +318,10 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *                form's bitwise.  Needs entries of at least 4 bytes (not a
  *                single system with 16-bit values: SS_E_ARG) and workspace
  *                for the copies (ss_sart_workspace_bytes counts it); the copy
- *                is made on every solve
+ *                is made on every solve.  A system stored in that order
+ *                (row_lanes / col_lanes nonzero) is read in place with the
+ *                interleaved form whatever these bits say, and fixes
+ *                rows_per_wave (cols_per_wave) to 64 / its lanes
  *   persistent   1: size the grid to the resident capacity and let each block
  *                loop over tiles (prefetching the next one); 0: one block
  *                per tile
@@ -340,7 +343,9 @@ typedef struct {
   int32_t nonneg;
 } ss_sart_opts;
 
-/* Workspace bytes for solving `nsys` systems together with these options. */
+/* Workspace bytes for solving `nsys` systems together with these options
+ * (with the interleaved stream form on systems stored in ascending order,
+ * this includes the copies of their streams). */
 ss_status ss_sart_workspace_bytes(const ss_system* sys, int32_t nsys,
                                   const ss_sart_opts* opts, size_t* bytes);
 
