@@ -1,6 +1,8 @@
 // Image-side operations: the recombination of Theorem 1 (eq. (5)), its
 // inverse, and the forward projection q = A f of eq. (1).
 
+#include <algorithm>
+
 #include "device.h"
 #include "internal.h"
 
@@ -16,6 +18,29 @@ __global__ void k_recombine(const float2* __restrict__ f12, int64_t n, float* __
   const float2 h = f12[j];
   f[j] = (h.y + h.x) * 0.5f;
   f[2 * n - 1 - j] = (h.y - h.x) * 0.5f;
+}
+
+// Up to kRecombineChunk images per launch, their descriptors in the kernel
+// arguments; image k owns blocks [blk0[k], blk0[k + 1]).
+constexpr int kRecombineChunk = 32;
+struct RecombineChunk {
+  const float2* f12[kRecombineChunk];
+  float* f[kRecombineChunk];
+  int64_t n[kRecombineChunk];
+  uint32_t blk0[kRecombineChunk + 1];
+  int32_t count;
+};
+
+__global__ void k_recombine_chunk(RecombineChunk ch) {
+  const uint32_t b = blockIdx.x;
+  int k = 0;
+  while (k + 1 < ch.count && ch.blk0[k + 1] <= b) ++k;  // uniform per block
+  const int64_t j = static_cast<int64_t>(b - ch.blk0[k]) * blockDim.x + threadIdx.x;
+  const int64_t n = ch.n[k];
+  if (j >= n) return;
+  const float2 h = ch.f12[k][j];
+  ch.f[k][j] = (h.y + h.x) * 0.5f;
+  ch.f[k][2 * n - 1 - j] = (h.y - h.x) * 0.5f;
 }
 
 // f1[j] = f[j] - f[N-1-j], f2[j] = f[j] + f[N-1-j].
@@ -68,9 +93,21 @@ extern "C" ss_status ss_recombine_batch(const float* const* f12, const int64_t* 
   for (int32_t k = 0; k < count; ++k)
     if (!f12[k] || !f[k] || n[k] <= 0) return fail(SS_E_ARG, "ss_recombine_batch: bad image %d", k);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  for (int32_t k = 0; k < count; ++k)
-    k_recombine<<<static_cast<unsigned>((n[k] + 255) / 256), 256, 0, st>>>(reinterpret_cast<const float2*>(f12[k]),
-                                                                           n[k], f[k]);
+  for (int32_t k0 = 0; k0 < count; k0 += kRecombineChunk) {
+    RecombineChunk ch{};
+    ch.count = std::min(kRecombineChunk, count - k0);
+    uint64_t blocks = 0;
+    for (int i = 0; i < ch.count; ++i) {
+      ch.f12[i] = reinterpret_cast<const float2*>(f12[k0 + i]);
+      ch.f[i] = f[k0 + i];
+      ch.n[i] = n[k0 + i];
+      ch.blk0[i] = static_cast<uint32_t>(blocks);
+      blocks += static_cast<uint64_t>((n[k0 + i] + 255) / 256);
+      if (blocks > UINT32_MAX) return fail(SS_E_ARG, "ss_recombine_batch: images too large");
+    }
+    ch.blk0[ch.count] = static_cast<uint32_t>(blocks);
+    k_recombine_chunk<<<static_cast<unsigned>(blocks), 256, 0, st>>>(ch);
+  }
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;
 }

@@ -113,13 +113,19 @@ __device__ inline int find_sys(const SysDesc* t, int nsys, int64_t b) {
   return lo;
 }
 
-// Writes up to kDescChunk descriptors into the table and resets each
-// system's state; block b also reduces ||p||^2 of its system.
+// Writes up to kDescChunk descriptors (from the kernel arguments) into the
+// table, and the parameters with the first chunk.
+__global__ void k_put_desc(DescChunk ch, SysDesc* table, Params prm_in, Params* prm) {
+  const int t = static_cast<int>(threadIdx.x);
+  if (t < ch.count) table[ch.first + t] = ch.d[t];
+  if (ch.first == 0 && t == 0) *prm = prm_in;
+}
+
+// Resets each system's state, clears its image (zero_start) and reduces
+// ||p||^2 in a fixed order: one block per system, all systems in one launch.
 template <int NV>
-__global__ __launch_bounds__(kThreads) void k_setup(DescChunk ch, SysDesc* table, Params prm_in,
-                                                    Params* prm, SetupFlags fl) {
-  const int b = blockIdx.x;
-  const SysDesc& d = ch.d[b];
+__global__ __launch_bounds__(kThreads) void k_setup(const SysDesc* table, SetupFlags fl) {
+  const SysDesc& d = table[blockIdx.x];
   if (fl.zero_start)
     for (int64_t i = threadIdx.x; i < d.n * NV; i += kThreads) d.f[0][i] = 0.0f;
   double s = 0.0;
@@ -130,13 +136,11 @@ __global__ __launch_bounds__(kThreads) void k_setup(DescChunk ch, SysDesc* table
   __shared__ double red[kWPB];
   s = block_sum<kWPB>(s, red);
   if (threadIdx.x == 0) {
-    table[ch.first + b] = d;
     d.st->pnorm2 = s;
     d.st->last_res = 0.0;
     d.st->k = 0;
     d.st->stop = 0;
     d.st->pending = 0;
-    if (ch.first == 0 && b == 0) *prm = prm_in;
   }
 }
 
@@ -552,13 +556,14 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
     bb += d.bp_nblocks;
     ch.d[ch.count++] = d;
     if (ch.count == kDescChunk || s == nsys - 1) {
-      const SetupFlags fl{zero_start};
-      if (c.nv == 2) k_setup<2><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm, fl);
-      else k_setup<1><<<ch.count, kThreads, 0, st>>>(ch, table, prm, dprm, fl);
+      k_put_desc<<<1, kWave, 0, st>>>(ch, table, prm, dprm);
       ch.first = s + 1;
       ch.count = 0;
     }
   }
+  const SetupFlags fl{zero_start};
+  if (c.nv == 2) k_setup<2><<<static_cast<unsigned>(nsys), kThreads, 0, st>>>(table, fl);
+  else k_setup<1><<<static_cast<unsigned>(nsys), kThreads, 0, st>>>(table, fl);
   if (fb > UINT32_MAX || bb > UINT32_MAX) return fail(SS_E_ARG, "SART: grid too large");
   g->fp_blocks = static_cast<uint32_t>(fb);
   g->bp_blocks = static_cast<uint32_t>(bb);

@@ -233,7 +233,9 @@ def test_batch_recombine_equals_single():
     import torch
     banner("batch recombine")
     g = torch.Generator().manual_seed(3)
-    f12 = [torch.randn(n, 2, generator=g).cuda() for n in (1, 7, 2048)]
+    # more images than one launch takes (32), sizes from 1 to a few blocks
+    sizes = [1, 7, 2048] + [int(v) for v in torch.randint(1, 1500, (67,), generator=g)]
+    f12 = [torch.randn(n, 2, generator=g).cuda() for n in sizes]
     want = [native.recombine(f) for f in f12]
     outs = [torch.full((2 * f.shape[0],), float("nan"), device="cuda") for f in f12]
     native.RecombineBatch(f12, outs)()
