@@ -8,9 +8,10 @@
 // of A's CSC: X = its rows < m, Y = its rows >= m mapped to M-1-row (which
 // reverses them into ascending order).  Both copies hold the same entries.
 //
-// One 64-lane wavefront merges one list pair without shared memory.  With
-// dX[k] = 1 when X[k] is also in Y (dY likewise), and exclusive prefix counts
-// of those flags taken with ballots:
+// A group of lanes (32 for a row pair, 8 for a column; a whole wavefront
+// when the input is checked) merges one list pair, staged in shared memory.
+// With dX[k] = 1 when X[k] is also in Y (dY likewise), and exclusive prefix
+// counts of those flags taken with ballots (cut to the group's lanes):
 //   union position of X[k]       = k + lower_bound(Y, X[k]) - prefix_dX[k]
 //   union position of Y[l] not in X = lower_bound(X, Y[l]) + l - prefix_dY[l]
 // (the union elements below a value are those of X and of Y below it, minus
@@ -113,6 +114,28 @@ struct LSeq {
 constexpr int kStageRow = 384;
 constexpr int kStageCol = 256;
 
+// The counting and filling passes fold several lines per wavefront, each by
+// a group of lanes (rows hold ~35 entries per list, columns ~20: a whole
+// wavefront per line would leave most lanes idle), each group with its own
+// part of the staging buffer: kRowCap entries per list (rows), kColCap
+// (columns).  Measured on the batched workload (fold of 256 slices): 64
+// lanes per row and per column 20.3 ms, 32 per row and 16 per column 10.3
+// ms, 32 and 8 10.0 ms; 16 per row slowed the row fill (3.9 -> 5.8 ms).
+constexpr int kRowLanes = 32, kColLanes = 8;
+constexpr int kRowCap = 192, kColCap = 64;
+template <bool COLS>
+constexpr int line_lanes() {
+  return COLS ? kColLanes : kRowLanes;
+}
+
+// Entries staged per list for a group of G lanes (G = 64: a wavefront per
+// line, as the input checks fold).
+template <bool COLS, int G>
+constexpr int stage_cap() {
+  if constexpr (G == 64) return COLS ? kStageCol : kStageRow;
+  else return COLS ? kColCap : kRowCap;
+}
+
 // A sorted list of len (<= R * 64) entries in registers, R per lane: all
 // its loads are issued before the first is waited for, so a line pair costs
 // one memory latency, not one per 64 entries.  VALS: also the values (the
@@ -123,11 +146,31 @@ struct Staged {
   float v[R];
 };
 
-template <int R, bool VALS>
+// A line is handled by a group of G lanes (G = 64: the whole wavefront;
+// G = 32: each half of it folds its own line).  Ballots are cut to the
+// group's bits.
+template <int G>
+__device__ inline int group_lane() {
+  return lane_id() & (G - 1);
+}
+
+template <int G>
+__device__ inline uint64_t group_ballot(bool v) {
+  const uint64_t b = __ballot(v);
+  if constexpr (G == kWave) return b;
+  else return (b >> (lane_id() & ~(G - 1))) & ((uint64_t{1} << G) - 1);
+}
+
+template <int G>
+__device__ inline uint64_t group_lanemask_lt() {
+  return (uint64_t{1} << group_lane<G>()) - 1;
+}
+
+template <int R, bool VALS, int G = kWave>
 __device__ inline void stage_load(const int32_t* gi, const float* gv, int64_t len, Staged<R, VALS>& s) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t k = static_cast<int64_t>(r) * kWave + lane_id();
+    const int64_t k = static_cast<int64_t>(r) * G + group_lane<G>();
     s.c[r] = INT32_MAX;
     if (k < len) {
       s.c[r] = gl(gi)[k];
@@ -138,18 +181,18 @@ __device__ inline void stage_load(const int32_t* gi, const float* gv, int64_t le
 
 // Writes the staged list to shared memory and returns how many of its
 // indices are below `limit` (a prefix).
-template <int R, bool VALS>
+template <int G = kWave, int R, bool VALS>
 __device__ inline int64_t stage_store(const Staged<R, VALS>& s, int64_t len, SS_LDS int32_t* si, SS_LDS float* sv,
                                       int32_t limit) {
   int64_t below = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t k = static_cast<int64_t>(r) * kWave + lane_id();
+    const int64_t k = static_cast<int64_t>(r) * G + group_lane<G>();
     if (k < len) {
       si[k] = s.c[r];
       if constexpr (VALS) sv[k] = s.v[r];
     }
-    below += __popcll(__ballot(s.c[r] < limit));
+    below += __popcll(group_ballot<G>(s.c[r] < limit));
   }
   return below;
 }
@@ -168,12 +211,12 @@ __device__ inline void wave_lds_sync() {
 // n_out entries) is permuted into the solver's interleaved order for groups
 // of that many lanes.  Returns the union size (in every lane) and adds each
 // entry's FP64 a + b to the lane's `sum`.
-template <bool FILL, int WT, class SX, class SY>
+template <bool FILL, int WT, int G = kWave, class SX, class SY>
 __device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_t* out_idx, void* out_val,
                               double& sum, int64_t n_out, int lanes) {
-  const int lane = lane_id();
+  const int lane = group_lane<G>();
   int64_t common = 0;
-  for (int64_t base = 0; base < X.len; base += kWave) {
+  for (int64_t base = 0; base < X.len; base += G) {
     const int64_t k = base + lane;
     const bool valid = k < X.len;
     int32_t x = 0;
@@ -184,9 +227,9 @@ __device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_
       r = Y.lower_bound(x);
       dup = r < Y.len && Y.key(r) == x;
     }
-    const uint64_t mask = __ballot(dup);
+    const uint64_t mask = group_ballot<G>(dup);
     if (FILL && valid) {
-      const int64_t before = common + __popcll(mask & lanemask_lt());
+      const int64_t before = common + __popcll(mask & group_lanemask_lt<G>());
       const int64_t pos0 = k + r - before;
       const int64_t pos = lanes ? interleaved_pos(pos0, n_out, lanes) : pos0;
       const float a = X.value(k);
@@ -198,7 +241,7 @@ __device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_
     common += __popcll(mask);
   }
   int64_t seen = 0;
-  for (int64_t base = 0; base < Y.len; base += kWave) {
+  for (int64_t base = 0; base < Y.len; base += G) {
     const int64_t l = base + lane;
     const bool valid = l < Y.len;
     int32_t y = 0;
@@ -209,9 +252,9 @@ __device__ int64_t wave_merge(const SX& X, const SY& Y, int64_t out_base, int32_
       s = X.lower_bound(y);
       dup = s < X.len && X.key(s) == y;
     }
-    const uint64_t mask = __ballot(dup);
+    const uint64_t mask = group_ballot<G>(dup);
     if (FILL && valid && !dup) {
-      const int64_t before = seen + __popcll(mask & lanemask_lt());
+      const int64_t before = seen + __popcll(mask & group_lanemask_lt<G>());
       const int64_t pos0 = s + l - before;
       const int64_t pos = lanes ? interleaved_pos(pos0, n_out, lanes) : pos0;
       const float b = Y.value(l);
@@ -266,50 +309,63 @@ struct StageBuf {
 
 // Merges output line t (a row, or a column when COLS) into the union: its
 // size, and with FILL the entries written at out_base.
-template <bool COLS, bool FILL, int WT>
+// G: lanes per line (columns only may use 32: two columns per wavefront,
+// each group with half of the wavefront's staging buffer).
+template <bool COLS, bool FILL, int WT, int G = kWave>
 __device__ int64_t fold_line(const ss_matrix_dev& A, int64_t t, int64_t out_base, int32_t* out_idx,
                              void* out_val, double& sum, StageBuf sb, int64_t n_out, int lanes) {
   if constexpr (COLS) {
+    constexpr int cap = stage_cap<true, G>();
     const int64_t cs = gl(A.col_ptr)[t], ce = gl(A.col_ptr)[t + 1];
     const int64_t len = ce - cs;
-    if (len <= kStageCol) {
-      Staged<kStageCol / kWave, FILL> sl;
-      stage_load(A.row_idx + cs, A.val_t + cs, len, sl);
-      const int64_t split = stage_store(sl, len, sb.idx, sb.val, static_cast<int32_t>(A.M / 2));
+    if (len <= cap) {
+      Staged<cap / G, FILL> sl;
+      stage_load<cap / G, FILL, G>(A.row_idx + cs, A.val_t + cs, len, sl);
+      const int64_t split = stage_store<G>(sl, len, sb.idx, sb.val, static_cast<int32_t>(A.M / 2));
       wave_lds_sync();
       const LSeq<false> X{sb.idx, sb.val, split, 0};
       const LSeq<true> Y{sb.idx + split, sb.val + split, len - split, static_cast<int32_t>(A.M - 1)};
-      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum, n_out, lanes);
+      return wave_merge<FILL, WT, G>(X, Y, out_base, out_idx, out_val, sum, n_out, lanes);
     }
     const ColLists L = col_lists(A, t);
-    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum, n_out, lanes);
+    return wave_merge<FILL, WT, G>(L.X, L.Y, out_base, out_idx, out_val, sum, n_out, lanes);
   } else {
+    constexpr int cap = stage_cap<false, G>();  // per list
     const int64_t t2 = A.M - 1 - t;
     const int64_t rs = gl(A.row_ptr)[t], re = gl(A.row_ptr)[t + 1];
     const int64_t ys = gl(A.row_ptr)[t2], ye = gl(A.row_ptr)[t2 + 1];
-    if (re - rs <= kStageRow && ye - ys <= kStageRow) {
+    if (re - rs <= cap && ye - ys <= cap) {
       const int32_t n = static_cast<int32_t>(A.N / 2);
-      Staged<kStageRow / kWave, FILL> sx, sy;
-      stage_load(A.col_idx + rs, A.val + rs, re - rs, sx);
-      stage_load(A.col_idx + ys, A.val + ys, ye - ys, sy);
-      const int64_t xl = stage_store(sx, re - rs, sb.idx, sb.val, n);
-      const int64_t yl = stage_store(sy, ye - ys, sb.idx + kStageRow, sb.val + kStageRow, n);
+      Staged<cap / G, FILL> sx, sy;
+      stage_load<cap / G, FILL, G>(A.col_idx + rs, A.val + rs, re - rs, sx);
+      stage_load<cap / G, FILL, G>(A.col_idx + ys, A.val + ys, ye - ys, sy);
+      const int64_t xl = stage_store<G>(sx, re - rs, sb.idx, sb.val, n);
+      const int64_t yl = stage_store<G>(sy, ye - ys, sb.idx + cap, sb.val + cap, n);
       wave_lds_sync();
       const LSeq<false> X{sb.idx, sb.val, xl, 0};
-      const LSeq<false> Y{sb.idx + kStageRow, sb.val + kStageRow, yl, 0};
-      return wave_merge<FILL, WT>(X, Y, out_base, out_idx, out_val, sum, n_out, lanes);
+      const LSeq<false> Y{sb.idx + cap, sb.val + cap, yl, 0};
+      return wave_merge<FILL, WT, G>(X, Y, out_base, out_idx, out_val, sum, n_out, lanes);
     }
     const RowLists L = row_lists(A, t);
-    return wave_merge<FILL, WT>(L.X, L.Y, out_base, out_idx, out_val, sum, n_out, lanes);
+    return wave_merge<FILL, WT, G>(L.X, L.Y, out_base, out_idx, out_val, sum, n_out, lanes);
   }
 }
 
 // This wavefront's staging buffers in the block's shared memory.
 #define SS_STAGE_BUF(name)                                                        \
-  constexpr int name##_cap = COLS ? kStageCol : 2 * kStageRow;                    \
+  constexpr int name##_cap = COLS ? std::max(kStageCol, kWave / kColLanes * kColCap) \
+                                  : std::max(2 * kStageRow, kWave / kRowLanes * 2 * kRowCap); \
   __shared__ int32_t name##_idx[kFoldWaves][name##_cap];                          \
   __shared__ float name##_val[kFoldWaves][name##_cap];                            \
   const StageBuf name{(SS_LDS int32_t*)(&name##_idx[wave_id()][0]), (SS_LDS float*)(&name##_val[wave_id()][0])}
+
+// Group grp's part of the wavefront's staging buffer.
+template <bool COLS, int G>
+__device__ inline StageBuf group_buf(StageBuf sb, int grp) {
+  constexpr int per = (COLS ? 1 : 2) * stage_cap<COLS, G>();
+  if constexpr (G == kWave) return sb;
+  else return StageBuf{sb.idx + grp * per, sb.val + grp * per};
+}
 
 __device__ inline unsigned long long mix64(unsigned long long z) {
   z += 0x9e3779b97f4a7c15ull;
@@ -410,7 +466,7 @@ struct FoldJob {
   ss_matrix_dev A;
   const float* p;
   ss_system out;
-  int64_t rblk0, cblk0;    // first block of its rows / columns (kFoldWaves lines per block)
+  int64_t rblk0, cblk0;    // first block of its rows / columns (line_blocks_for)
   int64_t rtile0, ctile0;  // first scan tile of its row / column offsets
 };
 
@@ -453,12 +509,15 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(JobArg J) {
   const FoldJob& jb = find_job<B, COLS, false>(J, blockIdx.x, &lb);
   const ss_matrix_dev& A = jb.A;
   const int64_t lines = COLS ? A.N / 2 : A.M / 2;
-  const int64_t t = lb * kFoldWaves + wave_id();
+  constexpr int G = line_lanes<COLS>();
+  const int grp = lane_id() / G;
+  const int64_t t = (lb * kFoldWaves + wave_id()) * (kWave / G) + grp;
   if (t >= lines) return;
   double unused = 0.0;
-  const int64_t cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb, 0, 0);
+  const int64_t cnt = fold_line<COLS, false, SS_F32, G>(A, t, 0, nullptr, nullptr, unused, group_buf<COLS, G>(sb, grp),
+                                                       0, 0);
   int64_t* ptr = COLS ? jb.out.col_ptr : jb.out.row_ptr;
-  if (lane_id() == 0) {
+  if (group_lane<G>() == 0) {
     ptr[t + 1] = cnt;
     if (t == 0) ptr[0] = 0;
   }
@@ -573,18 +632,22 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_fill(JobArg J) {
   const ss_system& out = jb.out;
   const float* p = jb.p;
   const int64_t lines = COLS ? out.n : out.m;
-  const int64_t t = lb * kFoldWaves + wave_id();
+  constexpr int G = line_lanes<COLS>();
+  const int grp = lane_id() / G;
+  const int64_t t = (lb * kFoldWaves + wave_id()) * (kWave / G) + grp;
   if (t >= lines) return;
   double sum = 0.0;
   if constexpr (COLS) {
     const int64_t o = out.col_ptr[t];
-    fold_line<true, true, WT>(A, t, o, out.row_idx, out.val_t, sum, sb, out.col_ptr[t + 1] - o, out.col_lanes);
+    fold_line<true, true, WT, G>(A, t, o, out.row_idx, out.val_t, sum, group_buf<COLS, G>(sb, grp),
+                                 out.col_ptr[t + 1] - o, out.col_lanes);
   } else {
     const int64_t o = out.row_ptr[t];
-    fold_line<false, true, WT>(A, t, o, out.col_idx, out.val, sum, sb, out.row_ptr[t + 1] - o, out.row_lanes);
+    fold_line<false, true, WT, G>(A, t, o, out.col_idx, out.val, sum, group_buf<COLS, G>(sb, grp),
+                                  out.row_ptr[t + 1] - o, out.row_lanes);
   }
-  sum = group_sum<kWave>(sum);
-  if (lane_id() == 0) {
+  sum = group_sum<G>(sum);
+  if (group_lane<G>() == 0) {
     if constexpr (COLS) {
       out.inv_col[t] = recip_or_zero(sum);
     } else {
@@ -620,6 +683,13 @@ __global__ void k_copy_f32(const float* src, int64_t count, float* dst) {
 
 inline unsigned blocks_for(int64_t lines) {
   return static_cast<unsigned>((lines + kFoldWaves - 1) / kFoldWaves);
+}
+
+// Blocks of the counting and filling passes (kWave / line_lanes lines per wavefront).
+template <bool COLS>
+inline unsigned line_blocks_for(int64_t lines) {
+  constexpr int64_t per = kFoldWaves * (kWave / line_lanes<COLS>());
+  return static_cast<unsigned>((lines + per - 1) / per);
 }
 
 ss_status check_dev_matrix(const ss_matrix_dev* A, const char* fn) {
@@ -703,8 +773,8 @@ FoldGrid layout_jobs(const ss_matrix_dev* A, const float* const* p, const ss_sys
     j.cblk0 = g.cblk;
     j.rtile0 = g.rtile;
     j.ctile0 = g.ctile;
-    g.rblk += blocks_for(A[k].M / 2);
-    g.cblk += blocks_for(A[k].N / 2);
+    g.rblk += line_blocks_for<false>(A[k].M / 2);
+    g.cblk += line_blocks_for<true>(A[k].N / 2);
     g.rtile += tiles_for(A[k].M / 2);
     g.ctile += tiles_for(A[k].N / 2);
     if (jobs) jobs->push_back(j);
