@@ -18,6 +18,7 @@
 // the common ones counted twice).  The union size is |X| + |Y| - #common.
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "device.h"
@@ -114,26 +115,23 @@ struct LSeq {
 constexpr int kStageRow = 384;
 constexpr int kStageCol = 256;
 
-// The counting and filling passes fold several lines per wavefront, each by
-// a group of lanes (rows hold ~35 entries per list, columns ~20: a whole
-// wavefront per line would leave most lanes idle), each group with its own
-// part of the staging buffer: kRowCap entries per list (rows), kColCap
-// (columns).  Measured on the batched workload (fold of 256 slices): 64
-// lanes per row and per column 20.3 ms, 32 per row and 16 per column 10.3
-// ms, 32 and 8 10.0 ms; 16 per row slowed the row fill (3.9 -> 5.8 ms).
-constexpr int kRowLanes = 32, kColLanes = 8;
-constexpr int kRowCap = 192, kColCap = 64;
-template <bool COLS>
-constexpr int line_lanes() {
-  return COLS ? kColLanes : kRowLanes;
-}
-
-// Entries staged per list for a group of G lanes (G = 64: a wavefront per
-// line, as the input checks fold).
+// The counting and filling passes can fold several lines per wavefront,
+// each by a group of G lanes with its own part of the staging buffer: a
+// short line (the batched workload's rows hold ~35 entries per list, its
+// columns ~40 in all) would leave most of a wavefront idle behind the same
+// chain of loads.  G is chosen per call from the mean line length (see
+// pick_lanes): rows 32 or 64 lanes, columns 8, 16 or 64.  Measured on the
+// batched workload (fold of 256 slices): 64 lanes per row and per column
+// 20.3 ms, 32 per row and 16 per column 10.3 ms, 32 and 8 10.0 ms; 16 per
+// row slowed the row fill (3.9 -> 5.8 ms).  On the polar grid (columns of
+// ~420 entries) 8 lanes per column would stage nothing: whole wavefronts.
+//
+// Entries staged per group: columns 8 per lane (a whole column), rows 6 per
+// lane and list; a wavefront per line (G = 64) keeps the larger buffers.
 template <bool COLS, int G>
 constexpr int stage_cap() {
   if constexpr (G == 64) return COLS ? kStageCol : kStageRow;
-  else return COLS ? kColCap : kRowCap;
+  else return COLS ? 8 * G : 6 * G;
 }
 
 // A sorted list of len (<= R * 64) entries in registers, R per lane: all
@@ -353,8 +351,7 @@ __device__ int64_t fold_line(const ss_matrix_dev& A, int64_t t, int64_t out_base
 
 // This wavefront's staging buffers in the block's shared memory.
 #define SS_STAGE_BUF(name)                                                        \
-  constexpr int name##_cap = COLS ? std::max(kStageCol, kWave / kColLanes * kColCap) \
-                                  : std::max(2 * kStageRow, kWave / kRowLanes * 2 * kRowCap); \
+  constexpr int name##_cap = COLS ? std::max(kStageCol, 8 * kWave) : std::max(2 * kStageRow, 12 * kWave); \
   __shared__ int32_t name##_idx[kFoldWaves][name##_cap];                          \
   __shared__ float name##_val[kFoldWaves][name##_cap];                            \
   const StageBuf name{(SS_LDS int32_t*)(&name##_idx[wave_id()][0]), (SS_LDS float*)(&name##_val[wave_id()][0])}
@@ -502,14 +499,13 @@ __device__ inline const FoldJob& find_job(const JobArg& J, int64_t b, int64_t* l
 }
 
 // Union size of every output line into ptr[t + 1]; ptr[0] = 0.
-template <bool COLS, bool B>
+template <bool COLS, bool B, int G>
 __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(JobArg J) {
   SS_STAGE_BUF(sb);
   int64_t lb;
   const FoldJob& jb = find_job<B, COLS, false>(J, blockIdx.x, &lb);
   const ss_matrix_dev& A = jb.A;
   const int64_t lines = COLS ? A.N / 2 : A.M / 2;
-  constexpr int G = line_lanes<COLS>();
   const int grp = lane_id() / G;
   const int64_t t = (lb * kFoldWaves + wave_id()) * (kWave / G) + grp;
   if (t >= lines) return;
@@ -623,7 +619,7 @@ __device__ inline float recip_or_zero(double s) {
 // with the FP32 reciprocal of the FP64 line sum of A (rows: W_i = sum over
 // row i of A = sum of a + b over the union; columns: V_j likewise), and for
 // rows also the folded p.
-template <bool COLS, int WT, bool B>
+template <bool COLS, int WT, bool B, int G>
 __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_fill(JobArg J) {
   SS_STAGE_BUF(sb);
   int64_t lb;
@@ -632,7 +628,6 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_fill(JobArg J) {
   const ss_system& out = jb.out;
   const float* p = jb.p;
   const int64_t lines = COLS ? out.n : out.m;
-  constexpr int G = line_lanes<COLS>();
   const int grp = lane_id() / G;
   const int64_t t = (lb * kFoldWaves + wave_id()) * (kWave / G) + grp;
   if (t >= lines) return;
@@ -685,11 +680,26 @@ inline unsigned blocks_for(int64_t lines) {
   return static_cast<unsigned>((lines + kFoldWaves - 1) / kFoldWaves);
 }
 
-// Blocks of the counting and filling passes (kWave / line_lanes lines per wavefront).
-template <bool COLS>
-inline unsigned line_blocks_for(int64_t lines) {
-  constexpr int64_t per = kFoldWaves * (kWave / line_lanes<COLS>());
+// Blocks of the counting and filling passes (kWave / G lines per wavefront).
+inline unsigned line_blocks_for(int64_t lines, int G) {
+  const int64_t per = kFoldWaves * (kWave / G);
   return static_cast<unsigned>((lines + per - 1) / per);
+}
+
+// Lanes per line for one fold call, from the mean source-line lengths of all
+// its matrices: a group is used where a mean row list fills half of its
+// staging buffer, or a mean column three quarters of it, so that most lines
+// are staged.
+inline void pick_lanes(const ss_matrix_dev* A, int32_t count, int* grow, int* gcol) {
+  double nnz = 0, M = 0, N = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    nnz += static_cast<double>(A[k].nnz);
+    M += static_cast<double>(A[k].M);
+    N += static_cast<double>(A[k].N);
+  }
+  const double row = nnz / std::max(M, 1.0), col = nnz / std::max(N, 1.0);
+  *grow = row <= 6.0 * 32 ? 32 : 64;  // a row pair: two lists of about row / 2
+  *gcol = col <= 4.0 * 8 * 1.5 ? 8 : col <= 4.0 * 16 * 1.5 ? 16 : 64;
 }
 
 ss_status check_dev_matrix(const ss_matrix_dev* A, const char* fn) {
@@ -717,6 +727,7 @@ __global__ void k_put_jobs(JobChunk ch, FoldJob* table) {
 // Grid sizes of one fold call: blocks of row and column lines, scan tiles.
 struct FoldGrid {
   int64_t rblk = 0, cblk = 0, rtile = 0, ctile = 0;
+  int grow = 64, gcol = 64;  // lanes per row pair / column
 };
 
 inline int64_t tiles_for(int64_t len) { return std::max<int64_t>(1, scan_tiles(len)); }
@@ -727,21 +738,35 @@ void run_fold(const JobArg& J, const FoldGrid& g, int wt, int64_t* tiles, hipStr
   const dim3 lb(kWave * kFoldWaves), sb(kScanThreads);
   const auto R = static_cast<unsigned>(g.rblk), Cb = static_cast<unsigned>(g.cblk);
   const auto RT = static_cast<unsigned>(g.rtile), CT = static_cast<unsigned>(g.ctile);
+  auto count = [&](auto cols, auto g, unsigned blocks) {
+    k_fold_count<decltype(cols)::value, B, decltype(g)::value><<<blocks, lb, 0, st>>>(J);
+  };
+  auto fill = [&](auto cols, auto g, unsigned blocks) {
+    constexpr bool C = decltype(cols)::value;
+    constexpr int G = decltype(g)::value;
+    if (wt == SS_F32) k_fold_fill<C, SS_F32, B, G><<<blocks, lb, 0, st>>>(J);
+    else if (wt == SS_BF16) k_fold_fill<C, SS_BF16, B, G><<<blocks, lb, 0, st>>>(J);
+    else k_fold_fill<C, SS_F16, B, G><<<blocks, lb, 0, st>>>(J);
+  };
+  using Rows = std::false_type;
+  using Cols = std::true_type;
   if (R > 0) {
-    k_fold_count<false, B><<<R, lb, 0, st>>>(J);
+    if (g.grow == 32) count(Rows{}, std::integral_constant<int, 32>{}, R);
+    else count(Rows{}, std::integral_constant<int, 64>{}, R);
     k_scan_tiles<false, B><<<RT, sb, 0, st>>>(J, tiles);
     k_scan_apply<false, B><<<RT, sb, 0, st>>>(J, tiles);
-    if (wt == SS_F32) k_fold_fill<false, SS_F32, B><<<R, lb, 0, st>>>(J);
-    else if (wt == SS_BF16) k_fold_fill<false, SS_BF16, B><<<R, lb, 0, st>>>(J);
-    else k_fold_fill<false, SS_F16, B><<<R, lb, 0, st>>>(J);
+    if (g.grow == 32) fill(Rows{}, std::integral_constant<int, 32>{}, R);
+    else fill(Rows{}, std::integral_constant<int, 64>{}, R);
   }
   if (Cb > 0) {
-    k_fold_count<true, B><<<Cb, lb, 0, st>>>(J);
+    if (g.gcol == 8) count(Cols{}, std::integral_constant<int, 8>{}, Cb);
+    else if (g.gcol == 16) count(Cols{}, std::integral_constant<int, 16>{}, Cb);
+    else count(Cols{}, std::integral_constant<int, 64>{}, Cb);
     k_scan_tiles<true, B><<<CT, sb, 0, st>>>(J, tiles);
     k_scan_apply<true, B><<<CT, sb, 0, st>>>(J, tiles);
-    if (wt == SS_F32) k_fold_fill<true, SS_F32, B><<<Cb, lb, 0, st>>>(J);
-    else if (wt == SS_BF16) k_fold_fill<true, SS_BF16, B><<<Cb, lb, 0, st>>>(J);
-    else k_fold_fill<true, SS_F16, B><<<Cb, lb, 0, st>>>(J);
+    if (g.gcol == 8) fill(Cols{}, std::integral_constant<int, 8>{}, Cb);
+    else if (g.gcol == 16) fill(Cols{}, std::integral_constant<int, 16>{}, Cb);
+    else fill(Cols{}, std::integral_constant<int, 64>{}, Cb);
   }
 }
 
@@ -764,6 +789,7 @@ ss_status check_fold_out(const ss_matrix_dev* A, const float* p, const ss_system
 FoldGrid layout_jobs(const ss_matrix_dev* A, const float* const* p, const ss_system* out, int32_t count,
                      std::vector<FoldJob>* jobs) {
   FoldGrid g;
+  pick_lanes(A, count, &g.grow, &g.gcol);
   for (int32_t k = 0; k < count; ++k) {
     FoldJob j{};
     j.A = A[k];
@@ -773,8 +799,8 @@ FoldGrid layout_jobs(const ss_matrix_dev* A, const float* const* p, const ss_sys
     j.cblk0 = g.cblk;
     j.rtile0 = g.rtile;
     j.ctile0 = g.ctile;
-    g.rblk += line_blocks_for<false>(A[k].M / 2);
-    g.cblk += line_blocks_for<true>(A[k].N / 2);
+    g.rblk += line_blocks_for(A[k].M / 2, g.grow);
+    g.cblk += line_blocks_for(A[k].N / 2, g.gcol);
     g.rtile += tiles_for(A[k].M / 2);
     g.ctile += tiles_for(A[k].N / 2);
     if (jobs) jobs->push_back(j);
