@@ -110,8 +110,9 @@ struct LSeq {
 // dependent global loads: rows of up to kStageRow entries (two lists), columns
 // of up to kStageCol entries; longer lines are merged from global memory.
 // The buffers are sized for the lines of the workloads (rows up to ~400,
-// columns up to ~80 entries) and small enough to keep 6 (rows) or 8
-// (columns) blocks per CU.
+// columns up to ~80 entries in the batched workload) and small enough to
+// keep 6 (rows: 768 entries per wavefront) or 8 (columns: 512) blocks per
+// CU.
 constexpr int kStageRow = 384;
 constexpr int kStageCol = 256;
 
@@ -134,7 +135,7 @@ constexpr int stage_cap() {
   else return COLS ? 8 * G : 6 * G;
 }
 
-// A sorted list of len (<= R * 64) entries in registers, R per lane: all
+// A sorted list of len (<= R * G) entries in registers, R per lane: all
 // its loads are issued before the first is waited for, so a line pair costs
 // one memory latency, not one per 64 entries.  VALS: also the values (the
 // counting pass needs only the indices).
@@ -145,8 +146,8 @@ struct Staged {
 };
 
 // A line is handled by a group of G lanes (G = 64: the whole wavefront;
-// G = 32: each half of it folds its own line).  Ballots are cut to the
-// group's bits.
+// G < 64: the wavefront folds 64 / G lines at once).  Ballots are cut to
+// the group's bits.
 template <int G>
 __device__ inline int group_lane() {
   return lane_id() & (G - 1);
