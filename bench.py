@@ -202,6 +202,7 @@ def main():
         return e0.elapsed_time(e1) / k, time.perf_counter() - t0
 
     if args.subsets_only:
+        ascending_order(slices, systems)
         print(json.dumps({"ordered_subsets": subsets_report(slices, systems, opts, dev, lam)}), flush=True)
         return
 
@@ -270,17 +271,9 @@ def main():
     out["split_vs_unsplit"] = ums / ms
     log(f"unsplit step {ums:.3f} ms; split/unsplit speedup {ums / ms:.2f}")
 
-    # ordered subsets (mirror-paired views) against SART, to rel_res 1e-2;
-    # the subset build needs each column's rows ascending: fold back into
-    # the ascending order first
-    if not args.no_subsets and any(S.row_lanes or S.col_lanes for S in systems):
-        for S in systems:
-            S.row_lanes = S.col_lanes = 0
-        if len(slices) > 1:
-            native.FoldBatch([x.A for x in slices], [x.p for x in slices], systems)()
-        else:
-            native.fold_into(slices[0].A, slices[0].p, systems[0])
+    # ordered subsets (mirror-paired views) against SART, to rel_res 1e-2
     if not args.no_subsets:
+        ascending_order(slices, systems)
         out["ordered_subsets"] = subsets_report(slices, systems, opts, dev, lam)
         log(f"ordered subsets: {out['ordered_subsets']}")
 
@@ -379,6 +372,21 @@ def pick_line_order(args, slices, systems, sol, scratch):
     for S in systems:
         S.row_lanes = S.col_lanes = 0
     return native.Solver(systems, opts)
+
+
+def ascending_order(slices, systems):
+    """Folds the systems back into ascending line order where the step
+    stored the interleaved one: the ordered-subset build needs each column's
+    rows ascending."""
+    from paper_1902_10559_amd import native
+    if not any(S.row_lanes or S.col_lanes for S in systems):
+        return
+    for S in systems:
+        S.row_lanes = S.col_lanes = 0
+    if len(slices) > 1:
+        native.FoldBatch([x.A for x in slices], [x.p for x in slices], systems)()
+    else:
+        native.fold_into(slices[0].A, slices[0].p, systems[0])
 
 
 def os_forms(chunked):
