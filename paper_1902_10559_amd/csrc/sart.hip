@@ -122,19 +122,23 @@ __global__ void k_put_desc(DescChunk ch, SysDesc* table, Params prm_in, Params* 
 }
 
 // Resets each system's state, clears its image (zero_start) and reduces
-// ||p||^2 in a fixed order: one block per system, all systems in one launch.
+// ||p||^2 in a fixed order: one block of kSetupWaves wavefronts per system
+// (a single system is one block: the wider, the sooner it is done), all
+// systems in one launch.
+constexpr int kSetupWaves = 16;
 template <int NV>
-__global__ __launch_bounds__(kThreads) void k_setup(const SysDesc* table, SetupFlags fl) {
+__global__ __launch_bounds__(kWave* kSetupWaves) void k_setup(const SysDesc* table, SetupFlags fl) {
+  constexpr int T = kWave * kSetupWaves;
   const SysDesc& d = table[blockIdx.x];
   if (fl.zero_start)
-    for (int64_t i = threadIdx.x; i < d.n * NV; i += kThreads) d.f[0][i] = 0.0f;
+    for (int64_t i = threadIdx.x; i < d.n * NV; i += T) d.f[0][i] = 0.0f;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < d.m * NV; i += kThreads) {
+  for (int64_t i = threadIdx.x; i < d.m * NV; i += T) {
     const double v = d.p[i];
     s += v * v;
   }
-  __shared__ double red[kWPB];
-  s = block_sum<kWPB>(s, red);
+  __shared__ double red[kSetupWaves];
+  s = block_sum<kSetupWaves>(s, red);
   if (threadIdx.x == 0) {
     d.st->pnorm2 = s;
     d.st->last_res = 0.0;
@@ -562,8 +566,8 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
     }
   }
   const SetupFlags fl{zero_start};
-  if (c.nv == 2) k_setup<2><<<static_cast<unsigned>(nsys), kThreads, 0, st>>>(table, fl);
-  else k_setup<1><<<static_cast<unsigned>(nsys), kThreads, 0, st>>>(table, fl);
+  if (c.nv == 2) k_setup<2><<<static_cast<unsigned>(nsys), kWave * kSetupWaves, 0, st>>>(table, fl);
+  else k_setup<1><<<static_cast<unsigned>(nsys), kWave * kSetupWaves, 0, st>>>(table, fl);
   if (fb > UINT32_MAX || bb > UINT32_MAX) return fail(SS_E_ARG, "SART: grid too large");
   g->fp_blocks = static_cast<uint32_t>(fb);
   g->bp_blocks = static_cast<uint32_t>(bb);
