@@ -194,6 +194,13 @@ def test_empty_matrix_folds_and_solves():
     h = [torch.zeros(6, dtype=torch.float64, device="cuda")]
     status, it = native.Solver([S], native.SartOptions(max_iter=5)).solve(f, h)
     assert it == [5] and np.all(to_np(f[0]) == 0) and np.allclose(to_np(h[0]), 1.0)
+    # the interleaved form (copies, and a stored order) on a system with no entries
+    S2 = native.fold(Ad, pd, row_lanes=8, col_lanes=4)
+    for sys_, ch in ((S, 12), (S2, 0)):
+        f = [sys_.new_image()]
+        h = [torch.zeros(6, dtype=torch.float64, device="cuda")]
+        status, it = native.Solver([sys_], native.SartOptions(max_iter=5, chunked=ch)).solve(f, h)
+        assert it == [5] and np.all(to_np(f[0]) == 0) and np.allclose(to_np(h[0]), 1.0)
 
 
 def _poison(S):
