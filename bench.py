@@ -125,8 +125,8 @@ def setup(args, dev):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the two halves and all slices run on one device); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(both halves and all slices run on one device); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import torch
