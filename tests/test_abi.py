@@ -239,3 +239,14 @@ def test_polar_voxel_centres_follow_the_numbering():
                 assert int(rho * 3 / 30.0) == r
                 assert int(math.atan2(abs(x[j]), z[j]) / (2 * math.pi / 8)) == h
                 assert (x[j] < 0) == left
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
