@@ -4,8 +4,11 @@ both halves of every slice solved in the same launches (graph replay).
 
 Parity on sampled outputs: two sampled slices (the deepest and the
 shallowest) carry projections made by the oracle, and their recombined images
-from the full batched solve are checked against the FP64 oracle; a small
-batch is checked bitwise against solo solves of the same slices."""
+from the full batched solve, in the launch configuration bench.py times (the
+fold writing the interleaved line order for 8 lanes, 8 rows and 8 columns per
+wavefront, 8 entries per lane and pass, XCD-ordered blocks), are checked
+against the FP64 oracle; a small batch is checked bitwise against solo solves
+of the same slices."""
 import numpy as np
 import pytest
 
@@ -43,7 +46,12 @@ def test_full_batch_sampled_slices_match_oracle(sampled):
     systems = [x.S for x in sl]
     total = sum(x.A.nnz for x in sl)
     banner(f"batched: nnz total {total}")
-    sol = native.Solver(systems, native.SartOptions(max_iter=ITERS, zero_start=True))
+    for S in systems:
+        S.row_lanes = S.col_lanes = 8
+    native.FoldBatch([x.A for x in sl], [x.p for x in sl], systems)()
+    opts = native.SartOptions(max_iter=ITERS, zero_start=True, rows_per_wave=8, cols_per_wave=8, xcd_remap=1,
+                              unroll=8, chunked=12)
+    sol = native.Solver(systems, opts)
     f = [S.new_image() for S in systems]
     hist = [torch.zeros(ITERS + 1, dtype=torch.float64, device="cuda") for _ in systems]
     status, iters = sol.solve(f, hist)
