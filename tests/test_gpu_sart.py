@@ -53,16 +53,23 @@ def test_split_sart_matches_fp64_oracle(cfg, iters):
 
 
 def test_split_sart_cfg2_100_iterations_matches_oracle():
-    # the benchmark workload at full size and iteration count
+    # the single-slice workload at full size and iteration count: default
+    # options, and the launch configuration bench.py times for it (the fold
+    # writing the interleaved order for 32 lanes per row and 8 per column,
+    # persistent grid)
+    import torch
     banner("split SART cfg2 100 iterations")
     pr = problem(2)
-    _, _, S = _split_system(pr)
-    f, h, status, it = _solve([S], 100)
+    Ad, pd, S = _split_system(pr)
     f_ref, res_ref = OS.sart_full(pr.A, pr.p, 0.5, 100)
-    err = rel_l2(to_np(native.recombine(f[0])), f_ref)
-    banner(f"cfg2 100 iterations rel L2 {err:.3e}")
-    assert err <= 1e-4
-    assert_res_close(to_np(h[0]), res_ref)
+    S_il = native.fold(Ad, pd, row_lanes=32, col_lanes=8)
+    bench_shape = dict(rows_per_wave=2, cols_per_wave=8, xcd_remap=1, unroll=8, persistent=1, chunked=12)
+    for sys_, kw in ((S, {}), (S_il, bench_shape)):
+        f, h, status, it = _solve([sys_], 100, **kw)
+        err = rel_l2(to_np(native.recombine(f[0])), f_ref)
+        banner(f"cfg2 100 iterations {kw} rel L2 {err:.3e}")
+        assert err <= 1e-4
+        assert_res_close(to_np(h[0]), res_ref)
 
 
 def test_unsplit_sart_matches_fp64_oracle():
