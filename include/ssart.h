@@ -26,12 +26,14 @@
  *   - Arrays of length 0 (an empty matrix, nnz = 0) may be NULL.
  *   - "device" pointers are caller-owned device memory of the current HIP
  *     device; the library never frees caller memory, and device calls never
- *     allocate device memory (scratch comes from caller workspaces).
+ *     allocate device memory (scratch comes from caller workspaces, except
+ *     for ss_fold_noalloc's fixed per-device array).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Device calls only enqueue work on it, except where a call says that it
  *     synchronises.
  *   - Calls are reentrant; the only shared state is the thread-local error
- *     text and an internal cache of instantiated HIP graphs (mutex-guarded).
+ *     text, an internal cache of instantiated HIP graphs (mutex-guarded) and
+ *     ss_fold_noalloc's per-device scratch array (see there).
  */
 #ifndef SSART_H
 #define SSART_H
@@ -255,6 +257,18 @@ ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* workspace,
  * contents on entry do not matter).  Asynchronous. */
 ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out,
                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* ss_fold with no workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation).  Same arguments, checks and results as ss_fold
+ * (bit for bit).  Its only scratch, the per-tile sums of the offset scans,
+ * lives in a 32 KiB array that the library holds in each device's memory
+ * until the process ends, located once per device on the first call there.
+ * It calls no allocating routine.  Limit: M/2 and N/2 at most 4095*4096 - 1
+ * (larger: SS_E_ARG, nothing enqueued).  Every call on one device shares
+ * that device's array, so calls that overlap on one device (other streams,
+ * other threads) race: serialise them.  Asynchronous. */
+ss_status ss_fold_noalloc(const ss_matrix_dev* A, const float* p, ss_system* out, void* stream);
 
 /* ss_fold for `count` matrices at once (Section 2 applied to each): every
  * phase (union sizes, offsets, fill; rows, then columns) is one launch over

@@ -18,6 +18,7 @@
 // the common ones counted twice).  The union size is |X| + |Y| - #common.
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -811,6 +812,35 @@ FoldGrid layout_jobs(const ss_matrix_dev* A, const float* const* p, const ss_sys
 
 size_t batch_table_bytes(int32_t count) { return (sizeof(FoldJob) * static_cast<size_t>(count) + 255) & ~size_t{255}; }
 
+// ---------------------------------------------------- allocation-free fold
+// ss_fold_noalloc keeps the scan's per-tile sums (its only scratch) in this
+// file-scope array instead of a caller workspace.  Each device holds its own
+// copy until the process ends.  In host code the name is only a stand-in for
+// the symbol: kernels are given the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+constexpr int64_t kNoallocTiles = 4096;  // 32 KiB: lines up to 4095 * kScanTile
+static __device__ __align__(256) int64_t scratch[kNoallocTiles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t* g_scratch_ptr[kMaxDevices] = {};
+
+ss_status noalloc_scratch(int64_t** out) {
+  int dev = 0;
+  SS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SS_E_ARG, "ss_fold_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SS_E_HIP, "ss_fold_noalloc: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<int64_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return SS_OK;
+}
+
 }  // namespace
 }  // namespace ss
 
@@ -860,6 +890,26 @@ extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* 
   ss_fold_workspace_bytes(A->M, A->N, &need);
   if (!workspace || workspace_bytes < need) return fail(SS_E_WORKSPACE, "ss_fold: workspace needs %zu bytes", need);
   int64_t* tiles = reinterpret_cast<int64_t*>(static_cast<char*>(workspace) + 512);
+  JobArg J{};
+  J.count = 1;
+  J.one.A = *A;
+  J.one.p = p;
+  J.one.out = *out;
+  const FoldGrid g = layout_jobs(A, nullptr, nullptr, 1, nullptr);
+  run_fold<false>(J, g, out->wdtype, tiles, static_cast<hipStream_t>(stream));
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+extern "C" ss_status ss_fold_noalloc(const ss_matrix_dev* A, const float* p, ss_system* out, void* stream) {
+  clear_error();
+  if (ss_status s = check_fold_out(A, p, out, "ss_fold_noalloc")) return s;
+  // every scan launch writes all the tile sums it reads: nothing to clear
+  if (tiles_for(std::max(A->M, A->N) / 2 + 1) + 1 > kNoallocTiles)
+    return fail(SS_E_ARG, "ss_fold_noalloc: M/2 and N/2 must be at most %lld (the scratch holds %lld tile sums)",
+                (long long)((kNoallocTiles - 1) * kScanTile - 1), (long long)kNoallocTiles);
+  int64_t* tiles = nullptr;
+  if (ss_status s = noalloc_scratch(&tiles)) return s;
   JobArg J{};
   J.count = 1;
   J.one.A = *A;

@@ -109,6 +109,7 @@ _SIGNATURES = {
                                  C.POINTER(C.c_int64), C.c_void_p]),
     "ss_fold": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p,
                             C.c_size_t, C.c_void_p]),
+    "ss_fold_noalloc": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p]),
     "ss_unsplit": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p]),
     "ss_sart_workspace_bytes": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(SartOptsC),
                                             C.POINTER(C.c_size_t)]),
@@ -398,6 +399,12 @@ def fold_into(A: DeviceMatrix, p, S: System) -> None:
     ws = fold_workspace(A)
     _check(lib().ss_fold(C.byref(mc), _ptr(p), C.byref(sc), _ptr(ws), ws.numel(),
                          _stream(A.val.device)))
+
+
+def fold_noalloc_into(A: DeviceMatrix, p, S: System) -> None:
+    """ss_fold_noalloc into an existing system's arrays (no workspace)."""
+    mc, sc = A.c(), S.c()
+    _check(lib().ss_fold_noalloc(C.byref(mc), _ptr(p), C.byref(sc), _stream(A.val.device)))
 
 
 class FoldBatch:

@@ -167,6 +167,23 @@ def test_fold_rejects_odd_sizes_before_device_work():
     assert L.ss_image_fold(one, 7, one, None) == -2
 
 
+def test_fold_noalloc_rejects_oversized_matrices_before_device_work():
+    """The allocation-free fold holds 4096 scan-tile sums of 4096 lines each:
+    a matrix with more than 2 * (4095 * 4096 - 1) rows is refused before any
+    device call (the fake pointers below are never touched)."""
+    L = native.lib()
+    one = C.c_void_p(16)
+    big = 2 * (4095 * 4096)
+    A = native.MatrixDevC(big, 8, 4, one, one, one, one, one, one)
+    S = native.SystemC(big // 2, 4, 4, 2, 0, one, one, one, one, one, one, one, one, one, 0, 0)
+    assert L.ss_fold_noalloc(C.byref(A), one, C.byref(S), None) == -1
+    assert "at most 16773119" in L.ss_last_error().decode()
+    A.M, S.m = 6, 3
+    A.N = 7   # odd N: the ordinary argument checks come first
+    assert L.ss_fold_noalloc(C.byref(A), one, C.byref(S), None) == -2
+    assert "even" in L.ss_last_error().decode()
+
+
 @pytest.mark.parametrize("which", ["tgs", "medium"])
 def test_host_build_polar_system_matches_oracle_bitwise(which):
     from oracle import polar as P
