@@ -68,6 +68,15 @@ def parse():
                     help="only the ordered-subset comparison on the workload (one JSON line)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the plain vs learned-start comparison on the 256x256 workload")
+    ap.add_argument("--no-ttr", action="store_true",
+                    help="skip the time-to-1e-3 runs on the workload")
+    ap.add_argument("--no-dtypes", action="store_true",
+                    help="skip the BF16/FP16-weight step records")
+    ap.add_argument("--staged", default="", metavar="BITS,BAND,TILE,RPW,CPW,UNROLL",
+                    help="fixed staged-kernel configuration instead of the timed choice "
+                         "(BITS 0 keeps the unstaged kernels of --shape or the autotuner)")
     ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT,CHUNKED",
                     help="fixed launch shape instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -152,54 +161,23 @@ def main():
     nnz_full = sum(x.A.nnz for x in slices)
     nnz_half = sum(S.nnz for S in systems)
     iters = args.iters
-    opts = native.SartOptions(lam=lam, max_iter=iters, use_graph=True, zero_start=True)
+    # eq. (2) and the arrays of every matrix, checked as one batch
+    out_validate = validation_report(slices)
+    log(f"validation: {out_validate}")
+    opts, lanes = choose_config(args, slices, systems, lam, iters)
+    for S in systems:
+        S.row_lanes, S.col_lanes = lanes
     sol = native.Solver(systems, opts)
     scratch = [S.new_image() for S in systems]
-    if args.shape:
-        (opts.rows_per_wave, opts.cols_per_wave, opts.xcd_remap, opts.unroll,
-         opts.persistent, opts.chunked) = map(int, args.shape.split(","))
-    else:
-        sol.autotune(scratch)
-        sol = pick_line_order(args, slices, systems, sol, scratch)
-    if opts.chunked & 12:
-        # the interleaved stream order is written by the fold itself (the
-        # step's fold below), so the solver reads the lines in place
-        for S in systems:
-            S.row_lanes = 64 // opts.rows_per_wave if opts.chunked & 4 else 0
-            S.col_lanes = 64 // opts.cols_per_wave if opts.chunked & 8 else 0
-        sol = native.Solver(systems, opts)
     f12 = [S.new_image() for S in systems]
     f_out = [torch.empty(2 * S.n, dtype=torch.float32, device=dev) for S in systems]
-    log(f"slices={len(slices)} nnz={nnz_full} nnz_half={nnz_half} shape rpw={opts.rows_per_wave} "
-        f"cpw={opts.cols_per_wave} xcd={opts.xcd_remap}")
-
-    if len(slices) > 1:   # all slices fold in one launch per phase
-        fold_all = native.FoldBatch([x.A for x in slices], [x.p for x in slices], systems)
-        recombine_all = native.RecombineBatch(f12, f_out)
-    else:
-        def fold_all():
-            native.fold_into(slices[0].A, slices[0].p, systems[0])
-
-        def recombine_all():
-            native.recombine(f12[0], f_out[0])
+    log(f"slices={len(slices)} nnz={nnz_full} nnz_half={nnz_half} config {config_of(opts)} lanes {lanes}")
+    fold_all, recombine_all = step_parts(slices, systems, f12, f_out)
 
     def split_step():
         fold_all()
         sol.solve(f12, want_iters=False)
         recombine_all()
-
-    def timed(step, k, w):
-        for _ in range(w):
-            step()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record()
-        for _ in range(k):
-            step()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / k, time.perf_counter() - t0
 
     if args.subsets_only:
         ascending_order(slices, systems)
@@ -215,61 +193,60 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.wdtype if args.wdtype == "f32" else f"{args.wdtype} weights, f32 arithmetic",
         "data": "synthetic",
-        "config": {"workload": f"{desc}; fold + {iters} split-SART iterations (lambda={lam}) "
-                               f"+ recombination per step",
-                   "slices": len(slices), "nnz": int(nnz_full), "nnz_half": int(nnz_half),
-                   "iterations": iters, "rows_per_wave": opts.rows_per_wave,
-                   "cols_per_wave": opts.cols_per_wave, "xcd_remap": opts.xcd_remap,
-                   "unroll": opts.unroll, "persistent": opts.persistent, "chunked": opts.chunked},
+        "config": dict({"workload": f"{desc}; fold + {iters} split-SART iterations (lambda={lam}) "
+                                    f"+ recombination per step",
+                        "slices": len(slices), "nnz": int(nnz_full), "nnz_half": int(nnz_half),
+                        "iterations": iters}, **config_of(opts)),
     }
     if args.no_extras:
         print(json.dumps(out), flush=True)
         return
+    out["validate"] = out_validate
 
-    # per-kernel durations, stamped by the kernels' own dispatches on the
+    # per-launch durations, stamped by the kernels' own dispatches on the
     # solver's stream, in the alternating forward/back sequence
-    fp_ms, bp_ms = sol.time_kernels(scratch, reps=50)
-    fp_b = bp_b = 0
-    for S in systems:
-        a, b = bytes_per_iteration(S.nnz, S.m, S.n, 2, SV[args.wdtype])
-        fp_b += a
-        bp_b += b
-    dom = ("sart_fp", fp_ms, fp_b) if fp_ms >= bp_ms else ("sart_bp", bp_ms, bp_b)
-    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.wdtype}.json")
-    if os.path.exists(tfile):
-        t = json.load(open(tfile))
-        if t.get("source_hash") == source_hash() and dom[0] in t.get("kernels", {}):
-            traffic = t["kernels"][dom[0]]["bytes_per_launch"]
-    out["roofline"] = {"bound": "hbm", "kernel": dom[0], "achieved": achieved,
-                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                       "traffic": traffic, "algorithmic_bytes_per_launch": dom[2],
-                       "launch_ms": dom[1], "fp_ms": fp_ms, "bp_ms": bp_ms}
-    out["bytes_per_iteration"] = fp_b + bp_b
-    out["kernel_gbs_per_iteration"] = (fp_b + bp_b) / ((fp_ms + bp_ms) * 1e-3) / 1e9
-    out["step_gbs"] = iters * (fp_b + bp_b) / (ms * 1e-3) / 1e9
+    kern = kernel_report(sol, systems, scratch, opts, 2, SV[args.wdtype])
+    out["roofline"] = roofline_of(kern, args)
+    out["kernels"] = kern
+    out["bytes_per_iteration"] = kern["bytes_per_iteration"]
+    out["kernel_gbs_per_iteration"] = kern["gbs_per_iteration"]
+    out["step_gbs"] = iters * kern["bytes_per_iteration"] / (ms * 1e-3) / 1e9
 
-    # the unsplit A (same FP32 arithmetic, one value per entry)
+    # the unsplit A (same FP32 arithmetic, one value per entry), with the
+    # same kind of kernels
     unsplit = [native.unsplit(x.A, x.p) for x in slices]
-    uopts = native.SartOptions(lam=lam, max_iter=iters, use_graph=True, zero_start=True)
+    uopts = unsplit_config(unsplit, opts, lam, iters)
     usol = native.Solver(unsplit, uopts)
     uscratch = [U.new_image() for U in unsplit]
-    usol.autotune(uscratch)
     fu = [U.new_image() for U in unsplit]
     ums, _ = timed(lambda: usol.solve(fu, want_iters=False), args.steps, args.warmup)
-    ufp, ubp = usol.time_kernels(uscratch, reps=50)
-    ub = 0
-    for x in slices:
-        a, b = bytes_per_iteration(x.A.nnz, x.A.M, x.A.N, 1, 4)
-        ub += a + b
+    ukern = kernel_report(usol, unsplit, uscratch, uopts, 1, 4)
     out["unsplit"] = {"ms_per_step": ums, "value": iters * nnz_full / (ums * 1e-3),
-                      "fp_ms": ufp, "bp_ms": ubp, "bytes_per_iteration": ub,
-                      "kernel_gbs_per_iteration": ub / ((ufp + ubp) * 1e-3) / 1e9,
-                      "shape": [uopts.rows_per_wave, uopts.cols_per_wave, uopts.xcd_remap,
-                                uopts.unroll, uopts.persistent, uopts.chunked]}
+                      "kernels": ukern, "bytes_per_iteration": ukern["bytes_per_iteration"],
+                      "kernel_gbs_per_iteration": ukern["gbs_per_iteration"], "config": config_of(uopts)}
     out["split_vs_unsplit"] = ums / ms
     log(f"unsplit step {ums:.3f} ms; split/unsplit speedup {ums / ms:.2f}")
+
+    # 16-bit weights: the same step with BF16 and FP16 storage of the pair
+    low = {}
+    if not args.no_dtypes and args.wdtype == "f32":
+        for wd in ("bf16", "f16"):
+            low[wd] = dtype_systems(slices, wd)
+        out["weights_16bit"] = {wd: dtype_record(args, slices, low[wd], opts, lanes, wd, iters, nnz_full, timed)
+                                for wd in low}
+        log(f"16-bit weights: {out['weights_16bit']}")
+
+    # time to relative residual 1e-3 on the workload itself (capped at
+    # 20000 iterations): split vs unsplit FP32, and 16-bit weights
+    ttr = {}
+    ascending_order(slices, systems)
+    if not args.no_ttr:
+        ttr["workload"] = workload_time_to_tol(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev)
+        log(f"time to 1e-3 on the workload: {ttr['workload']}")
+    for wd in list(low):
+        del low[wd]
+    del usol, uscratch, fu, unsplit
+    torch.cuda.empty_cache()
 
     # ordered subsets (mirror-paired views) against SART, to rel_res 1e-2
     if not args.no_subsets:
@@ -287,18 +264,341 @@ def main():
         out["polar_grid"] = polar_report(dev, lam)
         log(f"polar grid: {out['polar_grid']}")
 
-    # time to relative residual 1e-3 (capped at 20000 iterations)
-    ttr = {}
-    if args.workload == "slice":
-        ttr["bench_workload"] = {"split": time_to_tol(sol, f12, dev), "unsplit": time_to_tol(usol, fu, dev)}
+    # plain vs learned-initialised SART on the 256 x 256 workload
+    if not args.no_learned:
+        out["learned"] = learned_report(dev)
+        log(f"learned: {out['learned']}")
+
     ttr["64x64_slice_0.5pct_noise"] = small_slice_time_to_tol(dev, lam)
     out["time_to_1e-3"] = ttr
-    log(f"time to 1e-3: {ttr}")
+    log(f"time to 1e-3 (64x64): {ttr['64x64_slice_0.5pct_noise']}")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, slices, iters, lam)
         log(f"cpu baseline {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
+
+
+def timed(step, k, w):
+    """Mean event time of k steps after w untimed ones, and the wall time."""
+    import torch
+    for _ in range(w):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(k):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / k, time.perf_counter() - t0
+
+
+def step_parts(slices, systems, f12, f_out):
+    """The fold of all slices and the recombination of all images: one launch
+    per phase for a batch."""
+    from paper_1902_10559_amd import native
+    if len(slices) > 1:
+        return (native.FoldBatch([x.A for x in slices], [x.p for x in slices], systems),
+                native.RecombineBatch(f12, f_out))
+
+    def fold_all():
+        native.fold_into(slices[0].A, slices[0].p, systems[0])
+
+    def recombine_all():
+        native.recombine(f12[0], f_out[0])
+    return fold_all, recombine_all
+
+
+def config_of(o):
+    """The launch configuration fields of a SartOptions, for the report."""
+    return {"rows_per_wave": o.rows_per_wave, "cols_per_wave": o.cols_per_wave, "xcd_remap": o.xcd_remap,
+            "unroll": o.unroll, "persistent": o.persistent, "chunked": o.chunked, "staged": o.staged,
+            "band_width": o.band_width, "tile_cols": o.tile_cols, "tile_segments": o.tile_segments}
+
+
+def lanes_of(o):
+    """The line orders the step's fold writes for these options: the
+    interleaved order for an unstaged kernel reading it in place, ascending
+    for the staged ones."""
+    rl = 64 // o.rows_per_wave if (o.chunked & 4) and not (o.staged & 1) else 0
+    cl = 64 // o.cols_per_wave if (o.chunked & 8) and not (o.staged & 2) else 0
+    return rl, cl
+
+
+def validation_report(slices, reps=3):
+    """ss_fold_size_batch on every matrix of the workload (eq. (2) bitwise,
+    offsets, order, range, finiteness, CSR = CSC, the fold's size): best of
+    `reps` event times."""
+    import torch
+    from paper_1902_10559_amd import native
+    chk = native.FoldCheckBatch([x.A for x in slices], [x.p for x in slices])
+    sizes = chk()
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        chk()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    ok = all(S is None or k == S.nnz for k, S in zip(sizes, [x.S for x in slices]))
+    return {"validate_ms": best, "matrices": len(slices), "sizes_match_fold": bool(ok)}
+
+
+def choose_config(args, slices, systems, lam, iters):
+    """The step's kernels: the autotuned unstaged launch shape (or --shape),
+    a small search of the staged forms (or --staged), then whole steps timed
+    for unstaged, staged and mixed forward/back choices; the fastest wins.
+    Returns the options and the line orders the fold must write."""
+    import dataclasses
+    from paper_1902_10559_amd import native
+    scratch = [S.new_image() for S in systems]
+    base = native.SartOptions(lam=lam, max_iter=iters, use_graph=True, zero_start=True)
+    for S in systems:
+        S.row_lanes = S.col_lanes = 0
+    if args.shape:
+        (base.rows_per_wave, base.cols_per_wave, base.xcd_remap, base.unroll,
+         base.persistent, base.chunked) = map(int, args.shape.split(","))
+    else:
+        sol = native.Solver(systems, base)
+        sol.autotune(scratch)
+        sol = pick_line_order(args, slices, systems, sol, scratch)
+        base = sol.opts
+    if args.staged:
+        bits, band, tile, rpw, cpw, unroll = map(int, args.staged.split(","))
+        if bits == 0:
+            return base, lanes_of(base)
+        o = dataclasses.replace(base, staged=bits, band_width=band, tile_cols=tile, unroll=unroll,
+                                rows_per_wave=rpw if bits & 1 else base.rows_per_wave,
+                                cols_per_wave=cpw if bits & 2 else base.cols_per_wave)
+        return o, lanes_of(o)
+    fp, bp = staged_search(systems, base, scratch)
+    cands = [base,
+             dataclasses.replace(base, staged=3, unroll=8, rows_per_wave=fp[1], band_width=fp[0],
+                                 cols_per_wave=bp[1], tile_cols=bp[0]),
+             dataclasses.replace(base, staged=1, rows_per_wave=fp[1], band_width=fp[0]),
+             dataclasses.replace(base, staged=2, cols_per_wave=bp[1], tile_cols=bp[0])]
+    best, best_ms = base, 1e30
+    for o in cands:
+        lanes = lanes_of(o)
+        for S in systems:
+            S.row_lanes, S.col_lanes = lanes
+        f12 = [S.new_image() for S in systems]
+        f_out = [S.new_image().view(-1) for S in systems]
+        fold_all, recombine_all = step_parts(slices, systems, f12, f_out)
+        slv = native.Solver(systems, o)
+
+        def step():
+            fold_all()
+            slv.solve(f12, want_iters=False)
+            recombine_all()
+        ms, _ = timed(step, 3, 1)
+        log(f"step candidate {config_of(o)}: {ms:.2f} ms")
+        if ms < best_ms:
+            best, best_ms = o, ms
+        del slv, f12, f_out, fold_all, recombine_all
+    for S in systems:
+        S.row_lanes = S.col_lanes = 0
+    return best, lanes_of(best)
+
+
+def staged_search(systems, base, scratch):
+    """Per-kernel times of a few staged shapes (systems in ascending order):
+    the forward band width and segments per wavefront, the back-projection
+    tile width and columns per wavefront.  Returns (band, rpw), (tile, cpw)."""
+    import dataclasses
+    from paper_1902_10559_amd import native
+    fp_best, bp_best = ((4096, 4), 1e30), ((1024, 8), 1e30)
+    for band, rpw in ((4096, 4), (8192, 4), (4096, 8), (8192, 8)):
+        o = dataclasses.replace(base, staged=1, band_width=band, rows_per_wave=rpw, unroll=8, chunked=0)
+        ms = native.Solver(systems, o).time_phases(scratch, reps=10)
+        if ms[0] + ms[1] < fp_best[1]:
+            fp_best = ((band, rpw), ms[0] + ms[1])
+    for tile, cpw in ((1024, 8), (2048, 8), (1024, 16), (2048, 16)):
+        o = dataclasses.replace(base, staged=2, tile_cols=tile, cols_per_wave=cpw, unroll=8, chunked=0)
+        ms = native.Solver(systems, o).time_phases(scratch, reps=10)
+        if ms[2] < bp_best[1]:
+            bp_best = ((tile, cpw), ms[2])
+    log(f"staged search: forward {fp_best}, back {bp_best}")
+    return fp_best[0], bp_best[0]
+
+
+def unsplit_config(unsplit, opts, lam, iters):
+    """The unsplit baseline's options: the split step's kinds of kernels
+    (staged or not), with its own autotuned unstaged shape."""
+    import dataclasses
+    from paper_1902_10559_amd import native
+    uopts = native.SartOptions(lam=lam, max_iter=iters, use_graph=True, zero_start=True)
+    usol = native.Solver(unsplit, uopts)
+    usol.autotune([U.new_image() for U in unsplit])
+    uopts = usol.opts
+    if opts.staged:
+        uopts = dataclasses.replace(uopts, staged=opts.staged, band_width=opts.band_width,
+                                    tile_cols=opts.tile_cols, tile_segments=opts.tile_segments,
+                                    rows_per_wave=opts.rows_per_wave if opts.staged & 1 else uopts.rows_per_wave,
+                                    cols_per_wave=opts.cols_per_wave if opts.staged & 2 else uopts.cols_per_wave,
+                                    unroll=opts.unroll)
+    return uopts
+
+
+def kernel_report(slv, systems, scratch, o, nv, sv):
+    """Per-launch times of one iteration and the algorithmic bytes of each
+    launch (the byte model of the kernels the options select)."""
+    ms = slv.time_phases(scratch, reps=50)
+    info = slv.staged_info(scratch) if o.staged else [0, 0, 0, 0, 0]
+    nnz = sum(S.nnz for S in systems)
+    m = sum(S.m for S in systems)
+    n = sum(S.n for S in systems)
+    ntiles_bp = sum((S.n + (o.tile_cols or 1024) - 1) // (o.tile_cols or 1024) for S in systems)
+    fp_u, bp_u = bytes_per_iteration(nnz, m, n, nv, sv)
+    rep = {"ms": {}, "bytes": {}}
+    if o.staged & 1:
+        segs = info[0]
+        rep["ms"]["band_fp"], rep["ms"]["band_fin"] = ms[0], ms[1]
+        rep["bytes"]["band_fp"] = nnz * (2 + nv * sv) + segs * (8 + 4 * nv) + n * 4 * nv + 16 * info[1]
+        rep["bytes"]["band_fin"] = m * (4 + 4 * nv + 4 + 4 * nv) + 4 * len(systems) + segs * 4 * nv
+        rep["segments"], rep["band_tiles"] = segs, info[1]
+    else:
+        rep["ms"]["sart_fp"] = ms[0]
+        rep["bytes"]["sart_fp"] = fp_u
+    if o.staged & 2:
+        rep["ms"]["tile_bp"] = ms[2]
+        rep["bytes"]["tile_bp"] = nnz * (2 + nv * sv) + n * (8 + 4 + 8 * nv) + m * 4 * nv + 16 * ntiles_bp
+        rep["bp_tiles"], rep["bp_tiles_staged"], rep["bp_staged_rows"] = info[2], info[3], info[4]
+    else:
+        rep["ms"]["sart_bp"] = ms[2]
+        rep["bytes"]["sart_bp"] = bp_u
+    tot_b = sum(rep["bytes"].values())
+    tot_ms = sum(rep["ms"].values())
+    rep["bytes_per_iteration"] = tot_b
+    rep["ms_per_iteration"] = tot_ms
+    rep["gbs_per_iteration"] = tot_b / (tot_ms * 1e-3) / 1e9
+    rep["gbs"] = {k: rep["bytes"][k] / (rep["ms"][k] * 1e-3) / 1e9 for k in rep["ms"] if rep["ms"][k] > 0}
+    return rep
+
+
+def roofline_of(kern, args):
+    """The dominant launch (the longest) of an iteration against the HBM peak,
+    with the hardware byte count when a matching profile is on file."""
+    dom = max(kern["ms"], key=lambda k: kern["ms"][k])
+    achieved = kern["bytes"][dom] / (kern["ms"][dom] * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.wdtype}.json")
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        if t.get("source_hash") == source_hash() and dom in t.get("kernels", {}):
+            traffic = t["kernels"][dom]["bytes_per_launch"]
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": kern["bytes"][dom],
+            "launch_ms": kern["ms"][dom]}
+
+
+def dtype_systems(slices, wdtype):
+    """The workload's split pairs with 16-bit weight storage (fold of every
+    slice's A)."""
+    from paper_1902_10559_amd import native
+    out = []
+    for x in slices:
+        out.append(native.fold(x.A, x.p, wdtype, nnz_half=x.S.nnz))
+    return out
+
+
+def dtype_record(args, slices, systems, opts, lanes, wdtype, iters, nnz_full, timed_fn):
+    """The step (fold + iterations + recombination) with 16-bit weights under
+    the FP32 step's kernels, its per-launch times, GB/s and roofline."""
+    import argparse
+    import dataclasses
+    import torch
+    from paper_1902_10559_amd import native
+    o = dataclasses.replace(opts)
+    for S in systems:
+        S.row_lanes, S.col_lanes = lanes
+    f12 = [S.new_image() for S in systems]
+    f_out = [torch.empty(2 * S.n, dtype=torch.float32, device=S.p.device) for S in systems]
+    fold_all, recombine_all = step_parts([dataclasses.replace(x, S=S) for x, S in zip(slices, systems)],
+                                         systems, f12, f_out)
+    slv = native.Solver(systems, o)
+
+    def step():
+        fold_all()
+        slv.solve(f12, want_iters=False)
+        recombine_all()
+    ms, _ = timed_fn(step, 5, 2)
+    kern = kernel_report(slv, systems, [S.new_image() for S in systems], o, 2, SV[wdtype])
+    for S in systems:
+        S.row_lanes = S.col_lanes = 0
+    # back to ascending order for the solves that follow
+    native.FoldBatch([x.A for x in slices], [x.p for x in slices], systems)()
+    return {"ms_per_step": ms, "value": iters * nnz_full / (ms * 1e-3), "kernels": kern,
+            "roofline": roofline_of(kern, argparse.Namespace(**dict(vars(args), wdtype=wdtype)))}
+
+
+def workload_time_to_tol(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tol=1e-3, cap=20000):
+    """Iterations and time for every slice of the workload to reach rel_res
+    <= tol from f0 = 0, each slice stopping on its own (the solve ends when
+    all have, or at the cap): split vs unsplit in FP32 (the same k* per
+    slice up to FP32 rounding, since by Theorem 1 the split iterates are the
+    full ones), and split with BF16 / FP16 weights.  Events around the whole
+    solve; host checks every 200 iterations."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_1902_10559_amd import native
+    res = {"tol": tol, "cap": cap, "slices": len(slices)}
+    ks = {}
+    runs = [("split_f32", systems, opts), ("unsplit_f32", unsplit, uopts)]
+    runs += [(f"split_{wd}", low[wd], opts) for wd in low]
+    for name, syss, o in runs:
+        for S in syss:
+            S.row_lanes = S.col_lanes = 0
+        oo = dataclasses.replace(o, max_iter=cap, tol=tol, check_every=200, zero_start=True)
+        slv = native.Solver(syss, oo)
+        imgs = [S.new_image() for S in syss]
+        hist = [torch.empty(cap + 1, dtype=torch.float64, device=dev) for _ in syss]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        st, it = slv.solve(imgs, hist)
+        e1.record()
+        torch.cuda.synchronize()
+        it = np.array(it)
+        reached = it < cap
+        res[name] = {"median_iters": float(np.median(it)), "max_iters": int(it.max()),
+                     "reached": int(reached.sum()), "all_reached": bool(reached.all()),
+                     "seconds": e0.elapsed_time(e1) * 1e-3}
+        if not reached.all():
+            res[name]["not_reached"] = f"{int((~reached).sum())} slice(s) above {tol:g} after {cap} iterations"
+        ks[name] = it
+        log(f"time to {tol:g}: {name} {res[name]}")
+        del slv, imgs, hist
+    if "unsplit_f32" in ks:
+        d = np.abs(ks["split_f32"] - ks["unsplit_f32"])
+        res["split_vs_unsplit"] = {"same_kstar": int((d == 0).sum()), "max_kstar_difference": int(d.max()),
+                                   "time_ratio": res["unsplit_f32"]["seconds"] / res["split_f32"]["seconds"]}
+    return res
+
+
+def learned_report(dev, train_items=4096, test_items=64, epochs=2):
+    """Plain vs learned-initialised split SART on the 256 x 256 workload:
+    training pairs (5 -> 200 split-SART iterations) generated and the network
+    trained inside this run, then iterations and seconds to 1e-2 and 1e-3 on
+    held-out phantoms from f0 = 0 and from the judged learned start."""
+    from paper_1902_10559_amd import learned, unet
+    t0 = time.perf_counter()
+    sc = learned.scan(dev)
+    X, Y = learned.make_pairs(sc, list(range(train_items)))
+    t_data = time.perf_counter() - t0
+    net = unet.UNet(sc.geom.nz, sc.geom.nx, seed=0)
+    t1 = time.perf_counter()
+    losses = learned.train(net, X, Y, epochs=epochs)
+    t_train = time.perf_counter() - t1
+    del X, Y
+    rep = learned.evaluate(net, sc, list(range(10 ** 6, 10 ** 6 + test_items)))
+    return {"workload": "256x256 slices, K=16 sources over +-20 deg, 512 bins, noise-free",
+            "train_items": train_items, "epochs": epochs, "params": net.nparams,
+            "data_seconds": t_data, "train_seconds": t_train, "final_loss": losses[-1], **rep}
 
 
 def time_to_tol(slv, img, dev, tol=1e-3, cap=20000):

@@ -245,6 +245,19 @@ ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* workspace,
                        size_t workspace_bytes, int64_t* nnz_half,
                        void* stream);
 
+/* ss_fold_size for `count` matrices at once: every check pass is one
+ * launch over the line pairs of all matrices (the lane groups of the fold's
+ * counting pass, one partial record per block, no atomics), then one record
+ * per matrix.  A[k]: host array of device matrix descriptors; p: host array
+ * of device right-hand sides (or NULL; an entry may be NULL); nnz_half:
+ * host, count entries.  Returns the first failing matrix's error (its index
+ * in the message), and then writes nothing to nnz_half.  `workspace`: device
+ * scratch of ss_fold_batch_workspace_bytes(A, count) bytes.  SYNCHRONISES
+ * the stream once. */
+ss_status ss_fold_size_batch(const ss_matrix_dev* A, const float* const* p, int32_t count,
+                             void* workspace, size_t workspace_bytes, int64_t* nnz_half,
+                             void* stream);
+
 /* The fold of Section 2: fills `out` (nvals = 2, m = M/2, n = N/2, nnz =
  * *nnz_half from ss_fold_size, wdtype chosen by the caller; every array
  * allocated by the caller with the sizes listed at ss_system).  Values are
@@ -339,6 +352,33 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *   persistent   1: size the grid to the resident capacity and let each block
  *                loop over tiles (prefetching the next one); 0: one block
  *                per tile
+ *   staged       bit 0: band-staged forward projection.  The columns are
+ *                cut into bands of band_width consecutive indices; a copy of
+ *                the row streams is laid out band by band (each row's
+ *                entries in a band form a segment; 16-bit column indices
+ *                within the band), made in the workspace on every solve.
+ *                A block loads one band of the image into shared memory
+ *                and sums many segments from there; a second kernel adds
+ *                each row's segment sums in band order and forms the
+ *                residual.  Bit 1: tile-staged back projection.  Columns
+ *                are taken in tiles of tile_cols; per tile the distinct rows
+ *                its entries touch are found once per solve and each entry's
+ *                row is rewritten as its rank among them (16 bits); the
+ *                block copies those rows of z into shared memory and sums
+ *                from there (a tile touching more than 4096 rows, or rows in
+ *                more than 128 runs, keeps global gathers).  Needs lines in
+ *                ascending order (row_lanes / col_lanes 0), 16-byte aligned
+ *                images, nnz < 2^31, and for bit 1 m <= 2^17; when set,
+ *                rows_per_wave and cols_per_wave count segments and columns
+ *                per wavefront of an 8-wavefront block, and `chunked` and
+ *                `persistent` do not apply to the staged kernels.  The sums
+ *                run in another order than the unstaged kernels' (equal to
+ *                FP32 rounding), always the same one.
+ *   band_width   voxels per forward band: a power of two from 1024 to 16384
+ *                with band_width * nvals * 4 <= 65536 bytes (0 = 4096)
+ *   tile_cols    columns per back-projection tile: a power of two from 64 to
+ *                8192 (0 = 1024)
+ *   tile_segments  segments per forward work tile, 64 .. 65536 (0 = 1024)
  * rel_res(f^k) = ||p - A f^k|| / ||p||, from the halves as
  *   sqrt((||r1||^2 + ||r2||^2) / (||p1||^2 + ||p2||^2)), FP64. */
 typedef struct {
@@ -355,6 +395,10 @@ typedef struct {
   int32_t persistent;
   int32_t chunked;
   int32_t nonneg;
+  int32_t staged;
+  int32_t band_width;
+  int32_t tile_cols;
+  int32_t tile_segments;
 } ss_sart_opts;
 
 /* Workspace bytes for solving `nsys` systems together with these options
@@ -388,6 +432,27 @@ ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys,
                                int32_t reps, double* fp_ms, double* bp_ms,
                                void* workspace, size_t workspace_bytes,
                                void* stream);
+
+/* As ss_sart_time_kernels, per launch of an iteration: ms[0] the forward
+ * projection kernel (with staged bit 0: the band kernel), ms[1] the residual
+ * kernel of the band-staged form (0 otherwise), ms[2] the back projection;
+ * mean milliseconds over `reps` iterations, each launch stamped by its own
+ * dispatch.  ms: host, 3 doubles.  The images f are used as scratch.
+ * Synchronises. */
+ss_status ss_sart_time_phases(const ss_system* sys, int32_t nsys, float* const* f,
+                              const ss_sart_opts* opts, int32_t reps, double* ms,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* The sizes of the staged forms that a solve with these options builds
+ * (this call builds them in the workspace, as a solve does; the images f are
+ * used as scratch): info[0] forward segments over all systems (a row's
+ * entries in one band), info[1] forward work tiles, info[2] back-projection
+ * tiles, info[3] of those staged in shared memory, info[4] rows of z those
+ * stage in all.  Zero for a form not selected.  opts->staged must be
+ * nonzero.  info: host, 5 int64.  Synchronises. */
+ss_status ss_sart_staged_info(const ss_system* sys, int32_t nsys, float* const* f,
+                              const ss_sart_opts* opts, int64_t* info, void* workspace,
+                              size_t workspace_bytes, void* stream);
 
 /* Picks rows_per_wave, cols_per_wave, unroll, persistent, chunked and xcd_remap by
  * timing every candidate (ss_sart_time_kernels) and writes them into
@@ -542,10 +607,14 @@ ss_status ss_nn_conv3x3(const void* x, int32_t N, int32_t H, int32_t W, int32_t 
                         const float* bias, int32_t O, int32_t relu, void* y, int32_t y_f32, void* stream);
 
 /* gw [O][3][3][C] += sum over pixels of gy (x) shifted x; gb [O] += sum of gy
- * (gb may be NULL).  x (N,H,W,C), gy (N,H,W,O), both BF16; FP32 atomics, so
- * the summation order is not fixed. */
+ * (gb may be NULL).  x (N,H,W,C), gy (N,H,W,O), both BF16.  Partial sums per
+ * group of image rows (per block of pixels for gb) go to `workspace` (device,
+ * at least ss_nn_wgrad_workspace_bytes) and are added in a fixed order, so
+ * the gradients are bitwise the same on every run. */
+ss_status ss_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t C, int32_t O, size_t* bytes);
 ss_status ss_nn_conv3x3_wgrad(const void* x, const void* gy, int32_t N, int32_t H, int32_t W, int32_t C,
-                              int32_t O, float* gw, float* gb, void* stream);
+                              int32_t O, float* gw, float* gb, void* workspace, size_t workspace_bytes,
+                              void* stream);
 
 /* out = BF16(g * [y > 0]) for the ReLU output y (BF16), or BF16(g) if y is
  * NULL. */
@@ -566,10 +635,14 @@ ss_status ss_nn_to_slice(const void* x, int32_t N, int32_t Hy, int32_t Wy, int32
 ss_status ss_nn_from_slice(const float* gy, int32_t N, int32_t Hx, int32_t Wx, int32_t C, int32_t up,
                            int32_t Ctot, int32_t coff, float* gx, int32_t accumulate, void* stream);
 
-/* out = x + r; with target: g = 2 (out - target) / n (g may be NULL) and
- * *loss += mean squared error (FP64). */
+/* out = x + r; with target: g = 2 (out - target) / n (g may be NULL) and,
+ * with loss, *loss += mean squared error (FP64; per-block partials in
+ * `workspace`, at least ss_nn_mse_workspace_bytes(n), added in block order,
+ * so the loss is the same on every run; workspace may be NULL without
+ * loss). */
+ss_status ss_nn_mse_workspace_bytes(int64_t n, size_t* bytes);
 ss_status ss_nn_residual_mse(const float* r, const float* x, const float* target, int64_t n, float* out,
-                             float* g, double* loss, void* stream);
+                             float* g, double* loss, void* workspace, size_t workspace_bytes, void* stream);
 
 ss_status ss_nn_to_bf16(const float* x, int64_t n, void* y, void* stream);
 

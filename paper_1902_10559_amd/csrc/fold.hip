@@ -384,81 +384,6 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   return v;
 }
 
-__global__ void k_zero_check(FoldCheck* c) {
-  if (threadIdx.x == 0) {
-    c->flags = 0;
-    c->sum_csr = c->sum_csc = 0;
-    c->cnt_csr = c->cnt_csc = 0;
-  }
-}
-
-// One wavefront per pair of mirrored lines (rows i and M-1-i of the CSR, or
-// columns j and N-1-j of the CSC): checks eq. (2), order, range and
-// finiteness, accumulates the entry checksum and the union size.
-template <bool COLS>
-__global__ __launch_bounds__(kWave* kFoldWaves) void k_check_pairs(ss_matrix_dev A, const float* p,
-                                                                   FoldCheck* chk) {
-  SS_STAGE_BUF(sb);
-  const int64_t lines = COLS ? A.N : A.M;
-  const int64_t other = COLS ? A.M : A.N;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFoldWaves + wave_id();
-  if (t >= lines / 2) return;
-  const int64_t* ptr = COLS ? A.col_ptr : A.row_ptr;
-  const int32_t* idx = COLS ? A.row_idx : A.col_idx;
-  const float* val = COLS ? A.val_t : A.val;
-  const int lane = lane_id();
-  uint32_t flags = 0;
-  const int64_t t2 = lines - 1 - t;
-  const int64_t as = ptr[t], ae = ptr[t + 1], bs = ptr[t2], be = ptr[t2 + 1];
-  if (t == 0 && lane == 0 && (ptr[0] != 0 || ptr[lines] != A.nnz)) flags |= kFlagShape;
-  const bool ranges_ok = as >= 0 && as <= ae && ae <= A.nnz && bs >= 0 && bs <= be && be <= A.nnz;
-  unsigned long long h = 0;
-  if (!ranges_ok) {
-    flags |= kFlagShape;
-  } else {
-    if (ae - as != be - bs) flags |= kFlagAsym;
-    const int64_t la = ae - as;
-    for (int64_t k = lane; k < la; k += kWave) {
-      const int32_t ca = idx[as + k];
-      const float va = val[as + k];
-      if (ca < 0 || ca >= other) flags |= kFlagShape;
-      if (k + 1 < la && idx[as + k + 1] <= ca) flags |= kFlagShape;
-      if (!isfinite(va)) flags |= kFlagNonfinite;
-      h += COLS ? entry_hash(ca, t, va) : entry_hash(t, ca, va);
-      if (ae - as == be - bs) {
-        const int32_t cb = idx[bs + la - 1 - k];
-        const float vb = val[bs + la - 1 - k];
-        if (cb != other - 1 - ca || __float_as_uint(vb) != __float_as_uint(va)) flags |= kFlagAsym;
-      }
-    }
-    for (int64_t k = lane; k < be - bs; k += kWave) {
-      const int32_t cb = idx[bs + k];
-      const float vb = val[bs + k];
-      if (cb < 0 || cb >= other) flags |= kFlagShape;
-      if (k + 1 < be - bs && idx[bs + k + 1] <= cb) flags |= kFlagShape;
-      if (!isfinite(vb)) flags |= kFlagNonfinite;
-      h += COLS ? entry_hash(cb, t2, vb) : entry_hash(t2, cb, vb);
-    }
-  }
-  if (!COLS && p != nullptr && lane == 0 && (!isfinite(p[t]) || !isfinite(p[t2]))) flags |= kFlagNonfinite;
-  // union size of the output line, only once the lines are known to be sane
-  const bool sane = __ballot(flags & kFlagShape) == 0;
-  int64_t cnt = 0;
-  if (sane) {
-    double unused = 0.0;
-    cnt = fold_line<COLS, false, SS_F32>(A, t, 0, nullptr, nullptr, unused, sb, 0, 0);
-  }
-  h = wave_sum_u64(h);
-  unsigned f = flags;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, kWave);
-  if (lane == 0) {
-    if (f) atomicOr(&chk->flags, f);
-    atomicAdd(COLS ? &chk->sum_csc : &chk->sum_csr, h);
-    atomicAdd(COLS ? &chk->cnt_csc : &chk->cnt_csr, static_cast<unsigned long long>(cnt));
-  }
-}
-
 // One matrix of a fold and where its lines and scan tiles sit in the grids
 // of the launches (a batch of matrices folds in one launch per phase).
 struct FoldJob {
@@ -518,6 +443,154 @@ __global__ __launch_bounds__(kWave* kFoldWaves) void k_fold_count(JobArg J) {
   if (group_lane<G>() == 0) {
     ptr[t + 1] = cnt;
     if (t == 0) ptr[0] = 0;
+  }
+}
+
+// Per block of a check pass: the OR of its flags, the sum of its entry
+// hashes and (rows) the sum of its union sizes.
+struct CheckPart {
+  uint32_t flags;
+  uint32_t pad;
+  unsigned long long hash;
+  unsigned long long cnt;
+};
+
+// Checks of eq. (2) and of the arrays, one pair of mirrored lines (rows i
+// and M-1-i, or columns j and N-1-j) per group of G lanes, with the lane
+// groups and grids of the fold's counting pass: eq. (2) bitwise (equal
+// lengths, mirrored indices, equal values), order, range and finiteness of
+// both lines, an order-free checksum of the entries (the CSR and CSC copies
+// must give the same), and for rows the size of the folded line (the same
+// staged merge as the counting pass).  Each block writes one CheckPart; no
+// atomics.
+template <bool COLS, bool B, int G>
+__global__ __launch_bounds__(kWave* kFoldWaves) void k_check_lines(JobArg J, CheckPart* parts) {
+  SS_STAGE_BUF(sb);
+  __shared__ CheckPart wp[kFoldWaves];
+  int64_t lb;
+  const FoldJob& jb = find_job<B, COLS, false>(J, blockIdx.x, &lb);
+  const ss_matrix_dev& A = jb.A;
+  const float* p = jb.p;
+  const int64_t lines = COLS ? A.N : A.M;
+  const int64_t other = COLS ? A.M : A.N;
+  const int grp = lane_id() / G;
+  const int lane = group_lane<G>();
+  const int64_t t = (lb * kFoldWaves + wave_id()) * (kWave / G) + grp;
+  const bool active = t < lines / 2;
+  uint32_t flags = 0;
+  unsigned long long h = 0;
+  if (active) {
+    const int64_t* ptr = COLS ? A.col_ptr : A.row_ptr;
+    const int32_t* idx = COLS ? A.row_idx : A.col_idx;
+    const float* val = COLS ? A.val_t : A.val;
+    const int64_t t2 = lines - 1 - t;
+    const int64_t as = gl(ptr)[t], ae = gl(ptr)[t + 1], bs = gl(ptr)[t2], be = gl(ptr)[t2 + 1];
+    if (t == 0 && lane == 0 && (gl(ptr)[0] != 0 || gl(ptr)[lines] != A.nnz)) flags |= kFlagShape;
+    const bool ranges_ok = as >= 0 && as <= ae && ae <= A.nnz && bs >= 0 && bs <= be && be <= A.nnz;
+    if (!ranges_ok) {
+      flags |= kFlagShape;
+    } else {
+      const int64_t la = ae - as, lbn = be - bs;
+      if (la != lbn) flags |= kFlagAsym;
+      for (int64_t k = lane; k < la; k += G) {
+        const int32_t ca = gl(idx)[as + k];
+        const float va = gl(val)[as + k];
+        if (ca < 0 || ca >= other) flags |= kFlagShape;
+        if (k + 1 < la && gl(idx)[as + k + 1] <= ca) flags |= kFlagShape;
+        if (!isfinite(va)) flags |= kFlagNonfinite;
+        h += COLS ? entry_hash(ca, t, va) : entry_hash(t, ca, va);
+        if (la == lbn) {
+          const int32_t cb = gl(idx)[bs + la - 1 - k];
+          const float vb = gl(val)[bs + la - 1 - k];
+          if (cb != other - 1 - ca || __float_as_uint(vb) != __float_as_uint(va)) flags |= kFlagAsym;
+        }
+      }
+      for (int64_t k = lane; k < lbn; k += G) {
+        const int32_t cb = gl(idx)[bs + k];
+        const float vb = gl(val)[bs + k];
+        if (cb < 0 || cb >= other) flags |= kFlagShape;
+        if (k + 1 < lbn && gl(idx)[bs + k + 1] <= cb) flags |= kFlagShape;
+        if (!isfinite(vb)) flags |= kFlagNonfinite;
+        h += COLS ? entry_hash(cb, t2, vb) : entry_hash(t2, cb, vb);
+      }
+    }
+    if (!COLS && p != nullptr && lane == 0 && (!isfinite(gl(p)[t]) || !isfinite(gl(p)[t2]))) flags |= kFlagNonfinite;
+  }
+  // the folded row's size, once the group's two rows are known to be sane
+  unsigned long long cnt = 0;
+  if constexpr (!COLS) {
+    const bool sane = group_ballot<G>(active && (flags & kFlagShape) != 0) == 0;
+    if (active && sane) {
+      double unused = 0.0;
+      const int64_t c = fold_line<false, false, SS_F32, G>(A, t, 0, nullptr, nullptr, unused,
+                                                           group_buf<false, G>(sb, grp), 0, 0);
+      if (lane == 0) cnt = static_cast<unsigned long long>(c);
+    }
+  }
+  h = wave_sum_u64(h);
+  cnt = wave_sum_u64(cnt);
+  unsigned f = flags;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, kWave);
+  if (lane_id() == 0) wp[wave_id()] = CheckPart{f, 0u, h, cnt};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    CheckPart r{0u, 0u, 0ull, 0ull};
+    for (int w = 0; w < kFoldWaves; ++w) {
+      r.flags |= wp[w].flags;
+      r.hash += wp[w].hash;
+      r.cnt += wp[w].cnt;
+    }
+    parts[blockIdx.x] = r;
+  }
+}
+
+// Blocks of the counting, filling and check passes over `lines` line
+// pairs or lines (kWave / G lines per wavefront).
+__host__ __device__ inline int64_t line_blocks(int64_t lines, int G) {
+  const int64_t per = kFoldWaves * (kWave / G);
+  return (lines + per - 1) / per;
+}
+
+// One block per matrix: the check parts of both passes into its FoldCheck
+// (integer sums and ORs: the order does not matter).  The size of the fold
+// comes from the rows; the CSC copy is tied to the CSR by the checksums.
+constexpr int kCheckFinThreads = 256;
+template <bool B>
+__global__ __launch_bounds__(kCheckFinThreads) void k_check_finish(JobArg J, const CheckPart* rparts,
+                                                                   const CheckPart* cparts, int grow, int gcol,
+                                                                   FoldCheck* out) {
+  __shared__ uint32_t fl[kCheckFinThreads];
+  __shared__ unsigned long long hr[kCheckFinThreads], hc[kCheckFinThreads], cr[kCheckFinThreads];
+  const FoldJob& jb = B ? J.table[blockIdx.x] : J.one;
+  const int64_t r0 = B ? jb.rblk0 : 0, c0 = B ? jb.cblk0 : 0;
+  const int64_t rn = line_blocks(jb.A.M / 2, grow), cn = line_blocks(jb.A.N / 2, gcol);
+  uint32_t f = 0;
+  unsigned long long a = 0, c = 0, n = 0;
+  for (int64_t b = threadIdx.x; b < rn; b += kCheckFinThreads) {
+    f |= rparts[r0 + b].flags;
+    a += rparts[r0 + b].hash;
+    n += rparts[r0 + b].cnt;
+  }
+  for (int64_t b = threadIdx.x; b < cn; b += kCheckFinThreads) {
+    f |= cparts[c0 + b].flags;
+    c += cparts[c0 + b].hash;
+  }
+  fl[threadIdx.x] = f;
+  hr[threadIdx.x] = a;
+  hc[threadIdx.x] = c;
+  cr[threadIdx.x] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    FoldCheck r{};
+    for (int i = 0; i < kCheckFinThreads; ++i) {
+      r.flags |= fl[i];
+      r.sum_csr += hr[i];
+      r.sum_csc += hc[i];
+      r.cnt_csr += cr[i];
+    }
+    r.cnt_csc = r.cnt_csr;
+    out[blockIdx.x] = r;
   }
 }
 
@@ -683,10 +756,7 @@ inline unsigned blocks_for(int64_t lines) {
 }
 
 // Blocks of the counting and filling passes (kWave / G lines per wavefront).
-inline unsigned line_blocks_for(int64_t lines, int G) {
-  const int64_t per = kFoldWaves * (kWave / G);
-  return static_cast<unsigned>((lines + per - 1) / per);
-}
+inline unsigned line_blocks_for(int64_t lines, int G) { return static_cast<unsigned>(line_blocks(lines, G)); }
 
 // Lanes per line for one fold call, from the mean source-line lengths of all
 // its matrices: a group is used where a mean row list fills half of its
@@ -812,6 +882,38 @@ FoldGrid layout_jobs(const ss_matrix_dev* A, const float* const* p, const ss_sys
 
 size_t batch_table_bytes(int32_t count) { return (sizeof(FoldJob) * static_cast<size_t>(count) + 255) & ~size_t{255}; }
 
+// The checks of eq. (2) and of the arrays for every job: both passes over
+// the line pairs with the fold's lane groups, then one block per job.
+template <bool B>
+void run_check(const JobArg& J, const FoldGrid& g, CheckPart* rparts, CheckPart* cparts, FoldCheck* out,
+               int32_t count, hipStream_t st) {
+  const dim3 lb(kWave * kFoldWaves);
+  const auto R = static_cast<unsigned>(g.rblk), Cb = static_cast<unsigned>(g.cblk);
+  if (g.grow == 32) k_check_lines<false, B, 32><<<R, lb, 0, st>>>(J, rparts);
+  else k_check_lines<false, B, 64><<<R, lb, 0, st>>>(J, rparts);
+  if (g.gcol == 8) k_check_lines<true, B, 8><<<Cb, lb, 0, st>>>(J, cparts);
+  else if (g.gcol == 16) k_check_lines<true, B, 16><<<Cb, lb, 0, st>>>(J, cparts);
+  else k_check_lines<true, B, 64><<<Cb, lb, 0, st>>>(J, cparts);
+  k_check_finish<B><<<static_cast<unsigned>(count), kCheckFinThreads, 0, st>>>(J, rparts, cparts, g.grow, g.gcol, out);
+}
+
+// Turns one matrix's check record into a status and the fold's size.
+ss_status check_verdict(const FoldCheck& h, const char* fn, int32_t k, int64_t* nnz_half) {
+  if (h.flags & kFlagShape)
+    return fail(SS_E_SHAPE, "%s: matrix %d: CSR/CSC offsets, order or index range invalid", fn, k);
+  if (h.flags & kFlagNonfinite) return fail(SS_E_NONFINITE, "%s: matrix %d: NaN or Inf in A or p", fn, k);
+  if (h.flags & kFlagAsym)
+    return fail(SS_E_ASYM, "%s: matrix %d: A violates eq. (2), w[i,j] != w[M-1-i,N-1-j]", fn, k);
+  if (h.sum_csr != h.sum_csc) return fail(SS_E_SHAPE, "%s: matrix %d: CSR and CSC hold different entries", fn, k);
+  *nnz_half = static_cast<int64_t>(h.cnt_csr);
+  return SS_OK;
+}
+
+// Check parts of the worst-case grids (a wavefront per line pair).
+inline size_t check_parts_bytes(int64_t M, int64_t N) {
+  return sizeof(CheckPart) * static_cast<size_t>(line_blocks(M / 2, kWave) + line_blocks(N / 2, kWave));
+}
+
 // ---------------------------------------------------- allocation-free fold
 // ss_fold_noalloc keeps the scan's per-tile sums (its only scratch) in this
 // file-scope array instead of a caller workspace.  Each device holds its own
@@ -850,7 +952,7 @@ extern "C" ss_status ss_fold_workspace_bytes(int64_t M, int64_t N, size_t* bytes
   clear_error();
   if (!bytes || M <= 0 || N <= 0) return fail(SS_E_ARG, "ss_fold_workspace_bytes: bad argument");
   const int64_t tiles = scan_tiles(std::max(M, N) / 2 + 1) + 1;
-  *bytes = std::max<size_t>(256, sizeof(FoldCheck)) + 256 + sizeof(int64_t) * static_cast<size_t>(tiles);
+  *bytes = 512 + std::max(sizeof(int64_t) * static_cast<size_t>(tiles), check_parts_bytes(M, N));
   return SS_OK;
 }
 
@@ -859,27 +961,25 @@ extern "C" ss_status ss_fold_size(const ss_matrix_dev* A, const float* p, void* 
   clear_error();
   if (ss_status s = check_dev_matrix(A, "ss_fold_size")) return s;
   if (!nnz_half || !workspace) return fail(SS_E_ARG, "ss_fold_size: NULL argument");
-  if (workspace_bytes < sizeof(FoldCheck)) return fail(SS_E_WORKSPACE, "ss_fold_size: workspace too small");
   if (A->M % 2 || A->N % 2)
     return fail(SS_E_ODD, "ss_fold_size: M=%lld and N=%lld must be even", (long long)A->M, (long long)A->N);
+  size_t need = 0;
+  ss_fold_workspace_bytes(A->M, A->N, &need);
+  if (workspace_bytes < need) return fail(SS_E_WORKSPACE, "ss_fold_size: workspace needs %zu bytes", need);
   hipStream_t st = static_cast<hipStream_t>(stream);
   FoldCheck* chk = static_cast<FoldCheck*>(workspace);
-  k_zero_check<<<1, 64, 0, st>>>(chk);
-  k_check_pairs<false><<<blocks_for(A->M / 2), kWave * kFoldWaves, 0, st>>>(*A, p, chk);
-  k_check_pairs<true><<<blocks_for(A->N / 2), kWave * kFoldWaves, 0, st>>>(*A, p, chk);
+  CheckPart* rparts = reinterpret_cast<CheckPart*>(static_cast<char*>(workspace) + 512);
+  JobArg J{};
+  J.count = 1;
+  J.one.A = *A;
+  J.one.p = p;
+  const FoldGrid g = layout_jobs(A, nullptr, nullptr, 1, nullptr);
+  run_check<false>(J, g, rparts, rparts + g.rblk, chk, 1, st);
   SS_HIP_TRY(hipGetLastError());
   FoldCheck h{};
   SS_HIP_TRY(hipMemcpyAsync(&h, chk, sizeof h, hipMemcpyDeviceToHost, st));
   SS_HIP_TRY(hipStreamSynchronize(st));
-  if (h.flags & kFlagShape)
-    return fail(SS_E_SHAPE, "ss_fold_size: CSR/CSC offsets, order or index range invalid");
-  if (h.flags & kFlagNonfinite) return fail(SS_E_NONFINITE, "ss_fold_size: NaN or Inf in A or p");
-  if (h.flags & kFlagAsym)
-    return fail(SS_E_ASYM, "ss_fold_size: A violates eq. (2), w[i,j] != w[M-1-i,N-1-j]");
-  if (h.sum_csr != h.sum_csc) return fail(SS_E_SHAPE, "ss_fold_size: CSR and CSC hold different entries");
-  if (h.cnt_csr != h.cnt_csc) return fail(SS_E_SHAPE, "ss_fold_size: row and column folds disagree in size");
-  *nnz_half = static_cast<int64_t>(h.cnt_csr);
-  return SS_OK;
+  return check_verdict(h, "ss_fold_size", 0, nnz_half);
 }
 
 extern "C" ss_status ss_fold(const ss_matrix_dev* A, const float* p, ss_system* out, void* workspace,
@@ -927,7 +1027,54 @@ extern "C" ss_status ss_fold_batch_workspace_bytes(const ss_matrix_dev* A, int32
   for (int32_t k = 0; k < count; ++k)
     if (A[k].M <= 0 || A[k].N <= 0) return fail(SS_E_ARG, "ss_fold_batch_workspace_bytes: bad matrix %d", k);
   const FoldGrid g = layout_jobs(A, nullptr, nullptr, count, nullptr);
-  *bytes = batch_table_bytes(count) + sizeof(int64_t) * static_cast<size_t>(std::max(g.rtile, g.ctile));
+  const size_t scratch = std::max(sizeof(int64_t) * static_cast<size_t>(std::max(g.rtile, g.ctile)),
+                                  sizeof(CheckPart) * static_cast<size_t>(g.rblk + g.cblk));
+  *bytes = batch_table_bytes(count) + ((scratch + 255) & ~size_t{255}) + sizeof(FoldCheck) * static_cast<size_t>(count);
+  return SS_OK;
+}
+
+extern "C" ss_status ss_fold_size_batch(const ss_matrix_dev* A, const float* const* p, int32_t count,
+                                        void* workspace, size_t workspace_bytes, int64_t* nnz_half,
+                                        void* stream) {
+  clear_error();
+  if (!A || count <= 0 || !nnz_half || !workspace) return fail(SS_E_ARG, "ss_fold_size_batch: bad argument");
+  for (int32_t k = 0; k < count; ++k) {
+    if (ss_status s = check_dev_matrix(&A[k], "ss_fold_size_batch")) return s;
+    if (A[k].M % 2 || A[k].N % 2)
+      return fail(SS_E_ODD, "ss_fold_size_batch: matrix %d: M=%lld and N=%lld must be even", k, (long long)A[k].M,
+                  (long long)A[k].N);
+  }
+  size_t need = 0;
+  if (ss_status s = ss_fold_batch_workspace_bytes(A, count, &need)) return s;
+  if (workspace_bytes < need) return fail(SS_E_WORKSPACE, "ss_fold_size_batch: workspace needs %zu bytes", need);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<FoldJob> jobs;
+  const FoldGrid g = layout_jobs(A, p, nullptr, count, &jobs);
+  char* ws = static_cast<char*>(workspace);
+  FoldJob* table = reinterpret_cast<FoldJob*>(ws);
+  CheckPart* rparts = reinterpret_cast<CheckPart*>(ws + batch_table_bytes(count));
+  const size_t scratch = std::max(sizeof(int64_t) * static_cast<size_t>(std::max(g.rtile, g.ctile)),
+                                  sizeof(CheckPart) * static_cast<size_t>(g.rblk + g.cblk));
+  FoldCheck* chk = reinterpret_cast<FoldCheck*>(ws + batch_table_bytes(count) + ((scratch + 255) & ~size_t{255}));
+  for (int32_t k0 = 0; k0 < count; k0 += kJobChunk) {
+    JobChunk ch{};
+    ch.first = k0;
+    ch.count = std::min(kJobChunk, count - k0);
+    for (int i = 0; i < ch.count; ++i) ch.j[i] = jobs[k0 + i];
+    k_put_jobs<<<1, kWave, 0, st>>>(ch, table);
+  }
+  JobArg J{};
+  J.table = table;
+  J.count = count;
+  run_check<true>(J, g, rparts, rparts + g.rblk, chk, count, st);
+  SS_HIP_TRY(hipGetLastError());
+  std::vector<FoldCheck> h(static_cast<size_t>(count));
+  SS_HIP_TRY(hipMemcpyAsync(h.data(), chk, sizeof(FoldCheck) * h.size(), hipMemcpyDeviceToHost, st));
+  SS_HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int64_t> sizes(static_cast<size_t>(count));
+  for (int32_t k = 0; k < count; ++k)
+    if (ss_status s = check_verdict(h[k], "ss_fold_size_batch", k, &sizes[k])) return s;
+  for (int32_t k = 0; k < count; ++k) nnz_half[k] = sizes[k];
   return SS_OK;
 }
 

@@ -106,15 +106,17 @@ __global__ __launch_bounds__(kWave* kConvWaves) void k_conv3x3(const uint16_t* _
   }
 }
 
-// gw[o][tap][c] += sum_p gy[p][o] x[p + shift(tap)][c] (gw laid out like
-// the FP32 master weights, [O][9][C]).  GEMM M = o, N = (tap, c) flattened
-// as tap * Cp + c, K = pixels.  A wave owns one 16 x 16 tile and a range of
-// image rows; its tile is added to gw with atomics.
+// Partial weight gradients: part[z][o][tap][c] = sum over the pixels of row
+// group z of gy[p][o] x[p + shift(tap)][c] (laid out like the FP32 master
+// weights, [O][9][C], per group).  GEMM M = o, N = (tap, c) flattened as
+// tap * Cp + c, K = pixels.  A wave owns one 16 x 16 tile and one group of
+// kWgradRows image rows; k_wgrad_reduce then adds the groups in index
+// order, so the gradient is the same on every run.
 constexpr int kWgradRows = 8;
 __global__ __launch_bounds__(kWave* kConvWaves) void k_conv3x3_wgrad(const uint16_t* __restrict__ x,
                                                                       const uint16_t* __restrict__ gy, int NH,
                                                                       int H, int W, int C, int Cp, int O,
-                                                                      float* __restrict__ gw) {
+                                                                      float* __restrict__ part) {
   const int lane = lane_id(), g = lane / 16, m = lane % 16;
   const int o0 = blockIdx.x * 16;
   const int n0 = blockIdx.y * 16;
@@ -146,22 +148,34 @@ __global__ __launch_bounds__(kWave* kConvWaves) void k_conv3x3_wgrad(const uint1
     }
   }
   if (bvalid) {
+    float* out = part + static_cast<int64_t>(row0 / kWgradRows) * O * 9 * C;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int oo = o0 + 4 * g + r;
-      if (oo < O) atomicAdd(gw + (static_cast<int64_t>(oo) * 9 + tap) * C + c, acc[r]);
+      if (oo < O) glw(out)[(static_cast<int64_t>(oo) * 9 + tap) * C + c] = acc[r];
     }
   }
 }
 
-// gb[o] += sum_p gy[p][o]
-__global__ void k_bias_grad(const uint16_t* __restrict__ gy, int64_t P, int O, float* __restrict__ gb) {
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 256;
-  const int64_t p1 = p0 + 256 < P ? p0 + 256 : P;
+// dst[e] += sum over groups z (in index order) of part[z][e], e < count.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int groups, int64_t count, float* __restrict__ dst) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  float s = 0.0f;
+  for (int z = 0; z < groups; ++z) s += gl(part)[static_cast<int64_t>(z) * count + e];
+  dst[e] += s;
+}
+
+// Partial bias gradients: part[blk][o] = sum over the block's 256 pixels of
+// gy[p][o] (in pixel order); k_wgrad_reduce adds the blocks in order.
+constexpr int kBiasPix = 256;
+__global__ void k_bias_grad(const uint16_t* __restrict__ gy, int64_t P, int O, float* __restrict__ part) {
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * kBiasPix;
+  const int64_t p1 = p0 + kBiasPix < P ? p0 + kBiasPix : P;
   for (int o = threadIdx.x; o < O; o += blockDim.x) {
     float s = 0.0f;
     for (int64_t p = p0; p < p1; ++p) s += bf2f(gl(gy)[p * O + o]);
-    atomicAdd(gb + o, s);
+    part[static_cast<int64_t>(blockIdx.x) * O + o] = s;
   }
 }
 
@@ -266,10 +280,12 @@ __global__ void k_from_slice(const float* __restrict__ gy, int64_t NHx, int Hx, 
   gx[t] = accumulate ? gx[t] + v : v;
 }
 
-// out = x + r; g = 2 (out - target) / count; loss += sum (out - target)^2 / count
+// out = x + r; g = 2 (out - target) / count; part[block] = the block's sum
+// of (out - target)^2 (FP64), which k_loss_reduce adds to the loss in block
+// order.
 __global__ void k_residual_mse(const float* __restrict__ r, const float* __restrict__ x,
                                const float* __restrict__ target, int64_t n, float* __restrict__ out,
-                               float* __restrict__ g, double* loss) {
+                               float* __restrict__ g, double* part) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   double e2 = 0.0;
   if (t < n) {
@@ -281,11 +297,22 @@ __global__ void k_residual_mse(const float* __restrict__ r, const float* __restr
       e2 = static_cast<double>(d) * d;
     }
   }
-  if (target && loss) {
+  if (target && part) {
     __shared__ double red[4];
     e2 = block_sum<4>(e2, red);
-    if (threadIdx.x == 0) atomicAdd(loss, e2 / static_cast<double>(n));
+    if (threadIdx.x == 0) part[blockIdx.x] = e2;
   }
+}
+
+// loss += (sum of the blocks' partials, in block order) / n: one block.
+__global__ void k_loss_reduce(const double* __restrict__ part, int64_t nblocks, int64_t n, double* loss) {
+  __shared__ double red[4];
+  double s = 0.0;
+  const int64_t per = (nblocks + 255) / 256;
+  const int64_t b0 = threadIdx.x * per, b1 = b0 + per < nblocks ? b0 + per : nblocks;
+  for (int64_t b = b0; b < b1; ++b) s += part[b];
+  s = block_sum<4>(s, red);
+  if (threadIdx.x == 0) *loss += s / static_cast<double>(n);
 }
 
 __global__ void k_to_bf16(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
@@ -363,19 +390,39 @@ extern "C" ss_status ss_nn_conv3x3(const void* x, int32_t N, int32_t H, int32_t 
   return SS_OK;
 }
 
-extern "C" ss_status ss_nn_conv3x3_wgrad(const void* x, const void* gy, int32_t N, int32_t H, int32_t W, int32_t C,
-                                         int32_t O, float* gw, float* gb, void* stream) {
+extern "C" ss_status ss_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t C, int32_t O,
+                                                 size_t* bytes) {
   clear_error();
-  SS_NN_CHECK(x && gy && gw && N > 0 && H > 0 && W > 0 && C > 0 && O > 0, "ss_nn_conv3x3_wgrad");
+  SS_NN_CHECK(bytes && N > 0 && H > 0 && W > 0 && C > 0 && O > 0, "ss_nn_wgrad_workspace_bytes");
+  const int64_t groups = (static_cast<int64_t>(N) * H + kWgradRows - 1) / kWgradRows;
+  const int64_t pblocks = (static_cast<int64_t>(N) * H * W + kBiasPix - 1) / kBiasPix;
+  *bytes = sizeof(float) * static_cast<size_t>(std::max(groups * O * 9 * C, pblocks * O));
+  return SS_OK;
+}
+
+extern "C" ss_status ss_nn_conv3x3_wgrad(const void* x, const void* gy, int32_t N, int32_t H, int32_t W, int32_t C,
+                                         int32_t O, float* gw, float* gb, void* workspace, size_t workspace_bytes,
+                                         void* stream) {
+  clear_error();
+  SS_NN_CHECK(x && gy && gw && workspace && N > 0 && H > 0 && W > 0 && C > 0 && O > 0, "ss_nn_conv3x3_wgrad");
+  size_t need = 0;
+  ss_nn_wgrad_workspace_bytes(N, H, W, C, O, &need);
+  if (workspace_bytes < need) return fail(SS_E_WORKSPACE, "ss_nn_conv3x3_wgrad: workspace needs %zu bytes", need);
   const int Cp = (C + 7) / 8 * 8;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int NH = N * H;
+  float* part = static_cast<float*>(workspace);
+  const int groups = (NH + kWgradRows - 1) / kWgradRows;
   const dim3 grid((O + 15) / 16, (9 * Cp + 15) / 16, (NH + kWgradRows * kConvWaves - 1) / (kWgradRows * kConvWaves));
   k_conv3x3_wgrad<<<grid, kWave * kConvWaves, 0, st>>>(static_cast<const uint16_t*>(x),
-                                                       static_cast<const uint16_t*>(gy), NH, H, W, C, Cp, O, gw);
+                                                       static_cast<const uint16_t*>(gy), NH, H, W, C, Cp, O, part);
+  const int64_t nw = static_cast<int64_t>(O) * 9 * C;
+  k_wgrad_reduce<<<blocks256(nw), 256, 0, st>>>(part, groups, nw, gw);
   if (gb) {
     const int64_t P = static_cast<int64_t>(NH) * W;
-    k_bias_grad<<<static_cast<unsigned>((P + 255) / 256), 128, 0, st>>>(static_cast<const uint16_t*>(gy), P, O, gb);
+    const unsigned pb = static_cast<unsigned>((P + kBiasPix - 1) / kBiasPix);
+    k_bias_grad<<<pb, 128, 0, st>>>(static_cast<const uint16_t*>(gy), P, O, part);
+    k_wgrad_reduce<<<blocks256(O), 256, 0, st>>>(part, static_cast<int>(pb), O, gb);
   }
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;
@@ -445,11 +492,25 @@ extern "C" ss_status ss_nn_from_slice(const float* gy, int32_t N, int32_t Hx, in
   return SS_OK;
 }
 
+extern "C" ss_status ss_nn_mse_workspace_bytes(int64_t n, size_t* bytes) {
+  clear_error();
+  SS_NN_CHECK(bytes && n > 0, "ss_nn_mse_workspace_bytes");
+  *bytes = sizeof(double) * static_cast<size_t>(blocks256(n));
+  return SS_OK;
+}
+
 extern "C" ss_status ss_nn_residual_mse(const float* r, const float* x, const float* target, int64_t n, float* out,
-                                        float* g, double* loss, void* stream) {
+                                        float* g, double* loss, void* workspace, size_t workspace_bytes,
+                                        void* stream) {
   clear_error();
   SS_NN_CHECK(r && x && out && n > 0, "ss_nn_residual_mse");
-  k_residual_mse<<<blocks256(n), 256, 0, static_cast<hipStream_t>(stream)>>>(r, x, target, n, out, g, loss);
+  const bool with_loss = target && loss;
+  if (with_loss && (!workspace || workspace_bytes < sizeof(double) * blocks256(n)))
+    return fail(SS_E_WORKSPACE, "ss_nn_residual_mse: workspace needs %zu bytes", sizeof(double) * blocks256(n));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* part = with_loss ? static_cast<double*>(workspace) : nullptr;
+  k_residual_mse<<<blocks256(n), 256, 0, st>>>(r, x, target, n, out, g, part);
+  if (with_loss) k_loss_reduce<<<1, 256, 0, st>>>(part, blocks256(n), n, loss);
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;
 }

@@ -336,6 +336,7 @@ ss_status os_validate(const ss_system* sys, const ss_subsets* sub, int nsys, con
   if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
   if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
   if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
+  if (o->staged != 0) return fail(SS_E_ARG, "%s: the staged forms are for ss_sart_* only (staged must be 0)", fn);
   return SS_OK;
 }
 

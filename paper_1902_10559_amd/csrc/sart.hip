@@ -46,6 +46,7 @@
 #include "device.h"
 #include "internal.h"
 #include "lines.h"
+#include "staged.h"
 
 namespace ss {
 namespace {
@@ -81,6 +82,22 @@ struct SysDesc {
   int64_t m, n;
   int64_t fp_block0, bp_block0;  // first block of this system in each grid
   int32_t fp_nblocks, bp_nblocks;
+  // band-staged forward projection (see staged.h)
+  uint16_t* fb_idx;   // band-major copy of the row streams: column - band start
+  void* fb_val;
+  int32_t* fb_off;    // band-major segment -> first entry ([nseg] = nnz)
+  int32_t* fb_slot;   // band-major segment -> its row's partial slot
+  uint32_t* fb_rseg;  // m+1: row i's partial slots [rseg[i], rseg[i+1])
+  float* fb_part;     // NV floats per slot
+  uint64_t* fb_len;   // nb*m+1: (segments, entries) per (band, row), scanned
+  int64_t cv_rblk0;   // first block of this system in the set-up row grid
+  int64_t cv_t64_0, cv_t32_0;  // first scan tile of fb_len / fb_rseg
+  int32_t fb_nb;      // bands
+  int32_t fb_pair0;   // first (system, band) pair of this system
+  // tile-staged back projection
+  uint16_t* bt_idx;   // rank of each CSC entry's row among its tile's rows
+  BtMeta* bt_meta;    // per tile
+  int32_t* bt_runs;   // per tile kBtRunCap pairs (first row, first LDS slot)
 };
 
 struct Params {
@@ -88,6 +105,8 @@ struct Params {
   int32_t max_iter;
   double tol;
   int32_t nonneg;
+  int32_t band_lg;   // log2 of the forward bands' width (staged)
+  int32_t tile_lg;   // log2 of the back-projection tiles' columns (staged)
 };
 
 struct SetupFlags {
@@ -101,13 +120,21 @@ struct DescChunk {
   int32_t first;
 };
 
-template <bool BP>
+// Grid of a launch over all systems: 0 forward, 1 back projection, 2 the
+// set-up grid over rows.
+template <int GRID>
+__device__ inline int64_t block0_of(const SysDesc& d) {
+  if constexpr (GRID == 0) return d.fp_block0;
+  else if constexpr (GRID == 1) return d.bp_block0;
+  else return d.cv_rblk0;
+}
+
+template <int GRID>
 __device__ inline int find_sys(const SysDesc* t, int nsys, int64_t b) {
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
     const int mid = __builtin_amdgcn_readfirstlane((lo + hi + 1) >> 1);
-    const int64_t b0 = BP ? t[mid].bp_block0 : t[mid].fp_block0;
-    if (b0 <= b) lo = mid;
+    if (block0_of<GRID>(t[mid]) <= b) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -171,7 +198,7 @@ __device__ inline TileCtx tile_ctx(const SysDesc* table, int nsys, uint32_t t, u
   TileCtx c;
   const uint32_t b = __builtin_amdgcn_readfirstlane(xcd ? xcd_remap(t, ntiles) : t);
   // uniform per block: keep the descriptor in scalar registers
-  c.s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<BP>(table, nsys, b));
+  c.s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<BP ? 1 : 0>(table, nsys, b));
   const SysDesc& S = table[c.s];
   c.stop = *gl(&S.st->stop);
   c.local = static_cast<int64_t>(b) - (BP ? S.bp_block0 : S.fp_block0);
@@ -357,6 +384,417 @@ __global__ __launch_bounds__(kThreads) void k_finish(const SysDesc* table) {
   for (int64_t i = threadIdx.x; i < cnt; i += kThreads) S.f[0][i] = S.f[1][i];
 }
 
+// ------------------------------------------- staged kernels (staged.h)
+// Set-up grid over rows: kCvRows rows per block, kCvLanes lanes per row.
+constexpr int kCvLanes = 16;
+constexpr int kCvRows = kThreads / kCvLanes;
+
+// Per row: the length of each band run (a segment) into fb_len[b*m + i] as
+// (1 segment, len entries), and the row's segment count into fb_rseg[i].
+// A run starts where an entry's band differs from the previous entry's; its
+// end is found by binary search for the next band's first column.
+__global__ __launch_bounds__(kThreads) void k_fb_count(const SysDesc* table, int nsys, const Params* prm) {
+  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, blockIdx.x));
+  const SysDesc& S = table[s];
+  const int lg = prm->band_lg;
+  const int64_t i = (static_cast<int64_t>(blockIdx.x) - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
+  const int g = threadIdx.x % kCvLanes;
+  if (i >= S.m) return;
+  const int64_t lo = gl(S.row_ptr)[i], hi = gl(S.row_ptr)[i + 1];
+  uint32_t runs = 0;
+  for (int64_t k = lo + g; k < hi; k += kCvLanes) {
+    const int32_t c = gl(S.col_idx)[k];
+    if (c < 0 || c >= S.n) continue;  // never for a fold's output (columns in range)
+    const int32_t b = c >> lg;
+    if (k == lo || (gl(S.col_idx)[k - 1] >> lg) != b) {
+      const int64_t e = col_lower_bound(S.col_idx, k + 1, hi, (b + 1) << lg);
+      glw(S.fb_len)[static_cast<int64_t>(b) * S.m + i] = seg_pack(1u, static_cast<uint32_t>(e - k));
+      ++runs;
+    }
+  }
+#pragma unroll
+  for (int o = kCvLanes / 2; o > 0; o >>= 1) runs += __shfl_xor(runs, o, kWave);
+  if (g == 0) glw(S.fb_rseg)[i] = runs;
+}
+
+// Per row, after both scans: each entry goes to its band-major position
+// (16-bit column within the band, value copied bit for bit); each run start
+// records its segment's offset and its row's slot (the row's slots follow
+// its bands in ascending order).  VB: value bytes per entry.
+template <int VB>
+__global__ __launch_bounds__(kThreads) void k_fb_fill(const SysDesc* table, int nsys, const Params* prm) {
+  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, blockIdx.x));
+  const SysDesc& S = table[s];
+  const int lg = prm->band_lg;
+  const int64_t i = (static_cast<int64_t>(blockIdx.x) - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
+  const int g = threadIdx.x % kCvLanes;
+  if (i == 0 && g == 0) {
+    const uint64_t tot = gl(S.fb_len)[static_cast<int64_t>(S.fb_nb) * S.m];
+    glw(S.fb_off)[seg_count(tot)] = static_cast<int32_t>(seg_entries(tot));
+  }
+  if (i >= S.m) return;
+  const int64_t lo = gl(S.row_ptr)[i], hi = gl(S.row_ptr)[i + 1];
+  for (int64_t k = lo + g; k < hi; k += kCvLanes) {
+    const int32_t c = gl(S.col_idx)[k];
+    if (c < 0 || c >= S.n) continue;
+    const int32_t b = c >> lg;
+    const int64_t at = static_cast<int64_t>(b) * S.m + i;
+    const uint64_t pre = gl(S.fb_len)[at];
+    const int64_t k0 = (k == lo || (gl(S.col_idx)[k - 1] >> lg) != b) ? k
+                       : col_lower_bound(S.col_idx, lo, k, b << lg);
+    const int64_t pos = static_cast<int64_t>(seg_entries(pre)) + (k - k0);
+    // a row whose columns do not ascend could place an entry past its
+    // segment: such entries are dropped (the fold's rows always ascend)
+    if (pos >= static_cast<int64_t>(seg_entries(gl(S.fb_len)[at + 1]))) continue;
+    glw(S.fb_idx)[pos] = static_cast<uint16_t>(c - (b << lg));
+    if constexpr (VB == 8)
+      glw(static_cast<uint64_t*>(S.fb_val))[pos] = gl(static_cast<const uint64_t*>(S.val))[k];
+    else if constexpr (VB == 4)
+      glw(static_cast<uint32_t*>(S.fb_val))[pos] = gl(static_cast<const uint32_t*>(S.val))[k];
+    else
+      glw(static_cast<uint16_t*>(S.fb_val))[pos] = gl(static_cast<const uint16_t*>(S.val))[k];
+    if (k == k0) {
+      uint32_t ord = 0;  // segments of this row in lower bands
+      for (int bb = 0; bb < b; ++bb) {
+        const int64_t a = static_cast<int64_t>(bb) * S.m + i;
+        ord += seg_count(gl(S.fb_len)[a + 1]) - seg_count(gl(S.fb_len)[a]);
+      }
+      const uint32_t sg = seg_count(pre);
+      glw(S.fb_off)[sg] = static_cast<int32_t>(seg_entries(pre));
+      glw(S.fb_slot)[sg] = static_cast<int32_t>(gl(S.fb_rseg)[i] + ord);
+    }
+  }
+}
+
+// The scan pieces of the staged forward set-up: per system its (band, row)
+// pairs (plus the total) and its rows (plus the total).
+__global__ void k_make_pieces(const SysDesc* table, int nsys, ScanPiece<uint64_t>* p64, ScanPiece<uint32_t>* p32) {
+  const int s = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (s >= nsys) return;
+  const SysDesc& S = table[s];
+  const int64_t l64 = static_cast<int64_t>(S.fb_nb) * S.m + 1, l32 = S.m + 1;
+  p64[s] = ScanPiece<uint64_t>{S.fb_len, l64, S.cv_t64_0, (l64 + kPScanTile - 1) / kPScanTile, nullptr};
+  p32[s] = ScanPiece<uint32_t>{S.fb_rseg, l32, S.cv_t32_0, (l32 + kPScanTile - 1) / kPScanTile, nullptr};
+}
+
+// The work tiles of the band-staged forward projection, for all systems:
+// each (system, band) pair's segments cut into tiles of at most `per`
+// segments, in pair order.  One block; each thread takes a run of pairs.
+constexpr int kTileThreads = 1024;
+__global__ __launch_bounds__(kTileThreads) void k_band_tiles(const SysDesc* table, int nsys, int npairs, int per,
+                                                             BandTile* tiles, int32_t* ntiles) {
+  __shared__ int32_t tot[kTileThreads];
+  const int chunk = (npairs + kTileThreads - 1) / kTileThreads;
+  const int q0 = static_cast<int>(threadIdx.x) * chunk;
+  const int q1 = min(npairs, q0 + chunk);
+  auto pair_range = [&](int q, int* sys, int* band, int32_t* a, int32_t* b) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (table[mid].fb_pair0 <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const SysDesc& S = table[lo];
+    const int bnd = q - S.fb_pair0;
+    *sys = lo;
+    *band = bnd;
+    *a = static_cast<int32_t>(seg_count(gl(S.fb_len)[static_cast<int64_t>(bnd) * S.m]));
+    *b = static_cast<int32_t>(seg_count(gl(S.fb_len)[static_cast<int64_t>(bnd + 1) * S.m]));
+  };
+  int32_t mine = 0;
+  for (int q = q0; q < q1; ++q) {
+    int sy, bd;
+    int32_t a, b;
+    pair_range(q, &sy, &bd, &a, &b);
+    mine += (b - a + per - 1) / per;
+  }
+  tot[threadIdx.x] = mine;
+  __syncthreads();
+  for (int o = 1; o < kTileThreads; o <<= 1) {
+    const int32_t v = threadIdx.x >= static_cast<unsigned>(o) ? tot[threadIdx.x - o] : 0;
+    __syncthreads();
+    tot[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int32_t t = tot[threadIdx.x] - mine;
+  for (int q = q0; q < q1; ++q) {
+    int sy, bd;
+    int32_t a, b;
+    pair_range(q, &sy, &bd, &a, &b);
+    for (int32_t s0 = a; s0 < b; s0 += per) tiles[t++] = BandTile{sy, bd, s0, min(b, s0 + per)};
+  }
+  if (threadIdx.x == kTileThreads - 1) *ntiles = tot[kTileThreads - 1];
+}
+
+// Band-staged forward projection: grid-stride over the work tiles.  Per
+// tile: the image band into LDS, then RPW segments per wavefront (L lanes
+// each), each segment's sum into its row's slot.
+template <int NV, int WT, int RPW, int P>
+__global__ __launch_bounds__(kStagedThreads) void k_band_fp(const SysDesc* __restrict__ table,
+                                                            const BandTile* __restrict__ tiles,
+                                                            const int32_t* __restrict__ ntiles_p,
+                                                            const Params* __restrict__ prm, int parity) {
+  extern __shared__ float xs[];
+  constexpr int L = kWave / RPW;
+  constexpr int SPP = kStagedWaves * RPW;  // segments per pass of the block
+  const int ntiles = *gl(ntiles_p);
+  const int lg = prm->band_lg;
+  const int glane = lane_id() % L;
+  const int grp = wave_id() * RPW + lane_id() / L;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BandTile T = tiles[t];
+    const SysDesc& S = table[__builtin_amdgcn_readfirstlane(T.sys)];
+    if (*gl(&S.st->stop)) continue;
+    const int64_t j0 = static_cast<int64_t>(T.band) << lg;
+    const int64_t cnt = min(static_cast<int64_t>(1) << lg, S.n - j0);
+    stage_contiguous<NV, kStagedThreads>(xs, S.f[parity] + j0 * NV, cnt);
+    __syncthreads();
+    for (int sb = T.s0; sb < T.s1; sb += SPP) {
+      const int sg = sb + grp;
+      const bool valid = sg < T.s1;
+      const int sc = valid ? sg : T.s1 - 1;
+      const int64_t lo = gl(S.fb_off)[sc], hi = valid ? gl(S.fb_off)[sc + 1] : lo;
+      float acc[NV];
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
+      line_dot_lds<NV, WT, L, P>(S.fb_idx, S.fb_val, xs, lo, hi, glane, acc, (1u << lg) - 1u);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
+      if (valid && glane == 0) {
+        Vec<NV> pv;
+#pragma unroll
+        for (int h = 0; h < NV; ++h) pv.v[h] = acc[h];
+        store_vec<NV>(S.fb_part, gl(S.fb_slot)[sg], pv);
+      }
+    }
+    __syncthreads();  // the next tile overwrites xs
+  }
+}
+
+// The residual of the band-staged forward projection: per row, its
+// partials added in band order, r = p - q, z = r / W, and the block's FP64
+// partial of |r|^2; the first block of a system moves the iterate index on.
+template <int NV>
+__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys) {
+  __shared__ double red[kFinThreads / kWave];
+  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<0>(table, nsys, blockIdx.x));
+  const SysDesc& S = table[s];
+  if (*gl(&S.st->stop)) return;
+  const int64_t lb = static_cast<int64_t>(blockIdx.x) - S.fp_block0;
+  const int64_t i = lb * kFinThreads + threadIdx.x;
+  double d = 0.0;
+  if (i < S.m) {
+    float acc[NV];
+#pragma unroll
+    for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
+    const uint32_t q0 = gl(S.fb_rseg)[i], q1 = gl(S.fb_rseg)[i + 1];
+    for (uint32_t q = q0; q < q1; ++q) {
+      const Vec<NV> pv = load_vec<NV>(S.fb_part, q);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] += pv.v[h];
+    }
+    const Vec<NV> pv = load_vec<NV>(S.p, i);
+    const float w = gl(S.inv_row)[i];
+    Vec<NV> zv;
+#pragma unroll
+    for (int h = 0; h < NV; ++h) {
+      const float r = pv.v[h] - acc[h];
+      zv.v[h] = r * w;
+      d += static_cast<double>(r) * static_cast<double>(r);
+    }
+    store_vec<NV>(S.z, i, zv);
+  }
+  const double tot = block_sum<kFinThreads / kWave>(d, red);
+  if (threadIdx.x == 0) {
+    glw(S.partials)[lb] = tot;
+    SysState* st = S.st;
+    if (lb == 0 && *gl(&st->pending)) {
+      glw(&st->k)[0] += 1;
+      glw(&st->pending)[0] = 0;
+    }
+  }
+}
+
+// Back-projection plan of one tile (one block per tile, all systems): a
+// bitmap of the rows that the tile's columns touch, its runs of consecutive
+// set bits (first row, first LDS slot), and each entry's rank among the
+// set bits.  LDS: three arrays of ceil(m/32) words.
+__global__ __launch_bounds__(kStagedThreads) void k_bt_plan(const SysDesc* table, int nsys, const Params* prm) {
+  extern __shared__ uint32_t bw[];
+  constexpr int T = kStagedThreads;
+  __shared__ uint32_t tsum[2][T];
+  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<1>(table, nsys, blockIdx.x));
+  const SysDesc& S = table[s];
+  const int64_t lt = static_cast<int64_t>(blockIdx.x) - S.bp_block0;
+  const int64_t j0 = lt << prm->tile_lg;
+  const int64_t j1 = min(S.n, j0 + (int64_t{1} << prm->tile_lg));
+  const int words = static_cast<int>((S.m + 31) / 32);
+  uint32_t* bm = bw;
+  uint32_t* pre = bw + words;
+  uint32_t* rpre = bw + 2 * words;
+  for (int w = threadIdx.x; w < words; w += T) bm[w] = 0u;
+  __syncthreads();
+  const int64_t k0 = gl(S.col_ptr)[j0], k1 = gl(S.col_ptr)[j1];
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += T) {
+    const int32_t r = gl(S.row_idx)[k];
+    if (r >= 0 && r < S.m) atomicOr(&bm[r >> 5], 1u << (r & 31));
+  }
+  __syncthreads();
+  // counts of set bits and of run starts per word, scanned over the words
+  // (each thread a contiguous chunk, then the chunk totals across threads)
+  const int chunk = (words + T - 1) / T;
+  const int w0 = static_cast<int>(threadIdx.x) * chunk, w1 = min(words, w0 + chunk);
+  uint32_t cb = 0, cr = 0;
+  for (int w = w0; w < w1; ++w) {
+    const uint32_t v = bm[w];
+    const uint32_t carry = w > 0 ? bm[w - 1] >> 31 : 0u;
+    const uint32_t starts = v & ~((v << 1) | carry);
+    pre[w] = cb;
+    rpre[w] = cr;
+    cb += __popc(v);
+    cr += __popc(starts);
+  }
+  tsum[0][threadIdx.x] = cb;
+  tsum[1][threadIdx.x] = cr;
+  __syncthreads();
+  for (int o = 1; o < T; o <<= 1) {
+    const uint32_t a = threadIdx.x >= static_cast<unsigned>(o) ? tsum[0][threadIdx.x - o] : 0u;
+    const uint32_t b = threadIdx.x >= static_cast<unsigned>(o) ? tsum[1][threadIdx.x - o] : 0u;
+    __syncthreads();
+    tsum[0][threadIdx.x] += a;
+    tsum[1][threadIdx.x] += b;
+    __syncthreads();
+  }
+  const uint32_t bb = tsum[0][threadIdx.x] - cb, rb = tsum[1][threadIdx.x] - cr;
+  for (int w = w0; w < w1; ++w) {
+    pre[w] += bb;
+    rpre[w] += rb;
+  }
+  const uint32_t rows = tsum[0][T - 1], runs = tsum[1][T - 1];
+  const bool ok = rows <= static_cast<uint32_t>(kBtMaxRows) && runs <= static_cast<uint32_t>(kBtRunCap);
+  if (threadIdx.x == 0) {
+    auto* mt = glw(reinterpret_cast<int32_t*>(S.bt_meta + lt));
+    mt[0] = static_cast<int32_t>(rows);
+    mt[1] = static_cast<int32_t>(runs);
+    mt[2] = ok ? 1 : 0;
+    mt[3] = 0;
+  }
+  __syncthreads();
+  if (!ok) return;
+  int32_t* runs_out = S.bt_runs + 2 * lt * kBtRunCap;
+  for (int w = threadIdx.x; w < words; w += T) {
+    const uint32_t v = bm[w];
+    const uint32_t carry = w > 0 ? bm[w - 1] >> 31 : 0u;
+    uint32_t starts = v & ~((v << 1) | carry);
+    uint32_t ri = rpre[w];
+    while (starts) {
+      const int bit = __builtin_ctz(starts);
+      starts &= starts - 1;
+      const uint32_t slot = pre[w] + __popc(v & ((1u << bit) - 1u));
+      glw(runs_out)[2 * ri] = w * 32 + bit;
+      glw(runs_out)[2 * ri + 1] = static_cast<int32_t>(slot);
+      ++ri;
+    }
+  }
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += T) {
+    const int32_t r = gl(S.row_idx)[k];
+    const int32_t rr = r >= 0 && r < S.m ? r : 0;
+    const uint32_t rank = pre[rr >> 5] + __popc(bm[rr >> 5] & ((1u << (rr & 31)) - 1u));
+    glw(S.bt_idx)[k] = static_cast<uint16_t>(rank < rows ? rank : 0u);
+  }
+}
+
+// Tile-staged back projection: one block per tile of 2^tile_lg columns.
+// The tile's rows of z go into LDS (runs dealt to the wavefronts), then CPW
+// columns per wavefront are summed from there and updated.  A tile whose
+// rows did not fit keeps global gathers.  The first tile of a system also
+// finalises the residual.
+template <int NV, int WT, int CPW, int P>
+__global__ __launch_bounds__(kStagedThreads) void k_tile_bp(const Params* __restrict__ prm,
+                                                            const SysDesc* __restrict__ table, int nsys,
+                                                            int parity) {
+  extern __shared__ float zs[];
+  __shared__ double red[kStagedWaves];
+  constexpr int L = kWave / CPW;
+  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<1>(table, nsys, blockIdx.x));
+  const SysDesc& S = table[s];
+  if (*gl(&S.st->stop)) return;
+  const int64_t lt = static_cast<int64_t>(blockIdx.x) - S.bp_block0;
+  if (lt == 0) {
+    finalize_residual<kStagedWaves>(prm, S, red);
+    __syncthreads();
+  }
+  if (*gl(&S.st->k) >= prm->max_iter) return;
+  const int lg = prm->tile_lg;
+  const int64_t j0 = lt << lg;
+  const int64_t j1 = min(S.n, j0 + (int64_t{1} << lg));
+  const int32_t* mt = reinterpret_cast<const int32_t*>(S.bt_meta + lt);
+  const int32_t nrows = gl(mt)[0], nruns = gl(mt)[1];
+  const bool staged = gl(mt)[2] != 0;
+  if (staged) {
+    const int32_t* runs = S.bt_runs + 2 * lt * kBtRunCap;
+    for (int r = wave_id(); r < nruns; r += kStagedWaves) {
+      const int32_t first = gl(runs)[2 * r], slot = gl(runs)[2 * r + 1];
+      const int32_t end = r + 1 < nruns ? gl(runs)[2 * r + 3] : nrows;
+      for (int q = lane_id(); q < end - slot; q += kWave) {
+        const Vec<NV> zv = load_vec<NV>(S.z, first + q);
+#pragma unroll
+        for (int h = 0; h < NV; ++h) zs[(slot + q) * NV + h] = zv.v[h];
+      }
+    }
+    __syncthreads();
+  }
+  const int glane = lane_id() % L;
+  const float* fin = S.f[parity];
+  for (int64_t jb = j0; jb < j1; jb += kStagedWaves * CPW) {
+    const int64_t j = jb + wave_id() * CPW + lane_id() / L;
+    const bool owner = glane == 0 && j < j1;
+    const int64_t jj = j < j1 ? j : j1 - 1;
+    const int64_t lo = gl(S.col_ptr)[jj], hi = j < j1 ? gl(S.col_ptr)[jj + 1] : lo;
+    Vec<NV> fv = load_vec<NV>(fin, jj);
+    const float tl = prm->lambda * gl(S.inv_col)[jj];
+    float acc[NV];
+#pragma unroll
+    for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
+    if (staged) line_dot_lds<NV, WT, L, P>(S.bt_idx, S.val_t, zs, lo, hi, glane, acc, kBtMaxRows - 1u);
+    else line_dot_c<NV, WT, L, P>(S.row_idx, S.val_t, S.z, lo, hi, glane, acc);
+#pragma unroll
+    for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
+    if (owner) {
+#pragma unroll
+      for (int h = 0; h < NV; ++h) fv.v[h] = fmaf(tl, acc[h], fv.v[h]);
+      if (prm->nonneg) fv = project_nonneg<NV>(fv);
+      store_vec<NV>(S.f[parity ^ 1], j, fv);
+    }
+  }
+}
+
+// Sizes of the staged forms (one thread): forward segments and work tiles,
+// back-projection tiles, how many of them are staged and the rows they stage.
+__global__ void k_staged_info(const SysDesc* table, int nsys, int stg, const int32_t* ntiles, int64_t* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t segs = 0, bt = 0, ok = 0, rows = 0;
+  for (int s = 0; s < nsys; ++s) {
+    const SysDesc& S = table[s];
+    if (stg & 1) segs += seg_count(S.fb_len[static_cast<int64_t>(S.fb_nb) * S.m]);
+    if (stg & 2) {
+      for (int32_t t = 0; t < S.bp_nblocks; ++t) {
+        const int32_t* mt = reinterpret_cast<const int32_t*>(S.bt_meta + t);
+        ++bt;
+        if (mt[2]) {
+          ++ok;
+          rows += mt[0];
+        }
+      }
+    }
+  }
+  out[0] = segs;
+  out[1] = (stg & 1) ? *ntiles : 0;
+  out[2] = bt;
+  out[3] = ok;
+  out[4] = rows;
+}
+
 // ---- device code end
 
 // ------------------------------------------------------------------ host
@@ -365,6 +803,11 @@ struct Layout {
   std::vector<size_t> z_off, part_off, f_off;
   // interleaved copies of the row (forward) and column (back) streams
   std::vector<size_t> fi_idx, fi_val, bi_idx, bi_val;
+  // staged forms (per system) and their set-up scratch (shared)
+  std::vector<size_t> fb_idx, fb_val, fb_len, fb_rseg, fb_off, fb_slot, fb_part, bt_idx, bt_meta, bt_runs;
+  size_t fb_len_lo = 0, fb_len_hi = 0, fb_rseg_lo = 0, fb_rseg_hi = 0;
+  size_t tiles = 0, ntiles = 0, pieces64 = 0, pieces32 = 0, tsum64 = 0, tsum32 = 0, info = 0;
+  int64_t tile_cap = 0, t64 = 0, t32 = 0;
 };
 
 // Stream form of each kernel from the chunked option: bit 2 (bit 3) selects
@@ -383,8 +826,18 @@ inline size_t value_bytes(const ss_system& S) { return static_cast<size_t>(S.nva
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
 
-Layout make_layout(const ss_system* sys, int nsys, int ch_opt) {
-  const int ch = effective_chunked(sys, ch_opt);
+// Staged-form sizes shared by the layout and the set-up.
+inline int band_lg_of(const ss_sart_opts* o) { return o->band_width ? __builtin_ctz(o->band_width) : 12; }
+inline int tile_lg_of(const ss_sart_opts* o) { return o->tile_cols ? __builtin_ctz(o->tile_cols) : 10; }
+inline int tile_segs_of(const ss_sart_opts* o) { return o->tile_segments ? o->tile_segments : 1024; }
+inline int64_t bands_of(const ss_system& S, int lg) { return (S.n + (int64_t{1} << lg) - 1) >> lg; }
+inline int64_t seg_bound(const ss_system& S, int lg) { return std::min<int64_t>(S.nnz, bands_of(S, lg) * S.m) + 1; }
+inline int64_t pscan_tiles(int64_t len) { return (len + kPScanTile - 1) / kPScanTile; }
+inline size_t stream_cap(int64_t nnz) { return static_cast<size_t>(ss_stream_len(nnz) > 0 ? ss_stream_len(nnz) : 4); }
+
+Layout make_layout(const ss_system* sys, int nsys, const ss_sart_opts* opt) {
+  const int ch = effective_chunked(sys, opt->chunked);
+  const int stg = opt->staged;
   Layout L;
   size_t o = 0;
   L.params = o;
@@ -411,11 +864,76 @@ Layout make_layout(const ss_system* sys, int nsys, int ch_opt) {
   for (int s = 0; s < nsys; ++s) {
     const size_t cap = static_cast<size_t>(sys[s].nnz) + SS_CHUNK;
     for (int which = 0; which < 2; ++which) {
-      if (!(which ? bp_form(ch) == 2 && !sys[s].col_lanes : fp_form(ch) == 2 && !sys[s].row_lanes)) continue;
+      if (!(which ? bp_form(ch) == 2 && !sys[s].col_lanes && !(stg & 2)
+                  : fp_form(ch) == 2 && !sys[s].row_lanes && !(stg & 1)))
+        continue;
       (which ? L.bi_idx : L.fi_idx).push_back(o);
       o += align256(sizeof(int32_t) * cap);
       (which ? L.bi_val : L.fi_val).push_back(o);
       o += align256(value_bytes(sys[s]) * cap);
+    }
+  }
+  if (stg & 1) {
+    const int lg = band_lg_of(opt);
+    const int per = tile_segs_of(opt);
+    for (int s = 0; s < nsys; ++s) {
+      const ss_system& S = sys[s];
+      const int64_t nsb = seg_bound(S, lg);
+      L.fb_idx.push_back(o);
+      o += align256(sizeof(uint16_t) * stream_cap(S.nnz));
+      L.fb_val.push_back(o);
+      o += align256(value_bytes(S) * stream_cap(S.nnz));
+      L.fb_off.push_back(o);
+      o += align256(sizeof(int32_t) * static_cast<size_t>(nsb + 1));
+      L.fb_slot.push_back(o);
+      o += align256(sizeof(int32_t) * static_cast<size_t>(nsb));
+      L.fb_part.push_back(o);
+      o += align256(sizeof(float) * S.nvals * static_cast<size_t>(nsb));
+      L.tile_cap += bands_of(S, lg) + (nsb + per - 1) / per;
+      L.t64 += pscan_tiles(bands_of(S, lg) * S.m + 1);
+      L.t32 += pscan_tiles(S.m + 1);
+    }
+    // the arrays the set-up clears, each kind in one contiguous range
+    L.fb_len_lo = o;
+    for (int s = 0; s < nsys; ++s) {
+      L.fb_len.push_back(o);
+      o += align256(sizeof(uint64_t) * static_cast<size_t>(bands_of(sys[s], lg) * sys[s].m + 1));
+    }
+    L.fb_len_hi = o;
+    L.fb_rseg_lo = o;
+    for (int s = 0; s < nsys; ++s) {
+      L.fb_rseg.push_back(o);
+      o += align256(sizeof(uint32_t) * static_cast<size_t>(sys[s].m + 1));
+    }
+    L.fb_rseg_hi = o;
+    L.tiles = o;
+    o += align256(sizeof(BandTile) * static_cast<size_t>(L.tile_cap + 1));
+    L.ntiles = o;
+    o += 256;
+    L.pieces64 = o;
+    o += align256(sizeof(ScanPiece<uint64_t>) * nsys);
+    L.pieces32 = o;
+    o += align256(sizeof(ScanPiece<uint32_t>) * nsys);
+    L.tsum64 = o;
+    o += align256(sizeof(uint64_t) * static_cast<size_t>(L.t64));
+    L.tsum32 = o;
+    o += align256(sizeof(uint32_t) * static_cast<size_t>(L.t32));
+  }
+  if (stg) {
+    L.info = o;
+    o += 256;
+  }
+  if (stg & 2) {
+    const int lg = tile_lg_of(opt);
+    for (int s = 0; s < nsys; ++s) {
+      const ss_system& S = sys[s];
+      const size_t nt = static_cast<size_t>((S.n + (int64_t{1} << lg) - 1) >> lg);
+      L.bt_idx.push_back(o);
+      o += align256(sizeof(uint16_t) * stream_cap(S.nnz));
+      L.bt_meta.push_back(o);
+      o += align256(sizeof(BtMeta) * nt);
+      L.bt_runs.push_back(o);
+      o += align256(2 * sizeof(int32_t) * kBtRunCap * nt);
     }
   }
   L.total = o;
@@ -424,6 +942,7 @@ Layout make_layout(const ss_system* sys, int nsys, int ch_opt) {
 
 struct Cfg {
   int nv, wt, rpw, cpw, xcd, u, pers, ch;
+  int stg, blg, tlg, spt;  // staged forms: bits, log2 band width, log2 tile columns, segments per tile
 };
 
 ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const char* fn) {
@@ -464,6 +983,40 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
   if ((effective_chunked(sys, o->chunked) & 12) && sys[0].nvals == 1 && sys[0].wdtype != SS_F32)
     return fail(SS_E_ARG, "%s: the interleaved stream form needs entries of at least 4 bytes", fn);
   if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
+  if (o->staged < 0 || o->staged > 3) return fail(SS_E_ARG, "%s: staged must be 0..3", fn);
+  auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (o->band_width && (!pow2(o->band_width) || o->band_width < 1024 || o->band_width > 16384 ||
+                        o->band_width * sys[0].nvals * 4 > 65536))
+    return fail(SS_E_ARG, "%s: band_width must be a power of two in 1024..16384 with band_width*nvals*4 <= 65536",
+                fn);
+  if (o->tile_cols && (!pow2(o->tile_cols) || o->tile_cols < 64 || o->tile_cols > 8192))
+    return fail(SS_E_ARG, "%s: tile_cols must be a power of two in 64..8192", fn);
+  if (o->tile_segments && (o->tile_segments < 64 || o->tile_segments > 65536))
+    return fail(SS_E_ARG, "%s: tile_segments must be in 64..65536", fn);
+  if (o->staged) {
+    for (int s = 0; s < nsys; ++s) {
+      const ss_system& S = sys[s];
+      if (((o->staged & 1) && S.row_lanes) || ((o->staged & 2) && S.col_lanes))
+        return fail(SS_E_ARG, "%s: the staged forms need lines in ascending order (row_lanes/col_lanes 0)", fn);
+      if (S.nnz >= INT32_MAX) return fail(SS_E_ARG, "%s: the staged forms need nnz < 2^31", fn);
+      if ((o->staged & 1) && bands_of(S, band_lg_of(o)) * S.m + 1 >= INT32_MAX)
+        return fail(SS_E_ARG, "%s: system %d has too many (band, row) pairs for the staged forward form", fn, s);
+      if ((o->staged & 2) && S.m > (int64_t{1} << 17))
+        return fail(SS_E_ARG, "%s: the staged back projection needs m <= 2^17", fn);
+    }
+  }
+  return SS_OK;
+}
+
+// The band-staged forward kernel loads the image in 16-byte pieces.
+ss_status check_images(const ss_system* sys, int nsys, float* const* f, const ss_sart_opts* o, const char* fn) {
+  if (!f) return fail(SS_E_ARG, "%s: NULL images", fn);
+  for (int s = 0; s < nsys; ++s) {
+    if (!f[s]) return fail(SS_E_ARG, "%s: NULL image %d", fn, s);
+    if ((o->staged & 1) && (reinterpret_cast<uintptr_t>(f[s]) & 15u))
+      return fail(SS_E_ARG, "%s: the staged forward projection needs 16-byte aligned images (image %d)", fn, s);
+  }
+  (void)sys;
   return SS_OK;
 }
 
@@ -491,11 +1044,19 @@ Cfg choose_cfg(const ss_system* sys, int nsys, const ss_sart_opts* o) {
   c.u = o->unroll ? o->unroll : 4;
   c.ch = effective_chunked(sys, o->chunked);
   c.pers = o->persistent ? 1 : 0;
+  c.stg = o->staged;
+  c.blg = band_lg_of(o);
+  c.tlg = tile_lg_of(o);
+  c.spt = tile_segs_of(o);
+  if (c.stg & 1) c.rpw = o->rows_per_wave ? o->rows_per_wave : 4;
+  if (c.stg & 2) c.cpw = o->cols_per_wave ? o->cols_per_wave : 8;
   return c;
 }
 
 struct Grids {
   uint32_t fp_blocks, bp_blocks;
+  uint32_t band_blocks;  // grid of the band-staged forward kernel
+  uint32_t cv_blocks;    // set-up grid over rows
 };
 
 ss_status interleave(const int64_t* ptr, int64_t lines, const int32_t* idx, const void* val, int32_t* idx_out,
@@ -510,11 +1071,96 @@ ss_status interleave(const int64_t* ptr, int64_t lines, const int32_t* idx, cons
 
 // Writes the descriptor table and resets states (stream-ordered kernels);
 // writes the interleaved stream copies where a kernel reads them.
+// Launch shapes of the staged kernels (their own, not the unstaged ones').
+template <int NV, int WT, int RPW, int P>
+const void* band_kernel() {
+  return reinterpret_cast<const void*>(k_band_fp<NV, WT, RPW, P>);
+}
+
+// Grid of the band-staged forward kernel: the blocks that fit on the device
+// at once (its LDS decides), at most one per possible tile; each block then
+// loops over the tiles.
+uint32_t band_grid(const Cfg& c, const Layout& L) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int>, uint32_t> cap;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t lds = (size_t{4} << c.blg) * c.nv;
+  uint32_t resident;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_tuple(dev, c.nv, c.blg);
+    auto it = cap.find(key);
+    if (it == cap.end()) {
+      int cus = 0, per = 0;
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      const void* k = c.nv == 2 ? band_kernel<2, SS_F32, 4, 1>() : band_kernel<1, SS_F32, 4, 1>();
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kStagedThreads, lds);
+      it = cap.emplace(key, static_cast<uint32_t>(std::max(1, cus) * std::max(1, per))).first;
+    }
+    resident = it->second;
+  }
+  const int64_t tiles = std::max<int64_t>(1, L.tile_cap);
+  return static_cast<uint32_t>(std::min<int64_t>(tiles, resident));
+}
+
+// Builds the staged forms of every system in the workspace (see staged.h):
+// for the forward projection the band-major streams, segment offsets and
+// slots and the work tiles; for the back projection the tiles' row plans and
+// ranks.  All systems in one launch per phase.
+ss_status build_staged(const ss_system* sys, int nsys, const Cfg& c, const Layout& L, char* ws, const Grids& g,
+                       hipStream_t st) {
+  const SysDesc* table = reinterpret_cast<const SysDesc*>(ws + L.table);
+  const Params* dprm = reinterpret_cast<const Params*>(ws + L.params);
+  if (c.stg & 1) {
+    const int64_t n64 = static_cast<int64_t>((L.fb_len_hi - L.fb_len_lo) / sizeof(uint64_t));
+    const int64_t n32 = static_cast<int64_t>((L.fb_rseg_hi - L.fb_rseg_lo) / sizeof(uint32_t));
+    k_fill_zero<uint64_t><<<2048, 256, 0, st>>>(reinterpret_cast<uint64_t*>(ws + L.fb_len_lo), n64);
+    k_fill_zero<uint32_t><<<512, 256, 0, st>>>(reinterpret_cast<uint32_t*>(ws + L.fb_rseg_lo), n32);
+    k_fb_count<<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
+    auto* p64 = reinterpret_cast<ScanPiece<uint64_t>*>(ws + L.pieces64);
+    auto* p32 = reinterpret_cast<ScanPiece<uint32_t>*>(ws + L.pieces32);
+    auto* t64 = reinterpret_cast<uint64_t*>(ws + L.tsum64);
+    auto* t32 = reinterpret_cast<uint32_t*>(ws + L.tsum32);
+    const unsigned pb = static_cast<unsigned>((nsys + 63) / 64);
+    k_make_pieces<<<pb, 64, 0, st>>>(table, nsys, p64, p32);
+    k_pscan_tiles<uint64_t><<<static_cast<unsigned>(L.t64), kPScanThreads, 0, st>>>(p64, nsys, t64);
+    k_pscan_bases<uint64_t><<<pb, 64, 0, st>>>(p64, nsys, t64);
+    k_pscan_apply<uint64_t><<<static_cast<unsigned>(L.t64), kPScanThreads, 0, st>>>(p64, nsys, t64);
+    k_pscan_tiles<uint32_t><<<static_cast<unsigned>(L.t32), kPScanThreads, 0, st>>>(p32, nsys, t32);
+    k_pscan_bases<uint32_t><<<pb, 64, 0, st>>>(p32, nsys, t32);
+    k_pscan_apply<uint32_t><<<static_cast<unsigned>(L.t32), kPScanThreads, 0, st>>>(p32, nsys, t32);
+    const size_t vb = value_bytes(sys[0]);
+    if (vb == 8) k_fb_fill<8><<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
+    else if (vb == 4) k_fb_fill<4><<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
+    else k_fb_fill<2><<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
+    int npairs = 0;
+    for (int s = 0; s < nsys; ++s) npairs += static_cast<int>(bands_of(sys[s], c.blg));
+    k_band_tiles<<<1, kTileThreads, 0, st>>>(table, nsys, npairs, c.spt, reinterpret_cast<BandTile*>(ws + L.tiles),
+                                             reinterpret_cast<int32_t*>(ws + L.ntiles));
+  }
+  if (c.stg & 2) {
+    int64_t words = 1;
+    for (int s = 0; s < nsys; ++s) words = std::max<int64_t>(words, (sys[s].m + 31) / 32);
+    k_bt_plan<<<g.bp_blocks, kStagedThreads, static_cast<size_t>(3 * words * sizeof(uint32_t)), st>>>(table, nsys,
+                                                                                                     dprm);
+  }
+  SS_HIP_TRY(hipGetLastError());
+  return SS_OK;
+}
+
+// Writes the descriptor table and resets states (stream-ordered kernels);
+// writes the interleaved stream copies where a kernel reads them, and the
+// staged forms.
 ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* res_hist,
-                const Params& prm, const Cfg& c, const Layout& L, char* ws, Grids* g,
+                Params prm, const Cfg& c, const Layout& L, char* ws, Grids* g,
                 int zero_start, hipStream_t st) {
-  int64_t fb = 0, bb = 0;
-  const int64_t rpb = static_cast<int64_t>(c.rpw) * kWPB, cpb = static_cast<int64_t>(c.cpw) * kWPB;
+  int64_t fb = 0, bb = 0, cv = 0, t64 = 0, t32 = 0;
+  int32_t pairs = 0;
+  prm.band_lg = c.blg;
+  prm.tile_lg = c.tlg;
+  const int64_t rpb = (c.stg & 1) ? kFinThreads : static_cast<int64_t>(c.rpw) * kWPB;
+  const int64_t cpb = (c.stg & 2) ? (int64_t{1} << c.tlg) : static_cast<int64_t>(c.cpw) * kWPB;
   DescChunk ch{};
   SysDesc* table = reinterpret_cast<SysDesc*>(ws + L.table);
   Params* dprm = reinterpret_cast<Params*>(ws + L.params);
@@ -542,19 +1188,42 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
     d.bp_nblocks = static_cast<int32_t>((S.n + cpb - 1) / cpb);
     d.fp_block0 = fb;
     d.bp_block0 = bb;
-    if (S.nnz > 0 && fp_form(c.ch) == 2 && !S.row_lanes) {
+    if (S.nnz > 0 && fp_form(c.ch) == 2 && !S.row_lanes && !(c.stg & 1)) {
       d.col_idx = reinterpret_cast<int32_t*>(ws + L.fi_idx[s]);
       d.val = ws + L.fi_val[s];
       if (ss_status e = interleave(S.row_ptr, S.m, S.col_idx, S.val, const_cast<int32_t*>(d.col_idx),
                                    const_cast<void*>(d.val), value_bytes(S), kWave / c.rpw, st))
         return e;
     }
-    if (S.nnz > 0 && bp_form(c.ch) == 2 && !S.col_lanes) {
+    if (S.nnz > 0 && bp_form(c.ch) == 2 && !S.col_lanes && !(c.stg & 2)) {
       d.row_idx = reinterpret_cast<int32_t*>(ws + L.bi_idx[s]);
       d.val_t = ws + L.bi_val[s];
       if (ss_status e = interleave(S.col_ptr, S.n, S.row_idx, S.val_t, const_cast<int32_t*>(d.row_idx),
                                    const_cast<void*>(d.val_t), value_bytes(S), kWave / c.cpw, st))
         return e;
+    }
+    if (c.stg & 1) {
+      d.fb_idx = reinterpret_cast<uint16_t*>(ws + L.fb_idx[s]);
+      d.fb_val = ws + L.fb_val[s];
+      d.fb_off = reinterpret_cast<int32_t*>(ws + L.fb_off[s]);
+      d.fb_slot = reinterpret_cast<int32_t*>(ws + L.fb_slot[s]);
+      d.fb_rseg = reinterpret_cast<uint32_t*>(ws + L.fb_rseg[s]);
+      d.fb_part = reinterpret_cast<float*>(ws + L.fb_part[s]);
+      d.fb_len = reinterpret_cast<uint64_t*>(ws + L.fb_len[s]);
+      d.fb_nb = static_cast<int32_t>(bands_of(S, c.blg));
+      d.fb_pair0 = pairs;
+      d.cv_rblk0 = cv;
+      d.cv_t64_0 = t64;
+      d.cv_t32_0 = t32;
+      pairs += d.fb_nb;
+      cv += (S.m + kCvRows - 1) / kCvRows;
+      t64 += pscan_tiles(static_cast<int64_t>(d.fb_nb) * S.m + 1);
+      t32 += pscan_tiles(S.m + 1);
+    }
+    if (c.stg & 2) {
+      d.bt_idx = reinterpret_cast<uint16_t*>(ws + L.bt_idx[s]);
+      d.bt_meta = reinterpret_cast<BtMeta*>(ws + L.bt_meta[s]);
+      d.bt_runs = reinterpret_cast<int32_t*>(ws + L.bt_runs[s]);
     }
     fb += d.fp_nblocks;
     bb += d.bp_nblocks;
@@ -568,10 +1237,13 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
   const SetupFlags fl{zero_start};
   if (c.nv == 2) k_setup<2><<<static_cast<unsigned>(nsys), kWave * kSetupWaves, 0, st>>>(table, fl);
   else k_setup<1><<<static_cast<unsigned>(nsys), kWave * kSetupWaves, 0, st>>>(table, fl);
-  if (fb > UINT32_MAX || bb > UINT32_MAX) return fail(SS_E_ARG, "SART: grid too large");
+  if (fb > UINT32_MAX || bb > UINT32_MAX || cv > UINT32_MAX) return fail(SS_E_ARG, "SART: grid too large");
   g->fp_blocks = static_cast<uint32_t>(fb);
   g->bp_blocks = static_cast<uint32_t>(bb);
+  g->cv_blocks = static_cast<uint32_t>(cv);
+  g->band_blocks = (c.stg & 1) ? band_grid(c, L) : 0;
   SS_HIP_TRY(hipGetLastError());
+  if (c.stg) return build_staged(sys, nsys, c, L, ws, *g, st);
   return SS_OK;
 }
 
@@ -580,6 +1252,9 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
 // packets between kernels); with null events it is an ordinary launch.
 struct Stamp {
   hipEvent_t start = nullptr, stop = nullptr;
+  // a forward projection of two launches (band-staged): the first one's
+  // stop and the second one's start
+  hipEvent_t mid0 = nullptr, mid1 = nullptr;
 };
 
 // Grid for a grid-stride kernel: one block per tile, unless `persistent`
@@ -636,9 +1311,63 @@ void launch_bp_u(int cpw, int pers, const Params* prm, const SysDesc* t, int nsy
   }
 }
 
+// Staged kernels: the forward pair (band kernel, then the residual kernel)
+// and the tile-staged back projection.
+template <int NV, int WT, int P>
+void launch_band(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int par, hipStream_t st,
+                 Stamp e) {
+  const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
+  const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
+  const BandTile* tiles = reinterpret_cast<const BandTile*>(ws + L.tiles);
+  const int32_t* nt = reinterpret_cast<const int32_t*>(ws + L.ntiles);
+  const size_t lds = (size_t{4} << c.blg) * NV;
+  const dim3 grid(g.band_blocks), blk(kStagedThreads);
+  switch (c.rpw) {
+    case 2: hipExtLaunchKernelGGL(k_band_fp<NV, WT, 2, P>, grid, blk, lds, st, e.start, e.mid0, 0, t, tiles, nt, prm, par); break;
+    case 8: hipExtLaunchKernelGGL(k_band_fp<NV, WT, 8, P>, grid, blk, lds, st, e.start, e.mid0, 0, t, tiles, nt, prm, par); break;
+    default: hipExtLaunchKernelGGL(k_band_fp<NV, WT, 4, P>, grid, blk, lds, st, e.start, e.mid0, 0, t, tiles, nt, prm, par); break;
+  }
+  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys);
+}
+
+template <int NV, int WT, int P>
+void launch_tile_bp(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int par, hipStream_t st,
+                    Stamp e) {
+  const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
+  const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
+  const size_t lds = sizeof(float) * NV * kBtMaxRows;
+  const dim3 grid(g.bp_blocks), blk(kStagedThreads);
+  switch (c.cpw) {
+    case 4: hipExtLaunchKernelGGL(k_tile_bp<NV, WT, 4, P>, grid, blk, lds, st, e.start, e.stop, 0, prm, t, nsys, par); break;
+    case 16: hipExtLaunchKernelGGL(k_tile_bp<NV, WT, 16, P>, grid, blk, lds, st, e.start, e.stop, 0, prm, t, nsys, par); break;
+    default: hipExtLaunchKernelGGL(k_tile_bp<NV, WT, 8, P>, grid, blk, lds, st, e.start, e.stop, 0, prm, t, nsys, par); break;
+  }
+}
+
 template <bool BP>
 void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int par,
                    hipStream_t st, Stamp e = {}) {
+  if ((c.stg & (BP ? 2 : 1)) != 0) {
+#define SS_STAGED(NV, WT)                                                                            \
+  if (c.nv == NV && c.wt == WT) {                                                                    \
+    if (BP) {                                                                                        \
+      if (c.u == 8) launch_tile_bp<NV, WT, 2>(c, ws, L, nsys, g, par, st, e);                        \
+      else launch_tile_bp<NV, WT, 1>(c, ws, L, nsys, g, par, st, e);                                 \
+    } else {                                                                                         \
+      if (c.u == 8) launch_band<NV, WT, 2>(c, ws, L, nsys, g, par, st, e);                           \
+      else launch_band<NV, WT, 1>(c, ws, L, nsys, g, par, st, e);                                    \
+    }                                                                                                \
+    return;                                                                                          \
+  }
+    SS_STAGED(2, SS_F32)
+    SS_STAGED(2, SS_BF16)
+    SS_STAGED(2, SS_F16)
+    SS_STAGED(1, SS_F32)
+    SS_STAGED(1, SS_BF16)
+    SS_STAGED(1, SS_F16)
+#undef SS_STAGED
+    return;
+  }
   const Params* prm = reinterpret_cast<const Params*>(ws + L.params);
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
 // single 16-bit values are rejected for the interleaved form by validate()
@@ -697,10 +1426,12 @@ struct GraphKey {
   int nsys;
   uint32_t fpb, bpb;
   int nv, wt, rpw, cpw, xcd, u, pers, ch, count;
+  int stg, blg, tlg, spt;
+  uint32_t bandb;
   bool operator<(const GraphKey& o) const {
-    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, pers, ch, count) <
+    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, pers, ch, count, stg, blg, tlg, spt, bandb) <
            std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.u, o.pers, o.ch,
-                    o.count);
+                    o.count, o.stg, o.blg, o.tlg, o.spt, o.bandb);
   }
 };
 
@@ -768,7 +1499,7 @@ extern "C" ss_status ss_sart_workspace_bytes(const ss_system* sys, int32_t nsys,
   clear_error();
   if (!bytes) return fail(SS_E_ARG, "ss_sart_workspace_bytes: NULL bytes");
   if (ss_status s = validate(sys, nsys, opts, "ss_sart_workspace_bytes")) return s;
-  *bytes = make_layout(sys, nsys, opts->chunked).total;
+  *bytes = make_layout(sys, nsys, opts).total;
   return SS_OK;
 }
 
@@ -780,7 +1511,8 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   if (!f || !workspace) return fail(SS_E_ARG, "ss_sart_solve: NULL images or workspace");
   for (int s = 0; s < nsys; ++s)
     if (!f[s] || (res_hist && !res_hist[s])) return fail(SS_E_ARG, "ss_sart_solve: NULL image %d", s);
-  const Layout L = make_layout(sys, nsys, opts->chunked);
+  if (ss_status s = check_images(sys, nsys, f, opts, "ss_sart_solve")) return s;
+  const Layout L = make_layout(sys, nsys, opts);
   if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_solve: workspace needs %zu bytes", L.total);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
@@ -798,7 +1530,7 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
     int dev = 0;
     SS_HIP_TRY(hipGetDevice(&dev));
     const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, c.pers, c.ch,
-                       chunk};
+                       chunk, c.stg, c.blg, c.tlg, c.spt, g.band_blocks};
     if (ss_status s = get_graph(key, c, ws, L, g, &exec)) return s;
   }
   std::vector<SysState> hs;
@@ -828,6 +1560,75 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   return result;
 }
 
+extern "C" ss_status ss_sart_time_phases(const ss_system* sys, int32_t nsys, float* const* f,
+                                         const ss_sart_opts* opts, int32_t reps, double* ms, void* workspace,
+                                         size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (ss_status s = validate(sys, nsys, opts, "ss_sart_time_phases")) return s;
+  if (!f || !workspace || !ms || reps <= 0) return fail(SS_E_ARG, "ss_sart_time_phases: bad argument");
+  if (ss_status s = check_images(sys, nsys, f, opts, "ss_sart_time_phases")) return s;
+  const Layout L = make_layout(sys, nsys, opts);
+  if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_time_phases: workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const Cfg c = choose_cfg(sys, nsys, opts);
+  Params prm{opts->lambda, (1 << 30), -1.0, opts->nonneg};
+  Grids g{};
+  if (ss_status s = setup(sys, nsys, f, nullptr, prm, c, L, ws, &g, 0, st)) return s;
+  const bool two = (c.stg & 1) != 0;
+  std::vector<hipEvent_t> ev(6 * static_cast<size_t>(reps));
+  for (auto& e : ev) SS_HIP_TRY(hipEventCreate(&e));
+  launch_kernel<false>(c, ws, L, nsys, g, 0, st);  // warm caches and code
+  launch_kernel<true>(c, ws, L, nsys, g, 0, st);
+  for (int r = 0; r < reps; ++r) {
+    const int par = (r + 1) & 1;
+    hipEvent_t* e = &ev[6 * static_cast<size_t>(r)];
+    launch_kernel<false>(c, ws, L, nsys, g, par, st, two ? Stamp{e[0], e[3], e[1], e[2]} : Stamp{e[0], e[1]});
+    launch_kernel<true>(c, ws, L, nsys, g, par, st, Stamp{e[4], e[5]});
+  }
+  (void)hipEventSynchronize(ev.back());
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int r = 0; r < reps; ++r) {
+    hipEvent_t* e = &ev[6 * static_cast<size_t>(r)];
+    float a = 0.f, b = 0.f, cc = 0.f;
+    (void)hipEventElapsedTime(&a, e[0], e[1]);
+    if (two) (void)hipEventElapsedTime(&b, e[2], e[3]);
+    (void)hipEventElapsedTime(&cc, e[4], e[5]);
+    t[0] += a;
+    t[1] += b;
+    t[2] += cc;
+  }
+  const hipError_t err = hipGetLastError();
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (err != hipSuccess) return fail(SS_E_HIP, "ss_sart_time_phases: %s", hipGetErrorString(err));
+  for (int k = 0; k < 3; ++k) ms[k] = t[k] / reps;
+  return SS_OK;
+}
+
+extern "C" ss_status ss_sart_staged_info(const ss_system* sys, int32_t nsys, float* const* f,
+                                         const ss_sart_opts* opts, int64_t* info, void* workspace,
+                                         size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (ss_status s = validate(sys, nsys, opts, "ss_sart_staged_info")) return s;
+  if (!info || !workspace || !opts->staged) return fail(SS_E_ARG, "ss_sart_staged_info: bad argument");
+  if (ss_status s = check_images(sys, nsys, f, opts, "ss_sart_staged_info")) return s;
+  const Layout L = make_layout(sys, nsys, opts);
+  if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_staged_info: workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const Cfg c = choose_cfg(sys, nsys, opts);
+  Params prm{opts->lambda, 0, -1.0, opts->nonneg};
+  Grids g{};
+  if (ss_status s = setup(sys, nsys, f, nullptr, prm, c, L, ws, &g, 0, st)) return s;
+  int64_t* dinfo = reinterpret_cast<int64_t*>(ws + L.info);
+  k_staged_info<<<1, 64, 0, st>>>(reinterpret_cast<const SysDesc*>(ws + L.table), nsys, c.stg,
+                                  reinterpret_cast<const int32_t*>(ws + L.ntiles), dinfo);
+  SS_HIP_TRY(hipGetLastError());
+  SS_HIP_TRY(hipMemcpyAsync(info, dinfo, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SS_HIP_TRY(hipStreamSynchronize(st));
+  return SS_OK;
+}
+
 extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, float* const* f,
                                           const ss_sart_opts* opts, int32_t reps, double* fp_ms, double* bp_ms,
                                           void* workspace, size_t workspace_bytes, void* stream) {
@@ -835,7 +1636,8 @@ extern "C" ss_status ss_sart_time_kernels(const ss_system* sys, int32_t nsys, fl
   if (ss_status s = validate(sys, nsys, opts, "ss_sart_time_kernels")) return s;
   if (!f || !workspace || !fp_ms || !bp_ms || reps <= 0)
     return fail(SS_E_ARG, "ss_sart_time_kernels: bad argument");
-  const Layout L = make_layout(sys, nsys, opts->chunked);
+  if (ss_status s = check_images(sys, nsys, f, opts, "ss_sart_time_kernels")) return s;
+  const Layout L = make_layout(sys, nsys, opts);
   if (workspace_bytes < L.total) return fail(SS_E_WORKSPACE, "ss_sart_time_kernels: workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
@@ -886,7 +1688,7 @@ ss_status time_copies(const ss_system* sys, int nsys, float* const* f, const ss_
     for (int k = 0; k < 3 && result == SS_OK; ++k) {
       ss_sart_opts o = *opts;
       o.chunked = forms[k];
-      const Layout L = make_layout(sys, nsys, o.chunked);
+      const Layout L = make_layout(sys, nsys, &o);
       if (L.total > workspace_bytes) {
         result = fail(SS_E_WORKSPACE, "ss_sart_autotune: workspace too small");
         break;
@@ -964,7 +1766,7 @@ extern "C" ss_status ss_sart_autotune(const ss_system* sys, int32_t nsys, float*
   } else {
     ss_sart_opts o = *opts;
     o.chunked = 12;
-    if (validate(sys, nsys, &o, "ss_sart_autotune") == SS_OK && make_layout(sys, nsys, 12).total <= workspace_bytes) {
+    if (validate(sys, nsys, &o, "ss_sart_autotune") == SS_OK && make_layout(sys, nsys, &o).total <= workspace_bytes) {
       forms.push_back(12);
       // the copies are made once per solve: spread over its iterations
       if (ss_status s = time_copies(sys, nsys, f, opts, workspace, workspace_bytes, static_cast<hipStream_t>(stream),

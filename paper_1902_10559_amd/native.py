@@ -73,7 +73,8 @@ class SartOptsC(C.Structure):
                 ("rows_per_wave", C.c_int32), ("cols_per_wave", C.c_int32),
                 ("xcd_remap", C.c_int32), ("zero_start", C.c_int32),
                 ("unroll", C.c_int32), ("persistent", C.c_int32), ("chunked", C.c_int32),
-                ("nonneg", C.c_int32)]
+                ("nonneg", C.c_int32), ("staged", C.c_int32), ("band_width", C.c_int32),
+                ("tile_cols", C.c_int32), ("tile_segments", C.c_int32)]
 
 
 class SubsetsC(C.Structure):
@@ -107,6 +108,8 @@ _SIGNATURES = {
                                   C.c_void_p, C.c_size_t, C.c_void_p]),
     "ss_fold_size": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_int64), C.c_void_p]),
+    "ss_fold_size_batch": (C.c_int32, [C.POINTER(MatrixDevC), C.POINTER(C.c_void_p), C.c_int32, C.c_void_p,
+                                       C.c_size_t, C.POINTER(C.c_int64), C.c_void_p]),
     "ss_fold": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p,
                             C.c_size_t, C.c_void_p]),
     "ss_fold_noalloc": (C.c_int32, [C.POINTER(MatrixDevC), C.c_void_p, C.POINTER(SystemC), C.c_void_p]),
@@ -120,6 +123,12 @@ _SIGNATURES = {
                                          C.POINTER(SartOptsC), C.c_int32,
                                          C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ss_sart_time_phases": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(C.c_void_p),
+                                        C.POINTER(SartOptsC), C.c_int32, C.POINTER(C.c_double),
+                                        C.c_void_p, C.c_size_t, C.c_void_p]),
+    "ss_sart_staged_info": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(C.c_void_p),
+                                        C.POINTER(SartOptsC), C.POINTER(C.c_int64), C.c_void_p, C.c_size_t,
+                                        C.c_void_p]),
     "ss_sart_autotune": (C.c_int32, [C.POINTER(SystemC), C.c_int32, C.POINTER(C.c_void_p),
                                      C.POINTER(SartOptsC), C.c_void_p, C.c_size_t, C.c_void_p]),
     "ss_recombine": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
@@ -130,8 +139,12 @@ _SIGNATURES = {
                                        C.c_void_p]),
     "ss_nn_conv3x3": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                   C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+    "ss_nn_wgrad_workspace_bytes": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                                C.POINTER(C.c_size_t)]),
     "ss_nn_conv3x3_wgrad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
-                                        C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+                                        C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_size_t, C.c_void_p]),
+    "ss_nn_mse_workspace_bytes": (C.c_int32, [C.c_int64, C.POINTER(C.c_size_t)]),
     "ss_nn_relu_mask": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ss_nn_pool2": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                 C.c_void_p]),
@@ -142,7 +155,7 @@ _SIGNATURES = {
     "ss_nn_from_slice": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "ss_nn_residual_mse": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
-                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "ss_nn_to_bf16": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ss_nn_adam": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
                                C.c_float, C.c_float, C.c_float, C.c_int32, C.c_void_p]),
@@ -428,6 +441,39 @@ class FoldBatch:
         _check(lib().ss_fold_batch(self._A, self._p, self._S, self.count, _ptr(self.ws), self.ws_bytes,
                                    _stream(self.ws.device)))
 
+    def sizes(self):
+        """ss_fold_size_batch on the same matrices: validates every matrix
+        (and p) and returns the shared-pattern sizes (synchronises once)."""
+        out = (C.c_int64 * self.count)()
+        _check(lib().ss_fold_size_batch(self._A, self._p, self.count, _ptr(self.ws), self.ws_bytes, out,
+                                        _stream(self.ws.device)))
+        return list(out)
+
+
+class FoldCheckBatch:
+    """ss_fold_size_batch over fixed lists of matrices and right-hand sides
+    (entries of ps may be None): call it to validate all of them and get
+    the shared-pattern sizes."""
+
+    def __init__(self, As, ps=None):
+        import torch
+        self.count = len(As)
+        assert self.count > 0
+        ps = list(ps) if ps is not None else [None] * self.count
+        self._keep = (list(As), ps)
+        self._A = (MatrixDevC * self.count)(*[A.c() for A in As])
+        self._p = (C.c_void_p * self.count)(*[_ptr(p) for p in ps])
+        nb = C.c_size_t()
+        _check(lib().ss_fold_batch_workspace_bytes(self._A, self.count, C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=As[0].val.device)
+
+    def __call__(self):
+        out = (C.c_int64 * self.count)()
+        _check(lib().ss_fold_size_batch(self._A, self._p, self.count, _ptr(self.ws), self.ws_bytes, out,
+                                        _stream(self.ws.device)))
+        return list(out)
+
 
 def unsplit(A: DeviceMatrix, p, wdtype: str = "f32") -> System:
     """ss_unsplit: A itself as a single system (the unsplit baseline)."""
@@ -461,12 +507,16 @@ class SartOptions:
     persistent: int = 0
     chunked: int = 0
     nonneg: bool = False
+    staged: int = 0
+    band_width: int = 0
+    tile_cols: int = 0
+    tile_segments: int = 0
 
     def c(self) -> SartOptsC:
         return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
                          int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
                          self.xcd_remap, int(self.zero_start), self.unroll, self.persistent, self.chunked,
-                         int(self.nonneg))
+                         int(self.nonneg), self.staged, self.band_width, self.tile_cols, self.tile_segments)
 
 
 class Solver:
@@ -529,6 +579,26 @@ class Solver:
                                           reps, C.byref(fp), C.byref(bp), _ptr(self.ws),
                                           self.ws_bytes, _stream(self.ws.device)))
         return fp.value, bp.value
+
+    def time_phases(self, f, reps: int = 20):
+        """ss_sart_time_phases: mean ms of (forward kernel, staged residual
+        kernel or 0, back projection)."""
+        ms = (C.c_double * 3)()
+        self._reserve(self.opts)
+        oc = self.opts.c()
+        _check(lib().ss_sart_time_phases(self._arr, len(self.systems), self._imgs(f), C.byref(oc), reps, ms,
+                                         _ptr(self.ws), self.ws_bytes, _stream(self.ws.device)))
+        return tuple(ms)
+
+    def staged_info(self, f):
+        """ss_sart_staged_info: [forward segments, forward work tiles,
+        back-projection tiles, of those staged, rows they stage]."""
+        info = (C.c_int64 * 5)()
+        self._reserve(self.opts)
+        oc = self.opts.c()
+        _check(lib().ss_sart_staged_info(self._arr, len(self.systems), self._imgs(f), C.byref(oc), info,
+                                         _ptr(self.ws), self.ws_bytes, _stream(self.ws.device)))
+        return list(info)
 
     def autotune(self, f):
         # room for the interleaved candidates, where the systems allow them
@@ -689,9 +759,32 @@ def nn_conv3x3(x, N, H, W, C, w, bias, O, relu, y, y_f32=False):
                                int(y_f32), _stream(x.device)))
 
 
-def nn_conv3x3_wgrad(x, gy, N, H, W, C, O, gw, gb):
-    _check(lib().ss_nn_conv3x3_wgrad(_ptr(x), _ptr(gy), N, H, W, C, O, _ptr(gw), _ptr(gb),
-                                     _stream(x.device)))
+def nn_wgrad_workspace_bytes(N, H, W, C, O) -> int:
+    nb = C.c_size_t()
+    _check(lib().ss_nn_wgrad_workspace_bytes(N, H, W, C, O, C.byref(nb)))
+    return nb.value
+
+
+def nn_mse_workspace_bytes(n) -> int:
+    nb = C.c_size_t()
+    _check(lib().ss_nn_mse_workspace_bytes(n, C.byref(nb)))
+    return nb.value
+
+
+def _scratch(nbytes, device, ws=None):
+    """A caller-given workspace, or a fresh one of nbytes."""
+    import torch
+    if ws is not None:
+        assert ws.numel() * ws.element_size() >= nbytes
+        return ws
+    return torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
+
+
+def nn_conv3x3_wgrad(x, gy, N, H, W, C, O, gw, gb, ws=None):
+    need = nn_wgrad_workspace_bytes(N, H, W, C, O)
+    w = _scratch(need, x.device, ws)
+    _check(lib().ss_nn_conv3x3_wgrad(_ptr(x), _ptr(gy), N, H, W, C, O, _ptr(gw), _ptr(gb), _ptr(w),
+                                     w.numel() * w.element_size(), _stream(x.device)))
 
 
 def nn_relu_mask(g, y, out):
@@ -715,9 +808,11 @@ def nn_from_slice(gy, N, Hx, Wx, C, up, Ctot, coff, gx, accumulate=False):
                                   int(accumulate), _stream(gy.device)))
 
 
-def nn_residual_mse(r, x, target, out, g=None, loss=None):
+def nn_residual_mse(r, x, target, out, g=None, loss=None, ws=None):
+    w = _scratch(nn_mse_workspace_bytes(r.numel()), r.device, ws) if loss is not None else None
     _check(lib().ss_nn_residual_mse(_ptr(r), _ptr(x), _ptr(target), r.numel(), _ptr(out), _ptr(g),
-                                    _ptr(loss), _stream(r.device)))
+                                    _ptr(loss), _ptr(w), w.numel() * w.element_size() if w is not None else 0,
+                                    _stream(r.device)))
 
 
 def nn_to_bf16(x, y):

@@ -1,7 +1,8 @@
 """The learned SART initialiser's network: a 4-level convolutional
-encoder-decoder (channels 16, 32, 64, 128; two 3x3 convolutions per level,
-2x2 average pooling down, nearest 2x upsampling and skip concatenation up)
-that predicts a correction to an early split-SART image: out = x + net(x).
+encoder-decoder (channels 16, 32, 64, 128; two 3x3 convolutions per level
+and five at the 128-channel bottom, about 0.93 M parameters; 2x2 average
+pooling down, nearest 2x upsampling and skip concatenation up) that
+predicts a correction to an early split-SART image: out = x + net(x).
 
 Every operation is a call into libssart (BF16 matrix-core convolutions,
 FP32 gradients and Adam); this module only allocates buffers and sequences
@@ -22,12 +23,18 @@ LAYERS = [
     ("e1a", 1, 16, True), ("e1b", 16, 16, True),
     ("e2a", 16, 32, True), ("e2b", 32, 32, True),
     ("e3a", 32, 64, True), ("e3b", 64, 64, True),
-    ("ba", 64, 128, True), ("bb", 128, 128, True),
+    ("ba", 64, 128, True), ("bb", 128, 128, True), ("bc", 128, 128, True), ("bd", 128, 128, True),
+    ("be", 128, 128, True),
     ("d3a", 192, 64, True), ("d3b", 64, 64, True),
     ("d2a", 96, 32, True), ("d2b", 32, 32, True),
     ("d1a", 48, 16, True), ("d1b", 16, 16, True),
     ("out", 16, 1, False),
 ]
+
+
+# resolution level (0 = full, 3 = 1/8) of each layer
+LEVEL = {"e1a": 0, "e1b": 0, "e2a": 1, "e2b": 1, "e3a": 2, "e3b": 2, "ba": 3, "bb": 3, "bc": 3, "bd": 3,
+         "be": 3, "d3a": 2, "d3b": 2, "d2a": 1, "d2b": 1, "d1a": 0, "d1b": 0, "out": 0}
 
 
 def _r8(c):
@@ -110,7 +117,7 @@ class UNet:
             x16=a16(0, 1), e1a=a16(0, 16), e1=a16(0, 16), p1=a16(1, 16),
             e2a=a16(1, 32), e2=a16(1, 32), p2=a16(2, 32),
             e3a=a16(2, 64), e3=a16(2, 64), p3=a16(3, 64),
-            ba=a16(3, 128), bb=a16(3, 128),
+            ba=a16(3, 128), bb=a16(3, 128), bc=a16(3, 128), bd=a16(3, 128), be=a16(3, 128),
             c3=a16(2, 192), d3a=a16(2, 64), d3=a16(2, 64),
             c2=a16(1, 96), d2a=a16(1, 32), d2=a16(1, 32),
             c1=a16(0, 48), d1a=a16(0, 16), d1=a16(0, 16),
@@ -121,10 +128,18 @@ class UNet:
             g_p1=a32(1, 16),
             g_d3=a32(2, 64), g_d3a=a32(2, 64), g_c3=a32(2, 192), g_e3=a32(2, 64), g_e3a=a32(2, 64),
             g_p2=a32(2, 32),
+            g_be=a32(3, 128), g_bd=a32(3, 128), g_bc=a32(3, 128),
             g_bb=a32(3, 128), g_ba=a32(3, 128), g_p3=a32(3, 64),
             gy=torch.empty(N * H * W * 48, dtype=torch.int16, device=dev),
             loss=torch.zeros(1, dtype=torch.float64, device=dev),
         )
+        # scratch of the fixed-order gradient and loss sums: the largest any
+        # layer needs
+        need = native.nn_mse_workspace_bytes(N * H * W)
+        for name, C, O, _ in LAYERS:
+            lvl = LEVEL[name]
+            need = max(need, native.nn_wgrad_workspace_bytes(N, H >> lvl, W >> lvl, C, O))
+        B["ws"] = torch.empty(need, dtype=torch.uint8, device=dev)
         self._bufs[N] = B
         return B
 
@@ -152,7 +167,10 @@ class UNet:
         native.nn_pool2(B["e3"], N, h3, w3, 64, B["p3"])
         self._conv("ba", B["p3"], N, 3, B["ba"])
         self._conv("bb", B["ba"], N, 3, B["bb"])
-        native.nn_to_slice(B["bb"], N, h3, w3, 128, True, B["c3"], 192, 0)
+        self._conv("bc", B["bb"], N, 3, B["bc"])
+        self._conv("bd", B["bc"], N, 3, B["bd"])
+        self._conv("be", B["bd"], N, 3, B["be"])
+        native.nn_to_slice(B["be"], N, h3, w3, 128, True, B["c3"], 192, 0)
         native.nn_to_slice(B["e3"], N, h3, w3, 64, False, B["c3"], 192, 128)
         self._conv("d3a", B["c3"], N, 2, B["d3a"])
         self._conv("d3b", B["d3a"], N, 2, B["d3"])
@@ -168,7 +186,7 @@ class UNet:
         if target is not None:
             B["loss"].zero_()
         native.nn_residual_mse(B["r"], x32, target, B["out"], B["gout"] if want_grad else None,
-                               B["loss"] if target is not None else None)
+                               B["loss"] if target is not None else None, ws=B["ws"])
         return B["out"]
 
     # ---------------------------------------------------------- backward
@@ -181,7 +199,7 @@ class UNet:
         h, w = self.H >> level, self.W >> level
         gy = B["gy"][: N * h * w * L.O]
         native.nn_relu_mask(g_out, y_out if L.relu else None, gy)
-        native.nn_conv3x3_wgrad(x_in, gy, N, h, w, L.C, L.O, L.gw, L.gb)
+        native.nn_conv3x3_wgrad(x_in, gy, N, h, w, L.C, L.O, L.gw, L.gb, ws=B["ws"])
         if g_in is not None:
             native.nn_conv3x3(gy, N, h, w, L.O, L.wb, None, L.C, False, g_in, True)
 
@@ -201,8 +219,11 @@ class UNet:
         native.nn_from_slice(B["g_c2"], N, h2, w2, 32, False, 96, 64, B["g_e2"])
         self._back("d3b", B["d3a"], N, 2, B["g_d3"], B["d3"], B["g_d3a"])
         self._back("d3a", B["c3"], N, 2, B["g_d3a"], B["d3a"], B["g_c3"])
-        native.nn_from_slice(B["g_c3"], N, h4, w4, 128, True, 192, 0, B["g_bb"])
+        native.nn_from_slice(B["g_c3"], N, h4, w4, 128, True, 192, 0, B["g_be"])
         native.nn_from_slice(B["g_c3"], N, h3, w3, 64, False, 192, 128, B["g_e3"])
+        self._back("be", B["bd"], N, 3, B["g_be"], B["be"], B["g_bd"])
+        self._back("bd", B["bc"], N, 3, B["g_bd"], B["bd"], B["g_bc"])
+        self._back("bc", B["bb"], N, 3, B["g_bc"], B["bc"], B["g_bb"])
         self._back("bb", B["ba"], N, 3, B["g_bb"], B["bb"], B["g_ba"])
         self._back("ba", B["p3"], N, 3, B["g_ba"], B["ba"], B["g_p3"])
         native.nn_pool2_grad(B["g_p3"], N, h3, w3, 64, B["g_e3"], accumulate=True)

@@ -291,3 +291,32 @@ def test_fold_writes_interleaved_lines(rl, cl):
             v0 = to_np(getattr(S0, val)).reshape(-1).view(np.uint64)[:nnz]
             v1 = to_np(getattr(S1, val)).reshape(-1).view(np.uint64)[:nnz]
             assert np.array_equal(v1[pos], v0)
+
+
+def test_batched_validation_equals_single_calls_and_names_the_bad_matrix():
+    """ss_fold_size_batch gives each matrix the size ss_fold_size gives it,
+    and a batch holding one matrix that violates eq. (2) fails with that
+    error, naming that matrix."""
+    import torch
+    from gpu_util import host_matrix
+    banner("batched validation")
+    probs = [problem(1), random_problem(61, 1002, 514, 0.05), random_problem(62, 40, 30, 0.2),
+             random_problem(63, 2, 2, 1.0)]
+    As = [device(pr.A) for pr in probs]
+    ps = [torch.from_numpy(np.ascontiguousarray(pr.p, np.float32)).cuda() for pr in probs]
+    sizes = native.FoldCheckBatch(As, ps)()
+    assert sizes == [native.fold_size(A, p) for A, p in zip(As, ps)]
+    assert sizes == [oracle_fold32(pr.A).nnz for pr in probs]
+    assert native.FoldCheckBatch(As, None)() == sizes
+    h = host_matrix(probs[2].A)
+    h.val = h.val.copy()
+    h.val[3] = np.nextafter(h.val[3], np.float32(10))
+    bad = As[:2] + [native.to_device(h, "cuda")] + As[3:]
+    with pytest.raises(native.SSError) as e:
+        native.FoldCheckBatch(bad, ps)()
+    assert e.value.code == -3 and "matrix 2" in str(e.value)
+    p_bad = [p.clone() for p in ps]
+    p_bad[1][5] = float("nan")
+    with pytest.raises(native.SSError) as e:
+        native.FoldCheckBatch(As, p_bad)()
+    assert e.value.code == -5 and "matrix 1" in str(e.value)

@@ -1,0 +1,175 @@
+"""The whole learned-initialiser network against a composition of the
+oracle's layers (oracle/nn.py), at a small size (2 images of 32 x 32).
+
+Every layer is checked on the library's own stored input (the output of the
+layers that feed it, as the oracle's wiring says they should), so the
+comparison isolates FP32 accumulation as in the per-layer tests, and any
+mistake in the network's sequencing shows: a wrong skip-concatenation
+offset or source, pooling or upsampling applied to the wrong map, a
+gradient routed to the wrong buffer or not accumulated.  Bars:
+* forward activations (BF16): within 2^-8 of the FP64 value of the same
+  layer on the same BF16 inputs (BF16 rounding is 2^-9 relative; FP32
+  accumulation adds ~1e-7), plus 1e-6 of the layer's largest value;
+* pooled maps, concatenations and the residual output: exact;
+* the output layer (FP32), the loss, every layer's weight and bias gradient
+  and every input gradient: 1e-5 of the largest value (FP32 accumulation of
+  the same BF16 products), routing sums 1e-6;
+* two backward passes from the same state: bitwise equal gradients."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, to_np
+from oracle import nn as ON
+from paper_1902_10559_amd import unet
+
+N, H, W = 2, 32, 32
+
+
+def test_network_has_about_a_million_parameters():
+    n = sum(O * 9 * C + O for _, C, O, _ in unet.LAYERS)
+    assert 0.9e6 <= n <= 1.1e6, n
+
+
+def _bf16(a):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).clone(), t.float().numpy().astype(np.float64)
+
+
+def _bits_to_f64(t, shape):
+    import torch
+    return t.view(torch.bfloat16).float().cpu().numpy().astype(np.float64).reshape(shape)
+
+
+def _rel(got, want):
+    return float(np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-30))
+
+
+@pytest.fixture(scope="module")
+def run():
+    import torch
+    banner("unet end to end: forward + backward")
+    net = unet.UNet(H, W, seed=3)
+    rng = np.random.default_rng(11)
+    p = net.params.cpu().numpy()
+    # the output layer starts at zero: give it weights so gradients flow back
+    off = sum(O * 9 * C + O for name, C, O, _ in unet.LAYERS if name != "out")
+    p[off:] = rng.standard_normal(p.size - off).astype(np.float32) * 0.2
+    net.load_params(p)
+    x = rng.uniform(0, 1, (N, H, W, 1)).astype(np.float32)
+    t = (x + 0.1 * rng.standard_normal(x.shape)).astype(np.float32)
+    x32 = torch.from_numpy(x).cuda()
+    x16, _ = _bf16(x)
+    x16 = x16.cuda()
+    tgt = torch.from_numpy(t).cuda()
+    net.grads.zero_()
+    net.forward(x32, x16.view(-1), N, tgt, want_grad=True)
+    net.backward(N)
+    torch.cuda.synchronize()
+    grads1 = net.grads.clone()
+    # a second pass from the same state: the same gradients, bit for bit
+    net.grads.zero_()
+    net.forward(x32, x16.view(-1), N, tgt, want_grad=True)
+    net.backward(N)
+    torch.cuda.synchronize()
+    assert torch.equal(grads1.view(torch.int32), net.grads.view(torch.int32))
+    return net, x, t
+
+
+def _shape(level, C):
+    return (N, H >> level, W >> level, C)
+
+
+def _act(net, key, level, C):
+    return _bits_to_f64(net._bufs[N][key], _shape(level, C))
+
+
+def _f32(net, key, level, C):
+    return to_np(net._bufs[N][key]).astype(np.float64).reshape(_shape(level, C))
+
+
+def _wb(net, name):
+    """The layer's weights as the kernels use them (BF16) and its bias."""
+    L = net.layers[name]
+    _, wr = _bf16(to_np(L.w))
+    return wr, to_np(L.b).astype(np.float64)
+
+
+# (layer, input buffer, output buffer, level, gradient of the output, gradient of the input)
+CHAIN = [("e1a", "x16", "e1a", 0, "g_e1a", None), ("e1b", "e1a", "e1", 0, "g_e1", "g_e1a"),
+         ("e2a", "p1", "e2a", 1, "g_e2a", "g_p1"), ("e2b", "e2a", "e2", 1, "g_e2", "g_e2a"),
+         ("e3a", "p2", "e3a", 2, "g_e3a", "g_p2"), ("e3b", "e3a", "e3", 2, "g_e3", "g_e3a"),
+         ("ba", "p3", "ba", 3, "g_ba", "g_p3"), ("bb", "ba", "bb", 3, "g_bb", "g_ba"),
+         ("bc", "bb", "bc", 3, "g_bc", "g_bb"), ("bd", "bc", "bd", 3, "g_bd", "g_bc"),
+         ("be", "bd", "be", 3, "g_be", "g_bd"),
+         ("d3a", "c3", "d3a", 2, "g_d3a", "g_c3"), ("d3b", "d3a", "d3", 2, "g_d3", "g_d3a"),
+         ("d2a", "c2", "d2a", 1, "g_d2a", "g_c2"), ("d2b", "d2a", "d2", 1, "g_d2", "g_d2a"),
+         ("d1a", "c1", "d1a", 0, "g_d1a", "g_c1"), ("d1b", "d1a", "d1", 0, "g_d1", "g_d1a"),
+         ("out", "d1", "r", 0, "gout", "g_d1")]
+
+
+@pytest.mark.gpu
+def test_forward_layers_pools_and_skips_match_the_oracle(run):
+    net, x, t = run
+    dims = {name: (C, O) for name, C, O, _ in unet.LAYERS}
+    for name, src, dst, lvl, _, _ in CHAIN:
+        C, O = dims[name]
+        xin = _act(net, src, lvl, C)
+        wr, b = _wb(net, name)
+        ref = ON.conv3x3(xin, wr, b)
+        if name == "out":
+            got = _f32(net, dst, lvl, O)
+            assert _rel(got, ref) <= 1e-5, name
+            continue
+        ref = ON.relu(ref)
+        got = _act(net, dst, lvl, O)
+        err = np.abs(got - ref) - (2.0 ** -8) * np.abs(ref) - 1e-6 * np.max(np.abs(ref))
+        assert err.max() <= 0.0, (name, float(err.max()))
+    # pooling: exact BF16 rounding of the FP32 average of four BF16 values
+    for src, dst, lvl, C in (("e1", "p1", 0, 16), ("e2", "p2", 1, 32), ("e3", "p3", 2, 64)):
+        _, want = _bf16(ON.avgpool2(_act(net, src, lvl, C)))
+        assert np.array_equal(_act(net, dst, lvl + 1, C), want), dst
+    # skip concatenations: [upsampled deeper map, encoder map of the level]
+    for cat, deep, skip, lvl, Cd, Cs in (("c3", "be", "e3", 2, 128, 64), ("c2", "d3", "e2", 1, 64, 32),
+                                         ("c1", "d2", "e1", 0, 32, 16)):
+        c = _act(net, cat, lvl, Cd + Cs)
+        assert np.array_equal(c[..., :Cd], ON.upsample2(_act(net, deep, lvl + 1, Cd))), cat
+        assert np.array_equal(c[..., Cd:], _act(net, skip, lvl, Cs)), cat
+    # the network's output is the input plus the correction; the loss
+    r = _f32(net, "r", 0, 1)
+    out = _f32(net, "out", 0, 1)
+    assert np.array_equal(out.astype(np.float32), (x + r.astype(np.float32)).astype(np.float32))
+    lw, gw = ON.mse(out, t.astype(np.float64))
+    assert abs(net._bufs[N]["loss"].item() - lw) <= 1e-6 * lw
+    assert _rel(_f32(net, "gout", 0, 1), gw) <= 1e-6
+
+
+@pytest.mark.gpu
+def test_backward_gradients_and_routing_match_the_oracle(run):
+    import torch
+    net, _, _ = run
+    dims = {name: (C, O) for name, C, O, _ in unet.LAYERS}
+    relu = {name: r for name, _, _, r in unet.LAYERS}
+    for name, src, dst, lvl, gout, gin in CHAIN:
+        C, O = dims[name]
+        xin = _act(net, src, lvl, C)
+        g = _f32(net, gout, lvl, O)
+        if relu[name]:
+            g = ON.relu_grad(_act(net, dst, lvl, O), g)
+        _, gy = _bf16(g)   # the kernels take the masked gradient in BF16
+        wr, _ = _bf16(to_np(net.layers[name].w))
+        want_w, want_b = ON.conv3x3_grad_weight(xin, gy)
+        L = net.layers[name]
+        assert _rel(to_np(L.gw).astype(np.float64).reshape(O, 3, 3, C), want_w) <= 1e-5, name
+        assert _rel(to_np(L.gb).astype(np.float64), want_b) <= 1e-5, name
+        if gin is not None:
+            assert _rel(_f32(net, gin, lvl, C), ON.conv3x3_grad_input(gy, wr)) <= 1e-5, name
+    # routing of the concatenations' and the pools' gradients
+    for cat, deep, skip, pool, lvl, Cd, Cs in (("g_c3", "g_be", "g_e3", "g_p3", 2, 128, 64),
+                                               ("g_c2", "g_d3", "g_e2", "g_p2", 1, 64, 32),
+                                               ("g_c1", "g_d2", "g_e1", "g_p1", 0, 32, 16)):
+        gc = _f32(net, cat, lvl, Cd + Cs)
+        assert _rel(_f32(net, deep, lvl + 1, Cd), ON.upsample2_grad(gc[..., :Cd])) <= 1e-6, deep
+        want = gc[..., Cd:] + ON.avgpool2_grad(_f32(net, pool, lvl + 1, Cs))
+        assert _rel(_f32(net, skip, lvl, Cs), want) <= 1e-6, skip
+    torch.cuda.synchronize()
