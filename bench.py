@@ -410,13 +410,13 @@ def staged_search(systems, base, scratch):
     tile width and columns per wavefront.  Returns (band, rpw), (tile, cpw)."""
     import dataclasses
     from paper_1902_10559_amd import native
-    fp_best, bp_best = ((4096, 4), 1e30), ((1024, 8), 1e30)
-    for band, rpw in ((4096, 4), (8192, 4), (4096, 8), (8192, 8)):
+    fp_best, bp_best = ((8192, 8), 1e30), ((512, 8), 1e30)
+    for band, rpw in ((8192, 8), (8192, 4), (4096, 8), (4096, 4)):
         o = dataclasses.replace(base, staged=1, band_width=band, rows_per_wave=rpw, unroll=8, chunked=0)
         ms = native.Solver(systems, o).time_phases(scratch, reps=10)
         if ms[0] + ms[1] < fp_best[1]:
             fp_best = ((band, rpw), ms[0] + ms[1])
-    for tile, cpw in ((1024, 8), (2048, 8), (1024, 16), (2048, 16)):
+    for tile, cpw in ((512, 8), (1024, 8), (256, 8), (512, 16)):
         o = dataclasses.replace(base, staged=2, tile_cols=tile, cols_per_wave=cpw, unroll=8, chunked=0)
         ms = native.Solver(systems, o).time_phases(scratch, reps=10)
         if ms[2] < bp_best[1]:
@@ -535,7 +535,13 @@ def dtype_record(args, slices, systems, opts, lanes, wdtype, iters, nnz_full, ti
             "roofline": roofline_of(kern, argparse.Namespace(**dict(vars(args), wdtype=wdtype)))}
 
 
-def workload_time_to_tol(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tol=1e-3, cap=20000):
+def workload_time_to_tol(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tols=(1e-2, 1e-3), cap=20000):
+    """workload_time_to_tol_one for each tolerance."""
+    return {f"{tol:g}": workload_time_to_tol_one(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tol, cap)
+            for tol in tols}
+
+
+def workload_time_to_tol_one(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tol, cap):
     """Iterations and time for every slice of the workload to reach rel_res
     <= tol from f0 = 0, each slice stopping on its own (the solve ends when
     all have, or at the cap): split vs unsplit in FP32 (the same k* per
@@ -705,15 +711,19 @@ def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
     from paper_1902_10559_amd import native
     S_count = slices[0].geom.K // 2
     subsets = [native.Subsets(S, S_count) for S in systems]
+    import dataclasses
     rep = {"subsets": S_count, "tol": tol, "cap": cap}
-    for name in ("sart", "os_sart"):
-        # the subset back projection picks its own lanes per column (1/S of
-        # each column per launch); the rest of the shape is the autotuned one
-        o = native.SartOptions(lam=lam, max_iter=cap, tol=tol, check_every=25, zero_start=True,
-                               rows_per_wave=opts.rows_per_wave,
-                               cols_per_wave=opts.cols_per_wave if name == "sart" else 0,
-                               xcd_remap=opts.xcd_remap, unroll=opts.unroll,
-                               chunked=opts.chunked if name == "sart" else os_forms(opts.chunked))
+    for name, every in (("sart", 0), ("os_sart", 1), ("os_sart_residual_every_4", 4)):
+        if name == "sart":   # the step's kernels (staged where chosen)
+            o = dataclasses.replace(opts, lam=lam, max_iter=cap, tol=tol, check_every=25, zero_start=True)
+        else:
+            # the subset back projection picks its own lanes per column (1/S
+            # of each column per launch); the rest of the shape is the
+            # autotuned unstaged one
+            o = native.SartOptions(lam=lam, max_iter=cap, tol=tol, check_every=24, zero_start=True,
+                                   rows_per_wave=opts.rows_per_wave if not opts.staged & 1 else 8,
+                                   cols_per_wave=0, xcd_remap=opts.xcd_remap, unroll=opts.unroll,
+                                   chunked=os_forms(opts.chunked), residual_every=every)
         slv = native.Solver(systems, o) if name == "sart" else native.OsSolver(systems, subsets, o)
         imgs = [S.new_image() for S in systems]
         slv.solve(imgs)                     # warm-up (graph capture)
@@ -726,6 +736,7 @@ def subsets_report(slices, systems, opts, dev, lam, tol=1e-2, cap=5000):
         rep[name] = {"median_steps": float(np.median(it)), "max_steps": int(max(it)), "reached": bool(st == 0),
                      "seconds": e0.elapsed_time(e1) * 1e-3}
     rep["speedup"] = rep["sart"]["seconds"] / rep["os_sart"]["seconds"]
+    rep["speedup_residual_every_4"] = rep["sart"]["seconds"] / rep["os_sart_residual_every_4"]["seconds"]
     return rep
 
 

@@ -379,6 +379,11 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *   tile_cols    columns per back-projection tile: a power of two from 64 to
  *                8192 (0 = 1024)
  *   tile_segments  segments per forward work tile, 64 .. 65536 (0 = 1024)
+ *   residual_every  ordered subsets only (ss_ossart_solve; here 0 or 1): the
+ *                residual of the pass-start image, a full forward sweep, is
+ *                taken on passes k with k % residual_every == 0 and at
+ *                k = max_iter only (0 or 1: every pass); tol is then tested
+ *                on those passes, and res_hist[k] is written for them only
  * rel_res(f^k) = ||p - A f^k|| / ||p||, from the halves as
  *   sqrt((||r1||^2 + ||r2||^2) / (||p1||^2 + ||p2||^2)), FP64. */
 typedef struct {
@@ -399,6 +404,7 @@ typedef struct {
   int32_t band_width;
   int32_t tile_cols;
   int32_t tile_segments;
+  int32_t residual_every;
 } ss_sart_opts;
 
 /* Workspace bytes for solving `nsys` systems together with these options
@@ -515,8 +521,9 @@ ss_status ss_ossart_workspace_bytes(const ss_system* sys, const ss_subsets* sub,
  * cols_per_wave up to 64 (a subset sees 1/S of each column); `persistent`
  * is ignored.  res_hist[s][k] = rel_res of the image after k passes, for
  * k = 0 .. passes[s] (max_iter + 1 doubles); passes (host, or NULL)
- * receives the passes applied.  Every pass evaluates the residual of its
- * starting image (one extra forward projection of every row).  Returns
+ * receives the passes applied.  A pass evaluates the residual of its
+ * starting image (one extra forward projection of every row) on every
+ * residual_every-th pass (every pass by default).  Returns
  * SS_NOT_CONVERGED as ss_sart_solve does. */
 ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub,
                           int32_t nsys, float* const* f,

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "device.h"
+#include "graph_cache.h"
 #include "internal.h"
 #include "lines.h"
 
@@ -79,7 +80,13 @@ struct OsParams {
   int32_t max_iter;
   double tol;
   int32_t nonneg;
+  int32_t res_every;  // the pass-start residual is taken when k % res_every == 0, and at k = max_iter
 };
+
+// Whether the residual of the image after k passes is evaluated.
+__device__ inline bool residual_pass(const OsParams* prm, int k) {
+  return k % prm->res_every == 0 || k >= prm->max_iter;
+}
 
 constexpr int kOsChunk = 16;
 struct OsChunk {
@@ -134,7 +141,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_setup(OsChunk ch, OsDesc* tab
 // RES: FP64 partial of |p - A f|^2 per block into `partials`; otherwise
 // z = W^-1 (p - A f).
 template <int WT, int RPW, int U, bool CH, bool RES>
-__global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsDesc* __restrict__ table,
+__global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsParams* __restrict__ prm,
+                                                      const OsDesc* __restrict__ table,
                                                       const int32_t* __restrict__ b2s, int nsys, uint32_t ntiles,
                                                       int xcd, int sub) {
   constexpr int L = kWave / RPW;
@@ -144,6 +152,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsDesc* __restrict__
   const int si = os_block<RES ? kAllRows : kSubRows>(table, b2s, nsys, ntiles, xcd, &local);
   const OsDesc& S = table[si];
   if (*gl(&S.st->stop)) return;
+  if (RES && !residual_pass(prm, *gl(&S.st->k))) return;
   const int64_t r0 = RES ? 0 : static_cast<int64_t>(sub) * S.R;
   const int64_t r1 = RES ? S.m : r0 + S.R;
   const int glane = lane_id() % L;
@@ -174,6 +183,11 @@ __global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsDesc* __restrict__
 __global__ __launch_bounds__(kOsThreads) void k_os_fin(const OsDesc* __restrict__ table, const OsParams* prm) {
   const OsDesc& S = table[blockIdx.x];
   if (*gl(&S.st->stop)) return;
+  if (!residual_pass(prm, *gl(&S.st->k))) {  // a pass without the residual
+    __syncthreads();
+    if (threadIdx.x == 0) S.st->k += 1;
+    return;
+  }
   __shared__ double red[kOsWPB];
   double acc = 0.0;
   for (int64_t t = threadIdx.x; t < S.nblk[kAllRows]; t += kOsThreads) acc += gl(S.partials)[t];
@@ -337,6 +351,7 @@ ss_status os_validate(const ss_system* sys, const ss_subsets* sub, int nsys, con
   if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
   if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
   if (o->staged != 0) return fail(SS_E_ARG, "%s: the staged forms are for ss_sart_* only (staged must be 0)", fn);
+  if (o->residual_every < 0) return fail(SS_E_ARG, "%s: residual_every must be >= 0", fn);
   return SS_OK;
 }
 
@@ -380,14 +395,14 @@ struct OsGrid {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <int WT, int U, bool CH, bool RES>
-void os_fp_rpw(int rpw, const OsDesc* t, const int32_t* b2s, int nsys, uint32_t nb, int xcd, int sub,
-               hipStream_t st) {
+void os_fp_rpw(int rpw, const OsParams* prm, const OsDesc* t, const int32_t* b2s, int nsys, uint32_t nb, int xcd,
+               int sub, hipStream_t st) {
   const dim3 g(nb), b(kOsThreads);
   switch (rpw) {
-    case 1: k_os_fp<WT, 1, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
-    case 2: k_os_fp<WT, 2, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
-    case 4: k_os_fp<WT, 4, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
-    default: k_os_fp<WT, 8, U, CH, RES><<<g, b, 0, st>>>(t, b2s, nsys, nb, xcd, sub); break;
+    case 1: k_os_fp<WT, 1, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 2: k_os_fp<WT, 2, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 4: k_os_fp<WT, 4, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    default: k_os_fp<WT, 8, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
   }
 }
 
@@ -411,12 +426,12 @@ template <int U>
 void os_pass(const OsCfg& c, const OsParams* prm, const OsDesc* t, const int32_t* const* b2s, int nsys, int S,
              const OsGrid& g, hipStream_t st) {
   const bool fch = c.ch & 1, bch = c.ch & 2;
-  if (fch) os_fp_rpw<SS_F32, U, true, true>(c.rpw, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
-  else os_fp_rpw<SS_F32, U, false, true>(c.rpw, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
+  if (fch) os_fp_rpw<SS_F32, U, true, true>(c.rpw, prm, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
+  else os_fp_rpw<SS_F32, U, false, true>(c.rpw, prm, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
   k_os_fin<<<nsys, kOsThreads, 0, st>>>(t, prm);
   for (int s = 0; s < S; ++s) {
-    if (fch) os_fp_rpw<SS_F32, U, true, false>(c.rpw, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
-    else os_fp_rpw<SS_F32, U, false, false>(c.rpw, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
+    if (fch) os_fp_rpw<SS_F32, U, true, false>(c.rpw, prm, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
+    else os_fp_rpw<SS_F32, U, false, false>(c.rpw, prm, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
     if (bch) os_bp_cpw<SS_F32, U, true>(c.cpw, prm, t, b2s[kCols], nsys, g.nb[kCols], c.xcd, s, st);
     else os_bp_cpw<SS_F32, U, false>(c.cpw, prm, t, b2s[kCols], nsys, g.nb[kCols], c.xcd, s, st);
   }
@@ -447,50 +462,9 @@ struct OsKey {
   }
 };
 
-struct OsGraphs {
-  std::mutex mu;
-  std::map<OsKey, hipGraphExec_t> execs;
-  std::map<int, hipStream_t> capture;
-};
-
-OsGraphs& os_graphs() {
-  static OsGraphs* g = new OsGraphs();  // lives until process exit
+GraphCache<OsKey>& os_graphs() {
+  static auto* g = new GraphCache<OsKey>(16);  // lives until process exit
   return *g;
-}
-
-ss_status os_graph(const OsKey& key, const OsCfg& c, const char* ws, const OsLayout& L, const OsGrid& g,
-                   hipGraphExec_t* out) {
-  OsGraphs& G = os_graphs();
-  std::lock_guard<std::mutex> lock(G.mu);
-  auto it = G.execs.find(key);
-  if (it != G.execs.end()) {
-    *out = it->second;
-    return SS_OK;
-  }
-  if (G.execs.size() >= 16) {
-    for (auto& kv : G.execs) (void)hipGraphExecDestroy(kv.second);
-    G.execs.clear();
-  }
-  hipStream_t cs;
-  auto sit = G.capture.find(key.device);
-  if (sit == G.capture.end()) {
-    SS_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    G.capture[key.device] = cs;
-  } else {
-    cs = sit->second;
-  }
-  SS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  os_passes(c, ws, L, key.nsys, key.S, g, key.count, cs);
-  hipGraph_t graph;
-  const hipError_t ce = hipStreamEndCapture(cs, &graph);
-  if (ce != hipSuccess) return fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-  hipGraphExec_t exec;
-  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (ie != hipSuccess) return fail(SS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
-  G.execs[key] = exec;
-  *out = exec;
-  return SS_OK;
 }
 
 }  // namespace
@@ -611,7 +585,8 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     ch.first = s0;
     ch.count = std::min(kOsChunk, nsys - s0);
     ch.zero_start = opts->zero_start;
-    ch.prm = OsParams{opts->lambda, opts->max_iter, opts->tol, opts->nonneg};
+    ch.prm = OsParams{opts->lambda, opts->max_iter, opts->tol, opts->nonneg,
+                      opts->residual_every > 0 ? opts->residual_every : 1};
     for (int i = 0; i < ch.count; ++i) ch.d[i] = ds[s0 + i];
     k_os_setup<<<ch.count, kOsThreads, 0, st>>>(ch, reinterpret_cast<OsDesc*>(ws + L.table),
                                                   reinterpret_cast<OsParams*>(ws + L.params));
@@ -626,12 +601,13 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
   const int64_t total = static_cast<int64_t>(opts->max_iter) + 1;
   const int chunk = opts->tol > 0.0 ? static_cast<int>(std::min<int64_t>(opts->check_every, total))
                                     : static_cast<int>(std::min<int64_t>(total, 32));
-  hipGraphExec_t exec = nullptr;
+  GraphEntry* graph = nullptr;
   if (opts->use_graph) {
     int dev = 0;
     SS_HIP_TRY(hipGetDevice(&dev));
     const OsKey key{dev, workspace, nsys, S, g.nb[0], g.nb[1], g.nb[2], c.rpw, c.cpw, c.xcd, c.u, c.ch, chunk};
-    if (ss_status s = os_graph(key, c, ws, L, g, &exec)) return s;
+    auto capture = [&](hipStream_t cs) { os_passes(c, ws, L, nsys, S, g, chunk, cs); };
+    if (ss_status s = os_graphs().acquire(key, dev, capture, &graph)) return s;
   }
   std::vector<OsState> hs(nsys);
   auto read_states = [&]() -> ss_status {
@@ -639,20 +615,25 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     SS_HIP_TRY(hipStreamSynchronize(st));
     return SS_OK;
   };
-  for (int64_t done = 0; done < total; done += chunk) {
-    if (exec) {
-      SS_HIP_TRY(hipGraphLaunch(exec, st));
+  ss_status loop = SS_OK;
+  for (int64_t done = 0; done < total && loop == SS_OK; done += chunk) {
+    if (graph) {
+      const hipError_t e = hipGraphLaunch(graph->exec, st);
+      if (e != hipSuccess) loop = fail(SS_E_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
     } else {
       os_passes(c, ws, L, nsys, S, g, static_cast<int>(std::min<int64_t>(chunk, total - done)), st);
-      SS_HIP_TRY(hipGetLastError());
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) loop = fail(SS_E_HIP, "ordered-subset launch failed: %s", hipGetErrorString(e));
     }
-    if (opts->tol > 0.0 && done + chunk < total) {
-      if (ss_status s = read_states()) return s;
+    if (loop == SS_OK && opts->tol > 0.0 && done + chunk < total) {
+      loop = read_states();
       bool all = true;
       for (const auto& x : hs) all = all && x.stop;
-      if (all) break;
+      if (loop == SS_OK && all) break;
     }
   }
+  if (graph) os_graphs().release(graph, st);
+  if (loop != SS_OK) return loop;
   if (!passes && opts->tol <= 0.0) return SS_OK;
   if (ss_status s = read_states()) return s;
   ss_status result = SS_OK;

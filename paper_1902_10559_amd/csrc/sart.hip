@@ -44,6 +44,7 @@
 #include <hip/hip_ext.h>
 
 #include "device.h"
+#include "graph_cache.h"
 #include "internal.h"
 #include "lines.h"
 #include "staged.h"
@@ -523,48 +524,77 @@ __global__ __launch_bounds__(kTileThreads) void k_band_tiles(const SysDesc* tabl
     pair_range(q, &sy, &bd, &a, &b);
     for (int32_t s0 = a; s0 < b; s0 += per) tiles[t++] = BandTile{sy, bd, s0, min(b, s0 + per)};
   }
-  if (threadIdx.x == kTileThreads - 1) *ntiles = tot[kTileThreads - 1];
+  if (threadIdx.x == kTileThreads - 1) {
+    ntiles[0] = tot[kTileThreads - 1];
+    ntiles[1] = 0;  // the band kernel's tile queue
+  }
 }
 
 // Band-staged forward projection: grid-stride over the work tiles.  Per
 // tile: the image band into LDS, then RPW segments per wavefront (L lanes
-// each), each segment's sum into its row's slot.
-template <int NV, int WT, int RPW, int P>
-__global__ __launch_bounds__(kStagedThreads) void k_band_fp(const SysDesc* __restrict__ table,
-                                                            const BandTile* __restrict__ tiles,
-                                                            const int32_t* __restrict__ ntiles_p,
-                                                            const Params* __restrict__ prm, int parity) {
+// each), each segment's sum into its row's slot.  The offsets and slot of
+// the next pass's segment are loaded before this pass's streams, so a pass
+// does not start with a dependent load.  WPB wavefronts per block: 16 when a
+// band takes 64 KB of LDS (two blocks per compute unit), else 8; both held
+// to 8 wavefronts per SIMD (at most 64 registers).
+template <int NV, int WT, int RPW, int P, int WPB>
+__global__ __launch_bounds__(kWave* WPB) __attribute__((amdgpu_waves_per_eu(8))) void k_band_fp(const SysDesc* __restrict__ table,
+                                                          const BandTile* __restrict__ tiles,
+                                                          const int32_t* __restrict__ ntiles_p,
+                                                          int32_t* __restrict__ queue,
+                                                          const Params* __restrict__ prm, int parity) {
   extern __shared__ float xs[];
+  __shared__ int32_t next_tile;
   constexpr int L = kWave / RPW;
-  constexpr int SPP = kStagedWaves * RPW;  // segments per pass of the block
+  constexpr int SPP = WPB * RPW;  // segments per pass of the block
   const int ntiles = *gl(ntiles_p);
   const int lg = prm->band_lg;
   const int glane = lane_id() % L;
   const int grp = wave_id() * RPW + lane_id() / L;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // tiles are taken from a queue (a counter that k_band_fin resets), so a
+  // block that drew short tiles takes more; which block sums a tile does not
+  // change its result
+  for (;;) {
+    if (threadIdx.x == 0) next_tile = atomicAdd(queue, 1);
+    __syncthreads();
+    const int t = next_tile;
+    if (t >= ntiles) break;
     const BandTile T = tiles[t];
     const SysDesc& S = table[__builtin_amdgcn_readfirstlane(T.sys)];
-    if (*gl(&S.st->stop)) continue;
+    if (*gl(&S.st->stop)) {
+      __syncthreads();  // next_tile is rewritten by the next draw
+      continue;
+    }
+    // the first pass's segment, before the band is staged
+    int sg = T.s0 + grp;
+    int sc = sg < T.s1 ? sg : T.s1 - 1;
+    int64_t lo = gl(S.fb_off)[sc], hi = gl(S.fb_off)[sc + 1];
+    int slot = gl(S.fb_slot)[sc];
     const int64_t j0 = static_cast<int64_t>(T.band) << lg;
     const int64_t cnt = min(static_cast<int64_t>(1) << lg, S.n - j0);
-    stage_contiguous<NV, kStagedThreads>(xs, S.f[parity] + j0 * NV, cnt);
+    stage_contiguous<NV, kWave * WPB>(xs, S.f[parity] + j0 * NV, cnt);
     __syncthreads();
     for (int sb = T.s0; sb < T.s1; sb += SPP) {
-      const int sg = sb + grp;
       const bool valid = sg < T.s1;
-      const int sc = valid ? sg : T.s1 - 1;
-      const int64_t lo = gl(S.fb_off)[sc], hi = valid ? gl(S.fb_off)[sc + 1] : lo;
+      const int64_t clo = lo, chi = valid ? hi : lo;
+      const int cslot = slot;
+      // the next pass's segment
+      sg += SPP;
+      sc = sg < T.s1 ? sg : T.s1 - 1;
+      lo = gl(S.fb_off)[sc];
+      hi = gl(S.fb_off)[sc + 1];
+      slot = gl(S.fb_slot)[sc];
       float acc[NV];
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-      line_dot_lds<NV, WT, L, P>(S.fb_idx, S.fb_val, xs, lo, hi, glane, acc, (1u << lg) - 1u);
+      line_dot_lds<NV, WT, L, P>(S.fb_idx, S.fb_val, xs, clo, chi, glane, acc, (1u << lg) - 1u);
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
       if (valid && glane == 0) {
         Vec<NV> pv;
 #pragma unroll
         for (int h = 0; h < NV; ++h) pv.v[h] = acc[h];
-        store_vec<NV>(S.fb_part, gl(S.fb_slot)[sg], pv);
+        store_vec<NV>(S.fb_part, cslot, pv);
       }
     }
     __syncthreads();  // the next tile overwrites xs
@@ -575,8 +605,10 @@ __global__ __launch_bounds__(kStagedThreads) void k_band_fp(const SysDesc* __res
 // partials added in band order, r = p - q, z = r / W, and the block's FP64
 // partial of |r|^2; the first block of a system moves the iterate index on.
 template <int NV>
-__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys) {
+__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys,
+                                                          int32_t* __restrict__ queue) {
   __shared__ double red[kFinThreads / kWave];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;  // for the next band launch
   const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<0>(table, nsys, blockIdx.x));
   const SysDesc& S = table[s];
   if (*gl(&S.st->stop)) return;
@@ -710,7 +742,7 @@ __global__ __launch_bounds__(kStagedThreads) void k_bt_plan(const SysDesc* table
 // rows did not fit keeps global gathers.  The first tile of a system also
 // finalises the residual.
 template <int NV, int WT, int CPW, int P>
-__global__ __launch_bounds__(kStagedThreads) void k_tile_bp(const Params* __restrict__ prm,
+__global__ __launch_bounds__(kStagedThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_bp(const Params* __restrict__ prm,
                                                             const SysDesc* __restrict__ table, int nsys,
                                                             int parity) {
   extern __shared__ float zs[];
@@ -728,6 +760,10 @@ __global__ __launch_bounds__(kStagedThreads) void k_tile_bp(const Params* __rest
   const int lg = prm->tile_lg;
   const int64_t j0 = lt << lg;
   const int64_t j1 = min(S.n, j0 + (int64_t{1} << lg));
+  // the first pass's column offsets, before the tile's rows are staged
+  int64_t j = j0 + wave_id() * CPW + lane_id() / L;
+  int64_t jj = j < j1 ? j : j1 - 1;
+  int64_t nlo = gl(S.col_ptr)[jj], nhi = gl(S.col_ptr)[jj + 1];
   const int32_t* mt = reinterpret_cast<const int32_t*>(S.bt_meta + lt);
   const int32_t nrows = gl(mt)[0], nruns = gl(mt)[1];
   const bool staged = gl(mt)[2] != 0;
@@ -746,13 +782,17 @@ __global__ __launch_bounds__(kStagedThreads) void k_tile_bp(const Params* __rest
   }
   const int glane = lane_id() % L;
   const float* fin = S.f[parity];
+  // each pass loads the next pass's column offsets before its own streams
   for (int64_t jb = j0; jb < j1; jb += kStagedWaves * CPW) {
-    const int64_t j = jb + wave_id() * CPW + lane_id() / L;
-    const bool owner = glane == 0 && j < j1;
-    const int64_t jj = j < j1 ? j : j1 - 1;
-    const int64_t lo = gl(S.col_ptr)[jj], hi = j < j1 ? gl(S.col_ptr)[jj + 1] : lo;
-    Vec<NV> fv = load_vec<NV>(fin, jj);
-    const float tl = prm->lambda * gl(S.inv_col)[jj];
+    const int64_t jc = j, jjc = jj;
+    const bool owner = glane == 0 && jc < j1;
+    const int64_t lo = nlo, hi = jc < j1 ? nhi : nlo;
+    j += kStagedWaves * CPW;
+    jj = j < j1 ? j : j1 - 1;
+    nlo = gl(S.col_ptr)[jj];
+    nhi = gl(S.col_ptr)[jj + 1];
+    Vec<NV> fv = load_vec<NV>(fin, jjc);
+    const float tl = prm->lambda * gl(S.inv_col)[jjc];
     float acc[NV];
 #pragma unroll
     for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
@@ -764,7 +804,7 @@ __global__ __launch_bounds__(kStagedThreads) void k_tile_bp(const Params* __rest
 #pragma unroll
       for (int h = 0; h < NV; ++h) fv.v[h] = fmaf(tl, acc[h], fv.v[h]);
       if (prm->nonneg) fv = project_nonneg<NV>(fv);
-      store_vec<NV>(S.f[parity ^ 1], j, fv);
+      store_vec<NV>(S.f[parity ^ 1], jc, fv);
     }
   }
 }
@@ -984,6 +1024,7 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
     return fail(SS_E_ARG, "%s: the interleaved stream form needs entries of at least 4 bytes", fn);
   if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
   if (o->staged < 0 || o->staged > 3) return fail(SS_E_ARG, "%s: staged must be 0..3", fn);
+  if (o->residual_every > 1) return fail(SS_E_ARG, "%s: residual_every is for ordered subsets (0 or 1 here)", fn);
   auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
   if (o->band_width && (!pow2(o->band_width) || o->band_width < 1024 || o->band_width > 16384 ||
                         o->band_width * sys[0].nvals * 4 > 65536))
@@ -1072,9 +1113,12 @@ ss_status interleave(const int64_t* ptr, int64_t lines, const int32_t* idx, cons
 // Writes the descriptor table and resets states (stream-ordered kernels);
 // writes the interleaved stream copies where a kernel reads them.
 // Launch shapes of the staged kernels (their own, not the unstaged ones').
-template <int NV, int WT, int RPW, int P>
+// Wavefronts per block of the band kernel for a band of 2^lg voxels.
+inline int band_waves(int nv, int lg) { return (size_t{4} << lg) * nv > 40960 ? 16 : 8; }
+
+template <int NV, int WT, int RPW, int P, int WPB>
 const void* band_kernel() {
-  return reinterpret_cast<const void*>(k_band_fp<NV, WT, RPW, P>);
+  return reinterpret_cast<const void*>(k_band_fp<NV, WT, RPW, P, WPB>);
 }
 
 // Grid of the band-staged forward kernel: the blocks that fit on the device
@@ -1094,8 +1138,10 @@ uint32_t band_grid(const Cfg& c, const Layout& L) {
     if (it == cap.end()) {
       int cus = 0, per = 0;
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      const void* k = c.nv == 2 ? band_kernel<2, SS_F32, 4, 1>() : band_kernel<1, SS_F32, 4, 1>();
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kStagedThreads, lds);
+      const int wpb = band_waves(c.nv, c.blg);
+      const void* k = c.nv == 2 ? (wpb == 16 ? band_kernel<2, SS_F32, 8, 2, 16>() : band_kernel<2, SS_F32, 8, 2, 8>())
+                                : (wpb == 16 ? band_kernel<1, SS_F32, 8, 2, 16>() : band_kernel<1, SS_F32, 8, 2, 8>());
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kWave * wpb, lds);
       it = cap.emplace(key, static_cast<uint32_t>(std::max(1, cus) * std::max(1, per))).first;
     }
     resident = it->second;
@@ -1320,14 +1366,28 @@ void launch_band(const Cfg& c, const char* ws, const Layout& L, int nsys, const 
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
   const BandTile* tiles = reinterpret_cast<const BandTile*>(ws + L.tiles);
   const int32_t* nt = reinterpret_cast<const int32_t*>(ws + L.ntiles);
+  int32_t* queue = const_cast<int32_t*>(nt) + 1;
   const size_t lds = (size_t{4} << c.blg) * NV;
-  const dim3 grid(g.band_blocks), blk(kStagedThreads);
-  switch (c.rpw) {
-    case 2: hipExtLaunchKernelGGL(k_band_fp<NV, WT, 2, P>, grid, blk, lds, st, e.start, e.mid0, 0, t, tiles, nt, prm, par); break;
-    case 8: hipExtLaunchKernelGGL(k_band_fp<NV, WT, 8, P>, grid, blk, lds, st, e.start, e.mid0, 0, t, tiles, nt, prm, par); break;
-    default: hipExtLaunchKernelGGL(k_band_fp<NV, WT, 4, P>, grid, blk, lds, st, e.start, e.mid0, 0, t, tiles, nt, prm, par); break;
+  const dim3 grid(g.band_blocks);
+#define SS_BAND(RPW, WPB) \
+  hipExtLaunchKernelGGL(k_band_fp<NV, WT, RPW, P, WPB>, grid, dim3(kWave * WPB), lds, st, e.start, e.mid0, 0, t, \
+                        tiles, nt, queue, prm, par)
+  if (band_waves(NV, c.blg) == 16) {
+    switch (c.rpw) {
+      case 2: SS_BAND(2, 16); break;
+      case 8: SS_BAND(8, 16); break;
+      default: SS_BAND(4, 16); break;
+    }
+  } else {
+    switch (c.rpw) {
+      case 2: SS_BAND(2, 8); break;
+      case 8: SS_BAND(8, 8); break;
+      default: SS_BAND(4, 8); break;
+    }
   }
-  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys);
+#undef SS_BAND
+  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys,
+                        queue);
 }
 
 template <int NV, int WT, int P>
@@ -1435,51 +1495,9 @@ struct GraphKey {
   }
 };
 
-struct GraphCache {
-  std::mutex mu;
-  std::map<GraphKey, hipGraphExec_t> execs;
-  std::map<int, hipStream_t> capture_streams;
-  uint64_t uses = 0;
-};
-
-GraphCache& graph_cache() {
-  static GraphCache* c = new GraphCache();  // lives until process exit
+GraphCache<GraphKey>& graph_cache() {
+  static auto* c = new GraphCache<GraphKey>(32);  // lives until process exit
   return *c;
-}
-
-ss_status get_graph(const GraphKey& key, const Cfg& c, const char* ws, const Layout& L, const Grids& g,
-                    hipGraphExec_t* out) {
-  GraphCache& gc = graph_cache();
-  std::lock_guard<std::mutex> lock(gc.mu);
-  auto it = gc.execs.find(key);
-  if (it != gc.execs.end()) {
-    *out = it->second;
-    return SS_OK;
-  }
-  if (gc.execs.size() >= 32) {
-    for (auto& kv : gc.execs) (void)hipGraphExecDestroy(kv.second);
-    gc.execs.clear();
-  }
-  hipStream_t cs;
-  auto sit = gc.capture_streams.find(key.device);
-  if (sit == gc.capture_streams.end()) {
-    SS_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    gc.capture_streams[key.device] = cs;
-  } else {
-    cs = sit->second;
-  }
-  SS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  launch_iterations(c, ws, L, key.nsys, g, 0, key.count, cs);
-  hipGraph_t graph;
-  const hipError_t ce = hipStreamEndCapture(cs, &graph);
-  if (ce != hipSuccess) return fail(SS_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-  hipGraphExec_t exec;
-  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (ie != hipSuccess) return fail(SS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
-  gc.execs[key] = exec;
-  *out = exec;
-  return SS_OK;
 }
 
 ss_status read_states(const char* ws, const Layout& L, int nsys, std::vector<SysState>* h, hipStream_t st) {
@@ -1525,29 +1543,35 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
   int chunk = opts->tol > 0.0 ? static_cast<int>(std::min<int64_t>(opts->check_every, total))
                               : static_cast<int>(std::min<int64_t>(total, 256));
   chunk += chunk & 1;
-  hipGraphExec_t exec = nullptr;
+  GraphEntry* graph = nullptr;
   if (opts->use_graph) {
     int dev = 0;
     SS_HIP_TRY(hipGetDevice(&dev));
     const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, c.pers, c.ch,
                        chunk, c.stg, c.blg, c.tlg, c.spt, g.band_blocks};
-    if (ss_status s = get_graph(key, c, ws, L, g, &exec)) return s;
+    auto capture = [&](hipStream_t cs) { launch_iterations(c, ws, L, nsys, g, 0, chunk, cs); };
+    if (ss_status s = graph_cache().acquire(key, dev, capture, &graph)) return s;
   }
   std::vector<SysState> hs;
-  for (int64_t done = 0; done < total; done += chunk) {
-    if (exec) {
-      SS_HIP_TRY(hipGraphLaunch(exec, st));
+  ss_status loop = SS_OK;
+  for (int64_t done = 0; done < total && loop == SS_OK; done += chunk) {
+    if (graph) {
+      const hipError_t e = hipGraphLaunch(graph->exec, st);
+      if (e != hipSuccess) loop = fail(SS_E_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
     } else {
       launch_iterations(c, ws, L, nsys, g, done, static_cast<int>(std::min<int64_t>(chunk, total - done)), st);
-      SS_HIP_TRY(hipGetLastError());
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) loop = fail(SS_E_HIP, "SART launch failed: %s", hipGetErrorString(e));
     }
-    if (opts->tol > 0.0 && done + chunk < total) {
-      if (ss_status s = read_states(ws, L, nsys, &hs, st)) return s;
+    if (loop == SS_OK && opts->tol > 0.0 && done + chunk < total) {
+      loop = read_states(ws, L, nsys, &hs, st);
       bool all = true;
       for (const auto& x : hs) all = all && x.stop;
-      if (all) break;
+      if (loop == SS_OK && all) break;
     }
   }
+  if (graph) graph_cache().release(graph, st);
+  if (loop != SS_OK) return loop;
   launch_finish(c, ws, L, nsys, st);
   SS_HIP_TRY(hipGetLastError());
   if (!iters && opts->tol <= 0.0) return SS_OK;

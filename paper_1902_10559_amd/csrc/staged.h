@@ -98,16 +98,27 @@ __device__ inline void line_dot_lds(const uint16_t* idx, const void* val, const 
       c[u] = load_idx16_chunk(idx, kk);
       load_val_chunk<NV, WT>(val, kk, v[u]);
     }
+    // all of the pass's gathers first, then the products: the reads are in
+    // flight together instead of each waiting before the next is issued
+    Vec<NV> xv[P][SS_CHUNK];
 #pragma unroll
     for (int u = 0; u < P; ++u) {
 #pragma unroll
       for (int j = 0; j < SS_CHUNK; ++j) {
         const int64_t k = base + C * u * L + j;
         const bool in = k >= lo && k < hi;
-        const Vec<NV> xv = lds_vec<NV>(xs, in ? idx16_at(c[u], j) & mask : 0u);
+        xv[u][j] = lds_vec<NV>(xs, in ? idx16_at(c[u], j) & mask : 0u);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+#pragma unroll
+      for (int j = 0; j < SS_CHUNK; ++j) {
+        const int64_t k = base + C * u * L + j;
+        const bool in = k >= lo && k < hi;
 #pragma unroll
         for (int h = 0; h < NV; ++h) {
-          const float s = fmaf(v[u][j].v[h], xv.v[h], acc[h]);
+          const float s = fmaf(v[u][j].v[h], xv[u][j].v[h], acc[h]);
           acc[h] = in ? s : acc[h];
         }
       }

@@ -168,3 +168,29 @@ def test_nonnegative_os_sart_matches_the_oracle():
     img = to_np(native.recombine(f[0]))
     assert img.min() >= 0.0 and rel_l2(img, OSp.recombine(f1, f2)) <= 1e-5
     assert_res_close(to_np(h[0]), res)
+
+
+def test_residual_every_r_passes_keeps_the_iterates_and_checks_less_often():
+    """With residual_every = 4 the pass-start residual is taken on passes
+    0, 4, 8, ... only: the images are those of the every-pass run bit for
+    bit (the residual does not touch them), the recorded entries equal its
+    entries, the others stay unwritten, and a tolerance stops at the first
+    multiple of 4 at or after the every-pass stop."""
+    banner("ordered subsets: residual every 4 passes")
+    pr = problem(1)
+    S = _system(pr)
+    B = native.Subsets(S, inputs.geometry_for(1).K // 2)
+    f1, h1, _, it1 = _solve([S], [B], 10)
+    f4, h4, _, it4 = _solve([S], [B], 10, residual_every=4)
+    assert it1 == it4 == [10]
+    assert np.array_equal(to_np(f1[0]).view(np.uint32), to_np(f4[0]).view(np.uint32))
+    a, b = to_np(h1[0]), to_np(h4[0])
+    for k in range(11):
+        if k % 4 == 0 or k == 10:
+            assert a[k] == b[k], k
+        else:
+            assert b[k] == -1.0, k
+    tol = 0.5 * (a[5] + a[6])          # reached at pass 6 when checked every pass
+    _, _, _, it_all = _solve([S], [B], 40, tol=tol, check_every=3)
+    _, _, _, it_r = _solve([S], [B], 40, tol=tol, check_every=3, residual_every=4)
+    assert it_all == [6] and it_r == [8]

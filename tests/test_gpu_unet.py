@@ -157,7 +157,7 @@ def test_backward_gradients_and_routing_match_the_oracle(run):
         if relu[name]:
             g = ON.relu_grad(_act(net, dst, lvl, O), g)
         _, gy = _bf16(g)   # the kernels take the masked gradient in BF16
-        wr, _ = _bf16(to_np(net.layers[name].w))
+        _, wr = _bf16(to_np(net.layers[name].w))
         want_w, want_b = ON.conv3x3_grad_weight(xin, gy)
         L = net.layers[name]
         assert _rel(to_np(L.gw).astype(np.float64).reshape(O, 3, 3, C), want_w) <= 1e-5, name
