@@ -74,7 +74,7 @@ def parse():
                     help="skip the time-to-1e-3 runs on the workload")
     ap.add_argument("--no-dtypes", action="store_true",
                     help="skip the BF16/FP16-weight step records")
-    ap.add_argument("--staged", default="", metavar="BITS,BAND,TILE,RPW,CPW,UNROLL",
+    ap.add_argument("--staged", default="", metavar="BITS,BAND,TILE,ENTRIES,CPW,UNROLL",
                     help="fixed staged-kernel configuration instead of the timed choice "
                          "(BITS 0 keeps the unstaged kernels of --shape or the autotuner)")
     ap.add_argument("--shape", default="", metavar="RPW,CPW,XCD,UNROLL,PERSISTENT,CHUNKED",
@@ -100,12 +100,13 @@ def bytes_per_iteration(nnz, m, n, nv, sv):
 
 
 def source_hash():
-    """Hash of the solver's device code (device.h, lines.h and the kernel
-    section of sart.hip): traffic counted for other kernel code is not
+    """Hash of the solver's device code (device.h, lines.h, staged.h and the
+    kernel section of sart.hip): traffic counted for other kernel code is not
     reported."""
     csrc = os.path.join(ROOT, "paper_1902_10559_amd", "csrc")
     h = hashlib.sha256(open(os.path.join(csrc, "device.h"), "rb").read())
     h.update(open(os.path.join(csrc, "lines.h"), "rb").read())
+    h.update(open(os.path.join(csrc, "staged.h"), "rb").read())
     text = open(os.path.join(csrc, "sart.hip")).read()
     a, b = text.index("// ---- device code begin"), text.index("// ---- device code end")
     h.update(text[a:b].encode())
@@ -315,7 +316,7 @@ def config_of(o):
     """The launch configuration fields of a SartOptions, for the report."""
     return {"rows_per_wave": o.rows_per_wave, "cols_per_wave": o.cols_per_wave, "xcd_remap": o.xcd_remap,
             "unroll": o.unroll, "persistent": o.persistent, "chunked": o.chunked, "staged": o.staged,
-            "band_width": o.band_width, "tile_cols": o.tile_cols, "tile_segments": o.tile_segments}
+            "band_width": o.band_width, "tile_cols": o.tile_cols, "tile_entries": o.tile_entries}
 
 
 def lanes_of(o):
@@ -367,18 +368,20 @@ def choose_config(args, slices, systems, lam, iters):
         sol = pick_line_order(args, slices, systems, sol, scratch)
         base = sol.opts
     if args.staged:
-        bits, band, tile, rpw, cpw, unroll = map(int, args.staged.split(","))
+        bits, band, tile, entries, cpw, unroll = map(int, args.staged.split(","))
         if bits == 0:
             return base, lanes_of(base)
         o = dataclasses.replace(base, staged=bits, band_width=band, tile_cols=tile, unroll=unroll,
-                                rows_per_wave=rpw if bits & 1 else base.rows_per_wave,
+                                tile_entries=entries if bits & 1 else 0,
                                 cols_per_wave=cpw if bits & 2 else base.cols_per_wave)
         return o, lanes_of(o)
     fp, bp = staged_search(systems, base, scratch)
+    # one unroll serves both staged kernels: the back projection's (8), or
+    # the forward one's when only it is staged
     cands = [base,
-             dataclasses.replace(base, staged=3, unroll=8, rows_per_wave=fp[1], band_width=fp[0],
+             dataclasses.replace(base, staged=3, unroll=8, band_width=fp[0], tile_entries=fp[1],
                                  cols_per_wave=bp[1], tile_cols=bp[0]),
-             dataclasses.replace(base, staged=1, rows_per_wave=fp[1], band_width=fp[0]),
+             dataclasses.replace(base, staged=1, unroll=fp[2], band_width=fp[0], tile_entries=fp[1]),
              dataclasses.replace(base, staged=2, cols_per_wave=bp[1], tile_cols=bp[0])]
     best, best_ms = base, 1e30
     for o in cands:
@@ -406,16 +409,18 @@ def choose_config(args, slices, systems, lam, iters):
 
 def staged_search(systems, base, scratch):
     """Per-kernel times of a few staged shapes (systems in ascending order):
-    the forward band width and segments per wavefront, the back-projection
-    tile width and columns per wavefront.  Returns (band, rpw), (tile, cpw)."""
+    the forward band width, work-tile entries and windows in flight (unroll),
+    the back-projection tile width and columns per wavefront.  Returns
+    (band, entries, unroll), (tile, cpw)."""
     import dataclasses
     from paper_1902_10559_amd import native
-    fp_best, bp_best = ((8192, 8), 1e30), ((512, 8), 1e30)
-    for band, rpw in ((8192, 8), (8192, 4), (4096, 8), (4096, 4)):
-        o = dataclasses.replace(base, staged=1, band_width=band, rows_per_wave=rpw, unroll=8, chunked=0)
+    fp_best, bp_best = ((4096, 4096, 4), 1e30), ((512, 8), 1e30)
+    for band, entries, unroll in ((4096, 4096, 4), (4096, 2048, 4), (4096, 4096, 8), (4096, 8192, 4),
+                                  (2048, 4096, 4)):
+        o = dataclasses.replace(base, staged=1, band_width=band, tile_entries=entries, unroll=unroll, chunked=0)
         ms = native.Solver(systems, o).time_phases(scratch, reps=10)
         if ms[0] + ms[1] < fp_best[1]:
-            fp_best = ((band, rpw), ms[0] + ms[1])
+            fp_best = ((band, entries, unroll), ms[0] + ms[1])
     for tile, cpw in ((512, 8), (1024, 8), (256, 8), (512, 16)):
         o = dataclasses.replace(base, staged=2, tile_cols=tile, cols_per_wave=cpw, unroll=8, chunked=0)
         ms = native.Solver(systems, o).time_phases(scratch, reps=10)
@@ -436,8 +441,7 @@ def unsplit_config(unsplit, opts, lam, iters):
     uopts = usol.opts
     if opts.staged:
         uopts = dataclasses.replace(uopts, staged=opts.staged, band_width=opts.band_width,
-                                    tile_cols=opts.tile_cols, tile_segments=opts.tile_segments,
-                                    rows_per_wave=opts.rows_per_wave if opts.staged & 1 else uopts.rows_per_wave,
+                                    tile_cols=opts.tile_cols, tile_entries=opts.tile_entries,
                                     cols_per_wave=opts.cols_per_wave if opts.staged & 2 else uopts.cols_per_wave,
                                     unroll=opts.unroll)
     return uopts
@@ -457,8 +461,12 @@ def kernel_report(slv, systems, scratch, o, nv, sv):
     if o.staged & 1:
         segs = info[0]
         rep["ms"]["band_fp"], rep["ms"]["band_fin"] = ms[0], ms[1]
-        rep["bytes"]["band_fp"] = nnz * (2 + nv * sv) + segs * (8 + 4 * nv) + n * 4 * nv + 16 * info[1]
-        rep["bytes"]["band_fin"] = m * (4 + 4 * nv + 4 + 4 * nv) + 4 * len(systems) + segs * 4 * nv
+        # per entry its 16-bit index and values; per segment its sum; one
+        # start bit per chunk of 4; the image once; 32 bytes per tile
+        rep["bytes"]["band_fp"] = (nnz * (2 + nv * sv) + segs * 4 * nv + nnz // 32 + n * 4 * nv
+                                   + 32 * info[1])
+        # per row its slot range, p, 1/W and z; per segment its slot and sum
+        rep["bytes"]["band_fin"] = m * (4 + 4 * nv + 4 + 4 * nv) + segs * (4 + 4 * nv)
         rep["segments"], rep["band_tiles"] = segs, info[1]
     else:
         rep["ms"]["sart_fp"] = ms[0]

@@ -355,30 +355,39 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *   staged       bit 0: band-staged forward projection.  The columns are
  *                cut into bands of band_width consecutive indices; a copy of
  *                the row streams is laid out band by band (each row's
- *                entries in a band form a segment; 16-bit column indices
- *                within the band), made in the workspace on every solve.
- *                A block loads one band of the image into shared memory
- *                and sums many segments from there; a second kernel adds
- *                each row's segment sums in band order and forms the
- *                residual.  Bit 1: tile-staged back projection.  Columns
- *                are taken in tiles of tile_cols; per tile the distinct rows
- *                its entries touch are found once per solve and each entry's
- *                row is rewritten as its rank among them (16 bits); the
- *                block copies those rows of z into shared memory and sums
- *                from there (a tile touching more than 4096 rows, or rows in
- *                more than 128 runs, keeps global gathers).  Needs lines in
- *                ascending order (row_lanes / col_lanes 0), 16-byte aligned
- *                images, nnz < 2^31, and for bit 1 m <= 2^17; when set,
- *                rows_per_wave and cols_per_wave count segments and columns
- *                per wavefront of an 8-wavefront block, and `chunked` and
- *                `persistent` do not apply to the staged kernels.  The sums
- *                run in another order than the unstaged kernels' (equal to
- *                FP32 rounding), always the same one.
+ *                entries in a band form a segment, padded with zero entries
+ *                to whole chunks of SS_CHUNK; 16-bit column indices within
+ *                the band), made in the workspace on every solve.  A band's
+ *                chunks are cut into work tiles of about tile_entries; a
+ *                block loads one band of the image into shared memory and
+ *                its wavefronts stream the band's tiles, one chunk per lane,
+ *                summing each segment with a segmented scan across the
+ *                lanes; a second
+ *                kernel adds each row's segment sums in band order and
+ *                forms the residual.  A row whose columns do not strictly
+ *                ascend inside [0, n) gets no segments (it adds nothing to
+ *                the forward projection).  Bit 1: tile-staged back
+ *                projection.  Columns are taken in tiles of tile_cols; per
+ *                tile the distinct rows its entries touch are found once per
+ *                solve and each entry's row is rewritten as its rank among
+ *                them (16 bits); the block copies those rows of z into
+ *                shared memory and sums from there (a tile touching more
+ *                than 4096 rows, or rows in more than 128 runs, keeps global
+ *                gathers).  Needs lines in ascending order (row_lanes /
+ *                col_lanes 0), 16-byte aligned images, nnz < 2^31, and for
+ *                bit 1 m <= 2^17.  With bit 1, cols_per_wave counts columns
+ *                per wavefront of an 8-wavefront block; rows_per_wave,
+ *                `chunked` and `persistent` do not apply to the staged
+ *                kernels; `unroll` 8 has the band kernel keep three
+ *                windows of loads per wavefront in flight (4: two).  The sums run in another order than the unstaged
+ *                kernels' (equal to FP32 rounding), always the same one.
  *   band_width   voxels per forward band: a power of two from 1024 to 16384
- *                with band_width * nvals * 4 <= 65536 bytes (0 = 4096)
+ *                with band_width * nvals * 4 + 4096 * nvals <= 65536 bytes
+ *                of shared memory (0 = 4096)
  *   tile_cols    columns per back-projection tile: a power of two from 64 to
  *                8192 (0 = 1024)
- *   tile_segments  segments per forward work tile, 64 .. 65536 (0 = 1024)
+ *   tile_entries  padded entries per forward work tile: a multiple of 256
+ *                from 1024 to 65536 (0 = 4096)
  *   residual_every  ordered subsets only (ss_ossart_solve; here 0 or 1): the
  *                residual of the pass-start image, a full forward sweep, is
  *                taken on passes k with k % residual_every == 0 and at
@@ -403,7 +412,7 @@ typedef struct {
   int32_t staged;
   int32_t band_width;
   int32_t tile_cols;
-  int32_t tile_segments;
+  int32_t tile_entries;
   int32_t residual_every;
 } ss_sart_opts;
 

@@ -86,11 +86,12 @@ struct SysDesc {
   // band-staged forward projection (see staged.h)
   uint16_t* fb_idx;   // band-major copy of the row streams: column - band start
   void* fb_val;
-  int32_t* fb_off;    // band-major segment -> first entry ([nseg] = nnz)
-  int32_t* fb_slot;   // band-major segment -> its row's partial slot
+  int32_t* fb_off;    // band-major segment -> first entry ([nseg] = padded total)
+  uint32_t* fb_bits;  // one bit per chunk: set where a segment starts
+  int32_t* fb_slot;   // row partial slot -> its band-major segment
   uint32_t* fb_rseg;  // m+1: row i's partial slots [rseg[i], rseg[i+1])
-  float* fb_part;     // NV floats per slot
-  uint64_t* fb_len;   // nb*m+1: (segments, entries) per (band, row), scanned
+  float* fb_part;     // NV floats per band-major segment
+  uint64_t* fb_len;   // nb*m+1: (segments, padded entries) per (band, row), scanned
   int64_t cv_rblk0;   // first block of this system in the set-up row grid
   int64_t cv_t64_0, cv_t32_0;  // first scan tile of fb_len / fb_rseg
   int32_t fb_nb;      // bands
@@ -108,6 +109,7 @@ struct Params {
   int32_t nonneg;
   int32_t band_lg;   // log2 of the forward bands' width (staged)
   int32_t tile_lg;   // log2 of the back-projection tiles' columns (staged)
+  int32_t band_q;    // chunks per forward work tile (staged)
 };
 
 struct SetupFlags {
@@ -390,28 +392,81 @@ __global__ __launch_bounds__(kThreads) void k_finish(const SysDesc* table) {
 constexpr int kCvLanes = 16;
 constexpr int kCvRows = kThreads / kCvLanes;
 
-// Per row: the length of each band run (a segment) into fb_len[b*m + i] as
-// (1 segment, len entries), and the row's segment count into fb_rseg[i].
-// A run starts where an entry's band differs from the previous entry's; its
-// end is found by binary search for the next band's first column.
+// The band runs of one row, as its kCvLanes lanes walk it in windows of
+// kCvLanes entries: per entry its band, whether it starts and whether it
+// ends a run (the next entry is in another band, or there is none), and the
+// first entry of its run.  The lanes of a row call it together (the
+// shuffles stay inside the row's lanes); `run0` and `band0` carry the
+// previous window's last run start and band.
+struct RunLane {
+  int32_t band;
+  bool valid, start, end;
+  int64_t k, ks;
+};
+
+__device__ inline RunLane run_lane(const int32_t* col, int64_t base, int64_t hi, int lg, int g, int64_t run0,
+                                   int32_t band0) {
+  RunLane r;
+  r.k = base + g;
+  r.valid = r.k < hi;
+  r.band = r.valid ? (gl(col)[r.k] >> lg) : -1;
+  int32_t bp = __shfl_up(r.band, 1, kCvLanes);
+  if (g == 0) bp = band0;
+  int32_t bn = __shfl_down(r.band, 1, kCvLanes);
+  if (g == kCvLanes - 1) bn = r.k + 1 < hi ? (gl(col)[r.k + 1] >> lg) : -1;
+  r.start = r.valid && r.band != bp;
+  r.end = r.valid && r.band != bn;
+  int64_t ks = r.start ? r.k : int64_t{-1};
+#pragma unroll
+  for (int d = 1; d < kCvLanes; d <<= 1) {
+    const int64_t t = __shfl_up(ks, d, kCvLanes);
+    if (g >= d) ks = max(ks, t);
+  }
+  r.ks = ks >= 0 ? ks : run0;
+  return r;
+}
+
+// Whether row i's columns strictly ascend inside [0, n) (every lane of the
+// row gets the answer).  The staged forward form gives a row that does not
+// no segments.
+__device__ inline bool row_ascends(const SysDesc& S, int64_t lo, int64_t hi, int g) {
+  bool bad = false;
+  for (int64_t k = lo + g; k < hi; k += kCvLanes) {
+    const int32_t c = gl(S.col_idx)[k];
+    bad |= c < 0 || c >= S.n || (k > lo && gl(S.col_idx)[k - 1] >= c);
+  }
+  int b = bad ? 1 : 0;
+#pragma unroll
+  for (int o = kCvLanes / 2; o > 0; o >>= 1) b |= __shfl_xor(b, o, kWave);
+  return b == 0;
+}
+
+// Per row: the padded length of each band run (a segment) into
+// fb_len[b*m + i] as (1 segment, entries rounded up to whole chunks), and
+// the row's segment count into fb_rseg[i].
 __global__ __launch_bounds__(kThreads) void k_fb_count(const SysDesc* table, int nsys, const Params* prm) {
   const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, blockIdx.x));
   const SysDesc& S = table[s];
   const int lg = prm->band_lg;
   const int64_t i = (static_cast<int64_t>(blockIdx.x) - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
   const int g = threadIdx.x % kCvLanes;
-  if (i >= S.m) return;
+  if (i >= S.m) return;  // the row's lanes leave together
   const int64_t lo = gl(S.row_ptr)[i], hi = gl(S.row_ptr)[i + 1];
+  if (!row_ascends(S, lo, hi, g)) {
+    if (g == 0) glw(S.fb_rseg)[i] = 0u;
+    return;
+  }
+  int64_t run0 = lo;
+  int32_t band0 = -1;
   uint32_t runs = 0;
-  for (int64_t k = lo + g; k < hi; k += kCvLanes) {
-    const int32_t c = gl(S.col_idx)[k];
-    if (c < 0 || c >= S.n) continue;  // never for a fold's output (columns in range)
-    const int32_t b = c >> lg;
-    if (k == lo || (gl(S.col_idx)[k - 1] >> lg) != b) {
-      const int64_t e = col_lower_bound(S.col_idx, k + 1, hi, (b + 1) << lg);
-      glw(S.fb_len)[static_cast<int64_t>(b) * S.m + i] = seg_pack(1u, static_cast<uint32_t>(e - k));
-      ++runs;
-    }
+  for (int64_t base = lo; base < hi; base += kCvLanes) {
+    const RunLane r = run_lane(S.col_idx, base, hi, lg, g, run0, band0);
+    if (r.end)
+      glw(S.fb_len)[static_cast<int64_t>(r.band) * S.m + i] =
+          seg_pack(1u, static_cast<uint32_t>(pad_chunk(r.k + 1 - r.ks)));
+    runs += r.start ? 1u : 0u;
+    run0 = __shfl(r.ks, kCvLanes - 1, kCvLanes);
+    band0 = __shfl(r.band, kCvLanes - 1, kCvLanes);
   }
 #pragma unroll
   for (int o = kCvLanes / 2; o > 0; o >>= 1) runs += __shfl_xor(runs, o, kWave);
@@ -419,9 +474,12 @@ __global__ __launch_bounds__(kThreads) void k_fb_count(const SysDesc* table, int
 }
 
 // Per row, after both scans: each entry goes to its band-major position
-// (16-bit column within the band, value copied bit for bit); each run start
-// records its segment's offset and its row's slot (the row's slots follow
-// its bands in ascending order).  VB: value bytes per entry.
+// (16-bit column within the band, value copied bit for bit) and each
+// segment's padding entries get value 0 and index 0; each run start records
+// its segment's offset and its chunk's bit in fb_bits, and the row's slot
+// for the run (the row's slots follow its bands in ascending order) records
+// the segment.  VB: value bytes per
+// entry.
 template <int VB>
 __global__ __launch_bounds__(kThreads) void k_fb_fill(const SysDesc* table, int nsys, const Params* prm) {
   const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, blockIdx.x));
@@ -434,36 +492,55 @@ __global__ __launch_bounds__(kThreads) void k_fb_fill(const SysDesc* table, int 
     glw(S.fb_off)[seg_count(tot)] = static_cast<int32_t>(seg_entries(tot));
   }
   if (i >= S.m) return;
+  const uint32_t slot0 = gl(S.fb_rseg)[i];
+  if (gl(S.fb_rseg)[i + 1] == slot0) return;  // an empty row, or one given no segments
   const int64_t lo = gl(S.row_ptr)[i], hi = gl(S.row_ptr)[i + 1];
-  for (int64_t k = lo + g; k < hi; k += kCvLanes) {
-    const int32_t c = gl(S.col_idx)[k];
-    if (c < 0 || c >= S.n) continue;
-    const int32_t b = c >> lg;
-    const int64_t at = static_cast<int64_t>(b) * S.m + i;
-    const uint64_t pre = gl(S.fb_len)[at];
-    const int64_t k0 = (k == lo || (gl(S.col_idx)[k - 1] >> lg) != b) ? k
-                       : col_lower_bound(S.col_idx, lo, k, b << lg);
-    const int64_t pos = static_cast<int64_t>(seg_entries(pre)) + (k - k0);
-    // a row whose columns do not ascend could place an entry past its
-    // segment: such entries are dropped (the fold's rows always ascend)
-    if (pos >= static_cast<int64_t>(seg_entries(gl(S.fb_len)[at + 1]))) continue;
-    glw(S.fb_idx)[pos] = static_cast<uint16_t>(c - (b << lg));
-    if constexpr (VB == 8)
-      glw(static_cast<uint64_t*>(S.fb_val))[pos] = gl(static_cast<const uint64_t*>(S.val))[k];
-    else if constexpr (VB == 4)
-      glw(static_cast<uint32_t*>(S.fb_val))[pos] = gl(static_cast<const uint32_t*>(S.val))[k];
-    else
-      glw(static_cast<uint16_t*>(S.fb_val))[pos] = gl(static_cast<const uint16_t*>(S.val))[k];
-    if (k == k0) {
-      uint32_t ord = 0;  // segments of this row in lower bands
-      for (int bb = 0; bb < b; ++bb) {
-        const int64_t a = static_cast<int64_t>(bb) * S.m + i;
-        ord += seg_count(gl(S.fb_len)[a + 1]) - seg_count(gl(S.fb_len)[a]);
-      }
-      const uint32_t sg = seg_count(pre);
-      glw(S.fb_off)[sg] = static_cast<int32_t>(seg_entries(pre));
-      glw(S.fb_slot)[sg] = static_cast<int32_t>(gl(S.fb_rseg)[i] + ord);
+  int64_t run0 = lo;
+  int32_t band0 = -1;
+  uint32_t ord = 0;  // the row's runs in earlier windows
+  for (int64_t base = lo; base < hi; base += kCvLanes) {
+    const RunLane r = run_lane(S.col_idx, base, hi, lg, g, run0, band0);
+    uint32_t nst = r.start ? 1u : 0u;  // runs started at or before this lane in the window
+#pragma unroll
+    for (int d = 1; d < kCvLanes; d <<= 1) {
+      const uint32_t t = __shfl_up(nst, d, kCvLanes);
+      if (g >= d) nst += t;
     }
+    if (r.valid) {
+      const int64_t at = static_cast<int64_t>(r.band) * S.m + i;
+      const uint64_t pre = gl(S.fb_len)[at];
+      const int64_t e0 = seg_entries(pre);
+      const int64_t e1 = seg_entries(gl(S.fb_len)[at + 1]);  // e0 + the padded length
+      const int64_t pos = e0 + (r.k - r.ks);
+      if (pos < e1) {
+        const int32_t c = gl(S.col_idx)[r.k];
+        glw(S.fb_idx)[pos] = static_cast<uint16_t>(c - (r.band << lg));
+        if constexpr (VB == 8)
+          glw(static_cast<uint64_t*>(S.fb_val))[pos] = gl(static_cast<const uint64_t*>(S.val))[r.k];
+        else if constexpr (VB == 4)
+          glw(static_cast<uint32_t*>(S.fb_val))[pos] = gl(static_cast<const uint32_t*>(S.val))[r.k];
+        else
+          glw(static_cast<uint16_t*>(S.fb_val))[pos] = gl(static_cast<const uint16_t*>(S.val))[r.k];
+      }
+      if (r.end) {
+        for (int64_t q = pos + 1; q < e1; ++q) {
+          glw(S.fb_idx)[q] = 0;
+          if constexpr (VB == 8) glw(static_cast<uint64_t*>(S.fb_val))[q] = 0;
+          else if constexpr (VB == 4) glw(static_cast<uint32_t*>(S.fb_val))[q] = 0;
+          else glw(static_cast<uint16_t*>(S.fb_val))[q] = 0;
+        }
+      }
+      if (r.start) {
+        const uint32_t sg = seg_count(pre);
+        glw(S.fb_off)[sg] = static_cast<int32_t>(e0);
+        glw(S.fb_slot)[slot0 + ord + nst - 1u] = static_cast<int32_t>(sg);
+        const int64_t c4 = e0 / SS_CHUNK;
+        atomicOr(S.fb_bits + (c4 >> 5), 1u << (c4 & 31));
+      }
+    }
+    ord += __shfl(nst, kCvLanes - 1, kCvLanes);
+    run0 = __shfl(r.ks, kCvLanes - 1, kCvLanes);
+    band0 = __shfl(r.band, kCvLanes - 1, kCvLanes);
   }
 }
 
@@ -478,37 +555,38 @@ __global__ void k_make_pieces(const SysDesc* table, int nsys, ScanPiece<uint64_t
   p32[s] = ScanPiece<uint32_t>{S.fb_rseg, l32, S.cv_t32_0, (l32 + kPScanTile - 1) / kPScanTile, nullptr};
 }
 
-// The work tiles of the band-staged forward projection, for all systems:
-// each (system, band) pair's segments cut into tiles of at most `per`
-// segments, in pair order.  One block; each thread takes a run of pairs.
+// The (system, band) pair q of all systems: its system and band.
+__device__ inline void pair_of(const SysDesc* table, int nsys, int q, int* sys, int* band) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].fb_pair0 <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  *sys = lo;
+  *band = q - table[lo].fb_pair0;
+}
+
+// The work tiles per (system, band) pair: its chunks cut into ceil(chunks
+// / q) tiles; their exclusive scan into pair_t0 (npairs + 1) and the total
+// into ntiles[0].  One block; each thread takes a run of pairs.
 constexpr int kTileThreads = 1024;
-__global__ __launch_bounds__(kTileThreads) void k_band_tiles(const SysDesc* table, int nsys, int npairs, int per,
-                                                             BandTile* tiles, int32_t* ntiles) {
+__global__ __launch_bounds__(kTileThreads) void k_band_pairs(const SysDesc* table, int nsys, int npairs, int q,
+                                                             int32_t* pair_t0, int32_t* ntiles) {
   __shared__ int32_t tot[kTileThreads];
   const int chunk = (npairs + kTileThreads - 1) / kTileThreads;
   const int q0 = static_cast<int>(threadIdx.x) * chunk;
   const int q1 = min(npairs, q0 + chunk);
-  auto pair_range = [&](int q, int* sys, int* band, int32_t* a, int32_t* b) {
-    int lo = 0, hi = nsys - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (table[mid].fb_pair0 <= q) lo = mid;
-      else hi = mid - 1;
-    }
-    const SysDesc& S = table[lo];
-    const int bnd = q - S.fb_pair0;
-    *sys = lo;
-    *band = bnd;
-    *a = static_cast<int32_t>(seg_count(gl(S.fb_len)[static_cast<int64_t>(bnd) * S.m]));
-    *b = static_cast<int32_t>(seg_count(gl(S.fb_len)[static_cast<int64_t>(bnd + 1) * S.m]));
+  auto tiles_of = [&](int p) {
+    int sy, bd;
+    pair_of(table, nsys, p, &sy, &bd);
+    const SysDesc& S = table[sy];
+    const int64_t e0 = seg_entries(gl(S.fb_len)[static_cast<int64_t>(bd) * S.m]);
+    const int64_t e1 = seg_entries(gl(S.fb_len)[static_cast<int64_t>(bd + 1) * S.m]);
+    return static_cast<int32_t>((e1 - e0) / SS_CHUNK + q - 1) / q;
   };
   int32_t mine = 0;
-  for (int q = q0; q < q1; ++q) {
-    int sy, bd;
-    int32_t a, b;
-    pair_range(q, &sy, &bd, &a, &b);
-    mine += (b - a + per - 1) / per;
-  }
+  for (int p = q0; p < q1; ++p) mine += tiles_of(p);
   tot[threadIdx.x] = mine;
   __syncthreads();
   for (int o = 1; o < kTileThreads; o <<= 1) {
@@ -518,97 +596,282 @@ __global__ __launch_bounds__(kTileThreads) void k_band_tiles(const SysDesc* tabl
     __syncthreads();
   }
   int32_t t = tot[threadIdx.x] - mine;
-  for (int q = q0; q < q1; ++q) {
-    int sy, bd;
-    int32_t a, b;
-    pair_range(q, &sy, &bd, &a, &b);
-    for (int32_t s0 = a; s0 < b; s0 += per) tiles[t++] = BandTile{sy, bd, s0, min(b, s0 + per)};
+  for (int p = q0; p < q1; ++p) {
+    pair_t0[p] = t;
+    t += tiles_of(p);
   }
   if (threadIdx.x == kTileThreads - 1) {
+    pair_t0[npairs] = tot[kTileThreads - 1];
     ntiles[0] = tot[kTileThreads - 1];
-    ntiles[1] = 0;  // the band kernel's tile queue
   }
 }
 
-// Band-staged forward projection: grid-stride over the work tiles.  Per
-// tile: the image band into LDS, then RPW segments per wavefront (L lanes
-// each), each segment's sum into its row's slot.  The offsets and slot of
-// the next pass's segment are loaded before this pass's streams, so a pass
-// does not start with a dependent load.  WPB wavefronts per block: 16 when a
-// band takes 64 KB of LDS (two blocks per compute unit), else 8; both held
-// to 8 wavefronts per SIMD (at most 64 registers).
-template <int NV, int WT, int RPW, int P, int WPB>
-__global__ __launch_bounds__(kWave* WPB) __attribute__((amdgpu_waves_per_eu(8))) void k_band_fp(const SysDesc* __restrict__ table,
-                                                          const BandTile* __restrict__ tiles,
-                                                          const int32_t* __restrict__ ntiles_p,
-                                                          int32_t* __restrict__ queue,
-                                                          const Params* __restrict__ prm, int parity) {
-  extern __shared__ float xs[];
-  __shared__ int32_t next_tile;
-  constexpr int L = kWave / RPW;
-  constexpr int SPP = WPB * RPW;  // segments per pass of the block
-  const int ntiles = *gl(ntiles_p);
-  const int lg = prm->band_lg;
-  const int glane = lane_id() % L;
-  const int grp = wave_id() * RPW + lane_id() / L;
-  // tiles are taken from a queue (a counter that k_band_fin resets), so a
-  // block that drew short tiles takes more; which block sums a tile does not
-  // change its result
-  for (;;) {
-    if (threadIdx.x == 0) next_tile = atomicAdd(queue, 1);
-    __syncthreads();
-    const int t = next_tile;
-    if (t >= ntiles) break;
-    const BandTile T = tiles[t];
-    const SysDesc& S = table[__builtin_amdgcn_readfirstlane(T.sys)];
-    if (*gl(&S.st->stop)) {
-      __syncthreads();  // next_tile is rewritten by the next draw
-      continue;
-    }
-    // the first pass's segment, before the band is staged
-    int sg = T.s0 + grp;
-    int sc = sg < T.s1 ? sg : T.s1 - 1;
-    int64_t lo = gl(S.fb_off)[sc], hi = gl(S.fb_off)[sc + 1];
-    int slot = gl(S.fb_slot)[sc];
-    const int64_t j0 = static_cast<int64_t>(T.band) << lg;
-    const int64_t cnt = min(static_cast<int64_t>(1) << lg, S.n - j0);
-    stage_contiguous<NV, kWave * WPB>(xs, S.f[parity] + j0 * NV, cnt);
-    __syncthreads();
-    for (int sb = T.s0; sb < T.s1; sb += SPP) {
-      const bool valid = sg < T.s1;
-      const int64_t clo = lo, chi = valid ? hi : lo;
-      const int cslot = slot;
-      // the next pass's segment
-      sg += SPP;
-      sc = sg < T.s1 ? sg : T.s1 - 1;
-      lo = gl(S.fb_off)[sc];
-      hi = gl(S.fb_off)[sc + 1];
-      slot = gl(S.fb_slot)[sc];
-      float acc[NV];
+// First segment in [a, b) whose offset is >= e (offsets ascend).
+__device__ inline int32_t seg_lower_bound(const int32_t* off, int32_t a, int32_t b, int64_t e) {
+  while (a < b) {
+    const int32_t mid = a + ((b - a) >> 1);
+    if (gl(off)[mid] < e) a = mid + 1;
+    else b = mid;
+  }
+  return a;
+}
+
+// One thread per work tile: tile j of its pair holds the segments that
+// start in the pair's chunks [j q, (j + 1) q).
+__global__ void k_band_tile_fill(const SysDesc* table, int nsys, int npairs, int q, const int32_t* pair_t0,
+                                 const int32_t* ntiles, BandTile* tiles) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= gl(ntiles)[0]) return;
+  int lo = 0, hi = npairs - 1;  // the last pair whose first tile is <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (gl(pair_t0)[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  int sy, bd;
+  pair_of(table, nsys, lo, &sy, &bd);
+  const SysDesc& S = table[sy];
+  const uint64_t ba = gl(S.fb_len)[static_cast<int64_t>(bd) * S.m];
+  const uint64_t bb = gl(S.fb_len)[static_cast<int64_t>(bd + 1) * S.m];
+  const int32_t a = static_cast<int32_t>(seg_count(ba)), b = static_cast<int32_t>(seg_count(bb));
+  const int64_t e0 = seg_entries(ba);
+  const int64_t j = t - gl(pair_t0)[lo];
+  const bool last = t + 1 == gl(pair_t0)[lo + 1];
+  const int64_t qe = static_cast<int64_t>(q) * SS_CHUNK;
+  const int32_t s0 = seg_lower_bound(S.fb_off, a, b, e0 + j * qe);
+  const int32_t s1 = last ? b : seg_lower_bound(S.fb_off, a, b, e0 + (j + 1) * qe);
+  BandTile T;
+  T.sys = sy;
+  T.band = bd;
+  T.s0 = s0;
+  T.s1 = s1;
+  T.c0 = gl(S.fb_off)[s0] / SS_CHUNK;
+  T.c1 = gl(S.fb_off)[s1] / SS_CHUNK;
+  T.pad[0] = T.pad[1] = 0;
+  int32_t* dst = reinterpret_cast<int32_t*>(tiles + t);
+  const int32_t* src = reinterpret_cast<const int32_t*>(&T);
 #pragma unroll
-      for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-      line_dot_lds<NV, WT, L, P>(S.fb_idx, S.fb_val, xs, clo, chi, glane, acc, (1u << lg) - 1u);
+  for (int w = 0; w < 8; ++w) glw(dst)[w] = src[w];
+}
+
+// The loads of U windows of a band tile: per lane its chunk's indices,
+// values and the word of start bits that holds its chunk's bit.
+template <int NV, int U>
+struct BandBatch {
+  u32x2 ci[U];
+  Vec<NV> v[U][SS_CHUNK];
+  uint32_t bw[U];
+};
+
+// A wavefront's walk over one tile; the carried segment's state; the
+// wavefront's LDS buffer of finished segment sums (kSegBuf segments from
+// buf_base on), written to memory in contiguous runs.
+
+template <int NV>
+struct BandWalk {
+  const uint16_t* tidx;
+  const char* tval;
+  const uint32_t* bits;
+  float* buf;
+  int64_t c0;
+  int32_t nch;
+  int32_t seg_base;  // the segment of the next window's first start
+  int32_t carry_seg;
+  int32_t buf_base;
+  bool carry;        // a segment runs on from the previous window
+  float carry_sum[NV];
+};
+
+// Writes the buffered sums of segments [buf_base, end) (the whole wavefront:
+// 64 consecutive segments per store) and moves the buffer on to `end`.
+template <int NV>
+__device__ inline void band_flush(BandWalk<NV>& W, int32_t end, float* part, int lane) {
+  __builtin_amdgcn_wave_barrier();
+  float* dst = part + static_cast<int64_t>(W.buf_base) * NV;  // the run's first sum (uniform)
+  const int32_t cnt = end - W.buf_base;  // at most kSegBuf
 #pragma unroll
-      for (int h = 0; h < NV; ++h) acc[h] = group_sum<L>(acc[h]);
-      if (valid && glane == 0) {
-        Vec<NV> pv;
+  for (int k = 0; k < kSegBuf / kWave; ++k) {
+    const int32_t i = k * kWave + lane;
+    if (i < cnt) store_vec<NV>(dst, i, lds_vec<NV>(W.buf, static_cast<uint32_t>(i)));
+  }
+  __builtin_amdgcn_wave_barrier();
+  W.buf_base = end;
+}
+
+template <int NV>
+__device__ inline void band_put(const BandWalk<NV>& W, int32_t seg, const float* v) {
 #pragma unroll
-        for (int h = 0; h < NV; ++h) pv.v[h] = acc[h];
-        store_vec<NV>(S.fb_part, cslot, pv);
+  for (int h = 0; h < NV; ++h) W.buf[(seg - W.buf_base) * NV + h] = v[h];
+}
+
+template <int NV, int WT, int U>
+__device__ inline void band_load(BandBatch<NV, U>& B, const BandWalk<NV>& W, int32_t wb, int lane) {
+  constexpr uint32_t kChunkValBytes = SS_CHUNK * NV * (WT == SS_F32 ? 4 : 2);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int32_t c = wb + u * kWin + lane;
+    // byte offsets in 32 bits: the loads keep the tile's bases in scalar registers
+    const uint32_t cc = static_cast<uint32_t>(c < W.nch ? c : W.nch - 1);
+    B.ci[u] = *gl(reinterpret_cast<const u32x2*>(reinterpret_cast<const char*>(W.tidx) + cc * 8u));
+    load_val_chunk<NV, WT>(W.tval + cc * kChunkValBytes, 0, B.v[u]);
+    B.bw[u] = gl(W.bits)[(static_cast<uint32_t>(W.c0 & 31) + cc) >> 5];
+  }
+}
+
+// Per window: the chunk's products from the band in LDS, the start mask (a
+// ballot of the chunks' start bits) and a segmented scan (the batch's
+// windows independently, so their work overlaps).  Then in window order:
+// the lane holding a segment's last chunk stores the segment's sum; the
+// segment still open at the window's last lane is carried into the next
+// window, whose lanes before its first start add to it, and is stored once a
+// window starts a new segment or the tile ends.  The carried sum grows
+// window by window, in order: results are reproducible.  Finished sums go to
+// the wavefront's LDS buffer, which is written out once it holds at least
+// kSegBuf - 64 of them (a window finishes at most 64 more) and at the tile's
+// end.
+template <int NV, int U>
+__device__ inline void band_windows(const BandBatch<NV, U>& B, BandWalk<NV>& W, int32_t wb, const float* xs,
+                                    uint32_t xmask, float* part, int lane) {
+  const uint64_t le_mask = ~uint64_t{0} >> (kWave - 1 - lane);
+  float p[U][NV];
+  uint64_t m[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int32_t c = wb + u * kWin + lane;
+    const bool in = c < W.nch;
+    m[u] = __ballot(in && ((B.bw[u] >> ((W.c0 + c) & 31)) & 1u) != 0);
+    chunk_dot_lds<NV>(B.ci[u], B.v[u], xs, xmask, p[u]);
+#pragma unroll
+    for (int h = 0; h < NV; ++h) p[u][h] = in ? p[u][h] : 0.0f;
+    seg_scan64<NV>(p[u], start_dist(m[u] & le_mask, lane));
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int32_t cw = wb + u * kWin;  // the window's first chunk
+    if (cw >= W.nch) break;
+    const int32_t c = cw + lane;
+    const bool tile_ends = cw + kWin >= W.nch;  // the tile's last window
+    if (W.carry) {
+      // lanes before the first start (all valid lanes if none) continue it
+      const int first = m[u] ? static_cast<int>(__builtin_ctzll(m[u])) : kWin;
+      const int hl = min(first, W.nch - cw) - 1;
+      if (hl >= 0) {
+#pragma unroll
+        for (int h = 0; h < NV; ++h)
+          W.carry_sum[h] += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[u][h]), hl));
+      }
+      if (m[u] != 0 || tile_ends) {
+        if (lane == 0) band_put<NV>(W, W.carry_seg, W.carry_sum);
+        W.carry = false;
       }
     }
-    __syncthreads();  // the next tile overwrites xs
+    // segments that start in this window: stored from their last lane,
+    // except the one still open at lane 63, which is carried
+    const uint64_t le = m[u] & le_mask;
+    const bool next_starts = lane < kWave - 1 && ((m[u] >> (lane + 1)) & 1u) != 0;
+    if (c < W.nch && le != 0 && (next_starts || c == W.nch - 1)) band_put<NV>(W, W.seg_base + __popcll(le) - 1, p[u]);
+    if (m[u] != 0 && !tile_ends) {
+      W.carry = true;
+      W.carry_seg = W.seg_base + __popcll(m[u]) - 1;
+#pragma unroll
+      for (int h = 0; h < NV; ++h)
+        W.carry_sum[h] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[u][h]), kWave - 1));
+    }
+    W.seg_base += __popcll(m[u]);
+    const int32_t done = W.carry ? W.carry_seg : W.seg_base;  // segments below are finished
+    if (done - W.buf_base >= kSegBuf - kWin || tile_ends) band_flush<NV>(W, done, part, lane);
+  }
+}
+
+// One work tile of the band-staged forward projection, by one wavefront, in
+// batches of U windows of 64 chunks (one chunk per lane): the next batch's
+// loads are issued before the current batch is summed, so the wavefront
+// always has loads in flight.  They are issued even past the tile's end (the
+// clamped chunk is re-read): the compiler then counts them, and waits only
+// for the batch it sums.
+template <int NV, int WT, int U>
+__device__ inline void band_tile(const SysDesc& S, const int32_t* tp, const float* xs, uint32_t xmask, float* buf,
+                                 int lane) {
+  constexpr uint32_t kChunkValBytes = SS_CHUNK * NV * (WT == SS_F32 ? 4 : 2);
+  constexpr int32_t kStep = kWin * U;
+  BandWalk<NV> W;
+  W.seg_base = __builtin_amdgcn_readfirstlane(tp[2]);
+  W.c0 = __builtin_amdgcn_readfirstlane(tp[4]);
+  W.nch = __builtin_amdgcn_readfirstlane(tp[5]) - static_cast<int32_t>(W.c0);
+  if (W.nch <= 0) return;
+  W.tidx = S.fb_idx + W.c0 * SS_CHUNK;
+  W.tval = static_cast<const char*>(S.fb_val) + W.c0 * kChunkValBytes;
+  W.bits = S.fb_bits + (W.c0 >> 5);  // the word of the tile's first chunk
+  W.buf = buf;
+  W.buf_base = W.seg_base;
+  W.carry = false;
+  W.carry_seg = 0;
+#pragma unroll
+  for (int h = 0; h < NV; ++h) W.carry_sum[h] = 0.0f;
+  BandBatch<NV, U> a, b;
+  band_load<NV, WT, U>(a, W, 0, lane);
+  for (int32_t wb = 0; wb < W.nch; wb += 2 * kStep) {
+    band_load<NV, WT, U>(b, W, wb + kStep, lane);
+    band_windows<NV, U>(a, W, wb, xs, xmask, S.fb_part, lane);
+    if (wb + kStep >= W.nch) break;
+    band_load<NV, WT, U>(a, W, wb + 2 * kStep, lane);
+    band_windows<NV, U>(b, W, wb + kStep, xs, xmask, S.fb_part, lane);
+  }
+}
+
+// Band-staged forward projection.  Block b takes the tiles [b T/G, (b+1)
+// T/G) of the T tiles (G blocks), in runs of one band (tiles of a band are
+// adjacent): per run the block loads the band of the image into LDS and its
+// wavefronts take the run's tiles in turn, each tile whole (band_tile).  Only
+// a change of band synchronises the block.  At most 64 registers (80 with
+// batches of two windows), so that 8 (6) wavefronts per SIMD fit.
+template <int NV, int WT, int U>
+__global__ __launch_bounds__(kWave* kBandWaves) __attribute__((amdgpu_waves_per_eu(U > 1 ? 6 : 8))) void k_band_fp(
+    const SysDesc* __restrict__ table, const BandTile* __restrict__ tiles, const int32_t* __restrict__ ntiles_p,
+    const Params* __restrict__ prm, int parity) {
+  extern __shared__ float xs[];
+  constexpr int T = kWave * kBandWaves;
+  const int lg = prm->band_lg;
+  const uint32_t xmask = (1u << lg) - 1u;
+  const int lane = lane_id();
+  const int64_t nt = *gl(ntiles_p);
+  const int64_t t0 = static_cast<int64_t>(blockIdx.x) * nt / gridDim.x;
+  const int64_t t1 = static_cast<int64_t>(blockIdx.x + 1) * nt / gridDim.x;
+  const int32_t* tw = reinterpret_cast<const int32_t*>(tiles);
+  constexpr int kTw = sizeof(BandTile) / sizeof(int32_t);
+  for (int64_t g0 = t0; g0 < t1;) {
+    const int sys = __builtin_amdgcn_readfirstlane(tw[g0 * kTw]);
+    const int band = __builtin_amdgcn_readfirstlane(tw[g0 * kTw + 1]);
+    // the end of the run of tiles of this band (every wavefront finds it)
+    int64_t g1 = g0 + 1;
+    for (;;) {
+      const int64_t tq = g1 + lane;
+      const bool same = tq < t1 && tw[tq * kTw] == sys && tw[tq * kTw + 1] == band;
+      const uint64_t diff = ~__ballot(same);
+      const int run = diff ? static_cast<int>(__builtin_ctzll(diff)) : kWave;
+      g1 += run;
+      if (run < kWave) break;
+    }
+    const SysDesc& S = table[sys];
+    if (!*gl(&S.st->stop)) {
+      const int64_t j0 = static_cast<int64_t>(band) << lg;
+      stage_contiguous<NV, T>(xs, S.f[parity] + j0 * NV, min(static_cast<int64_t>(1) << lg, S.n - j0));
+      __syncthreads();
+      float* buf = xs + (NV << lg) + wave_id() * (kSegBuf * NV);
+      for (int64_t t = g0 + wave_id(); t < g1; t += kBandWaves)
+        band_tile<NV, WT, U>(S, tw + t * kTw, xs, xmask, buf, lane);
+      __syncthreads();  // the next run's band overwrites xs
+    }
+    g0 = g1;
   }
 }
 
 // The residual of the band-staged forward projection: per row, its
-// partials added in band order, r = p - q, z = r / W, and the block's FP64
+// segments' sums added in band order (through the row's slots), r = p - q, z = r / W, and the block's FP64
 // partial of |r|^2; the first block of a system moves the iterate index on.
 template <int NV>
-__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys,
-                                                          int32_t* __restrict__ queue) {
+__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys) {
   __shared__ double red[kFinThreads / kWave];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;  // for the next band launch
   const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<0>(table, nsys, blockIdx.x));
   const SysDesc& S = table[s];
   if (*gl(&S.st->stop)) return;
@@ -621,7 +884,7 @@ __global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restr
     for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
     const uint32_t q0 = gl(S.fb_rseg)[i], q1 = gl(S.fb_rseg)[i + 1];
     for (uint32_t q = q0; q < q1; ++q) {
-      const Vec<NV> pv = load_vec<NV>(S.fb_part, q);
+      const Vec<NV> pv = load_vec<NV>(S.fb_part, gl(S.fb_slot)[q]);
 #pragma unroll
       for (int h = 0; h < NV; ++h) acc[h] += pv.v[h];
     }
@@ -844,10 +1107,10 @@ struct Layout {
   // interleaved copies of the row (forward) and column (back) streams
   std::vector<size_t> fi_idx, fi_val, bi_idx, bi_val;
   // staged forms (per system) and their set-up scratch (shared)
-  std::vector<size_t> fb_idx, fb_val, fb_len, fb_rseg, fb_off, fb_slot, fb_part, bt_idx, bt_meta, bt_runs;
-  size_t fb_len_lo = 0, fb_len_hi = 0, fb_rseg_lo = 0, fb_rseg_hi = 0;
-  size_t tiles = 0, ntiles = 0, pieces64 = 0, pieces32 = 0, tsum64 = 0, tsum32 = 0, info = 0;
-  int64_t tile_cap = 0, t64 = 0, t32 = 0;
+  std::vector<size_t> fb_idx, fb_val, fb_len, fb_rseg, fb_off, fb_slot, fb_part, fb_bits, bt_idx, bt_meta, bt_runs;
+  size_t fb_len_lo = 0, fb_len_hi = 0, fb_rseg_lo = 0, fb_rseg_hi = 0, fb_bits_lo = 0, fb_bits_hi = 0;
+  size_t tiles = 0, ntiles = 0, pair_t0 = 0, pieces64 = 0, pieces32 = 0, tsum64 = 0, tsum32 = 0, info = 0;
+  int64_t tile_cap = 0, t64 = 0, t32 = 0, npairs = 0;
 };
 
 // Stream form of each kernel from the chunked option: bit 2 (bit 3) selects
@@ -869,9 +1132,14 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
 // Staged-form sizes shared by the layout and the set-up.
 inline int band_lg_of(const ss_sart_opts* o) { return o->band_width ? __builtin_ctz(o->band_width) : 12; }
 inline int tile_lg_of(const ss_sart_opts* o) { return o->tile_cols ? __builtin_ctz(o->tile_cols) : 10; }
-inline int tile_segs_of(const ss_sart_opts* o) { return o->tile_segments ? o->tile_segments : 1024; }
+inline int band_q_of(const ss_sart_opts* o) { return (o->tile_entries ? o->tile_entries : 4096) / SS_CHUNK; }
 inline int64_t bands_of(const ss_system& S, int lg) { return (S.n + (int64_t{1} << lg) - 1) >> lg; }
 inline int64_t seg_bound(const ss_system& S, int lg) { return std::min<int64_t>(S.nnz, bands_of(S, lg) * S.m) + 1; }
+// entries of the band-major copy at most: every segment padded by up to
+// SS_CHUNK - 1 entries
+inline int64_t padded_bound(const ss_system& S, int lg) {
+  return S.nnz + (SS_CHUNK - 1) * (seg_bound(S, lg) - 1) + SS_CHUNK;
+}
 inline int64_t pscan_tiles(int64_t len) { return (len + kPScanTile - 1) / kPScanTile; }
 inline size_t stream_cap(int64_t nnz) { return static_cast<size_t>(ss_stream_len(nnz) > 0 ? ss_stream_len(nnz) : 4); }
 
@@ -915,21 +1183,23 @@ Layout make_layout(const ss_system* sys, int nsys, const ss_sart_opts* opt) {
   }
   if (stg & 1) {
     const int lg = band_lg_of(opt);
-    const int per = tile_segs_of(opt);
+    const int q = band_q_of(opt);
     for (int s = 0; s < nsys; ++s) {
       const ss_system& S = sys[s];
       const int64_t nsb = seg_bound(S, lg);
+      const int64_t pe = padded_bound(S, lg);
       L.fb_idx.push_back(o);
-      o += align256(sizeof(uint16_t) * stream_cap(S.nnz));
+      o += align256(sizeof(uint16_t) * static_cast<size_t>(pe));
       L.fb_val.push_back(o);
-      o += align256(value_bytes(S) * stream_cap(S.nnz));
+      o += align256(value_bytes(S) * static_cast<size_t>(pe));
       L.fb_off.push_back(o);
       o += align256(sizeof(int32_t) * static_cast<size_t>(nsb + 1));
       L.fb_slot.push_back(o);
       o += align256(sizeof(int32_t) * static_cast<size_t>(nsb));
       L.fb_part.push_back(o);
       o += align256(sizeof(float) * S.nvals * static_cast<size_t>(nsb));
-      L.tile_cap += bands_of(S, lg) + (nsb + per - 1) / per;
+      L.tile_cap += bands_of(S, lg) + pe / SS_CHUNK / q + 1;
+      L.npairs += bands_of(S, lg);
       L.t64 += pscan_tiles(bands_of(S, lg) * S.m + 1);
       L.t32 += pscan_tiles(S.m + 1);
     }
@@ -946,6 +1216,15 @@ Layout make_layout(const ss_system* sys, int nsys, const ss_sart_opts* opt) {
       o += align256(sizeof(uint32_t) * static_cast<size_t>(sys[s].m + 1));
     }
     L.fb_rseg_hi = o;
+    L.fb_bits_lo = o;
+    for (int s = 0; s < nsys; ++s) {
+      L.fb_bits.push_back(o);
+      // one bit per chunk, plus the words a window's mask reads past the last
+      o += align256(sizeof(uint32_t) * static_cast<size_t>(padded_bound(sys[s], lg) / SS_CHUNK / 32 + 3));
+    }
+    L.fb_bits_hi = o;
+    L.pair_t0 = o;
+    o += align256(sizeof(int32_t) * static_cast<size_t>(L.npairs + 1));
     L.tiles = o;
     o += align256(sizeof(BandTile) * static_cast<size_t>(L.tile_cap + 1));
     L.ntiles = o;
@@ -982,7 +1261,7 @@ Layout make_layout(const ss_system* sys, int nsys, const ss_sart_opts* opt) {
 
 struct Cfg {
   int nv, wt, rpw, cpw, xcd, u, pers, ch;
-  int stg, blg, tlg, spt;  // staged forms: bits, log2 band width, log2 tile columns, segments per tile
+  int stg, blg, tlg, bq;  // staged forms: bits, log2 band width, log2 tile columns, chunks per forward tile
 };
 
 ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const char* fn) {
@@ -1026,20 +1305,22 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
   if (o->staged < 0 || o->staged > 3) return fail(SS_E_ARG, "%s: staged must be 0..3", fn);
   if (o->residual_every > 1) return fail(SS_E_ARG, "%s: residual_every is for ordered subsets (0 or 1 here)", fn);
   auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
-  if (o->band_width && (!pow2(o->band_width) || o->band_width < 1024 || o->band_width > 16384 ||
-                        o->band_width * sys[0].nvals * 4 > 65536))
-    return fail(SS_E_ARG, "%s: band_width must be a power of two in 1024..16384 with band_width*nvals*4 <= 65536",
-                fn);
+  if (o->band_width && (!pow2(o->band_width) || o->band_width < 1024 || o->band_width > 16384))
+    return fail(SS_E_ARG, "%s: band_width must be a power of two in 1024..16384", fn);
   if (o->tile_cols && (!pow2(o->tile_cols) || o->tile_cols < 64 || o->tile_cols > 8192))
     return fail(SS_E_ARG, "%s: tile_cols must be a power of two in 64..8192", fn);
-  if (o->tile_segments && (o->tile_segments < 64 || o->tile_segments > 65536))
-    return fail(SS_E_ARG, "%s: tile_segments must be in 64..65536", fn);
+  if (o->tile_entries && (o->tile_entries % 256 != 0 || o->tile_entries < 1024 || o->tile_entries > 65536))
+    return fail(SS_E_ARG, "%s: tile_entries must be a multiple of 256 in 1024..65536", fn);
+  if ((o->staged & 1) && band_lds_bytes(sys[0].nvals, band_lg_of(o)) > 65536)
+    return fail(SS_E_ARG, "%s: the staged forward projection needs band_width*nvals*4 + 4096*nvals <= 65536", fn);
   if (o->staged) {
     for (int s = 0; s < nsys; ++s) {
       const ss_system& S = sys[s];
       if (((o->staged & 1) && S.row_lanes) || ((o->staged & 2) && S.col_lanes))
         return fail(SS_E_ARG, "%s: the staged forms need lines in ascending order (row_lanes/col_lanes 0)", fn);
       if (S.nnz >= INT32_MAX) return fail(SS_E_ARG, "%s: the staged forms need nnz < 2^31", fn);
+      if ((o->staged & 1) && padded_bound(S, band_lg_of(o)) >= INT32_MAX)
+        return fail(SS_E_ARG, "%s: system %d: the padded band-major copy needs fewer than 2^31 entries", fn, s);
       if ((o->staged & 1) && bands_of(S, band_lg_of(o)) * S.m + 1 >= INT32_MAX)
         return fail(SS_E_ARG, "%s: system %d has too many (band, row) pairs for the staged forward form", fn, s);
       if ((o->staged & 2) && S.m > (int64_t{1} << 17))
@@ -1088,7 +1369,7 @@ Cfg choose_cfg(const ss_system* sys, int nsys, const ss_sart_opts* o) {
   c.stg = o->staged;
   c.blg = band_lg_of(o);
   c.tlg = tile_lg_of(o);
-  c.spt = tile_segs_of(o);
+  c.bq = band_q_of(o);
   if (c.stg & 1) c.rpw = o->rows_per_wave ? o->rows_per_wave : 4;
   if (c.stg & 2) c.cpw = o->cols_per_wave ? o->cols_per_wave : 8;
   return c;
@@ -1110,38 +1391,26 @@ ss_status interleave(const int64_t* ptr, int64_t lines, const int32_t* idx, cons
   return SS_OK;
 }
 
-// Writes the descriptor table and resets states (stream-ordered kernels);
-// writes the interleaved stream copies where a kernel reads them.
-// Launch shapes of the staged kernels (their own, not the unstaged ones').
-// Wavefronts per block of the band kernel for a band of 2^lg voxels.
-inline int band_waves(int nv, int lg) { return (size_t{4} << lg) * nv > 40960 ? 16 : 8; }
-
-template <int NV, int WT, int RPW, int P, int WPB>
-const void* band_kernel() {
-  return reinterpret_cast<const void*>(k_band_fp<NV, WT, RPW, P, WPB>);
-}
-
 // Grid of the band-staged forward kernel: the blocks that fit on the device
 // at once (its LDS decides), at most one per possible tile; each block then
-// loops over the tiles.
+// takes a contiguous run of the tiles.
 uint32_t band_grid(const Cfg& c, const Layout& L) {
   static std::mutex mu;
-  static std::map<std::tuple<int, int, int>, uint32_t> cap;
+  static std::map<std::tuple<int, int, int, int>, uint32_t> cap;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  const size_t lds = (size_t{4} << c.blg) * c.nv;
+  const size_t lds = band_lds_bytes(c.nv, c.blg);
   uint32_t resident;
   {
     std::lock_guard<std::mutex> lock(mu);
-    auto key = std::make_tuple(dev, c.nv, c.blg);
+    auto key = std::make_tuple(dev, c.nv, c.blg, c.bq);
     auto it = cap.find(key);
     if (it == cap.end()) {
       int cus = 0, per = 0;
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      const int wpb = band_waves(c.nv, c.blg);
-      const void* k = c.nv == 2 ? (wpb == 16 ? band_kernel<2, SS_F32, 8, 2, 16>() : band_kernel<2, SS_F32, 8, 2, 8>())
-                                : (wpb == 16 ? band_kernel<1, SS_F32, 8, 2, 16>() : band_kernel<1, SS_F32, 8, 2, 8>());
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kWave * wpb, lds);
+      const void* k = c.nv == 2 ? reinterpret_cast<const void*>(k_band_fp<2, SS_F32, 1>)
+                                : reinterpret_cast<const void*>(k_band_fp<1, SS_F32, 1>);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kWave * kBandWaves, lds);
       it = cap.emplace(key, static_cast<uint32_t>(std::max(1, cus) * std::max(1, per))).first;
     }
     resident = it->second;
@@ -1163,6 +1432,8 @@ ss_status build_staged(const ss_system* sys, int nsys, const Cfg& c, const Layou
     const int64_t n32 = static_cast<int64_t>((L.fb_rseg_hi - L.fb_rseg_lo) / sizeof(uint32_t));
     k_fill_zero<uint64_t><<<2048, 256, 0, st>>>(reinterpret_cast<uint64_t*>(ws + L.fb_len_lo), n64);
     k_fill_zero<uint32_t><<<512, 256, 0, st>>>(reinterpret_cast<uint32_t*>(ws + L.fb_rseg_lo), n32);
+    const int64_t nbits = static_cast<int64_t>((L.fb_bits_hi - L.fb_bits_lo) / sizeof(uint32_t));
+    k_fill_zero<uint32_t><<<512, 256, 0, st>>>(reinterpret_cast<uint32_t*>(ws + L.fb_bits_lo), nbits);
     k_fb_count<<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
     auto* p64 = reinterpret_cast<ScanPiece<uint64_t>*>(ws + L.pieces64);
     auto* p32 = reinterpret_cast<ScanPiece<uint32_t>*>(ws + L.pieces32);
@@ -1180,10 +1451,12 @@ ss_status build_staged(const ss_system* sys, int nsys, const Cfg& c, const Layou
     if (vb == 8) k_fb_fill<8><<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
     else if (vb == 4) k_fb_fill<4><<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
     else k_fb_fill<2><<<g.cv_blocks, kThreads, 0, st>>>(table, nsys, dprm);
-    int npairs = 0;
-    for (int s = 0; s < nsys; ++s) npairs += static_cast<int>(bands_of(sys[s], c.blg));
-    k_band_tiles<<<1, kTileThreads, 0, st>>>(table, nsys, npairs, c.spt, reinterpret_cast<BandTile*>(ws + L.tiles),
-                                             reinterpret_cast<int32_t*>(ws + L.ntiles));
+    const int npairs = static_cast<int>(L.npairs);
+    auto* pt0 = reinterpret_cast<int32_t*>(ws + L.pair_t0);
+    auto* nt = reinterpret_cast<int32_t*>(ws + L.ntiles);
+    k_band_pairs<<<1, kTileThreads, 0, st>>>(table, nsys, npairs, c.bq, pt0, nt);
+    const unsigned tb = static_cast<unsigned>((L.tile_cap + 255) / 256);
+    k_band_tile_fill<<<tb, 256, 0, st>>>(table, nsys, npairs, c.bq, pt0, nt, reinterpret_cast<BandTile*>(ws + L.tiles));
   }
   if (c.stg & 2) {
     int64_t words = 1;
@@ -1205,6 +1478,7 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
   int32_t pairs = 0;
   prm.band_lg = c.blg;
   prm.tile_lg = c.tlg;
+  prm.band_q = c.bq;
   const int64_t rpb = (c.stg & 1) ? kFinThreads : static_cast<int64_t>(c.rpw) * kWPB;
   const int64_t cpb = (c.stg & 2) ? (int64_t{1} << c.tlg) : static_cast<int64_t>(c.cpw) * kWPB;
   DescChunk ch{};
@@ -1252,6 +1526,7 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
       d.fb_idx = reinterpret_cast<uint16_t*>(ws + L.fb_idx[s]);
       d.fb_val = ws + L.fb_val[s];
       d.fb_off = reinterpret_cast<int32_t*>(ws + L.fb_off[s]);
+      d.fb_bits = reinterpret_cast<uint32_t*>(ws + L.fb_bits[s]);
       d.fb_slot = reinterpret_cast<int32_t*>(ws + L.fb_slot[s]);
       d.fb_rseg = reinterpret_cast<uint32_t*>(ws + L.fb_rseg[s]);
       d.fb_part = reinterpret_cast<float*>(ws + L.fb_part[s]);
@@ -1358,7 +1633,8 @@ void launch_bp_u(int cpw, int pers, const Params* prm, const SysDesc* t, int nsy
 }
 
 // Staged kernels: the forward pair (band kernel, then the residual kernel)
-// and the tile-staged back projection.
+// and the tile-staged back projection.  The band kernel loads batches of one
+// window per wavefront (unroll 4) or two (unroll 8).
 template <int NV, int WT, int P>
 void launch_band(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int par, hipStream_t st,
                  Stamp e) {
@@ -1366,28 +1642,10 @@ void launch_band(const Cfg& c, const char* ws, const Layout& L, int nsys, const 
   const SysDesc* t = reinterpret_cast<const SysDesc*>(ws + L.table);
   const BandTile* tiles = reinterpret_cast<const BandTile*>(ws + L.tiles);
   const int32_t* nt = reinterpret_cast<const int32_t*>(ws + L.ntiles);
-  int32_t* queue = const_cast<int32_t*>(nt) + 1;
-  const size_t lds = (size_t{4} << c.blg) * NV;
-  const dim3 grid(g.band_blocks);
-#define SS_BAND(RPW, WPB) \
-  hipExtLaunchKernelGGL(k_band_fp<NV, WT, RPW, P, WPB>, grid, dim3(kWave * WPB), lds, st, e.start, e.mid0, 0, t, \
-                        tiles, nt, queue, prm, par)
-  if (band_waves(NV, c.blg) == 16) {
-    switch (c.rpw) {
-      case 2: SS_BAND(2, 16); break;
-      case 8: SS_BAND(8, 16); break;
-      default: SS_BAND(4, 16); break;
-    }
-  } else {
-    switch (c.rpw) {
-      case 2: SS_BAND(2, 8); break;
-      case 8: SS_BAND(8, 8); break;
-      default: SS_BAND(4, 8); break;
-    }
-  }
-#undef SS_BAND
-  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys,
-                        queue);
+  const size_t lds = band_lds_bytes(NV, c.blg);
+  hipExtLaunchKernelGGL(k_band_fp<NV, WT, P>, dim3(g.band_blocks), dim3(kWave * kBandWaves), lds, st, e.start,
+                        e.mid0, 0, t, tiles, nt, prm, par);
+  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys);
 }
 
 template <int NV, int WT, int P>
@@ -1486,12 +1744,12 @@ struct GraphKey {
   int nsys;
   uint32_t fpb, bpb;
   int nv, wt, rpw, cpw, xcd, u, pers, ch, count;
-  int stg, blg, tlg, spt;
+  int stg, blg, tlg, bq;
   uint32_t bandb;
   bool operator<(const GraphKey& o) const {
-    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, pers, ch, count, stg, blg, tlg, spt, bandb) <
+    return std::tie(device, ws, nsys, fpb, bpb, nv, wt, rpw, cpw, xcd, u, pers, ch, count, stg, blg, tlg, bq, bandb) <
            std::tie(o.device, o.ws, o.nsys, o.fpb, o.bpb, o.nv, o.wt, o.rpw, o.cpw, o.xcd, o.u, o.pers, o.ch,
-                    o.count, o.stg, o.blg, o.tlg, o.spt, o.bandb);
+                    o.count, o.stg, o.blg, o.tlg, o.bq, o.bandb);
   }
 };
 
@@ -1548,7 +1806,7 @@ extern "C" ss_status ss_sart_solve(const ss_system* sys, int32_t nsys, float* co
     int dev = 0;
     SS_HIP_TRY(hipGetDevice(&dev));
     const GraphKey key{dev, workspace, nsys, g.fp_blocks, g.bp_blocks, c.nv, c.wt, c.rpw, c.cpw, c.xcd, c.u, c.pers, c.ch,
-                       chunk, c.stg, c.blg, c.tlg, c.spt, g.band_blocks};
+                       chunk, c.stg, c.blg, c.tlg, c.bq, g.band_blocks};
     auto capture = [&](hipStream_t cs) { launch_iterations(c, ws, L, nsys, g, 0, chunk, cs); };
     if (ss_status s = graph_cache().acquire(key, dev, capture, &graph)) return s;
   }

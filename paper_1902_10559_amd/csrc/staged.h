@@ -7,13 +7,19 @@
 // Each row's entries in one band form a segment (the columns of a row
 // ascend, so a segment is a contiguous part of the row).  A copy of the row
 // streams is laid out band-major: band 0's segments (rows ascending), then
-// band 1's, ..., with 16-bit column indices relative to the band's start.
-// A work tile is a run of segments of one band: its block loads the band of
-// the image into LDS once, then every segment's sum gathers from there, and
-// the segment's partial sum goes to the row's slot.  Rays of every view cross
-// a band, so each image value is read from memory about once per tile
-// instead of once per ray that crosses it.  A second kernel adds each row's
-// partials in band order (a fixed order: results are reproducible), forms
+// band 1's, ..., with 16-bit column indices relative to the band's start,
+// and every segment padded with zero entries to whole chunks of SS_CHUNK
+// entries, so that no chunk holds two segments; a bitmap marks the chunks
+// that start a segment.  A band's chunks are cut into work tiles of about
+// the same number of chunks (whole segments each).  The tiles are dealt to
+// the blocks in contiguous runs; a block loads the band of the image into
+// LDS when its band changes, and each tile is streamed flat by one
+// wavefront, one chunk per lane and 64 consecutive chunks (a window) at a
+// time, with no lane left idle at a segment's end.  Per window a segmented
+// scan across the lanes forms each segment's sum; a segment that runs past
+// its window is carried in registers into the next one.
+// Each segment's sum is stored by segment; a second kernel adds each row's
+// segments in band order (a fixed order: results are reproducible), forms
 // the residual, z and the FP64 residual partials.
 //
 // Back projection, tile-staged.  A tile is a run of Tv consecutive columns
@@ -44,12 +50,26 @@ struct BtMeta {
   int32_t pad;
 };
 
-// One work tile of the band-staged forward projection.
+// One work tile of the band-staged forward projection: segments [s0, s1)
+// of one band of one system, stored as its padded chunks [c0, c1).
 struct BandTile {
   int32_t sys;
   int32_t band;
-  int32_t s0, s1;  // band-major segments [s0, s1)
+  int32_t s0, s1;
+  int32_t c0, c1;
+  int32_t pad[2];
 };
+
+constexpr int kBandWaves = 8;  // wavefronts per band-kernel block
+constexpr int kWin = kWave;    // chunks per window: one per lane
+
+constexpr int kSegBuf = 128;  // finished segment sums a band wavefront buffers
+
+// Bytes of the band kernel's LDS: the band's NV floats per voxel, then per
+// wavefront its buffer of segment sums.
+__host__ __device__ inline size_t band_lds_bytes(int nv, int lg) {
+  return (sizeof(float) * nv << lg) + sizeof(float) * nv * kSegBuf * kBandWaves;
+}
 
 // ------------------------------------------------------------ loads
 // Four 16-bit indices of entries k0 .. k0+3 (k0 a multiple of 4).
@@ -73,6 +93,61 @@ __device__ inline Vec<NV> lds_vec(const float* x, uint32_t i) {
     r.v[0] = x[i];
   }
   return r;
+}
+
+// p = sum over the chunk's SS_CHUNK entries of val * xs[idx] (xs in LDS),
+// in entry order from 0.  Padding entries hold value 0 and index 0.  Every
+// index is cut to `mask` (the band's capacity minus one): no read leaves
+// the band.
+template <int NV>
+__device__ inline void chunk_dot_lds(const u32x2& ci, const Vec<NV>* v, const float* xs, uint32_t mask, float* p) {
+  Vec<NV> x[SS_CHUNK];
+#pragma unroll
+  for (int j = 0; j < SS_CHUNK; ++j) x[j] = lds_vec<NV>(xs, idx16_at(ci, j) & mask);
+#pragma unroll
+  for (int h = 0; h < NV; ++h) {
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < SS_CHUNK; ++j) s = fmaf(v[j].v[h], x[j].v[h], s);
+    p[h] = s;
+  }
+}
+
+// One step of the segmented scan: v += the value CTRL brings from a lower
+// lane, where `take`.
+template <int NV, int CTRL, int ROWS>
+__device__ inline void seg_scan_step(float* v, bool take) {
+#pragma unroll
+  for (int h = 0; h < NV; ++h) {
+    const float t = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[h]), CTRL, ROWS, 0xf, false));
+    v[h] = take ? v[h] + t : v[h];
+  }
+}
+
+// Segmented inclusive scan over the 64 lanes of a wavefront: lane l ends
+// with the sum of lanes a..l, a the last lane <= l that starts a segment,
+// or lane 0 if none does.  `dist` is l - a (l + 1 if no lane <= l starts
+// one).  Steps of 1, 2, 4, 8 lanes within rows of 16 (DPP row shifts), then
+// the ends of rows 0 and 2 into rows 1 and 3 and the end of row 1 into rows
+// 2 and 3 (DPP row broadcasts); a lane adds what a step brings only when no
+// segment starts in the lanes that step spans.  The pattern of additions is
+// fixed: results are reproducible.
+template <int NV>
+__device__ inline void seg_scan64(float* v, int dist) {
+  const int l = lane_id();
+  const int r = l & 15;
+  seg_scan_step<NV, 0x111, 0xf>(v, r >= 1 && dist >= 1);
+  seg_scan_step<NV, 0x112, 0xf>(v, r >= 2 && dist >= 2);
+  seg_scan_step<NV, 0x114, 0xf>(v, r >= 4 && dist >= 4);
+  seg_scan_step<NV, 0x118, 0xf>(v, r >= 8 && dist >= 8);
+  seg_scan_step<NV, 0x142, 0xa>(v, (l & 16) != 0 && dist > r);
+  seg_scan_step<NV, 0x143, 0xc>(v, l >= 32 && dist > l - 32);
+}
+
+// l - (the last lane <= l whose bit is set in `le`, the mask cut to lanes
+// <= l), or l + 1 if none is.
+__device__ inline int start_dist(uint64_t le, int l) {
+  return le ? l - (63 - static_cast<int>(__builtin_clzll(le))) : l + 1;
 }
 
 // acc += sum over entries [lo, hi) of val[k] * xs[idx[k]], xs in LDS, by the
@@ -254,6 +329,9 @@ __host__ __device__ inline uint64_t seg_pack(uint32_t segs, uint32_t entries) {
 }
 __host__ __device__ inline uint32_t seg_count(uint64_t v) { return static_cast<uint32_t>(v >> 32); }
 __host__ __device__ inline uint32_t seg_entries(uint64_t v) { return static_cast<uint32_t>(v); }
+
+// Entries of a segment padded to whole chunks.
+__host__ __device__ inline int64_t pad_chunk(int64_t n) { return (n + SS_CHUNK - 1) & ~int64_t{SS_CHUNK - 1}; }
 
 // First position in [lo, hi) whose column is >= key (columns ascend).
 __device__ inline int64_t col_lower_bound(const int32_t* col, int64_t lo, int64_t hi, int32_t key) {

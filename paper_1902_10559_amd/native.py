@@ -74,7 +74,7 @@ class SartOptsC(C.Structure):
                 ("xcd_remap", C.c_int32), ("zero_start", C.c_int32),
                 ("unroll", C.c_int32), ("persistent", C.c_int32), ("chunked", C.c_int32),
                 ("nonneg", C.c_int32), ("staged", C.c_int32), ("band_width", C.c_int32),
-                ("tile_cols", C.c_int32), ("tile_segments", C.c_int32), ("residual_every", C.c_int32)]
+                ("tile_cols", C.c_int32), ("tile_entries", C.c_int32), ("residual_every", C.c_int32)]
 
 
 class SubsetsC(C.Structure):
@@ -510,14 +510,14 @@ class SartOptions:
     staged: int = 0
     band_width: int = 0
     tile_cols: int = 0
-    tile_segments: int = 0
+    tile_entries: int = 0
     residual_every: int = 0
 
     def c(self) -> SartOptsC:
         return SartOptsC(self.lam, self.max_iter, self.tol, self.check_every,
                          int(self.use_graph), self.rows_per_wave, self.cols_per_wave,
                          self.xcd_remap, int(self.zero_start), self.unroll, self.persistent, self.chunked,
-                         int(self.nonneg), self.staged, self.band_width, self.tile_cols, self.tile_segments,
+                         int(self.nonneg), self.staged, self.band_width, self.tile_cols, self.tile_entries,
                          self.residual_every)
 
 

@@ -62,13 +62,27 @@ def test_staged_split_sart_cfg1_matches_oracle(staged, rpw, cpw, unroll):
     _check_split(pr, S, f[0], h[0], 20)
 
 
-@pytest.mark.parametrize("band,tile,segs", [(1024, 64, 64), (4096, 1024, 1024), (2048, 256, 100)])
-def test_staged_split_sart_cfg2_matches_oracle(band, tile, segs):
-    # cfg2: 32768 columns, ragged last tile of segments per band
-    banner(f"staged cfg2 band={band} tile={tile} segs={segs}")
+@pytest.mark.parametrize("band,tile,entries,unroll", [(1024, 64, 1024, 4), (4096, 1024, 65536, 8),
+                                                    (2048, 256, 4096, 4), (4096, 512, 16384, 8)])
+def test_staged_split_sart_cfg2_matches_oracle(band, tile, entries, unroll):
+    # cfg2: 32768 columns; several work tiles per band, ragged last tiles
+    banner(f"staged cfg2 band={band} tile={tile} entries={entries} unroll={unroll}")
     pr = problem(2)
     _, _, S = _fold(pr)
-    f, h, status, it = _solve([S], 20, staged=3, band_width=band, tile_cols=tile, tile_segments=segs)
+    f, h, status, it = _solve([S], 20, staged=3, band_width=band, tile_cols=tile, tile_entries=entries,
+                              unroll=unroll)
+    _check_split(pr, S, f[0], h[0], 20)
+
+
+@pytest.mark.parametrize("entries", [1024, 4096])
+def test_staged_segments_spanning_many_windows_match_oracle(entries):
+    # dense rows: a row's segment in a band of 1024 columns holds up to 1024
+    # entries (256 chunks, four windows of 64 chunks), so segments run across
+    # windows and tiles hold a few segments each
+    banner(f"staged long segments entries={entries}")
+    pr = random_problem(61, 120, 4096, 0.9)
+    _, _, S = _fold(pr)
+    f, h, status, it = _solve([S], 20, staged=1, band_width=1024, tile_entries=entries)
     _check_split(pr, S, f[0], h[0], 20)
 
 
