@@ -414,9 +414,9 @@ def staged_search(systems, base, scratch):
     (band, entries, unroll), (tile, cpw)."""
     import dataclasses
     from paper_1902_10559_amd import native
-    fp_best, bp_best = ((4096, 4096, 4), 1e30), ((512, 8), 1e30)
-    for band, entries, unroll in ((4096, 4096, 4), (4096, 2048, 4), (4096, 4096, 8), (4096, 8192, 4),
-                                  (2048, 4096, 4)):
+    fp_best, bp_best = ((4096, 2048, 4), 1e30), ((512, 8), 1e30)
+    for band, entries, unroll in ((4096, 2048, 4), (4096, 4096, 4), (4096, 1024, 4), (4096, 2048, 8),
+                                  (2048, 2048, 4)):
         o = dataclasses.replace(base, staged=1, band_width=band, tile_entries=entries, unroll=unroll, chunked=0)
         ms = native.Solver(systems, o).time_phases(scratch, reps=10)
         if ms[0] + ms[1] < fp_best[1]:

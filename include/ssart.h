@@ -382,12 +382,12 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *                windows of loads per wavefront in flight (4: two).  The sums run in another order than the unstaged
  *                kernels' (equal to FP32 rounding), always the same one.
  *   band_width   voxels per forward band: a power of two from 1024 to 16384
- *                with band_width * nvals * 4 + 4096 * nvals <= 65536 bytes
+ *                with band_width * nvals * 4 + 16384 * nvals <= 65536 bytes
  *                of shared memory (0 = 4096)
  *   tile_cols    columns per back-projection tile: a power of two from 64 to
  *                8192 (0 = 1024)
  *   tile_entries  padded entries per forward work tile: a multiple of 256
- *                from 1024 to 65536 (0 = 4096)
+ *                from 1024 to 65536 (0 = 2048)
  *   residual_every  ordered subsets only (ss_ossart_solve; here 0 or 1): the
  *                residual of the pass-start image, a full forward sweep, is
  *                taken on passes k with k % residual_every == 0 and at

@@ -727,8 +727,8 @@ __device__ inline void band_load(BandBatch<NV, U>& B, const BandWalk<NV>& W, int
 // window starts a new segment or the tile ends.  The carried sum grows
 // window by window, in order: results are reproducible.  Finished sums go to
 // the wavefront's LDS buffer, which is written out once it holds at least
-// kSegBuf - 64 of them (a window finishes at most 64 more) and at the tile's
-// end.
+// kSegBuf - 64 of them (a window finishes at most 64 more) and after the
+// wavefront's last tile of the band.
 template <int NV, int U>
 __device__ inline void band_windows(const BandBatch<NV, U>& B, BandWalk<NV>& W, int32_t wb, const float* xs,
                                     uint32_t xmask, float* part, int lane) {
@@ -779,7 +779,7 @@ __device__ inline void band_windows(const BandBatch<NV, U>& B, BandWalk<NV>& W, 
     }
     W.seg_base += __popcll(m[u]);
     const int32_t done = W.carry ? W.carry_seg : W.seg_base;  // segments below are finished
-    if (done - W.buf_base >= kSegBuf - kWin || tile_ends) band_flush<NV>(W, done, part, lane);
+    if (done - W.buf_base >= kSegBuf - kWin) band_flush<NV>(W, done, part, lane);
   }
 }
 
@@ -788,13 +788,13 @@ __device__ inline void band_windows(const BandBatch<NV, U>& B, BandWalk<NV>& W, 
 // loads are issued before the current batch is summed, so the wavefront
 // always has loads in flight.  They are issued even past the tile's end (the
 // clamped chunk is re-read): the compiler then counts them, and waits only
-// for the batch it sums.
+// for the batch it sums.  A tile ends with its last segment, so nothing is
+// carried into the next tile, whose first segment follows this tile's last.
 template <int NV, int WT, int U>
-__device__ inline void band_tile(const SysDesc& S, const int32_t* tp, const float* xs, uint32_t xmask, float* buf,
-                                 int lane) {
+__device__ inline void band_tile(const SysDesc& S, const int32_t* tp, const float* xs, uint32_t xmask,
+                                 BandWalk<NV>& W, int lane) {
   constexpr uint32_t kChunkValBytes = SS_CHUNK * NV * (WT == SS_F32 ? 4 : 2);
   constexpr int32_t kStep = kWin * U;
-  BandWalk<NV> W;
   W.seg_base = __builtin_amdgcn_readfirstlane(tp[2]);
   W.c0 = __builtin_amdgcn_readfirstlane(tp[4]);
   W.nch = __builtin_amdgcn_readfirstlane(tp[5]) - static_cast<int32_t>(W.c0);
@@ -802,20 +802,25 @@ __device__ inline void band_tile(const SysDesc& S, const int32_t* tp, const floa
   W.tidx = S.fb_idx + W.c0 * SS_CHUNK;
   W.tval = static_cast<const char*>(S.fb_val) + W.c0 * kChunkValBytes;
   W.bits = S.fb_bits + (W.c0 >> 5);  // the word of the tile's first chunk
-  W.buf = buf;
-  W.buf_base = W.seg_base;
   W.carry = false;
   W.carry_seg = 0;
 #pragma unroll
   for (int h = 0; h < NV; ++h) W.carry_sum[h] = 0.0f;
   BandBatch<NV, U> a, b;
   band_load<NV, WT, U>(a, W, 0, lane);
+  // the scheduling barriers keep each batch's loads ahead of the other
+  // batch's sums (the scheduler would otherwise hoist work that needs the
+  // new loads, and the loads would then be waited for at once)
   for (int32_t wb = 0; wb < W.nch; wb += 2 * kStep) {
     band_load<NV, WT, U>(b, W, wb + kStep, lane);
+    __builtin_amdgcn_sched_barrier(0);
     band_windows<NV, U>(a, W, wb, xs, xmask, S.fb_part, lane);
     if (wb + kStep >= W.nch) break;
+    __builtin_amdgcn_sched_barrier(0);
     band_load<NV, WT, U>(a, W, wb + 2 * kStep, lane);
+    __builtin_amdgcn_sched_barrier(0);
     band_windows<NV, U>(b, W, wb + kStep, xs, xmask, S.fb_part, lane);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -857,9 +862,17 @@ __global__ __launch_bounds__(kWave* kBandWaves) __attribute__((amdgpu_waves_per_
       const int64_t j0 = static_cast<int64_t>(band) << lg;
       stage_contiguous<NV, T>(xs, S.f[parity] + j0 * NV, min(static_cast<int64_t>(1) << lg, S.n - j0));
       __syncthreads();
-      float* buf = xs + (NV << lg) + wave_id() * (kSegBuf * NV);
-      for (int64_t t = g0 + wave_id(); t < g1; t += kBandWaves)
-        band_tile<NV, WT, U>(S, tw + t * kTw, xs, xmask, buf, lane);
+      // each wavefront takes a contiguous part of the run, so that its
+      // segments follow on and its buffer is written out in long runs
+      const int64_t a = g0 + (g1 - g0) * wave_id() / kBandWaves;
+      const int64_t b = g0 + (g1 - g0) * (wave_id() + 1) / kBandWaves;
+      if (a < b) {
+        BandWalk<NV> W;
+        W.buf = xs + (NV << lg) + wave_id() * (kSegBuf * NV);
+        W.buf_base = __builtin_amdgcn_readfirstlane(tw[a * kTw + 2]);
+        for (int64_t t = a; t < b; ++t) band_tile<NV, WT, U>(S, tw + t * kTw, xs, xmask, W, lane);
+        band_flush<NV>(W, W.seg_base, S.fb_part, lane);
+      }
       __syncthreads();  // the next run's band overwrites xs
     }
     g0 = g1;
@@ -1132,7 +1145,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
 // Staged-form sizes shared by the layout and the set-up.
 inline int band_lg_of(const ss_sart_opts* o) { return o->band_width ? __builtin_ctz(o->band_width) : 12; }
 inline int tile_lg_of(const ss_sart_opts* o) { return o->tile_cols ? __builtin_ctz(o->tile_cols) : 10; }
-inline int band_q_of(const ss_sart_opts* o) { return (o->tile_entries ? o->tile_entries : 4096) / SS_CHUNK; }
+inline int band_q_of(const ss_sart_opts* o) { return (o->tile_entries ? o->tile_entries : 2048) / SS_CHUNK; }
 inline int64_t bands_of(const ss_system& S, int lg) { return (S.n + (int64_t{1} << lg) - 1) >> lg; }
 inline int64_t seg_bound(const ss_system& S, int lg) { return std::min<int64_t>(S.nnz, bands_of(S, lg) * S.m) + 1; }
 // entries of the band-major copy at most: every segment padded by up to
@@ -1312,7 +1325,7 @@ ss_status validate(const ss_system* sys, int nsys, const ss_sart_opts* o, const 
   if (o->tile_entries && (o->tile_entries % 256 != 0 || o->tile_entries < 1024 || o->tile_entries > 65536))
     return fail(SS_E_ARG, "%s: tile_entries must be a multiple of 256 in 1024..65536", fn);
   if ((o->staged & 1) && band_lds_bytes(sys[0].nvals, band_lg_of(o)) > 65536)
-    return fail(SS_E_ARG, "%s: the staged forward projection needs band_width*nvals*4 + 4096*nvals <= 65536", fn);
+    return fail(SS_E_ARG, "%s: the staged forward projection needs band_width*nvals*4 + 16384*nvals <= 65536", fn);
   if (o->staged) {
     for (int s = 0; s < nsys; ++s) {
       const ss_system& S = sys[s];

@@ -63,7 +63,7 @@ struct BandTile {
 constexpr int kBandWaves = 8;  // wavefronts per band-kernel block
 constexpr int kWin = kWave;    // chunks per window: one per lane
 
-constexpr int kSegBuf = 128;  // finished segment sums a band wavefront buffers
+constexpr int kSegBuf = 512;  // finished segment sums a band wavefront buffers
 
 // Bytes of the band kernel's LDS: the band's NV floats per voxel, then per
 // wavefront its buffer of segment sums.
