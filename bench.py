@@ -19,7 +19,7 @@ Workloads:
 The same step on the unsplit A is timed beside it.  Extras: ordered-subset
 SART against SART to a residual of 1e-2, the direct path (normal equations by
 Cholesky, Theorem 2) on Table 1's three sizes, time to a residual of 1e-3,
-and the CPU oracle's rate.  ``--direct-only``, ``--polar-only`` and
+and the CPU oracle's rate.  ``--direct-only``, ``--polar-only``, ``--conv-only`` and
 ``--subsets-only`` print just that report.
 
 Output: one JSON line on stdout (progress on stderr).  ``value`` is
@@ -62,6 +62,8 @@ def parse():
                     help="skip the polar-grid SART comparison")
     ap.add_argument("--direct-only", action="store_true",
                     help="only the direct path's report (one JSON line), for profiling it")
+    ap.add_argument("--conv-only", action="store_true",
+                    help="only the learned initialiser's per-layer convolution report (one JSON line)")
     ap.add_argument("--polar-only", action="store_true",
                     help="only the polar-grid report (one JSON line), for profiling it")
     ap.add_argument("--subsets-only", action="store_true",
@@ -152,6 +154,9 @@ def main():
         del src, dst
     if args.direct_only:
         print(json.dumps({"direct_normal_equations": direct_report(dev)}), flush=True)
+        return
+    if args.conv_only:
+        print(json.dumps({"conv_layers": conv_report(dev)}), flush=True)
         return
     if args.polar_only:
         print(json.dumps({"polar_grid": polar_report(dev, 0.5)}), flush=True)
@@ -787,6 +792,66 @@ def polar_report(dev, lam, iters=100, reps=5):
 
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix cores and vector units alike)
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
+
+# each layer's input map in the network's buffers
+CONV_INPUT = {"e1a": "x16", "e1b": "e1a", "e2a": "p1", "e2b": "e2a", "e3a": "p2", "e3b": "e3a", "ba": "p3",
+              "bb": "ba", "bc": "bb", "bd": "bc", "be": "bd", "d3a": "c3", "d3b": "d3a", "d2a": "c2",
+              "d2b": "d2a", "d1a": "c1", "d1b": "d1a", "out": "d1"}
+
+
+def conv_report(dev, N=16, H=256, W=256, reps=20):
+    """The learned initialiser's convolutions at the training shape (N
+    images of H x W): per layer the forward, weight-gradient and
+    input-gradient launches timed with events (best of `reps`), each
+    2*9*C*O*N*h*w flop, against the BF16 matrix-core peak; and a whole
+    training step (forward, backward, Adam, weight preparation)."""
+    import torch
+    from paper_1902_10559_amd import native, unet
+    net = unet.UNet(H, W, device=dev, seed=0)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    x32 = torch.rand(N, H, W, 1, generator=g).to(dev)
+    tgt = (x32 + 0.05 * torch.randn(N, H, W, 1, generator=g).to(dev)).contiguous()
+    x16 = torch.empty(x32.numel(), dtype=torch.int16, device=dev)
+    native.nn_to_bf16(x32, x16)
+    net.train_step(x32, x16, tgt, N, 1e-4)   # buffers, and every map filled
+    B = net._bufs[N]
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return min(t)
+    layers, total_flop, total_ms = [], 0.0, 0.0
+    for name, C, O, relu in unet.LAYERS:
+        L = net.layers[name]
+        lvl = unet.LEVEL[name]
+        h, w = H >> lvl, W >> lvl
+        xin = B[CONV_INPUT[name]]
+        y = torch.empty(N * h * w * O, dtype=torch.float32 if name == "out" else torch.int16, device=dev)
+        gy = torch.zeros(N * h * w * O, dtype=torch.int16, device=dev)
+        gin = torch.empty(N * h * w * C, dtype=torch.float32, device=dev)
+        flop = 2.0 * 9 * C * O * N * h * w
+        t_f = best(lambda: native.nn_conv3x3(xin, N, h, w, C, L.wf, L.b, O, relu, y, name == "out"))
+        t_w = best(lambda: native.nn_conv3x3_wgrad(xin, gy, N, h, w, C, O, L.gw, L.gb, ws=B["ws"]))
+        t_d = best(lambda: native.nn_conv3x3(gy, N, h, w, O, L.wb, None, C, False, gin, True))
+        rec = {"layer": name, "C": C, "O": O, "h": h, "w": w, "gflop": flop / 1e9}
+        for k, t in (("forward", t_f), ("wgrad", t_w), ("dgrad", t_d)):
+            rec[k] = {"ms": t, "tflops": flop / t / 1e9, "frac_bf16_peak": flop / t / 1e9 / BF16_PEAK_TFLOPS}
+        layers.append(rec)
+        total_flop += 3 * flop
+        total_ms += t_f + t_w + t_d
+    step = best(lambda: net.train_step(x32, x16, tgt, N, 1e-4))
+    return {"shape": f"{N} x {H} x {W}", "layers": layers,
+            "conv_total": {"gflop": total_flop / 1e9, "ms": total_ms, "tflops": total_flop / total_ms / 1e9},
+            "train_step": {"ms": step, "tflops_conv": total_flop / step / 1e9}}
 
 
 def direct_report(dev, sizes=(32, 64, 128), reps=3):

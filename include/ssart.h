@@ -623,10 +623,10 @@ ss_status ss_nn_conv3x3(const void* x, int32_t N, int32_t H, int32_t W, int32_t 
                         const float* bias, int32_t O, int32_t relu, void* y, int32_t y_f32, void* stream);
 
 /* gw [O][3][3][C] += sum over pixels of gy (x) shifted x; gb [O] += sum of gy
- * (gb may be NULL).  x (N,H,W,C), gy (N,H,W,O), both BF16.  Partial sums per
- * group of image rows (per block of pixels for gb) go to `workspace` (device,
- * at least ss_nn_wgrad_workspace_bytes) and are added in a fixed order, so
- * the gradients are bitwise the same on every run. */
+ * (gb may be NULL; with gb, O <= 256).  x (N,H,W,C), gy (N,H,W,O), both
+ * BF16.  Partial sums per range of pixels go to `workspace` (device, at
+ * least ss_nn_wgrad_workspace_bytes) and are added in a fixed order, so the
+ * gradients are bitwise the same on every run. */
 ss_status ss_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t C, int32_t O, size_t* bytes);
 ss_status ss_nn_conv3x3_wgrad(const void* x, const void* gy, int32_t N, int32_t H, int32_t W, int32_t C,
                               int32_t O, float* gw, float* gb, void* workspace, size_t workspace_bytes,

@@ -157,6 +157,121 @@ __global__ __launch_bounds__(kWave* kConvWaves) void k_conv3x3_wgrad(const uint1
   }
 }
 
+// Weight gradient, staged: a wavefront owns one 16 x 16 tile of (o, c) and
+// all nine taps, and works through units of 32 pixels of one image row (the
+// units of its block's range, in turn).  Per unit it copies the output
+// gradient's 32 x 16 tile and the input's three rows of 34 x 16 (the 32
+// pixels and one on each side, zero outside the image) into LDS with
+// 16-byte loads, then reads the matrix-core operands from there: A[o][p] =
+// gy[p][o], B_tap[p][c] = x[p + shift(tap)][c], nine products per unit
+// sharing A.  The rows are stored 20 values apart, so the four 16-lane groups
+// of an operand read fall in different banks.  The block's four wavefronts
+// then add their tiles in order into the block's partial, [O][9][C] per
+// block row; k_wgrad_reduce adds those in order.  Needs W a multiple of 32;
+// VX (VG): C (O) a multiple of 8, the input's (output gradient's) values
+// in 16-byte loads, else value by value.
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+// Eight 16-bit values to LDS at an 8-byte aligned place.
+__device__ inline void store_lds8(uint16_t* d, const u16x8& v) {
+  reinterpret_cast<u16x4*>(d)[0] = u16x4{v[0], v[1], v[2], v[3]};
+  reinterpret_cast<u16x4*>(d)[1] = u16x4{v[4], v[5], v[6], v[7]};
+}
+
+// Values k0 .. k0+7 of one pixel's n channels (zero past n); VEC: n is a
+// multiple of 8, one 16-byte load.
+template <bool VEC>
+__device__ inline u16x8 load8(const uint16_t* px, int k0, int n) {
+  u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+  if constexpr (VEC) {
+    if (k0 < n) v = *gl(reinterpret_cast<const u16x8*>(px + k0));
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = k0 + q < n ? gl(px)[k0 + q] : uint16_t{0};
+  }
+  return v;
+}
+
+constexpr int kWgTile = 32;        // pixels per unit
+constexpr int kWgStride = 20;      // LDS row stride in 16-bit values
+constexpr int kWgWaves = 4;
+constexpr int kWgLdsPerWave = (kWgTile + 3 * (kWgTile + 2)) * kWgStride;  // 16-bit values
+template <bool VX, bool VG>
+__global__ __launch_bounds__(kWave* kWgWaves) void k_wgrad_tiles(const uint16_t* __restrict__ x,
+                                                                  const uint16_t* __restrict__ gy, int H, int W,
+                                                                  int C, int O, int64_t units, int groups,
+                                                                  float* __restrict__ part) {
+  __shared__ uint16_t lds[kWgWaves * kWgLdsPerWave];
+  __shared__ float red[kWgWaves - 1][9][4][kWave];
+  const int lane = lane_id(), g = lane / 16, m = lane % 16;
+  const int ct = (C + 15) / 16;
+  const int o0 = (blockIdx.x / ct) * 16, c0 = (blockIdx.x % ct) * 16;
+  const int z = blockIdx.y;
+  uint16_t* gs = lds + wave_id() * kWgLdsPerWave;  // [32][stride] output gradient
+  uint16_t* xs = gs + kWgTile * kWgStride;         // [3][34][stride] input rows
+  const int upr = W / kWgTile;                     // units per image row
+  const int64_t u0 = units * z / groups, u1 = units * (z + 1) / groups;
+  f32x4 acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t u = u0 + wave_id(); u < u1; u += kWgWaves) {
+    const int64_t row = u / upr;               // n * H + i
+    const int i = static_cast<int>(row % H);
+    const int x0 = static_cast<int>(u % upr) * kWgTile;
+    // the output gradient's tile: lane = (pixel, half of the 16 channels)
+    {
+      const int px = lane >> 1, h8 = (lane & 1) * 8;
+      store_lds8(gs + px * kWgStride + h8, load8<VG>(gy + (row * W + x0 + px) * O, o0 + h8, O));
+    }
+    // the input's three rows, pixels x0 - 1 .. x0 + 32
+    for (int it = lane; it < 3 * (kWgTile + 2) * 2; it += kWave) {
+      const int dy = it / ((kWgTile + 2) * 2), r = it % ((kWgTile + 2) * 2);
+      const int pq = r >> 1, h8 = (r & 1) * 8;
+      const int yy = i + dy - 1, xx = x0 + pq - 1;
+      u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = load8<VX>(x + ((row - i + yy) * W + xx) * C, c0 + h8, C);
+      store_lds8(xs + (dy * (kWgTile + 2) + pq) * kWgStride + h8, v);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    u16x8 a;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = gs[(8 * g + q) * kWgStride + m];
+    const bf16x8 av = as_bf16x8(a);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t % 3;
+      u16x8 b;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) b[q] = xs[(dy * (kWgTile + 2) + 8 * g + q + dx) * kWgStride + m];
+      acc[t] = mma(av, as_bf16x8(b), acc[t]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the next unit overwrites the tiles
+  }
+  // the block's four tiles, added in wavefront order
+  if (wave_id() > 0) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave_id() - 1][t][r][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (wave_id() == 0) {
+    const int c = c0 + m;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float s = acc[t][r];
+        for (int w = 0; w < kWgWaves - 1; ++w) s += red[w][t][r][lane];
+        const int o = o0 + 4 * g + r;
+        if (o < O && c < C) glw(part)[((static_cast<int64_t>(z) * O + o) * 9 + t) * C + c] = s;
+      }
+    }
+  }
+}
+
 // dst[e] += sum over groups z (in index order) of part[z][e], e < count.
 __global__ void k_wgrad_reduce(const float* __restrict__ part, int groups, int64_t count, float* __restrict__ dst) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -166,16 +281,63 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int groups, int64
   dst[e] += s;
 }
 
-// Partial bias gradients: part[blk][o] = sum over the block's 256 pixels of
-// gy[p][o] (in pixel order); k_wgrad_reduce adds the blocks in order.
-constexpr int kBiasPix = 256;
-__global__ void k_bias_grad(const uint16_t* __restrict__ gy, int64_t P, int O, float* __restrict__ part) {
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * kBiasPix;
-  const int64_t p1 = p0 + kBiasPix < P ? p0 + kBiasPix : P;
-  for (int o = threadIdx.x; o < O; o += blockDim.x) {
-    float s = 0.0f;
-    for (int64_t p = p0; p < p1; ++p) s += bf2f(gl(gy)[p * O + o]);
-    part[static_cast<int64_t>(blockIdx.x) * O + o] = s;
+// The same sum with many groups and few elements: one block per element,
+// thread t adding groups t, t + 256, ... in order, then the block's threads
+// in a fixed tree.
+constexpr int kReduceThreads = 256;
+__global__ __launch_bounds__(kReduceThreads) void k_wgrad_reduce_wide(const float* __restrict__ part, int groups,
+                                                                      int64_t count, float* __restrict__ dst) {
+  __shared__ float red[kReduceThreads / kWave];
+  const int64_t e = blockIdx.x;
+  float s = 0.0f;
+  for (int z = threadIdx.x; z < groups; z += kReduceThreads) s += gl(part)[static_cast<int64_t>(z) * count + e];
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+  if (lane_id() == 0) red[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < kReduceThreads / kWave; ++w) t += red[w];
+    dst[e] += t;
+  }
+}
+
+// dst[e] += the groups' partials of element e, by the kernel that suits the
+// shape (both add in a fixed order).
+void reduce_partials(const float* part, int groups, int64_t count, float* dst, hipStream_t st) {
+  if (groups > 64 && count <= 65536)
+    k_wgrad_reduce_wide<<<static_cast<unsigned>(count), kReduceThreads, 0, st>>>(part, groups, count, dst);
+  else
+    k_wgrad_reduce<<<static_cast<unsigned>((count + 255) / 256), 256, 0, st>>>(part, groups, count, dst);
+}
+
+// Partial bias gradients: part[blk][o] = sum over the block's `per`
+// pixels of gy[p][o].  The block's threads cover floor(256 / O) pixels x O
+// channels at a time (adjacent threads, adjacent values: coalesced); each
+// thread sums its pixels in order, then the pixel lanes are added in order;
+// k_wgrad_reduce adds the blocks in order.  O <= 256.
+constexpr int kBiasThreads = 256;
+
+// Pixels per bias block: about 512 blocks, between 64 and 4096 pixels.
+inline int64_t bias_pix(int64_t P) { return std::min<int64_t>(4096, std::max<int64_t>(64, (P + 511) / 512)); }
+
+__global__ __launch_bounds__(kBiasThreads) void k_bias_grad(const uint16_t* __restrict__ gy, int64_t P, int O,
+                                                            int64_t per, float* __restrict__ part) {
+  __shared__ float sums[kBiasThreads];
+  const int lanes = kBiasThreads / O;  // pixels at a time
+  const int t = threadIdx.x;
+  const int o = t % O, j = t / O;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t p1 = p0 + per < P ? p0 + per : P;
+  float s = 0.0f;
+  if (j < lanes)
+    for (int64_t p = p0 + j; p < p1; p += lanes) s += bf2f(gl(gy)[p * O + o]);
+  sums[t] = s;
+  __syncthreads();
+  if (t < O) {
+    float r = 0.0f;
+    for (int q = 0; q < lanes; ++q) r += sums[q * O + t];
+    part[static_cast<int64_t>(blockIdx.x) * O + t] = r;
   }
 }
 
@@ -390,12 +552,29 @@ extern "C" ss_status ss_nn_conv3x3(const void* x, int32_t N, int32_t H, int32_t 
   return SS_OK;
 }
 
+// The weight gradient's partial groups: with the staged kernel (W a
+// multiple of 32) enough block rows that the grid holds about 2048
+// blocks, partials at most 4 MiB and each block at least 4 units; else one
+// group per kWgradRows image rows.
+bool wgrad_staged(int C, int O, int W) { return W % kWgTile == 0; }
+
+int64_t wgrad_groups(int N, int H, int W, int C, int O) {
+  if (!wgrad_staged(C, O, W)) return (static_cast<int64_t>(N) * H + kWgradRows - 1) / kWgradRows;
+  const int64_t units = static_cast<int64_t>(N) * H * (W / kWgTile);
+  const int64_t tiles = static_cast<int64_t>((O + 15) / 16) * ((C + 15) / 16);
+  const int64_t by_blocks = (2048 + tiles - 1) / tiles;
+  const int64_t by_bytes = std::max<int64_t>(1, (int64_t{4} << 20) / (static_cast<int64_t>(O) * 9 * C * 4));
+  const int64_t by_units = std::max<int64_t>(1, units / (4 * kWgWaves));
+  return std::max<int64_t>(1, std::min({by_blocks, by_bytes, by_units, int64_t{65535}}));
+}
+
 extern "C" ss_status ss_nn_wgrad_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t C, int32_t O,
                                                  size_t* bytes) {
   clear_error();
   SS_NN_CHECK(bytes && N > 0 && H > 0 && W > 0 && C > 0 && O > 0, "ss_nn_wgrad_workspace_bytes");
-  const int64_t groups = (static_cast<int64_t>(N) * H + kWgradRows - 1) / kWgradRows;
-  const int64_t pblocks = (static_cast<int64_t>(N) * H * W + kBiasPix - 1) / kBiasPix;
+  const int64_t groups = wgrad_groups(N, H, W, C, O);
+  const int64_t P = static_cast<int64_t>(N) * H * W;
+  const int64_t pblocks = (P + bias_pix(P) - 1) / bias_pix(P);
   *bytes = sizeof(float) * static_cast<size_t>(std::max(groups * O * 9 * C, pblocks * O));
   return SS_OK;
 }
@@ -404,7 +583,8 @@ extern "C" ss_status ss_nn_conv3x3_wgrad(const void* x, const void* gy, int32_t 
                                          int32_t O, float* gw, float* gb, void* workspace, size_t workspace_bytes,
                                          void* stream) {
   clear_error();
-  SS_NN_CHECK(x && gy && gw && workspace && N > 0 && H > 0 && W > 0 && C > 0 && O > 0, "ss_nn_conv3x3_wgrad");
+  SS_NN_CHECK(x && gy && gw && workspace && N > 0 && H > 0 && W > 0 && C > 0 && O > 0 && (!gb || O <= 256),
+              "ss_nn_conv3x3_wgrad");
   size_t need = 0;
   ss_nn_wgrad_workspace_bytes(N, H, W, C, O, &need);
   if (workspace_bytes < need) return fail(SS_E_WORKSPACE, "ss_nn_conv3x3_wgrad: workspace needs %zu bytes", need);
@@ -412,17 +592,31 @@ extern "C" ss_status ss_nn_conv3x3_wgrad(const void* x, const void* gy, int32_t 
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int NH = N * H;
   float* part = static_cast<float*>(workspace);
-  const int groups = (NH + kWgradRows - 1) / kWgradRows;
-  const dim3 grid((O + 15) / 16, (9 * Cp + 15) / 16, (NH + kWgradRows * kConvWaves - 1) / (kWgradRows * kConvWaves));
-  k_conv3x3_wgrad<<<grid, kWave * kConvWaves, 0, st>>>(static_cast<const uint16_t*>(x),
-                                                       static_cast<const uint16_t*>(gy), NH, H, W, C, Cp, O, part);
+  const int groups = static_cast<int>(wgrad_groups(N, H, W, C, O));
+  if (wgrad_staged(C, O, W)) {
+    const int64_t units = static_cast<int64_t>(NH) * (W / kWgTile);
+    const dim3 grid(((O + 15) / 16) * ((C + 15) / 16), groups);
+    const auto* xi = static_cast<const uint16_t*>(x);
+    const auto* gi = static_cast<const uint16_t*>(gy);
+    const dim3 blk(kWave * kWgWaves);
+    if (C % 8 == 0 && O % 8 == 0) k_wgrad_tiles<true, true><<<grid, blk, 0, st>>>(xi, gi, H, W, C, O, units, groups, part);
+    else if (C % 8 == 0) k_wgrad_tiles<true, false><<<grid, blk, 0, st>>>(xi, gi, H, W, C, O, units, groups, part);
+    else if (O % 8 == 0) k_wgrad_tiles<false, true><<<grid, blk, 0, st>>>(xi, gi, H, W, C, O, units, groups, part);
+    else k_wgrad_tiles<false, false><<<grid, blk, 0, st>>>(xi, gi, H, W, C, O, units, groups, part);
+  } else {
+    const dim3 grid((O + 15) / 16, (9 * Cp + 15) / 16,
+                    (NH + kWgradRows * kConvWaves - 1) / (kWgradRows * kConvWaves));
+    k_conv3x3_wgrad<<<grid, kWave * kConvWaves, 0, st>>>(static_cast<const uint16_t*>(x),
+                                                         static_cast<const uint16_t*>(gy), NH, H, W, C, Cp, O, part);
+  }
   const int64_t nw = static_cast<int64_t>(O) * 9 * C;
-  k_wgrad_reduce<<<blocks256(nw), 256, 0, st>>>(part, groups, nw, gw);
+  reduce_partials(part, groups, nw, gw, st);
   if (gb) {
     const int64_t P = static_cast<int64_t>(NH) * W;
-    const unsigned pb = static_cast<unsigned>((P + kBiasPix - 1) / kBiasPix);
-    k_bias_grad<<<pb, 128, 0, st>>>(static_cast<const uint16_t*>(gy), P, O, part);
-    k_wgrad_reduce<<<blocks256(O), 256, 0, st>>>(part, static_cast<int>(pb), O, gb);
+    const int64_t per = bias_pix(P);
+    const unsigned pb = static_cast<unsigned>((P + per - 1) / per);
+    k_bias_grad<<<pb, kBiasThreads, 0, st>>>(static_cast<const uint16_t*>(gy), P, O, per, part);
+    reduce_partials(part, static_cast<int>(pb), O, gb, st);
   }
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;

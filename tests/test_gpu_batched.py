@@ -4,17 +4,23 @@ both halves of every slice solved in the same launches (graph replay).
 
 Parity on sampled outputs: two sampled slices (the deepest and the
 shallowest) carry projections made by the oracle, and their recombined images
-from the full batched solve, in the launch configuration bench.py times (the
-fold writing the interleaved line order for 8 lanes, 8 rows and 8 columns per
-wavefront, 8 entries per lane and pass, XCD-ordered blocks), are checked
-against the FP64 oracle; a small batch is checked bitwise against solo solves
-of the same slices."""
+from the full batched solve are checked against the FP64 oracle: in the
+staged launch configuration bench.py times (bands of 4096 voxels, work tiles
+of 2048 entries, back-projection tiles of 512 columns with 8 per wavefront,
+unroll 8) at the bench's 100 iterations, with BF16 weights against the oracle
+on the same rounded values, and in the unstaged interleaved configuration
+(the fold writing the interleaved line order for 8 lanes, 8 rows and 8
+columns per wavefront, 8 entries per lane and pass, XCD-ordered blocks); a
+small batch is checked bitwise against solo solves of the same slices."""
+import dataclasses
+
 import numpy as np
 import pytest
 
 from gpu_util import assert_res_close, banner, rel_l2, to_np
 from oracle import geometry as G
 from oracle import sart as OS
+from oracle import split as OSp
 from paper_1902_10559_amd import inputs, native, workloads
 
 pytestmark = pytest.mark.gpu
@@ -36,6 +42,54 @@ def sampled():
     depths = inputs.cfg4_depths()
     picks = [int(np.argmax(depths)), int(np.argmin(depths))]
     return {s: _oracle_problem(s) for s in picks}
+
+
+# the staged kernels in the shape bench.py times on this workload
+BENCH_STAGED = dict(staged=3, band_width=4096, tile_cols=512, tile_entries=2048, cols_per_wave=8, unroll=8)
+
+
+@pytest.fixture(scope="module")
+def batch(sampled):
+    banner("batched: building 256 slices (ascending fold)")
+    sl = workloads.batched_slices(256, p_override={s: v[1] for s, v in sampled.items()}, progress=banner)
+    return sl
+
+
+def _solve(systems, iters, **kw):
+    import torch
+    sol = native.Solver(systems, native.SartOptions(lam=0.5, max_iter=iters, zero_start=True, use_graph=True, **kw))
+    f = [S.new_image() for S in systems]
+    hist = [torch.zeros(iters + 1, dtype=torch.float64, device="cuda") for _ in systems]
+    status, it = sol.solve(f, hist)
+    assert status == 0 and it == [iters] * len(systems)
+    return f, hist
+
+
+def test_full_batch_staged_at_bench_length_matches_oracle(batch, sampled):
+    iters = 100
+    banner(f"batched: staged bench configuration, {iters} iterations")
+    f, hist = _solve([x.S for x in batch], iters, **BENCH_STAGED)
+    for s, (A, p) in sampled.items():
+        f_ref, res_ref = OS.sart_full(A, p, 0.5, iters)
+        err = rel_l2(to_np(native.recombine(f[s])), f_ref)
+        banner(f"slice {s} (nz={batch[s].geom.nz}) rel L2 {err:.2e} after {iters}")
+        assert err <= 1e-5
+        assert_res_close(to_np(hist[s]), res_ref)
+
+
+def test_full_batch_bf16_staged_matches_oracle_on_rounded_values(batch, sampled):
+    banner("batched: BF16 weights, staged configuration")
+    low = [native.fold(x.A, x.p, "bf16", nnz_half=x.S.nnz) for x in batch]
+    f, hist = _solve(low, ITERS, **BENCH_STAGED)
+    for s, (A, p) in sampled.items():
+        R = OSp.fold(A, "fp32")
+        R = dataclasses.replace(R, v1=OSp.round_storage(R.v1, "bf16"), v2=OSp.round_storage(R.v2, "bf16"))
+        p1, p2 = OSp.fold_p(p)
+        g1, g2, res = OS.sart_split(R, p1, p2, 0.5, ITERS)
+        err = rel_l2(to_np(native.recombine(f[s])), OSp.recombine(g1, g2))
+        banner(f"slice {s} bf16 rel L2 {err:.2e} against the oracle on the rounded values")
+        assert err <= 1e-5
+        assert_res_close(to_np(hist[s]), res)
 
 
 def test_full_batch_sampled_slices_match_oracle(sampled):

@@ -61,3 +61,7 @@ def test_brief_training_lowers_the_start_residual(sc):
     banner(f"report {rep}")
     assert rep["res_learned_start"] < rep["res_after_5"]
     assert rep["accepted"] >= 8
+    # and the learned start saves iterations to 1e-2 (median over the 16)
+    t = rep["tolerances"]["0.01"]
+    assert t["learned_reached"] == t["plain_reached"] == 16
+    assert t["learned_median_iters"] < t["plain_median_iters"], t

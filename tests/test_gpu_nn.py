@@ -64,8 +64,12 @@ def test_conv3x3_forward_and_input_gradient(N, H, W, C, O):
     assert _rel(to_np(gx).reshape(N, H, W, C), ON.conv3x3_grad_input(gr, wr)) <= 1e-5
 
 
+# staged kernel (W a multiple of 32): 16-byte loads (C, O multiples of 8)
+# or value by value (C = 1, O = 1), partial channel tiles, many partial
+# groups; the element-wise kernel: W not a multiple of 32
 @pytest.mark.parametrize("N,H,W,C,O", [(2, 8, 32, 1, 16), (1, 16, 32, 16, 32), (2, 8, 64, 48, 16),
-                                       (1, 8, 32, 64, 128), (3, 8, 40, 8, 8)])
+                                       (1, 8, 32, 64, 128), (3, 8, 40, 8, 8), (2, 8, 64, 8, 24),
+                                       (4, 32, 128, 16, 16), (2, 8, 32, 16, 1), (2, 12, 20, 3, 5)])
 def test_conv3x3_weight_and_bias_gradient(N, H, W, C, O):
     import torch
     banner(f"wgrad N={N} H={H} W={W} C={C} O={O}")
