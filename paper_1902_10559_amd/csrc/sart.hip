@@ -392,31 +392,56 @@ __global__ __launch_bounds__(kThreads) void k_finish(const SysDesc* table) {
 constexpr int kCvLanes = 16;
 constexpr int kCvRows = kThreads / kCvLanes;
 
-// The band runs of one row, as its kCvLanes lanes walk it in windows of
-// kCvLanes entries: per entry its band, whether it starts and whether it
-// ends a run (the next entry is in another band, or there is none), and the
-// first entry of its run.  The lanes of a row call it together (the
-// shuffles stay inside the row's lanes); `run0` and `band0` carry the
-// previous window's last run start and band.
+// A row's lanes load kRowWin windows of kCvLanes entries at once (a batch),
+// so that a row costs a few dependent load latencies instead of one or two
+// per window; rows longer than a batch take several.
+constexpr int kRowWin = 8;
+constexpr int kRowBatch = kRowWin * kCvLanes;
+
+// The columns of one batch from `base`, and the column of the entry after
+// it; positions past the row's end re-read its last entry (the row is not
+// empty), so every load is inside the row.
+struct RowBatch {
+  int32_t c[kRowWin];
+  int32_t after;
+};
+
+__device__ inline void row_batch_load(const int32_t* col, int64_t base, int64_t hi, int g, RowBatch& B) {
+#pragma unroll
+  for (int w = 0; w < kRowWin; ++w) {
+    const int64_t k = base + w * kCvLanes + g;
+    B.c[w] = gl(col)[k < hi ? k : hi - 1];
+  }
+  const int64_t ka = base + kRowBatch;
+  B.after = gl(col)[ka < hi ? ka : hi - 1];
+}
+
+// The band runs of one window of a row (entries k = base + g, g < kCvLanes):
+// per entry its band (-1 past the row's end), whether it starts a run and
+// whether it ends one (the next entry is in another band, or there is
+// none), and the first entry of its run.  `after` is the band of the entry
+// after the window (-1 if none); `run0` and `band0` carry the previous
+// window's last run start and band.  The lanes of a row call it together
+// (the shuffles stay inside the row's lanes).
 struct RunLane {
   int32_t band;
   bool valid, start, end;
   int64_t k, ks;
 };
 
-__device__ inline RunLane run_lane(const int32_t* col, int64_t base, int64_t hi, int lg, int g, int64_t run0,
-                                   int32_t band0) {
+__device__ inline RunLane run_of(int32_t band, int32_t after, int64_t k, bool valid, int g, int64_t run0,
+                                 int32_t band0) {
   RunLane r;
-  r.k = base + g;
-  r.valid = r.k < hi;
-  r.band = r.valid ? (gl(col)[r.k] >> lg) : -1;
-  int32_t bp = __shfl_up(r.band, 1, kCvLanes);
+  r.k = k;
+  r.valid = valid;
+  r.band = band;
+  int32_t bp = __shfl_up(band, 1, kCvLanes);
   if (g == 0) bp = band0;
-  int32_t bn = __shfl_down(r.band, 1, kCvLanes);
-  if (g == kCvLanes - 1) bn = r.k + 1 < hi ? (gl(col)[r.k + 1] >> lg) : -1;
-  r.start = r.valid && r.band != bp;
-  r.end = r.valid && r.band != bn;
-  int64_t ks = r.start ? r.k : int64_t{-1};
+  int32_t bn = __shfl_down(band, 1, kCvLanes);
+  if (g == kCvLanes - 1) bn = after;
+  r.start = valid && band != bp;
+  r.end = valid && band != bn;
+  int64_t ks = r.start ? k : int64_t{-1};
 #pragma unroll
   for (int d = 1; d < kCvLanes; d <<= 1) {
     const int64_t t = __shfl_up(ks, d, kCvLanes);
@@ -426,15 +451,39 @@ __device__ inline RunLane run_lane(const int32_t* col, int64_t base, int64_t hi,
   return r;
 }
 
-// Whether row i's columns strictly ascend inside [0, n) (every lane of the
-// row gets the answer).  The staged forward form gives a row that does not
-// no segments.
-__device__ inline bool row_ascends(const SysDesc& S, int64_t lo, int64_t hi, int g) {
-  bool bad = false;
-  for (int64_t k = lo + g; k < hi; k += kCvLanes) {
-    const int32_t c = gl(S.col_idx)[k];
-    bad |= c < 0 || c >= S.n || (k > lo && gl(S.col_idx)[k - 1] >= c);
+// The runs of window w of a loaded batch.
+__device__ inline RunLane batch_run(const RowBatch& B, int w, int64_t base, int64_t hi, int lg, int g, int64_t run0,
+                                    int32_t band0) {
+  const int64_t k = base + w * kCvLanes + g;
+  const bool valid = k < hi;
+  const int32_t band = valid ? (B.c[w] >> lg) : -1;
+  int32_t after;
+  if (w + 1 < kRowWin) {  // lane 0 of the next window
+    const int64_t kn = base + (w + 1) * kCvLanes;
+    const int32_t cn = __shfl(B.c[w + 1], 0, kCvLanes);
+    after = kn < hi ? (cn >> lg) : -1;
+  } else {
+    after = base + kRowBatch < hi ? (B.after >> lg) : -1;
   }
+  return run_of(band, after, k, valid, g, run0, band0);
+}
+
+// Whether the entries of a loaded batch strictly ascend inside [0, n), each
+// against the one before it (`prev`: the column before the batch, for a
+// batch that does not start the row); every lane of the row gets the
+// answer.  Returns the batch's last column in *last.
+__device__ inline bool batch_ascends(const RowBatch& B, int64_t base, int64_t lo, int64_t hi, int64_t n,
+                                     int32_t prev, int g, int32_t* last) {
+  bool bad = false;
+#pragma unroll
+  for (int w = 0; w < kRowWin; ++w) {
+    const int64_t k = base + w * kCvLanes + g;
+    const int32_t c = B.c[w];
+    int32_t p = __shfl_up(c, 1, kCvLanes);
+    if (g == 0) p = w == 0 ? prev : __shfl(B.c[w - 1], kCvLanes - 1, kCvLanes);
+    bad |= k < hi && (c < 0 || c >= n || (k > lo && p >= c));
+  }
+  *last = __shfl(B.c[kRowWin - 1], kCvLanes - 1, kCvLanes);
   int b = bad ? 1 : 0;
 #pragma unroll
   for (int o = kCvLanes / 2; o > 0; o >>= 1) b |= __shfl_xor(b, o, kWave);
@@ -443,30 +492,54 @@ __device__ inline bool row_ascends(const SysDesc& S, int64_t lo, int64_t hi, int
 
 // Per row: the padded length of each band run (a segment) into
 // fb_len[b*m + i] as (1 segment, entries rounded up to whole chunks), and
-// the row's segment count into fb_rseg[i].
+// the row's segment count into fb_rseg[i].  A row whose columns do not
+// strictly ascend inside [0, n) gets no segments (the staged forward form
+// then leaves it out).  The first batch is kept in registers between the
+// check and the count.  One block per group of kCvRows rows: adjacent rows
+// run together, so their band-major writes meet in the same cache lines
+// (blocks that each walk a range of groups measured slower).
 __global__ __launch_bounds__(kThreads) void k_fb_count(const SysDesc* table, int nsys, const Params* prm) {
-  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, blockIdx.x));
-  const SysDesc& S = table[s];
+  const int64_t vb = blockIdx.x;
+  const SysDesc& S = table[__builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, vb))];
   const int lg = prm->band_lg;
-  const int64_t i = (static_cast<int64_t>(blockIdx.x) - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
+  const int64_t i = (vb - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
   const int g = threadIdx.x % kCvLanes;
   if (i >= S.m) return;  // the row's lanes leave together
   const int64_t lo = gl(S.row_ptr)[i], hi = gl(S.row_ptr)[i + 1];
-  if (!row_ascends(S, lo, hi, g)) {
+  if (hi <= lo) {
+    if (g == 0) glw(S.fb_rseg)[i] = 0u;
+    return;
+  }
+  RowBatch B0;
+  row_batch_load(S.col_idx, lo, hi, g, B0);
+  int32_t last;
+  bool ok = batch_ascends(B0, lo, lo, hi, S.n, 0, g, &last);
+  for (int64_t base = lo + kRowBatch; ok && base < hi; base += kRowBatch) {
+    RowBatch B;
+    row_batch_load(S.col_idx, base, hi, g, B);
+    ok = batch_ascends(B, base, lo, hi, S.n, last, g, &last);
+  }
+  if (!ok) {
     if (g == 0) glw(S.fb_rseg)[i] = 0u;
     return;
   }
   int64_t run0 = lo;
   int32_t band0 = -1;
   uint32_t runs = 0;
-  for (int64_t base = lo; base < hi; base += kCvLanes) {
-    const RunLane r = run_lane(S.col_idx, base, hi, lg, g, run0, band0);
-    if (r.end)
-      glw(S.fb_len)[static_cast<int64_t>(r.band) * S.m + i] =
-          seg_pack(1u, static_cast<uint32_t>(pad_chunk(r.k + 1 - r.ks)));
-    runs += r.start ? 1u : 0u;
-    run0 = __shfl(r.ks, kCvLanes - 1, kCvLanes);
-    band0 = __shfl(r.band, kCvLanes - 1, kCvLanes);
+  for (int64_t base = lo; base < hi; base += kRowBatch) {
+    RowBatch B;
+    if (base == lo) B = B0;
+    else row_batch_load(S.col_idx, base, hi, g, B);
+#pragma unroll
+    for (int w = 0; w < kRowWin; ++w) {
+      const RunLane r = batch_run(B, w, base, hi, lg, g, run0, band0);
+      if (r.end)
+        glw(S.fb_len)[static_cast<int64_t>(r.band) * S.m + i] =
+            seg_pack(1u, static_cast<uint32_t>(pad_chunk(r.k + 1 - r.ks)));
+      runs += r.start ? 1u : 0u;
+      run0 = __shfl(r.ks, kCvLanes - 1, kCvLanes);
+      band0 = __shfl(r.band, kCvLanes - 1, kCvLanes);
+    }
   }
 #pragma unroll
   for (int o = kCvLanes / 2; o > 0; o >>= 1) runs += __shfl_xor(runs, o, kWave);
@@ -478,14 +551,16 @@ __global__ __launch_bounds__(kThreads) void k_fb_count(const SysDesc* table, int
 // segment's padding entries get value 0 and index 0; each run start records
 // its segment's offset and its chunk's bit in fb_bits, and the row's slot
 // for the run (the row's slots follow its bands in ascending order) records
-// the segment.  VB: value bytes per
-// entry.
+// the segment.  A batch at a time: its columns and values, then every
+// window's runs, then their (band, row) prefixes, then the stores.  VB:
+// value bytes per entry.
 template <int VB>
 __global__ __launch_bounds__(kThreads) void k_fb_fill(const SysDesc* table, int nsys, const Params* prm) {
-  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, blockIdx.x));
-  const SysDesc& S = table[s];
+  const int64_t vb = blockIdx.x;
+  const SysDesc& S = table[__builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, vb))];
+  using V = std::conditional_t<VB == 8, uint64_t, std::conditional_t<VB == 4, uint32_t, uint16_t>>;
   const int lg = prm->band_lg;
-  const int64_t i = (static_cast<int64_t>(blockIdx.x) - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
+  const int64_t i = (vb - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
   const int g = threadIdx.x % kCvLanes;
   if (i == 0 && g == 0) {
     const uint64_t tot = gl(S.fb_len)[static_cast<int64_t>(S.fb_nb) * S.m];
@@ -495,52 +570,72 @@ __global__ __launch_bounds__(kThreads) void k_fb_fill(const SysDesc* table, int 
   const uint32_t slot0 = gl(S.fb_rseg)[i];
   if (gl(S.fb_rseg)[i + 1] == slot0) return;  // an empty row, or one given no segments
   const int64_t lo = gl(S.row_ptr)[i], hi = gl(S.row_ptr)[i + 1];
+  const V* val = static_cast<const V*>(S.val);
+  V* fval = static_cast<V*>(S.fb_val);
   int64_t run0 = lo;
   int32_t band0 = -1;
   uint32_t ord = 0;  // the row's runs in earlier windows
-  for (int64_t base = lo; base < hi; base += kCvLanes) {
-    const RunLane r = run_lane(S.col_idx, base, hi, lg, g, run0, band0);
-    uint32_t nst = r.start ? 1u : 0u;  // runs started at or before this lane in the window
+  for (int64_t base = lo; base < hi; base += kRowBatch) {
+    RowBatch B;
+    row_batch_load(S.col_idx, base, hi, g, B);
+    V v[kRowWin];
 #pragma unroll
-    for (int d = 1; d < kCvLanes; d <<= 1) {
-      const uint32_t t = __shfl_up(nst, d, kCvLanes);
-      if (g >= d) nst += t;
+    for (int w = 0; w < kRowWin; ++w) {
+      const int64_t k = base + w * kCvLanes + g;
+      v[w] = gl(val)[k < hi ? k : hi - 1];
     }
-    if (r.valid) {
-      const int64_t at = static_cast<int64_t>(r.band) * S.m + i;
-      const uint64_t pre = gl(S.fb_len)[at];
-      const int64_t e0 = seg_entries(pre);
-      const int64_t e1 = seg_entries(gl(S.fb_len)[at + 1]);  // e0 + the padded length
-      const int64_t pos = e0 + (r.k - r.ks);
-      if (pos < e1) {
-        const int32_t c = gl(S.col_idx)[r.k];
-        glw(S.fb_idx)[pos] = static_cast<uint16_t>(c - (r.band << lg));
-        if constexpr (VB == 8)
-          glw(static_cast<uint64_t*>(S.fb_val))[pos] = gl(static_cast<const uint64_t*>(S.val))[r.k];
-        else if constexpr (VB == 4)
-          glw(static_cast<uint32_t*>(S.fb_val))[pos] = gl(static_cast<const uint32_t*>(S.val))[r.k];
-        else
-          glw(static_cast<uint16_t*>(S.fb_val))[pos] = gl(static_cast<const uint16_t*>(S.val))[r.k];
+    // every window's runs (per lane: its band, its run's first entry as an
+    // offset from the batch, and its flags with its run's slot), then the
+    // (band, row) prefixes of all windows, then the stores
+    int32_t band[kRowWin], ksr[kRowWin];
+    uint32_t fs[kRowWin];  // bit 0 valid, 1 start, 2 end; bits 8.. the run's slot in the row
+#pragma unroll
+    for (int w = 0; w < kRowWin; ++w) {
+      const RunLane r = batch_run(B, w, base, hi, lg, g, run0, band0);
+      uint32_t n = r.start ? 1u : 0u;  // runs started at or before this lane in the window
+#pragma unroll
+      for (int d = 1; d < kCvLanes; d <<= 1) {
+        const uint32_t t = __shfl_up(n, d, kCvLanes);
+        if (g >= d) n += t;
       }
-      if (r.end) {
-        for (int64_t q = pos + 1; q < e1; ++q) {
+      band[w] = r.band;
+      ksr[w] = static_cast<int32_t>(r.ks - base);  // negative for a run from an earlier batch
+      fs[w] = (r.valid ? 1u : 0u) | (r.start ? 2u : 0u) | (r.end ? 4u : 0u) | ((ord + n - 1u) << 8);
+      ord += __shfl(n, kCvLanes - 1, kCvLanes);
+      run0 = __shfl(r.ks, kCvLanes - 1, kCvLanes);
+      band0 = __shfl(r.band, kCvLanes - 1, kCvLanes);
+    }
+    uint64_t pre[kRowWin];
+    uint32_t e1[kRowWin];
+#pragma unroll
+    for (int w = 0; w < kRowWin; ++w) {
+      const int64_t at = static_cast<int64_t>((fs[w] & 1u) ? band[w] : 0) * S.m + i;
+      pre[w] = gl(S.fb_len)[at];
+      e1[w] = seg_entries(gl(S.fb_len)[at + 1]);  // the prefix plus the padded length
+    }
+#pragma unroll
+    for (int w = 0; w < kRowWin; ++w) {
+      if (!(fs[w] & 1u)) continue;
+      const int64_t e0 = seg_entries(pre[w]);
+      const int64_t pos = e0 + (w * kCvLanes + g - ksr[w]);
+      if (pos < e1[w]) {
+        glw(S.fb_idx)[pos] = static_cast<uint16_t>(B.c[w] - (band[w] << lg));
+        glw(fval)[pos] = v[w];
+      }
+      if (fs[w] & 4u) {
+        for (int64_t q = pos + 1; q < e1[w]; ++q) {
           glw(S.fb_idx)[q] = 0;
-          if constexpr (VB == 8) glw(static_cast<uint64_t*>(S.fb_val))[q] = 0;
-          else if constexpr (VB == 4) glw(static_cast<uint32_t*>(S.fb_val))[q] = 0;
-          else glw(static_cast<uint16_t*>(S.fb_val))[q] = 0;
+          glw(fval)[q] = V{0};
         }
       }
-      if (r.start) {
-        const uint32_t sg = seg_count(pre);
+      if (fs[w] & 2u) {
+        const uint32_t sg = seg_count(pre[w]);
         glw(S.fb_off)[sg] = static_cast<int32_t>(e0);
-        glw(S.fb_slot)[slot0 + ord + nst - 1u] = static_cast<int32_t>(sg);
+        glw(S.fb_slot)[slot0 + (fs[w] >> 8)] = static_cast<int32_t>(sg);
         const int64_t c4 = e0 / SS_CHUNK;
         atomicOr(S.fb_bits + (c4 >> 5), 1u << (c4 & 31));
       }
     }
-    ord += __shfl(nst, kCvLanes - 1, kCvLanes);
-    run0 = __shfl(r.ks, kCvLanes - 1, kCvLanes);
-    band0 = __shfl(r.band, kCvLanes - 1, kCvLanes);
   }
 }
 
