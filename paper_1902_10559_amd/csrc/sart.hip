@@ -110,6 +110,10 @@ struct Params {
   int32_t band_lg;   // log2 of the forward bands' width (staged)
   int32_t tile_lg;   // log2 of the back-projection tiles' columns (staged)
   int32_t band_q;    // chunks per forward work tile (staged)
+  // block -> system of the staged grids (one load instead of a search of
+  // dependent loads at every block's start): 0 the residual's rows, 1 the
+  // back-projection tiles, 2 the set-up's rows; unused for one system
+  const int32_t* b2s[3];
 };
 
 struct SetupFlags {
@@ -141,6 +145,25 @@ __device__ inline int find_sys(const SysDesc* t, int nsys, int64_t b) {
     else hi = mid - 1;
   }
   return lo;
+}
+
+// The system of block b of a staged grid, from the set-up's table.
+template <int GRID>
+__device__ inline int sys_of(const Params* prm, int nsys, int64_t b) {
+  return nsys == 1 ? 0 : __builtin_amdgcn_readfirstlane(gl(prm->b2s[GRID])[b]);
+}
+
+// Fills the block -> system tables of the staged grids (one block per
+// system; a NULL table is skipped).
+__global__ void k_fill_b2s(const SysDesc* table, int32_t* fp, int32_t* bp, int32_t* cv, int cv_rows) {
+  const SysDesc& d = table[blockIdx.x];
+  const int32_t s = static_cast<int32_t>(blockIdx.x);
+  if (fp)
+    for (int64_t i = threadIdx.x; i < d.fp_nblocks; i += blockDim.x) fp[d.fp_block0 + i] = s;
+  if (bp)
+    for (int64_t i = threadIdx.x; i < d.bp_nblocks; i += blockDim.x) bp[d.bp_block0 + i] = s;
+  if (cv)
+    for (int64_t i = threadIdx.x; i < (d.m + cv_rows - 1) / cv_rows; i += blockDim.x) cv[d.cv_rblk0 + i] = s;
 }
 
 // Writes up to kDescChunk descriptors (from the kernel arguments) into the
@@ -393,9 +416,12 @@ constexpr int kCvLanes = 16;
 constexpr int kCvRows = kThreads / kCvLanes;
 
 // A row's lanes load kRowWin windows of kCvLanes entries at once (a batch),
-// so that a row costs a few dependent load latencies instead of one or two
-// per window; rows longer than a batch take several.
-constexpr int kRowWin = 8;
+// so that a row costs fewer dependent load latencies than one or two per
+// window; rows longer than a batch take several.  These kernels are bound by
+// those latencies times the rows in flight: on the 256-slice batch, batches
+// of 2, 4 and 8 windows filled in 4.31, 4.55 and 5.59 ms (the registers of
+// larger batches cost residency).
+constexpr int kRowWin = 2;
 constexpr int kRowBatch = kRowWin * kCvLanes;
 
 // The columns of one batch from `base`, and the column of the entry after
@@ -500,7 +526,7 @@ __device__ inline bool batch_ascends(const RowBatch& B, int64_t base, int64_t lo
 // (blocks that each walk a range of groups measured slower).
 __global__ __launch_bounds__(kThreads) void k_fb_count(const SysDesc* table, int nsys, const Params* prm) {
   const int64_t vb = blockIdx.x;
-  const SysDesc& S = table[__builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, vb))];
+  const SysDesc& S = table[sys_of<2>(prm, nsys, vb)];
   const int lg = prm->band_lg;
   const int64_t i = (vb - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
   const int g = threadIdx.x % kCvLanes;
@@ -557,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_fb_count(const SysDesc* table, int
 template <int VB>
 __global__ __launch_bounds__(kThreads) void k_fb_fill(const SysDesc* table, int nsys, const Params* prm) {
   const int64_t vb = blockIdx.x;
-  const SysDesc& S = table[__builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<2>(table, nsys, vb))];
+  const SysDesc& S = table[sys_of<2>(prm, nsys, vb)];
   using V = std::conditional_t<VB == 8, uint64_t, std::conditional_t<VB == 4, uint32_t, uint16_t>>;
   const int lg = prm->band_lg;
   const int64_t i = (vb - S.cv_rblk0) * kCvRows + threadIdx.x / kCvLanes;
@@ -978,9 +1004,10 @@ __global__ __launch_bounds__(kWave* kBandWaves) __attribute__((amdgpu_waves_per_
 // segments' sums added in band order (through the row's slots), r = p - q, z = r / W, and the block's FP64
 // partial of |r|^2; the first block of a system moves the iterate index on.
 template <int NV>
-__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys) {
+__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys,
+                                                          const Params* __restrict__ prm) {
   __shared__ double red[kFinThreads / kWave];
-  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<0>(table, nsys, blockIdx.x));
+  const int s = sys_of<0>(prm, nsys, blockIdx.x);
   const SysDesc& S = table[s];
   if (*gl(&S.st->stop)) return;
   const int64_t lb = static_cast<int64_t>(blockIdx.x) - S.fp_block0;
@@ -1026,7 +1053,7 @@ __global__ __launch_bounds__(kStagedThreads) void k_bt_plan(const SysDesc* table
   extern __shared__ uint32_t bw[];
   constexpr int T = kStagedThreads;
   __shared__ uint32_t tsum[2][T];
-  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<1>(table, nsys, blockIdx.x));
+  const int s = sys_of<1>(prm, nsys, blockIdx.x);
   const SysDesc& S = table[s];
   const int64_t lt = static_cast<int64_t>(blockIdx.x) - S.bp_block0;
   const int64_t j0 = lt << prm->tile_lg;
@@ -1119,7 +1146,7 @@ __global__ __launch_bounds__(kStagedThreads) __attribute__((amdgpu_waves_per_eu(
   extern __shared__ float zs[];
   __shared__ double red[kStagedWaves];
   constexpr int L = kWave / CPW;
-  const int s = __builtin_amdgcn_readfirstlane(nsys == 1 ? 0 : find_sys<1>(table, nsys, blockIdx.x));
+  const int s = sys_of<1>(prm, nsys, blockIdx.x);
   const SysDesc& S = table[s];
   if (*gl(&S.st->stop)) return;
   const int64_t lt = static_cast<int64_t>(blockIdx.x) - S.bp_block0;
@@ -1218,6 +1245,7 @@ struct Layout {
   std::vector<size_t> fb_idx, fb_val, fb_len, fb_rseg, fb_off, fb_slot, fb_part, fb_bits, bt_idx, bt_meta, bt_runs;
   size_t fb_len_lo = 0, fb_len_hi = 0, fb_rseg_lo = 0, fb_rseg_hi = 0, fb_bits_lo = 0, fb_bits_hi = 0;
   size_t tiles = 0, ntiles = 0, pair_t0 = 0, pieces64 = 0, pieces32 = 0, tsum64 = 0, tsum32 = 0, info = 0;
+  size_t b2s[3] = {0, 0, 0};  // block -> system tables of the staged grids (0: none)
   int64_t tile_cap = 0, t64 = 0, t32 = 0, npairs = 0;
 };
 
@@ -1349,6 +1377,22 @@ Layout make_layout(const ss_system* sys, int nsys, const ss_sart_opts* opt) {
   if (stg) {
     L.info = o;
     o += 256;
+  }
+  if (stg && nsys > 1) {
+    const int lg = tile_lg_of(opt);
+    int64_t nb[3] = {0, 0, 0};
+    for (int s = 0; s < nsys; ++s) {
+      nb[0] += (sys[s].m + kFinThreads - 1) / kFinThreads;
+      nb[1] += (sys[s].n + (int64_t{1} << lg) - 1) >> lg;
+      nb[2] += (sys[s].m + kCvRows - 1) / kCvRows;
+    }
+    for (int k = 0; k < 3; ++k) {
+      if (k == 0 && !(stg & 1)) continue;
+      if (k == 1 && !(stg & 2)) continue;
+      if (k == 2 && !(stg & 1)) continue;
+      L.b2s[k] = o;
+      o += align256(sizeof(int32_t) * static_cast<size_t>(nb[k]));
+    }
   }
   if (stg & 2) {
     const int lg = tile_lg_of(opt);
@@ -1587,6 +1631,7 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
   prm.band_lg = c.blg;
   prm.tile_lg = c.tlg;
   prm.band_q = c.bq;
+  for (int k = 0; k < 3; ++k) prm.b2s[k] = L.b2s[k] ? reinterpret_cast<const int32_t*>(ws + L.b2s[k]) : nullptr;
   const int64_t rpb = (c.stg & 1) ? kFinThreads : static_cast<int64_t>(c.rpw) * kWPB;
   const int64_t cpb = (c.stg & 2) ? (int64_t{1} << c.tlg) : static_cast<int64_t>(c.cpw) * kWPB;
   DescChunk ch{};
@@ -1667,6 +1712,11 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
   if (c.nv == 2) k_setup<2><<<static_cast<unsigned>(nsys), kWave * kSetupWaves, 0, st>>>(table, fl);
   else k_setup<1><<<static_cast<unsigned>(nsys), kWave * kSetupWaves, 0, st>>>(table, fl);
   if (fb > UINT32_MAX || bb > UINT32_MAX || cv > UINT32_MAX) return fail(SS_E_ARG, "SART: grid too large");
+  if (L.b2s[0] || L.b2s[1] || L.b2s[2])
+    k_fill_b2s<<<static_cast<unsigned>(nsys), 256, 0, st>>>(
+        table, L.b2s[0] ? reinterpret_cast<int32_t*>(ws + L.b2s[0]) : nullptr,
+        L.b2s[1] ? reinterpret_cast<int32_t*>(ws + L.b2s[1]) : nullptr,
+        L.b2s[2] ? reinterpret_cast<int32_t*>(ws + L.b2s[2]) : nullptr, kCvRows);
   g->fp_blocks = static_cast<uint32_t>(fb);
   g->bp_blocks = static_cast<uint32_t>(bb);
   g->cv_blocks = static_cast<uint32_t>(cv);
@@ -1753,7 +1803,7 @@ void launch_band(const Cfg& c, const char* ws, const Layout& L, int nsys, const 
   const size_t lds = band_lds_bytes(NV, c.blg);
   hipExtLaunchKernelGGL(k_band_fp<NV, WT, P>, dim3(g.band_blocks), dim3(kWave * kBandWaves), lds, st, e.start,
                         e.mid0, 0, t, tiles, nt, prm, par);
-  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys);
+  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys, prm);
 }
 
 template <int NV, int WT, int P>
