@@ -381,10 +381,10 @@ def choose_config(args, slices, systems, lam, iters):
                                 cols_per_wave=cpw if bits & 2 else base.cols_per_wave)
         return o, lanes_of(o)
     fp, bp = staged_search(systems, base, scratch)
-    # one unroll serves both staged kernels: the back projection's (8), or
-    # the forward one's when only it is staged
+    # `unroll` sets the band kernel's batches only (the staged back
+    # projection's chunks per pass follow its columns per wavefront)
     cands = [base,
-             dataclasses.replace(base, staged=3, unroll=8, band_width=fp[0], tile_entries=fp[1],
+             dataclasses.replace(base, staged=3, unroll=fp[2], band_width=fp[0], tile_entries=fp[1],
                                  cols_per_wave=bp[1], tile_cols=bp[0]),
              dataclasses.replace(base, staged=1, unroll=fp[2], band_width=fp[0], tile_entries=fp[1]),
              dataclasses.replace(base, staged=2, cols_per_wave=bp[1], tile_cols=bp[0])]

@@ -379,8 +379,11 @@ ss_status ss_unsplit(const ss_matrix_dev* A, const float* p, ss_system* out,
  *                per wavefront of an 8-wavefront block; rows_per_wave,
  *                `chunked` and `persistent` do not apply to the staged
  *                kernels; `unroll` 8 has the band kernel keep three
- *                windows of loads per wavefront in flight (4: two).  The sums run in another order than the unstaged
- *                kernels' (equal to FP32 rounding), always the same one.
+ *                windows of loads per wavefront in flight (4: two); the
+ *                staged back projection takes two chunks per lane and pass
+ *                with 8 or more columns per wavefront, else one.  The sums
+ *                run in another order than the unstaged kernels' (equal to
+ *                FP32 rounding), always the same one.
  *   band_width   voxels per forward band: a power of two from 1024 to 16384
  *                with band_width * nvals * 4 + 16384 * nvals <= 65536 bytes
  *                of shared memory (0 = 4096)

@@ -1792,7 +1792,10 @@ void launch_bp_u(int cpw, int pers, const Params* prm, const SysDesc* t, int nsy
 
 // Staged kernels: the forward pair (band kernel, then the residual kernel)
 // and the tile-staged back projection.  The band kernel loads batches of one
-// window per wavefront (unroll 4) or two (unroll 8).
+// window per wavefront (unroll 4) or two (unroll 8); the back projection
+// takes two chunks per lane and pass when a lane group is 8 lanes or fewer
+// (8 or more columns per wavefront: a pass then still covers a column of 64
+// entries), else one.
 template <int NV, int WT, int P>
 void launch_band(const Cfg& c, const char* ws, const Layout& L, int nsys, const Grids& g, int par, hipStream_t st,
                  Stamp e) {
@@ -1827,7 +1830,7 @@ void launch_kernel(const Cfg& c, const char* ws, const Layout& L, int nsys, cons
 #define SS_STAGED(NV, WT)                                                                            \
   if (c.nv == NV && c.wt == WT) {                                                                    \
     if (BP) {                                                                                        \
-      if (c.u == 8) launch_tile_bp<NV, WT, 2>(c, ws, L, nsys, g, par, st, e);                        \
+      if (c.cpw >= 8) launch_tile_bp<NV, WT, 2>(c, ws, L, nsys, g, par, st, e);                      \
       else launch_tile_bp<NV, WT, 1>(c, ws, L, nsys, g, par, st, e);                                 \
     } else {                                                                                         \
       if (c.u == 8) launch_band<NV, WT, 2>(c, ws, L, nsys, g, par, st, e);                           \
