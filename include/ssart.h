@@ -531,7 +531,10 @@ ss_status ss_ossart_workspace_bytes(const ss_system* sys, const ss_subsets* sub,
  * iterates are ordered-subset SART on A with the mirror-closed subsets.
  * Options as for ss_sart_solve, with max_iter counting passes and
  * cols_per_wave up to 64 (a subset sees 1/S of each column); `persistent`
- * is ignored.  res_hist[s][k] = rel_res of the image after k passes, for
+ * is ignored, `staged` must be 0, and `chunked` takes bits 0 and 1 as there
+ * and bit 2 (the interleaved forward form: the workspace holds a copy of
+ * every system's rows in the interleaved order, made on every solve;
+ * results equal the entry-wise form's bit for bit), not bit 3 (SS_E_ARG).  res_hist[s][k] = rel_res of the image after k passes, for
  * k = 0 .. passes[s] (max_iter + 1 doubles); passes (host, or NULL)
  * receives the passes applied.  A pass evaluates the residual of its
  * starting image (one extra forward projection of every row) on every

@@ -33,6 +33,7 @@
 
 #include "device.h"
 #include "graph_cache.h"
+#include "interleave.h"
 #include "internal.h"
 #include "lines.h"
 
@@ -139,8 +140,11 @@ __global__ __launch_bounds__(kOsThreads) void k_os_setup(OsChunk ch, OsDesc* tab
 
 // Forward projection of rows [r0, r0 + rows) in tiles of RPW*kOsWPB rows.
 // RES: FP64 partial of |p - A f|^2 per block into `partials`; otherwise
-// z = W^-1 (p - A f).
-template <int WT, int RPW, int U, bool CH, bool RES>
+// z = W^-1 (p - A f).  Stream forms (SF): 0 entry-wise, 1 aligned chunks,
+// 2 interleaved (the rows read from the workspace copy in the interleaved
+// order; the sums run in the entry-wise order, so the results are the same
+// bit for bit).
+template <int WT, int RPW, int U, int SF, bool RES>
 __global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsParams* __restrict__ prm,
                                                       const OsDesc* __restrict__ table,
                                                       const int32_t* __restrict__ b2s, int nsys, uint32_t ntiles,
@@ -164,7 +168,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_fp(const OsParams* __restrict
   const int64_t lo = gl(S.row_ptr)[li];
   const int64_t hi = in ? gl(S.row_ptr)[li + 1] : lo;
   float acc[2] = {0.0f, 0.0f};
-  line_dot<2, WT, L, U, CH>(S.col_idx, S.val, S.f, lo, hi, glane, acc);
+  if constexpr (SF == 2) line_dot_i<2, WT, L, U / SS_CHUNK>(S.col_idx, S.val, S.f, lo, hi, glane, acc);
+  else line_dot<2, WT, L, U, SF == 1>(S.col_idx, S.val, S.f, lo, hi, glane, acc);
   acc[0] = group_sum<L>(acc[0]);
   acc[1] = group_sum<L>(acc[1]);
   const bool owner = glane == 0 && in;
@@ -283,11 +288,12 @@ struct OsCfg {
 struct OsLayout {
   size_t params, table, states, b2s[3], total;
   std::vector<size_t> z_off, part_off;
+  std::vector<size_t> fi_idx, fi_val;  // interleaved copies of the rows (chunked bit 2)
 };
 
 inline size_t al256(size_t v) { return (v + 255) & ~size_t{255}; }
 
-OsLayout os_layout(const ss_system* sys, int nsys) {
+OsLayout os_layout(const ss_system* sys, int nsys, int chunked) {
   OsLayout L;
   size_t o = 0;
   L.params = o;
@@ -314,6 +320,15 @@ OsLayout os_layout(const ss_system* sys, int nsys) {
   for (int s = 0; s < nsys; ++s) {
     L.part_off.push_back(o);
     o += al256(sizeof(double) * static_cast<size_t>((sys[s].m + kOsWPB - 1) / kOsWPB));  // 1 row per wave
+  }
+  if (chunked & 4) {
+    for (int s = 0; s < nsys; ++s) {
+      const size_t cap = static_cast<size_t>(sys[s].nnz) + SS_CHUNK;
+      L.fi_idx.push_back(o);
+      o += al256(sizeof(int32_t) * cap);
+      L.fi_val.push_back(o);
+      o += al256(2 * sizeof(float) * cap);
+    }
   }
   L.total = o;
   return L;
@@ -348,7 +363,7 @@ ss_status os_validate(const ss_system* sys, const ss_subsets* sub, int nsys, con
   if (!ok_pw(o->rows_per_wave, 8) || !ok_pw(o->cols_per_wave, 64))
     return fail(SS_E_ARG, "%s: rows_per_wave must be 0,1,2,4,8 and cols_per_wave 0,1,..,64", fn);
   if (o->unroll != 0 && o->unroll != 4 && o->unroll != 8) return fail(SS_E_ARG, "%s: unroll must be 0, 4 or 8", fn);
-  if (o->chunked < 0 || o->chunked > 3) return fail(SS_E_ARG, "%s: chunked must be 0..3", fn);
+  if (o->chunked < 0 || o->chunked > 7) return fail(SS_E_ARG, "%s: chunked must be 0..7", fn);
   if (o->nonneg != 0 && o->nonneg != 1) return fail(SS_E_ARG, "%s: nonneg must be 0 or 1", fn);
   if (o->staged != 0) return fail(SS_E_ARG, "%s: the staged forms are for ss_sart_* only (staged must be 0)", fn);
   if (o->residual_every < 0) return fail(SS_E_ARG, "%s: residual_every must be >= 0", fn);
@@ -394,16 +409,26 @@ struct OsGrid {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <int WT, int U, bool CH, bool RES>
+template <int WT, int U, int SF, bool RES>
 void os_fp_rpw(int rpw, const OsParams* prm, const OsDesc* t, const int32_t* b2s, int nsys, uint32_t nb, int xcd,
                int sub, hipStream_t st) {
   const dim3 g(nb), b(kOsThreads);
   switch (rpw) {
-    case 1: k_os_fp<WT, 1, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
-    case 2: k_os_fp<WT, 2, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
-    case 4: k_os_fp<WT, 4, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
-    default: k_os_fp<WT, 8, U, CH, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 1: k_os_fp<WT, 1, U, SF, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 2: k_os_fp<WT, 2, U, SF, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    case 4: k_os_fp<WT, 4, U, SF, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
+    default: k_os_fp<WT, 8, U, SF, RES><<<g, b, 0, st>>>(prm, t, b2s, nsys, nb, xcd, sub); break;
   }
+}
+
+// The forward launch in the stream form of the chunked bits: bit 2
+// interleaved, else bit 0 chunked, else entry-wise.
+template <int U, bool RES>
+void os_fp(const OsCfg& c, const OsParams* prm, const OsDesc* t, const int32_t* b2s, int nsys, uint32_t nb, int sub,
+           hipStream_t st) {
+  if (c.ch & 4) os_fp_rpw<SS_F32, U, 2, RES>(c.rpw, prm, t, b2s, nsys, nb, c.xcd, sub, st);
+  else if (c.ch & 1) os_fp_rpw<SS_F32, U, 1, RES>(c.rpw, prm, t, b2s, nsys, nb, c.xcd, sub, st);
+  else os_fp_rpw<SS_F32, U, 0, RES>(c.rpw, prm, t, b2s, nsys, nb, c.xcd, sub, st);
 }
 
 template <int WT, int U, bool CH>
@@ -425,13 +450,11 @@ void os_bp_cpw(int cpw, const OsParams* prm, const OsDesc* t, const int32_t* b2s
 template <int U>
 void os_pass(const OsCfg& c, const OsParams* prm, const OsDesc* t, const int32_t* const* b2s, int nsys, int S,
              const OsGrid& g, hipStream_t st) {
-  const bool fch = c.ch & 1, bch = c.ch & 2;
-  if (fch) os_fp_rpw<SS_F32, U, true, true>(c.rpw, prm, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
-  else os_fp_rpw<SS_F32, U, false, true>(c.rpw, prm, t, b2s[kAllRows], nsys, g.nb[kAllRows], c.xcd, 0, st);
+  const bool bch = c.ch & 2;
+  os_fp<U, true>(c, prm, t, b2s[kAllRows], nsys, g.nb[kAllRows], 0, st);
   k_os_fin<<<nsys, kOsThreads, 0, st>>>(t, prm);
   for (int s = 0; s < S; ++s) {
-    if (fch) os_fp_rpw<SS_F32, U, true, false>(c.rpw, prm, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
-    else os_fp_rpw<SS_F32, U, false, false>(c.rpw, prm, t, b2s[kSubRows], nsys, g.nb[kSubRows], c.xcd, s, st);
+    os_fp<U, false>(c, prm, t, b2s[kSubRows], nsys, g.nb[kSubRows], s, st);
     if (bch) os_bp_cpw<SS_F32, U, true>(c.cpw, prm, t, b2s[kCols], nsys, g.nb[kCols], c.xcd, s, st);
     else os_bp_cpw<SS_F32, U, false>(c.cpw, prm, t, b2s[kCols], nsys, g.nb[kCols], c.xcd, s, st);
   }
@@ -518,7 +541,7 @@ extern "C" ss_status ss_ossart_workspace_bytes(const ss_system* sys, const ss_su
   clear_error();
   if (!bytes) return fail(SS_E_ARG, "ss_ossart_workspace_bytes: NULL bytes");
   if (ss_status s = os_validate(sys, sub, nsys, opts, "ss_ossart_workspace_bytes")) return s;
-  *bytes = os_layout(sys, nsys).total;
+  *bytes = os_layout(sys, nsys, opts->chunked).total;
   return SS_OK;
 }
 
@@ -533,7 +556,7 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     if (!f[s] || (res_hist && !res_hist[s])) return fail(SS_E_ARG, "ss_ossart_solve: NULL image %d", s);
     if (sub[s].S != S) return fail(SS_E_ARG, "ss_ossart_solve: all systems must have the same S");
   }
-  const OsLayout L = os_layout(sys, nsys);
+  const OsLayout L = os_layout(sys, nsys, opts->chunked);
   if (workspace_bytes < L.total)
     return fail(SS_E_WORKSPACE, "ss_ossart_solve: workspace needs %zu bytes", L.total);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -551,6 +574,13 @@ extern "C" ss_status ss_ossart_solve(const ss_system* sys, const ss_subsets* sub
     d.row_ptr = Y.row_ptr;
     d.col_idx = Y.col_idx;
     d.val = Y.val;
+    if ((c.ch & 4) && Y.nnz > 0) {  // the rows in the interleaved order of the forward kernels' lanes
+      d.col_idx = reinterpret_cast<int32_t*>(ws + L.fi_idx[s]);
+      d.val = ws + L.fi_val[s];
+      if (ss_status e = interleave_lines(Y.row_ptr, Y.m, Y.col_idx, Y.val, const_cast<int32_t*>(d.col_idx),
+                                         const_cast<void*>(d.val), 2 * sizeof(float), kWave / c.rpw, st))
+        return e;
+    }
     d.col_ptr = Y.col_ptr;
     d.row_idx = Y.row_idx;
     d.val_t = Y.val_t;

@@ -46,6 +46,7 @@
 #include "device.h"
 #include "graph_cache.h"
 #include "internal.h"
+#include "interleave.h"
 #include "lines.h"
 #include "staged.h"
 
@@ -248,26 +249,6 @@ __device__ inline void line_sum(const int32_t* idx, const void* val, const float
                                 int glane, float* acc) {
   if constexpr (SF == 2) line_dot_i<NV, WT, L, U / SS_CHUNK>(idx, val, x, lo, hi, glane, acc);
   else line_dot<NV, WT, L, U, SF == 1>(idx, val, x, lo, hi, glane, acc);
-}
-
-// Copies one line list (CSR rows or CSC columns) into the interleaved order
-// of line_dot_i, one wavefront per line.  VB: value bytes per entry (4 or 8).
-template <int VB>
-__global__ __launch_bounds__(kThreads) void k_interleave(const int64_t* __restrict__ ptr, int64_t lines,
-                                                         const int32_t* __restrict__ idx,
-                                                         const void* __restrict__ val, int32_t* __restrict__ idx_out,
-                                                         void* __restrict__ val_out, int L) {
-  const int64_t line = static_cast<int64_t>(blockIdx.x) * kWPB + wave_id();
-  if (line >= lines) return;
-  const int64_t lo = gl(ptr)[line], n = gl(ptr)[line + 1] - lo;
-  for (int64_t e = lane_id(); e < n; e += kWave) {
-    const int64_t d = lo + interleaved_pos(e, n, L);
-    glw(idx_out)[d] = gl(idx)[lo + e];
-    if constexpr (VB == 8)
-      glw(static_cast<uint64_t*>(val_out))[d] = gl(static_cast<const uint64_t*>(val))[lo + e];
-    else
-      glw(static_cast<uint32_t*>(val_out))[d] = gl(static_cast<const uint32_t*>(val))[lo + e];
-  }
 }
 
 template <int NV, int WT, int RPW, int U, int SF>
@@ -1533,16 +1514,6 @@ struct Grids {
   uint32_t cv_blocks;    // set-up grid over rows
 };
 
-ss_status interleave(const int64_t* ptr, int64_t lines, const int32_t* idx, const void* val, int32_t* idx_out,
-                     void* val_out, size_t vb, int L, hipStream_t st) {
-  const int64_t blocks = (lines + kWPB - 1) / kWPB;
-  if (blocks > INT32_MAX) return fail(SS_E_ARG, "SART: too many lines to interleave");
-  if (vb == 8) k_interleave<8><<<static_cast<uint32_t>(blocks), kThreads, 0, st>>>(ptr, lines, idx, val, idx_out, val_out, L);
-  else k_interleave<4><<<static_cast<uint32_t>(blocks), kThreads, 0, st>>>(ptr, lines, idx, val, idx_out, val_out, L);
-  SS_HIP_TRY(hipGetLastError());
-  return SS_OK;
-}
-
 // Grid of the band-staged forward kernel: the blocks that fit on the device
 // at once (its LDS decides), at most one per possible tile; each block then
 // takes a contiguous run of the tiles.
@@ -1664,15 +1635,15 @@ ss_status setup(const ss_system* sys, int nsys, float* const* f, double* const* 
     if (S.nnz > 0 && fp_form(c.ch) == 2 && !S.row_lanes && !(c.stg & 1)) {
       d.col_idx = reinterpret_cast<int32_t*>(ws + L.fi_idx[s]);
       d.val = ws + L.fi_val[s];
-      if (ss_status e = interleave(S.row_ptr, S.m, S.col_idx, S.val, const_cast<int32_t*>(d.col_idx),
-                                   const_cast<void*>(d.val), value_bytes(S), kWave / c.rpw, st))
+      if (ss_status e = interleave_lines(S.row_ptr, S.m, S.col_idx, S.val, const_cast<int32_t*>(d.col_idx),
+                                         const_cast<void*>(d.val), value_bytes(S), kWave / c.rpw, st))
         return e;
     }
     if (S.nnz > 0 && bp_form(c.ch) == 2 && !S.col_lanes && !(c.stg & 2)) {
       d.row_idx = reinterpret_cast<int32_t*>(ws + L.bi_idx[s]);
       d.val_t = ws + L.bi_val[s];
-      if (ss_status e = interleave(S.col_ptr, S.n, S.row_idx, S.val_t, const_cast<int32_t*>(d.row_idx),
-                                   const_cast<void*>(d.val_t), value_bytes(S), kWave / c.cpw, st))
+      if (ss_status e = interleave_lines(S.col_ptr, S.n, S.row_idx, S.val_t, const_cast<int32_t*>(d.row_idx),
+                                         const_cast<void*>(d.val_t), value_bytes(S), kWave / c.cpw, st))
         return e;
     }
     if (c.stg & 1) {
