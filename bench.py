@@ -463,8 +463,11 @@ def unsplit_config(unsplit, opts, lam, iters):
 
 def kernel_report(slv, systems, scratch, o, nv, sv):
     """Per-launch times of one iteration and the algorithmic bytes of each
-    launch (the byte model of the kernels the options select)."""
-    ms = slv.time_phases(scratch, reps=50)
+    launch (the byte model of the kernels the options select); per launch
+    the median of three timings of 50 iterations."""
+    import statistics
+    runs = [slv.time_phases(scratch, reps=50) for _ in range(3)]
+    ms = [statistics.median(r[k] for r in runs) for k in range(3)]
     info = slv.staged_info(scratch) if o.staged else [0, 0, 0, 0, 0]
     nnz = sum(S.nnz for S in systems)
     m = sum(S.m for S in systems)
