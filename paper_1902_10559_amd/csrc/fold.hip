@@ -395,10 +395,13 @@ struct FoldJob {
 };
 
 // B = false: the job travels in the kernel arguments; B = true: a device
-// table of `count` jobs ordered by their first blocks.
+// table of `count` jobs ordered by their first blocks, and per grid (row
+// lines, column lines, row scan tiles, column scan tiles) the job of each
+// block, so that a block finds its job with one load.
 struct JobArg {
   const FoldJob* table;
   int32_t count;
+  const int32_t* b2j[4];
   FoldJob one;
 };
 
@@ -413,15 +416,9 @@ __device__ inline const FoldJob& find_job(const JobArg& J, int64_t b, int64_t* l
     auto first = [](const FoldJob& q) {
       return TILES ? (COLS ? q.ctile0 : q.rtile0) : (COLS ? q.cblk0 : q.rblk0);
     };
-    int lo = 0, hi = J.count - 1;
-    while (lo < hi) {
-      const int mid = __builtin_amdgcn_readfirstlane((lo + hi + 1) >> 1);
-      if (first(J.table[mid]) <= b) lo = mid;
-      else hi = mid - 1;
-    }
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    *local = b - first(J.table[lo]);
-    return J.table[lo];
+    const int k = __builtin_amdgcn_readfirstlane(gl(J.b2j[TILES ? (COLS ? 3 : 2) : (COLS ? 1 : 0)])[b]);
+    *local = b - first(J.table[k]);
+    return J.table[k];
   }
 }
 
@@ -796,6 +793,21 @@ __global__ void k_put_jobs(JobChunk ch, FoldJob* table) {
   if (static_cast<int>(threadIdx.x) < ch.count) table[ch.first + threadIdx.x] = ch.j[threadIdx.x];
 }
 
+// The job of every block of the four batched grids (one block per job; the
+// totals bound the last job's ranges).
+__global__ void k_fill_b2j(const FoldJob* table, int32_t count, int64_t rblk, int64_t cblk, int64_t rtile,
+                           int64_t ctile, int32_t* b_rows, int32_t* b_cols, int32_t* t_rows, int32_t* t_cols) {
+  const int32_t k = static_cast<int32_t>(blockIdx.x);
+  const FoldJob& q = table[k];
+  const bool last = k + 1 == count;
+  const int64_t r1 = last ? rblk : table[k + 1].rblk0, c1 = last ? cblk : table[k + 1].cblk0;
+  const int64_t rt1 = last ? rtile : table[k + 1].rtile0, ct1 = last ? ctile : table[k + 1].ctile0;
+  for (int64_t b = q.rblk0 + threadIdx.x; b < r1; b += blockDim.x) b_rows[b] = k;
+  for (int64_t b = q.cblk0 + threadIdx.x; b < c1; b += blockDim.x) b_cols[b] = k;
+  for (int64_t b = q.rtile0 + threadIdx.x; b < rt1; b += blockDim.x) t_rows[b] = k;
+  for (int64_t b = q.ctile0 + threadIdx.x; b < ct1; b += blockDim.x) t_cols[b] = k;
+}
+
 // Grid sizes of one fold call: blocks of row and column lines, scan tiles.
 struct FoldGrid {
   int64_t rblk = 0, cblk = 0, rtile = 0, ctile = 0;
@@ -881,6 +893,44 @@ FoldGrid layout_jobs(const ss_matrix_dev* A, const float* const* p, const ss_sys
 }
 
 size_t batch_table_bytes(int32_t count) { return (sizeof(FoldJob) * static_cast<size_t>(count) + 255) & ~size_t{255}; }
+
+inline size_t al256(size_t v) { return (v + 255) & ~size_t{255}; }
+
+// The head of a batch's workspace: the job table, then the block -> job
+// tables of the four grids.
+size_t batch_head_bytes(int32_t count, const FoldGrid& g) {
+  return batch_table_bytes(count) + al256(sizeof(int32_t) * static_cast<size_t>(g.rblk)) +
+         al256(sizeof(int32_t) * static_cast<size_t>(g.cblk)) + al256(sizeof(int32_t) * static_cast<size_t>(g.rtile)) +
+         al256(sizeof(int32_t) * static_cast<size_t>(g.ctile));
+}
+
+// Writes the job table and the block -> job tables into the workspace head
+// and returns the kernels' argument.
+JobArg put_batch(const std::vector<FoldJob>& jobs, const FoldGrid& g, char* ws, hipStream_t st) {
+  const int32_t count = static_cast<int32_t>(jobs.size());
+  FoldJob* table = reinterpret_cast<FoldJob*>(ws);
+  for (int32_t k0 = 0; k0 < count; k0 += kJobChunk) {
+    JobChunk ch{};
+    ch.first = k0;
+    ch.count = std::min(kJobChunk, count - k0);
+    for (int i = 0; i < ch.count; ++i) ch.j[i] = jobs[k0 + i];
+    k_put_jobs<<<1, kWave, 0, st>>>(ch, table);
+  }
+  JobArg J{};
+  J.table = table;
+  J.count = count;
+  char* o = ws + batch_table_bytes(count);
+  const int64_t sizes[4] = {g.rblk, g.cblk, g.rtile, g.ctile};
+  int32_t* t[4];
+  for (int k = 0; k < 4; ++k) {
+    t[k] = reinterpret_cast<int32_t*>(o);
+    J.b2j[k] = t[k];
+    o += al256(sizeof(int32_t) * static_cast<size_t>(sizes[k]));
+  }
+  k_fill_b2j<<<static_cast<unsigned>(count), 256, 0, st>>>(table, count, g.rblk, g.cblk, g.rtile, g.ctile, t[0], t[1],
+                                                           t[2], t[3]);
+  return J;
+}
 
 // The checks of eq. (2) and of the arrays for every job: both passes over
 // the line pairs with the fold's lane groups, then one block per job.
@@ -1029,7 +1079,7 @@ extern "C" ss_status ss_fold_batch_workspace_bytes(const ss_matrix_dev* A, int32
   const FoldGrid g = layout_jobs(A, nullptr, nullptr, count, nullptr);
   const size_t scratch = std::max(sizeof(int64_t) * static_cast<size_t>(std::max(g.rtile, g.ctile)),
                                   sizeof(CheckPart) * static_cast<size_t>(g.rblk + g.cblk));
-  *bytes = batch_table_bytes(count) + ((scratch + 255) & ~size_t{255}) + sizeof(FoldCheck) * static_cast<size_t>(count);
+  *bytes = batch_head_bytes(count, g) + ((scratch + 255) & ~size_t{255}) + sizeof(FoldCheck) * static_cast<size_t>(count);
   return SS_OK;
 }
 
@@ -1051,21 +1101,11 @@ extern "C" ss_status ss_fold_size_batch(const ss_matrix_dev* A, const float* con
   std::vector<FoldJob> jobs;
   const FoldGrid g = layout_jobs(A, p, nullptr, count, &jobs);
   char* ws = static_cast<char*>(workspace);
-  FoldJob* table = reinterpret_cast<FoldJob*>(ws);
-  CheckPart* rparts = reinterpret_cast<CheckPart*>(ws + batch_table_bytes(count));
+  CheckPart* rparts = reinterpret_cast<CheckPart*>(ws + batch_head_bytes(count, g));
   const size_t scratch = std::max(sizeof(int64_t) * static_cast<size_t>(std::max(g.rtile, g.ctile)),
                                   sizeof(CheckPart) * static_cast<size_t>(g.rblk + g.cblk));
-  FoldCheck* chk = reinterpret_cast<FoldCheck*>(ws + batch_table_bytes(count) + ((scratch + 255) & ~size_t{255}));
-  for (int32_t k0 = 0; k0 < count; k0 += kJobChunk) {
-    JobChunk ch{};
-    ch.first = k0;
-    ch.count = std::min(kJobChunk, count - k0);
-    for (int i = 0; i < ch.count; ++i) ch.j[i] = jobs[k0 + i];
-    k_put_jobs<<<1, kWave, 0, st>>>(ch, table);
-  }
-  JobArg J{};
-  J.table = table;
-  J.count = count;
+  FoldCheck* chk = reinterpret_cast<FoldCheck*>(ws + batch_head_bytes(count, g) + ((scratch + 255) & ~size_t{255}));
+  const JobArg J = put_batch(jobs, g, ws, st);
   run_check<true>(J, g, rparts, rparts + g.rblk, chk, count, st);
   SS_HIP_TRY(hipGetLastError());
   std::vector<FoldCheck> h(static_cast<size_t>(count));
@@ -1093,18 +1133,9 @@ extern "C" ss_status ss_fold_batch(const ss_matrix_dev* A, const float* const* p
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<FoldJob> jobs;
   const FoldGrid g = layout_jobs(A, p, out, count, &jobs);
-  FoldJob* table = static_cast<FoldJob*>(workspace);
-  int64_t* tiles = reinterpret_cast<int64_t*>(static_cast<char*>(workspace) + batch_table_bytes(count));
-  for (int32_t k0 = 0; k0 < count; k0 += kJobChunk) {
-    JobChunk ch{};
-    ch.first = k0;
-    ch.count = std::min(kJobChunk, count - k0);
-    for (int i = 0; i < ch.count; ++i) ch.j[i] = jobs[k0 + i];
-    k_put_jobs<<<1, kWave, 0, st>>>(ch, table);
-  }
-  JobArg J{};
-  J.table = table;
-  J.count = count;
+  char* ws = static_cast<char*>(workspace);
+  int64_t* tiles = reinterpret_cast<int64_t*>(ws + batch_head_bytes(count, g));
+  const JobArg J = put_batch(jobs, g, ws, st);
   run_fold<true>(J, g, out[0].wdtype, tiles, st);
   SS_HIP_TRY(hipGetLastError());
   return SS_OK;
