@@ -106,6 +106,100 @@ __global__ __launch_bounds__(kWave* kConvWaves) void k_conv3x3(const uint16_t* _
   }
 }
 
+// The same convolution with the operands staged in shared memory, for
+// input channels (padded) a multiple of 16: a block computes 64
+// consecutive pixels of one image row (16 per wavefront) for NT tiles of 16
+// output channels.  Per chunk of CC input channels it copies the three input
+// rows the tile reads (66 pixels with the borders, zeros outside the image)
+// and the chunk of the tile's weights into shared memory with 16-byte loads,
+// then every wavefront runs the chunk's nine taps on the matrix cores from
+// there: each input value is read from memory once per block instead of
+// once per tap, and each weight once per block instead of once per
+// wavefront.  K order within a chunk: with CC = 32 one tap per product (its
+// four groups of 8 channels), with CC = 16 two taps per product (taps 2s and
+// 2s + 1, the ninth paired with zeros).  The weights' rows are padded by one
+// vector in shared memory, so the 16 output channels of a read fall on
+// different banks.
+constexpr int kConvPx = 16 * kConvWaves;  // pixels per block
+template <int NT, int CC>
+__global__ __launch_bounds__(kWave* kConvWaves) void k_conv3x3_t(const uint16_t* __restrict__ x, int H, int W,
+                                                                  int C, int Cp, const uint16_t* __restrict__ w,
+                                                                  const float* __restrict__ bias, int O, int relu,
+                                                                  void* __restrict__ y, int y_f32) {
+  constexpr int V = CC / 8;               // 16-byte vectors per pixel and chunk
+  constexpr int XV = 3 * (kConvPx + 2) * V;
+  constexpr int WS = 9 * V + 1;           // vectors per output channel (padded)
+  constexpr int WV = NT * 16 * 9 * V;
+  __shared__ u16x8 xs[XV];
+  __shared__ u16x8 wsm[NT * 16 * WS];
+  const int lane = lane_id(), g = lane / 16, m = lane % 16, wv = wave_id();
+  const int row = blockIdx.y;  // n * H + i
+  const int i = row % H;
+  const int xb = blockIdx.x * kConvPx;
+  const int o0 = blockIdx.z * 16 * NT;
+  const int64_t img0 = static_cast<int64_t>(row - i) * W;  // first pixel of image n
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int p = 16 * wv + m;  // this lane's pixel in the block (A rows)
+  for (int c0 = 0; c0 < Cp; c0 += CC) {
+    for (int v = threadIdx.x; v < XV; v += kWave * kConvWaves) {
+      const int q = v % V, px = (v / V) % (kConvPx + 2), r = v / V / (kConvPx + 2);
+      const int yy = i + r - 1, xx = xb + px - 1;
+      u16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        val = *gl(reinterpret_cast<const u16x8*>(x + (img0 + static_cast<int64_t>(yy) * W + xx) * C + c0 + 8 * q));
+      xs[v] = val;
+    }
+    for (int v = threadIdx.x; v < WV; v += kWave * kConvWaves) {
+      const int q = v % V, tap = (v / V) % 9, oo = v / V / 9;
+      const int o = o0 + oo;
+      u16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (o < O) val = *gl(reinterpret_cast<const u16x8*>(w + (static_cast<int64_t>(o) * 9 + tap) * Cp + c0 + 8 * q));
+      wsm[oo * WS + tap * V + q] = val;
+    }
+    __syncthreads();
+    if constexpr (CC == 32) {
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const bf16x8 a = as_bf16x8(xs[((tap / 3) * (kConvPx + 2) + p + tap % 3) * V + g]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mma(a, as_bf16x8(wsm[(16 * t + m) * WS + tap * V + g]), acc[t]);
+      }
+    } else {
+#pragma unroll
+      for (int s2 = 0; s2 < 5; ++s2) {
+        const int tap = 2 * s2 + (g >> 1), q = g & 1;
+        const bool in = tap < 9;
+        const int tt = in ? tap : 0;
+        u16x8 av = xs[((tt / 3) * (kConvPx + 2) + p + tt % 3) * V + q];
+        if (!in) av = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        const bf16x8 a = as_bf16x8(av);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mma(a, as_bf16x8(wsm[(16 * t + m) * WS + tt * V + q]), acc[t]);
+      }
+    }
+    __syncthreads();
+  }
+  const int x0 = xb + 16 * wv;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int o = o0 + 16 * t + m;
+    if (o >= O) continue;
+    const float bo = bias ? gl(bias)[o] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int px = x0 + 4 * g + r;
+      if (px >= W) continue;
+      float v = acc[t][r] + bo;
+      if (relu) v = fmaxf(v, 0.0f);
+      const int64_t idx = (static_cast<int64_t>(row) * W + px) * O + o;
+      if (y_f32) glw(static_cast<float*>(y))[idx] = v;
+      else glw(static_cast<uint16_t*>(y))[idx] = f2bf(v);
+    }
+  }
+}
+
 // Partial weight gradients: part[z][o][tap][c] = sum over the pixels of row
 // group z of gy[p][o] x[p + shift(tap)][c] (laid out like the FP32 master
 // weights, [O][9][C], per group).  GEMM M = o, N = (tap, c) flattened as
@@ -539,7 +633,21 @@ extern "C" ss_status ss_nn_conv3x3(const void* x, int32_t N, int32_t H, int32_t 
   const unsigned gy = static_cast<unsigned>(N) * H;
   const auto* xi = static_cast<const uint16_t*>(x);
   const auto* wi = static_cast<const uint16_t*>(w);
-  if (O >= 64) {
+  if (C % 8 == 0 && Cp % 16 == 0) {  // operands staged in shared memory
+    const int nt = O >= 64 ? 4 : (O > 16 ? 2 : 1);
+    const dim3 grid(gx, gy, (O + 16 * nt - 1) / (16 * nt));
+#define SS_CONV_T(NT, CC) k_conv3x3_t<NT, CC><<<grid, block, 0, st>>>(xi, H, W, C, Cp, wi, bias, O, relu, y, y_f32)
+    if (Cp % 32 == 0) {
+      if (nt == 4) SS_CONV_T(4, 32);
+      else if (nt == 2) SS_CONV_T(2, 32);
+      else SS_CONV_T(1, 32);
+    } else {
+      if (nt == 4) SS_CONV_T(4, 16);
+      else if (nt == 2) SS_CONV_T(2, 16);
+      else SS_CONV_T(1, 16);
+    }
+#undef SS_CONV_T
+  } else if (O >= 64) {
     const dim3 grid(gx, gy, (O + 63) / 64);
     if (C % 8 == 0) k_conv3x3<4, true><<<grid, block, 0, st>>>(xi, H, W, C, Cp, wi, bias, O, relu, y, y_f32);
     else k_conv3x3<4, false><<<grid, block, 0, st>>>(xi, H, W, C, Cp, wi, bias, O, relu, y, y_f32);
