@@ -39,11 +39,12 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // kFormCols at a time; within one ray a column occurs once, and a barrier
 // separates rays, so every sum runs in ascending ray order (the result is
 // the same from run to run).  The rays' row ranges and a_ij are staged in
-// shared memory kFormRays at a time, and each thread loads its first entry
-// of the next ray before adding those of the current one.  Products of FP32
+// shared memory kFormRays at a time, and each thread's first entries of the
+// next rays are in flight while the current ray is added.  Products of FP32
 // values are exact in FP64.
 constexpr int kFormCols = 8192;
 constexpr int kFormRays = 256;
+constexpr int kFormAhead = 4;  // rays whose entries are loaded ahead
 constexpr int kFormThreads = 256;
 
 __global__ __launch_bounds__(kFormThreads) void k_form_b(ss_system sys, double* B, int64_t bs, double* c, int64_t vs) {
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(kFormThreads) void k_form_b(ss_system sys, double* 
   const float* vt = static_cast<const float*>(sys.val_t);
   const float* v = static_cast<const float*>(sys.val);
   const int64_t e0 = sys.col_ptr[j], e1 = sys.col_ptr[j + 1];
-  double cj = 0.0;  // thread 0
+  double cj = 0.0;  // the first wavefront
   for (int64_t c0 = 0; c0 <= j; c0 += kFormCols) {
     const int w = static_cast<int>(std::min<int64_t>(kFormCols, j + 1 - c0));
     for (int t = tid; t < w; t += kFormThreads) acc[t] = 0.0;
@@ -77,32 +78,57 @@ __global__ __launch_bounds__(kFormThreads) void k_form_b(ss_system sys, double* 
         rp[t] = static_cast<double>(sys.p[nv * i + h]);
       }
       __syncthreads();
-      if (c0 == 0 && tid == 0)
-        for (int t = 0; t < nr; ++t) cj += ra[t] * rp[t];
-      // entry tid of ray r, loaded one ray ahead
-      int64_t col = -1;
-      double val = 0.0;
-      if (tid < rl[0]) {
-        col = sys.col_idx[rs[0] + tid];
-        val = static_cast<double>(v[nv * (rs[0] + tid) + h]);
+      // c[j]: the first wavefront sums the batch's a_ij p_i, lane l taking
+      // rays l, l + 64, ... in order, then a butterfly across the lanes (a
+      // fixed order; partners add the same two values, so every lane holds
+      // the same sum) -- not one thread's serial loop, which the other
+      // wavefronts would wait for at the first barrier
+      if (c0 == 0 && tid < kWave) {
+        double s = 0.0;
+        for (int t = tid; t < nr; t += kWave) s += ra[t] * rp[t];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+        cj += s;
       }
-      for (int r = 0; r < nr; ++r) {
-        const double a = ra[r];
-        const int64_t b0 = rs[r];
-        const int len = rl[r];
-        const int64_t cur_col = col;
-        const double cur_val = val;
-        col = -1;
-        if (r + 1 < nr && tid < rl[r + 1]) {
-          col = sys.col_idx[rs[r + 1] + tid];
-          val = static_cast<double>(v[nv * (rs[r + 1] + tid) + h]);
+      // Entry tid of ray r is loaded kFormAhead rays ahead, into a ring of
+      // registers, raw (a position past the ray's end reads its first
+      // entry, which every ray through voxel j has; the value is dropped at
+      // use): the loads of the next rays are in flight while the current
+      // one is added, and nothing waits on them before their turn.
+      int32_t cq[kFormAhead];
+      float vq[kFormAhead];
+      auto fetch = [&](int r, int d) {
+        const int rr = r < nr ? r : nr - 1;
+        const int64_t e = rs[rr] + (tid < rl[rr] ? tid : 0);
+        cq[d] = sys.col_idx[e];
+        vq[d] = v[nv * e + h];
+      };
+      // issued in slot order, as in the loop (the loads complete in order,
+      // and the loop waits for slot d with the later slots still in flight)
+#pragma unroll
+      for (int d = 0; d < kFormAhead; ++d) {
+        fetch(d, d);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      for (int r0 = 0; r0 < nr; r0 += kFormAhead) {
+#pragma unroll
+        for (int d = 0; d < kFormAhead; ++d) {
+          // a group runs whole (a ray past the batch adds nothing), so that
+          // no exit in the middle makes the ring's registers be copied
+          const int r = r0 + d < nr ? r0 + d : nr - 1;
+          const double a = ra[r];
+          const int64_t b0 = rs[r];
+          const int len = r0 + d < nr ? rl[r] : 0;
+          const int64_t cur_col = cq[d];
+          if (tid < len && cur_col >= c0 && cur_col < c0 + w) acc[cur_col - c0] += a * static_cast<double>(vq[d]);
+          // refilled once read, so the slot keeps its registers
+          fetch(r0 + d + kFormAhead, d);
+          for (int k = tid + kFormThreads; k < len; k += kFormThreads) {
+            const int64_t cc = sys.col_idx[b0 + k];
+            if (cc >= c0 && cc < c0 + w) acc[cc - c0] += a * static_cast<double>(v[nv * (b0 + k) + h]);
+          }
+          __syncthreads();
         }
-        if (cur_col >= c0 && cur_col < c0 + w) acc[cur_col - c0] += a * cur_val;
-        for (int k = tid + kFormThreads; k < len; k += kFormThreads) {
-          const int64_t cc = sys.col_idx[b0 + k];
-          if (cc >= c0 && cc < c0 + w) acc[cc - c0] += a * static_cast<double>(v[nv * (b0 + k) + h]);
-        }
-        __syncthreads();
       }
     }
     for (int t = tid; t < w; t += kFormThreads) B[j * n + c0 + t] = acc[t];
@@ -224,72 +250,144 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_nt(const double* X, int64_t ld
 }
 
 // Cholesky of the diagonal block B[k0.., k0..] (size nb <= 64), padded to
-// 64 with the identity, and the inverse of its factor, by 4 wavefronts:
-// thread (t, q) (q = wavefront) holds columns 16q .. 16q+15 of row t of the
-// block (`row`) and of the identity (`r`), in registers.  Step j, one
-// barrier: the owners of column j put it in shared memory, and lane j of
-// every wavefront its part of row j of r (two buffers); then every thread
-// reads the pivot d and forms 1/sqrt(d) itself (the hardware estimate and
-// one Newton step: within an ulp or so), with L[c][j] = B[c][j] / sqrt(d)
-// subtracts L[t][j] L[c][j] from its entries c > j, and eliminates with row
-// j of L^{-1} (r_j / sqrt(d)) likewise, which turns r into L^{-1}.  The
-// inner loops are unrolled, so every register index is a constant.  L goes
-// back to B (lower part, nb x nb), L^{-1} to Linv (64 x 64 row-major, zero
-// above the diagonal).  A non-positive pivot sets *flag and is replaced by
-// 1 so that the rest stays finite.
-constexpr int kSeg = 16;
-__global__ __launch_bounds__(256) void k_potrf_diag(double* B, int64_t ld, int64_t k0, int nb, double* Linv,
-                                                    int32_t* flag, int64_t bs, int64_t ls) {
-  __shared__ double colj[2][kNb], xj[2][kNb];
+// 64 with the identity, and the inverse of its factor, by kDiagWaves
+// wavefronts.  The factorisation: thread (t, q) (q = wavefront) holds
+// columns kSeg q .. kSeg q + kSeg - 1 of row t of the block in registers.
+// Step j, one barrier: the owners of column j put its entries below the
+// diagonal in shared memory (zeros on and above it) and the pivot d in a
+// slot of its own; then every thread forms sc = B[t][j] / d (a reciprocal
+// estimate refined by one Newton step), which is zero for t <= j, and
+// subtracts sc B[c][j] from each of its entries -- no masks on this chain
+// of 64 dependent steps -- and the owners turn column j into L's
+// (B[t][j] / sqrt(d), from the reciprocal-square-root estimate and one
+// Newton step).  The inverse X = L^{-1} then comes from L in shared memory,
+// not from updates inside the chain (which doubled each step's work): the
+// four 16 x 16 diagonal blocks by forward substitution, one wavefront each
+// (lane = column, 1 / L_ii from the chain's 1/sqrt(d)), then two levels of
+// inv([A 0; C D]) = [X_A 0; -X_D C X_A  X_D] on the FP64 matrix cores
+// (16 x 16 blocks, then 32 x 32).  L goes back to B (lower part, nb x nb),
+// L^{-1} to Linv (64 x 64 row-major, zero above the diagonal).  A
+// non-positive pivot sets *flag and is replaced by 1 so that the rest stays
+// finite.
+constexpr int kDiagWaves = 8;
+constexpr int kSeg = kNb / kDiagWaves;
+constexpr int kDiagLd = kNb + 1;  // padded rows of L and X in shared memory
+constexpr int kDiagTd = 33;       // padded rows of the 32 x 32 product
+__global__ __launch_bounds__(64 * kDiagWaves) void k_potrf_diag(double* B, int64_t ld, int64_t k0, int nb,
+                                                               double* Linv, int32_t* flag, int64_t bs,
+                                                               int64_t ls) {
+  __shared__ double colj[2][kNb], dj[2], ipj[kNb];
+  __shared__ double Ls[kNb * kDiagLd], Xs[kNb * kDiagLd], Ts[32 * kDiagTd];
   const int t = lane_id(), q = wave_id();
   B += blockIdx.z * bs;  // the half
   Linv += blockIdx.z * ls;
-  double row[kSeg], r[kSeg];
+  double row[kSeg];
 #pragma unroll
   for (int cc = 0; cc < kSeg; ++cc) {
     const int c = kSeg * q + cc;
     row[cc] = (t < nb && c <= t) ? B[(k0 + t) * ld + k0 + c] : (c == t ? 1.0 : 0.0);
-    r[cc] = (c == t) ? 1.0 : 0.0;
   }
   bool bad = false;
   for (int s = 0; s < kNb / kSeg; ++s) {
 #pragma unroll
     for (int jj = 0; jj < kSeg; ++jj) {
       const int j = kSeg * s + jj, b = jj & 1;
-      if (q == s) colj[b][t] = row[jj];
-      if (t == j) {
-#pragma unroll
-        for (int cc = 0; cc < kSeg; ++cc) xj[b][kSeg * q + cc] = r[cc];
+      if (q == s) {
+        colj[b][t] = (t > j) ? row[jj] : 0.0;
+        if (t == j) dj[b] = row[jj];
       }
       __syncthreads();
-      double d = colj[b][j];
+      double d = dj[b];
       if (!(d > 0.0)) {
         bad = true;
         d = 1.0;
       }
+      double rd = __builtin_amdgcn_rcp(d);
+      rd = __builtin_fma(__builtin_fma(-d, rd, 1.0), rd, rd);
+      const double ct = colj[b][t];
+      const double sc = ct * rd;  // zero for t <= j
       double ip = __builtin_amdgcn_rsq(d);
       ip = ip * (1.5 - 0.5 * d * ip * ip);
-      const double lt = colj[b][t] * ip;  // L[t][j] for t > j
-      if (q == s) row[jj] = (t > j) ? lt : (t == j ? d * ip : 0.0);
-      // Branch-free: a zero multiplier leaves what must not change (rows
-      // t <= j, entries c <= j), so the shared-memory reads are not
-      // serialised behind per-entry branches.
-      const double sc = (t > j) ? lt * ip : 0.0;
-      const double rs = (t == j) ? ip : 1.0;
-#pragma unroll
-      for (int cc = 0; cc < kSeg; ++cc) {
-        const int c = kSeg * q + cc;
-        row[cc] -= (c > j ? sc : 0.0) * colj[b][c];
-        r[cc] = r[cc] * rs - sc * xj[b][c];
+      if (q == s) {
+        row[jj] = (t > j) ? ct * ip : (t == j ? d * ip : 0.0);
+        if (t == j) ipj[j] = ip;
       }
+#pragma unroll
+      for (int cc = 0; cc < kSeg; ++cc) row[cc] -= sc * colj[b][kSeg * q + cc];
     }
   }
   if (bad && t == 0 && q == 0) *flag = 1;
+  // entries above the diagonal took updates along the way: only c <= t is L
 #pragma unroll
   for (int cc = 0; cc < kSeg; ++cc) {
     const int c = kSeg * q + cc;
     if (t < nb && c <= t) B[(k0 + t) * ld + k0 + c] = row[cc];
-    Linv[t * kNb + c] = r[cc];
+    Ls[t * kDiagLd + c] = (c <= t) ? row[cc] : 0.0;
+  }
+  __syncthreads();
+  const int l16 = t & 15, g = t >> 4;
+  if (q < 4) {  // diagonal block q: lane l16 solves for column l16
+    const int o = 16 * q;
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double a = (r == l16) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < r; ++k) a -= Ls[(o + r) * kDiagLd + o + k] * x[k];
+      x[r] = a * ipj[o + r];
+    }
+    if (t < 16)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Xs[(o + r) * kDiagLd + o + l16] = x[r];
+  }
+  __syncthreads();
+  // 16 x 16 blocks (I, J) = (2q+1, 2q): X_IJ = -X_II (L_IJ X_JJ); the first
+  // product's accumulator element r holds rows 4r + g, which is the second
+  // product's k-chunk r as its B operand
+  if (q < 2) {
+    const int I = 2 * q + 1, J = 2 * q;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ls[(16 * I + l16) * kDiagLd + 16 * J + 4 * kc + g],
+                                                 Xs[(16 * J + 4 * kc + g) * kDiagLd + 16 * J + l16], acc, 0, 0, 0);
+    f64x4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[(16 * I + l16) * kDiagLd + 16 * I + 4 * r + g], acc[r], x, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Xs[(16 * I + 4 * r + g) * kDiagLd + 16 * J + l16] = -x[r];
+  }
+  __syncthreads();
+  // 32 x 32 level: T = C X_A (C = L[32:64, 0:32]), tile (I2, J2) per wavefront
+  const int I2 = 2 + (q >> 1), J2 = q & 1;
+  if (q < 4) {
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int K = J2; K < 2; ++K)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ls[(16 * I2 + l16) * kDiagLd + 16 * K + 4 * kc + g],
+                                                   Xs[(16 * K + 4 * kc + g) * kDiagLd + 16 * J2 + l16], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ts[(16 * (I2 - 2) + 4 * r + g) * kDiagTd + 16 * J2 + l16] = acc[r];
+  }
+  __syncthreads();
+  // X[I2][J2] = -sum over K = 2 .. I2 of X_D[I2][K] T[K][J2]
+  if (q < 4) {
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int K = 2; K <= I2; ++K)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[(16 * I2 + l16) * kDiagLd + 16 * K + 4 * kc + g],
+                                                   Ts[(16 * (K - 2) + 4 * kc + g) * kDiagTd + 16 * J2 + l16], acc,
+                                                   0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Xs[(16 * I2 + 4 * r + g) * kDiagLd + 16 * J2 + l16] = -acc[r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNb * kNb; e += 64 * kDiagWaves) {
+    const int i = e / kNb, c = e % kNb;
+    Linv[e] = (c <= i) ? Xs[i * kDiagLd + c] : 0.0;
   }
 }
 
@@ -575,7 +673,7 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
     for (int64_t k0 = K0; k0 < K0 + W; k0 += kNb) {
       const int nb = static_cast<int>(std::min<int64_t>(kNb, K0 + W - k0));
       double* Lk = Linv + (k0 / kNb) * kNb * kNb;
-      k_potrf_diag<<<dim3(1, 1, nv), 256, 0, st>>>(B, n, k0, nb, Lk, flag, bs, ls);
+      k_potrf_diag<<<dim3(1, 1, nv), 64 * kDiagWaves, 0, st>>>(B, n, k0, nb, Lk, flag, bs, ls);
       const int64_t below = n - k0 - nb;
       if (below <= 0) continue;  // nb < 64 only for the last block
       double* P = B + (k0 + nb) * n + k0;
