@@ -29,6 +29,7 @@ constexpr int kNb = 64;      // Cholesky block and GEMM tile
 constexpr int kPanel = 256;  // columns per trailing update
 constexpr int kTrail = 128;      // tile of the trailing update
 constexpr int kTrailWaves = 8;   // wavefronts per trailing-update block
+constexpr int64_t kNearSmall = 2048;  // rows below which the near update takes 64 x 64 tiles
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -690,8 +691,14 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
       double* Q = B + (K0 + W) * n + K0;
       const int64_t W1 = std::min<int64_t>(kPanel, rest);
       if (p >= 1) SS_HIP_TRY(hipStreamWaitEvent(st, evU[p - 1], 0));
-      k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(W1, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
-          Q, n, Q, n, Q + W, n, rest, W1, W, -1.0, 1.0, 1, bs, bs, bs);
+      // the near update is on the chain: where it is short, smaller tiles
+      // (four times the blocks) finish it sooner
+      if (rest <= kNearSmall)
+        k_gemm_nt<kNb, 4><<<dim3(tiles(rest, kNb), tiles(W1, kNb), nv), 256, 0, st>>>(Q, n, Q, n, Q + W, n, rest, W1, W,
+                                                                                   -1.0, 1.0, 1, bs, bs, bs);
+      else
+        k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(W1, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
+            Q, n, Q, n, Q + W, n, rest, W1, W, -1.0, 1.0, 1, bs, bs, bs);
       const int64_t far = rest - W1;
       if (far > 0) {
         SS_HIP_TRY(hipStreamWaitEvent(sb, evF[p], 0));
