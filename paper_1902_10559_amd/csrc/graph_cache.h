@@ -74,6 +74,17 @@ class GraphCache {
     return SS_OK;
   }
 
+  // Destroys an entry that this caller acquired and never launched (its
+  // capture did not complete as intended).
+  void drop(const Key& key) {
+    std::lock_guard<std::mutex> lock(mu_);
+    auto it = execs_.find(key);
+    if (it == execs_.end()) return;
+    (void)hipEventDestroy(it->second.done);
+    (void)hipGraphExecDestroy(it->second.exec);
+    execs_.erase(it);
+  }
+
   // Ends a solve's use of its graph; `st` is the stream it was launched on.
   void release(GraphEntry* e, hipStream_t st) {
     std::lock_guard<std::mutex> lock(mu_);

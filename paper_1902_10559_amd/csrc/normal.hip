@@ -17,9 +17,11 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "device.h"
+#include "graph_cache.h"
 #include "internal.h"
 
 namespace ss {
@@ -48,7 +50,9 @@ constexpr int kFormRays = 256;
 constexpr int kFormAhead = 4;  // rays whose entries are loaded ahead
 constexpr int kFormThreads = 256;
 
-__global__ __launch_bounds__(kFormThreads) void k_form_b(ss_system sys, double* B, int64_t bs, double* c, int64_t vs) {
+__global__ __launch_bounds__(kFormThreads) void k_form_b(const ss_system* sysp, double* B, int64_t bs, double* c,
+                                                         int64_t vs) {
+  const ss_system sys = *sysp;
   __shared__ double acc[kFormCols];
   __shared__ int64_t rs[kFormRays];
   __shared__ int32_t rl[kFormRays];
@@ -523,6 +527,12 @@ __global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, i
 
 // f[j] = (f2 + f1) / 2, f[N-1-j] = (f2 - f1) / 2 (eq. (5)), or a copy for
 // a single system.
+// Clears the factorisation's failure flag (a kernel, not a memset, so
+// that the solve's graph holds kernels only).
+__global__ void k_clear_flag(int32_t* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+
 __global__ void k_recombine_f64(const double* h1, const double* h2, int64_t n, int nv, double* f) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -537,7 +547,7 @@ __global__ void k_recombine_f64(const double* h1, const double* h2, int64_t n, i
 // Per half h (blockIdx.z of every launch): B at b + h*bs, c, y, x at
 // c/y/x + h*vs, the inverted diagonal blocks at linv + h*ls (in doubles).
 struct NormalLayout {
-  size_t b, c, y, x, linv, flag, total;
+  size_t b, c, y, x, linv, flag, sysc, total;
   int64_t bs, vs, ls;
 };
 
@@ -563,6 +573,8 @@ NormalLayout normal_layout(const ss_system* sys) {
   o += al(sizeof(double) * static_cast<size_t>(L.ls) * nv);
   L.flag = o;
   o += 256;
+  L.sysc = o;  // a copy of the system's descriptor, read by the formation
+  o += al(sizeof(ss_system));
   L.total = o;
   return L;
 }
@@ -602,6 +614,23 @@ ss_status lookahead_resources(Lookahead& la, size_t events) {
     la.ev.push_back(e);
   }
   return SS_OK;
+}
+
+// Graphs of whole solves, one per device, workspace, image and shape.
+struct NormalKey {
+  int device;
+  const void* ws;
+  const double* f;
+  int64_t n;
+  int nvals;
+  bool operator<(const NormalKey& o) const {
+    return std::tie(device, ws, f, n, nvals) < std::tie(o.device, o.ws, o.f, o.n, o.nvals);
+  }
+};
+
+GraphCache<NormalKey>& normal_graphs() {
+  static auto* c = new GraphCache<NormalKey>(16);  // lives until process exit
+  return *c;
 }
 
 }  // namespace
@@ -649,87 +678,111 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
   hipEvent_t evFork = la.ev[static_cast<size_t>(2 * npanel)];
   hipStream_t sb = la.side;
 
-  SS_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
-  // Both halves go through every launch together (blockIdx.z = half): they
-  // are independent systems, so the latency-bound steps of the
-  // factorisation are shared between them.
-  k_form_b<<<dim3(static_cast<unsigned>(n), 1, nv), kFormThreads, 0, st>>>(*sys, B, bs, c, vs);
-  SS_HIP_TRY(hipEventRecord(evFork, st));
-  SS_HIP_TRY(hipStreamWaitEvent(sb, evFork, 0));
-  // Blocked right-looking Cholesky, lower, in place, with a look-ahead of
-  // one panel.  Panel p (kPanel columns) is factored on the caller's stream
-  // 64 columns at a time (diagonal block, panel solve as a product with
-  // L_kk^{-T}, update of the panel's remaining columns).  Its trailing update
-  // is cut in two: the next panel's columns (near), on the caller's stream,
-  // and everything to their right (far), on the second stream, where it
-  // runs while the next panel is factored.  Ordering: panel p waits for the
-  // far update of panel p-2 (the last one that touches its columns and has
-  // not been waited for); the near update of panel p waits for the far
-  // update of panel p-1 (both write panel p+1's columns); the far update of
-  // panel p waits for panel p's factor.
-  for (int64_t p = 0; p < npanel; ++p) {
-    const int64_t K0 = p * kPanel;
-    const int64_t W = std::min<int64_t>(kPanel, n - K0);
-    if (p >= 2) SS_HIP_TRY(hipStreamWaitEvent(st, evU[p - 2], 0));
-    for (int64_t k0 = K0; k0 < K0 + W; k0 += kNb) {
-      const int nb = static_cast<int>(std::min<int64_t>(kNb, K0 + W - k0));
-      double* Lk = Linv + (k0 / kNb) * kNb * kNb;
-      k_potrf_diag<<<dim3(1, 1, nv), 64 * kDiagWaves, 0, st>>>(B, n, k0, nb, Lk, flag, bs, ls);
-      const int64_t below = n - k0 - nb;
-      if (below <= 0) continue;  // nb < 64 only for the last block
-      double* P = B + (k0 + nb) * n + k0;
-      k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
-                                                                      bs, ls, bs);
-      const int64_t pw = K0 + W - (k0 + nb);
-      if (pw > 0)
-        k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
-            P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
-    }
-    SS_HIP_TRY(hipEventRecord(evF[p], st));
-    const int64_t rest = n - K0 - W;
-    if (rest > 0) {
-      double* Q = B + (K0 + W) * n + K0;
-      const int64_t W1 = std::min<int64_t>(kPanel, rest);
-      if (p >= 1) SS_HIP_TRY(hipStreamWaitEvent(st, evU[p - 1], 0));
-      // the near update is on the chain: where it is short, smaller tiles
-      // (four times the blocks) finish it sooner
-      if (rest <= kNearSmall)
-        k_gemm_nt<kNb, 4><<<dim3(tiles(rest, kNb), tiles(W1, kNb), nv), 256, 0, st>>>(Q, n, Q, n, Q + W, n, rest, W1, W,
-                                                                                   -1.0, 1.0, 1, bs, bs, bs);
-      else
-        k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(W1, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
-            Q, n, Q, n, Q + W, n, rest, W1, W, -1.0, 1.0, 1, bs, bs, bs);
-      const int64_t far = rest - W1;
-      if (far > 0) {
-        SS_HIP_TRY(hipStreamWaitEvent(sb, evF[p], 0));
-        double* Qf = Q + W1 * n;
-        k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(far, kTrail), tiles(far, kTrail), nv), 64 * kTrailWaves, 0, sb>>>(
-            Qf, n, Qf, n, Qf + W + W1, n, far, far, W, -1.0, 1.0, 1, bs, bs, bs);
+  // The whole solve (some 3 n/64 + 2 n/256 dependent launches on two
+  // streams) is captured once per shape and workspace and replayed as a
+  // graph: the chain's launches then follow each other without the host's
+  // per-launch gaps.  The system's arrays are read through a descriptor
+  // copied into the workspace before every replay, so a cached graph holds
+  // no pointer of the caller's system.
+  const ss_system* sysd = reinterpret_cast<const ss_system*>(ws + L.sysc);
+  const int nvals = sys->nvals;
+  auto enqueue = [&](hipStream_t st) -> ss_status {
+    k_clear_flag<<<1, 64, 0, st>>>(flag);
+    // Both halves go through every launch together (blockIdx.z = half): they
+    // are independent systems, so the latency-bound steps of the
+    // factorisation are shared between them.
+    k_form_b<<<dim3(static_cast<unsigned>(n), 1, nv), kFormThreads, 0, st>>>(sysd, B, bs, c, vs);
+    SS_HIP_TRY(hipEventRecord(evFork, st));
+    SS_HIP_TRY(hipStreamWaitEvent(sb, evFork, 0));
+    // Blocked right-looking Cholesky, lower, in place, with a look-ahead of
+    // one panel.  Panel p (kPanel columns) is factored on the caller's stream
+    // 64 columns at a time (diagonal block, panel solve as a product with
+    // L_kk^{-T}, update of the panel's remaining columns).  Its trailing update
+    // is cut in two: the next panel's columns (near), on the caller's stream,
+    // and everything to their right (far), on the second stream, where it
+    // runs while the next panel is factored.  Ordering: panel p waits for the
+    // far update of panel p-2 (the last one that touches its columns and has
+    // not been waited for); the near update of panel p waits for the far
+    // update of panel p-1 (both write panel p+1's columns); the far update of
+    // panel p waits for panel p's factor.
+    for (int64_t p = 0; p < npanel; ++p) {
+      const int64_t K0 = p * kPanel;
+      const int64_t W = std::min<int64_t>(kPanel, n - K0);
+      if (p >= 2) SS_HIP_TRY(hipStreamWaitEvent(st, evU[p - 2], 0));
+      for (int64_t k0 = K0; k0 < K0 + W; k0 += kNb) {
+        const int nb = static_cast<int>(std::min<int64_t>(kNb, K0 + W - k0));
+        double* Lk = Linv + (k0 / kNb) * kNb * kNb;
+        k_potrf_diag<<<dim3(1, 1, nv), 64 * kDiagWaves, 0, st>>>(B, n, k0, nb, Lk, flag, bs, ls);
+        const int64_t below = n - k0 - nb;
+        if (below <= 0) continue;  // nb < 64 only for the last block
+        double* P = B + (k0 + nb) * n + k0;
+        k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
+                                                                        bs, ls, bs);
+        const int64_t pw = K0 + W - (k0 + nb);
+        if (pw > 0)
+          k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
+              P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
       }
+      SS_HIP_TRY(hipEventRecord(evF[p], st));
+      const int64_t rest = n - K0 - W;
+      if (rest > 0) {
+        double* Q = B + (K0 + W) * n + K0;
+        const int64_t W1 = std::min<int64_t>(kPanel, rest);
+        if (p >= 1) SS_HIP_TRY(hipStreamWaitEvent(st, evU[p - 1], 0));
+        // the near update is on the chain: where it is short, smaller tiles
+        // (four times the blocks) finish it sooner
+        if (rest <= kNearSmall)
+          k_gemm_nt<kNb, 4><<<dim3(tiles(rest, kNb), tiles(W1, kNb), nv), 256, 0, st>>>(Q, n, Q, n, Q + W, n, rest, W1, W,
+                                                                                     -1.0, 1.0, 1, bs, bs, bs);
+        else
+          k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(W1, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
+              Q, n, Q, n, Q + W, n, rest, W1, W, -1.0, 1.0, 1, bs, bs, bs);
+        const int64_t far = rest - W1;
+        if (far > 0) {
+          SS_HIP_TRY(hipStreamWaitEvent(sb, evF[p], 0));
+          double* Qf = Q + W1 * n;
+          k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(far, kTrail), tiles(far, kTrail), nv), 64 * kTrailWaves, 0, sb>>>(
+              Qf, n, Qf, n, Qf + W + W1, n, far, far, W, -1.0, 1.0, 1, bs, bs, bs);
+        }
+      }
+      SS_HIP_TRY(hipEventRecord(evU[p], sb));
     }
-    SS_HIP_TRY(hipEventRecord(evU[p], sb));
+    SS_HIP_TRY(hipStreamWaitEvent(st, evU[npanel - 1], 0));
+    // L y = c, then L^T x = y, 64 rows a step
+    k_diag_fwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv, c, y, 0, static_cast<int>(std::min<int64_t>(kNb, n)), ls, vs);
+    for (int64_t k = 0; k + 1 < nt; ++k) {
+      const int64_t k0 = k * kNb;
+      k_fwd_step<<<dim3(blocks(n - k0 - kNb, kNb), 1, nv), 256, 0, st>>>(B, n, n, k0, Linv + (k + 1) * kNb * kNb, c, y,
+                                                                        bs, ls, vs);
+    }
+    {
+      const int64_t k0 = (nt - 1) * kNb;
+      k_diag_bwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv + (nt - 1) * kNb * kNb, y, x, k0,
+                                                 static_cast<int>(n - k0), ls, vs);
+    }
+    for (int64_t k = nt - 1; k >= 1; --k) {
+      const int64_t k0 = k * kNb;
+      const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
+      k_bwd_step<<<dim3(static_cast<unsigned>(k0 / kNb), 1, nv), 256, 0, st>>>(B, n, n, k0, nb,
+                                                                                Linv + (k - 1) * kNb * kNb, y, x, bs,
+                                                                                ls, vs);
+    }
+    k_recombine_f64<<<blocks(n, 256), 256, 0, st>>>(x, x + vs, n, nvals, f);
+    return hipGetLastError() == hipSuccess ? SS_OK : fail(SS_E_HIP, "ss_normal_solve: launch failed");
+  };
+  SS_HIP_TRY(hipMemcpyAsync(ws + L.sysc, sys, sizeof(ss_system), hipMemcpyHostToDevice, st));
+  const NormalKey key{dev, ws, f, n, nvals};
+  ss_status cap = SS_OK;
+  GraphEntry* g = nullptr;
+  auto capture = [&](hipStream_t cs) { cap = enqueue(cs); };
+  if (ss_status s = normal_graphs().acquire(key, dev, capture, &g)) return s;
+  if (cap != SS_OK) {
+    normal_graphs().drop(key);
+    return cap;
   }
-  SS_HIP_TRY(hipStreamWaitEvent(st, evU[npanel - 1], 0));
-  // L y = c, then L^T x = y, 64 rows a step
-  k_diag_fwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv, c, y, 0, static_cast<int>(std::min<int64_t>(kNb, n)), ls, vs);
-  for (int64_t k = 0; k + 1 < nt; ++k) {
-    const int64_t k0 = k * kNb;
-    k_fwd_step<<<dim3(blocks(n - k0 - kNb, kNb), 1, nv), 256, 0, st>>>(B, n, n, k0, Linv + (k + 1) * kNb * kNb, c, y,
-                                                                      bs, ls, vs);
-  }
-  {
-    const int64_t k0 = (nt - 1) * kNb;
-    k_diag_bwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv + (nt - 1) * kNb * kNb, y, x, k0,
-                                               static_cast<int>(n - k0), ls, vs);
-  }
-  for (int64_t k = nt - 1; k >= 1; --k) {
-    const int64_t k0 = k * kNb;
-    const int nb = static_cast<int>(std::min<int64_t>(kNb, n - k0));
-    k_bwd_step<<<dim3(static_cast<unsigned>(k0 / kNb), 1, nv), 256, 0, st>>>(B, n, n, k0, nb,
-                                                                              Linv + (k - 1) * kNb * kNb, y, x, bs,
-                                                                              ls, vs);
-  }
-  k_recombine_f64<<<blocks(n, 256), 256, 0, st>>>(x, x + vs, n, sys->nvals, f);
+  const hipError_t le = hipGraphLaunch(g->exec, st);
+  normal_graphs().release(g, st);
+  if (le != hipSuccess) return fail(SS_E_HIP, "ss_normal_solve: graph launch failed: %s", hipGetErrorString(le));
   SS_HIP_TRY(hipGetLastError());
   int32_t hflag = 0;
   SS_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st));
