@@ -114,3 +114,27 @@ def test_repeated_and_interleaved_solves_are_reproducible():
         got = _solve(A32, p32, True)
     torch.cuda.synchronize()
     assert np.array_equal(got.view(np.uint64), first[0].view(np.uint64))
+
+
+def test_replayed_solve_reads_the_current_system():
+    """A solve is captured once per shape, workspace and image and then
+    replayed: systems with the same n but other rays (m, entries, values),
+    solved in turn into the same output, each match their own oracle
+    solution, so a replay reads the system it is given."""
+    import torch
+    banner("normal equations replay with other systems")
+    from symm import random_symmetric_sparse
+    cases = []
+    for seed, M in [(51, 600), (52, 900)]:
+        rng = np.random.default_rng(seed)
+        A = random_symmetric_sparse(rng, M, 266, 0.3 if M == 600 else 0.2)
+        assert np.linalg.matrix_rank(A.toarray()) == 266
+        p = (A.astype(np.float64) @ rng.uniform(0, 1, 266)).astype(np.float32)
+        cases.append((A, p, _oracle_split(A, p)))
+    out = torch.empty(266, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        for A, p, want in cases:
+            Ad = device(A)
+            pd = torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).cuda()
+            got = to_np(native.normal_solve(native.fold(Ad, pd), out=out))
+            assert rel_l2(got, want) <= 1e-7
