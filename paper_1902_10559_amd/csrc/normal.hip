@@ -10,9 +10,10 @@
 // Steps per half: B = A^T A, lower triangle, and c = A^T p from the sparse
 // rows (row-wise sums over the rays through each voxel, in shared memory);
 // right-looking blocked Cholesky of B in place (64 x 64 diagonal blocks
-// factored in shared memory, panel solves, trailing updates by an FP64
-// matrix-core GEMM, v_mfma_f64_16x16x4f64); forward and back substitution,
-// block by block.
+// factored in registers, their inverses formed on the FP64 matrix cores,
+// panel solves, trailing updates by an FP64 matrix-core GEMM,
+// v_mfma_f64_16x16x4f64); forward and back substitution, block by block.
+// The whole solve is replayed from a captured graph.
 
 #include <algorithm>
 #include <cmath>
@@ -44,7 +45,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // the same from run to run).  The rays' row ranges and a_ij are staged in
 // shared memory kFormRays at a time, and each thread's first entries of the
 // next rays are in flight while the current ray is added.  Products of FP32
-// values are exact in FP64.
+// values are exact in FP64.  The system's descriptor is read from device
+// memory (a replayed solve reads the system of the current call).
 constexpr int kFormCols = 8192;
 constexpr int kFormRays = 256;
 constexpr int kFormAhead = 4;  // rays whose entries are loaded ahead
