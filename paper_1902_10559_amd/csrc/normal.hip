@@ -32,7 +32,7 @@ constexpr int kNb = 64;      // Cholesky block and GEMM tile
 constexpr int kPanel = 256;  // columns per trailing update
 constexpr int kTrail = 128;      // tile of the trailing update
 constexpr int kTrailWaves = 8;   // wavefronts per trailing-update block
-constexpr int64_t kNearSmall = 2048;  // rows below which the near update takes 64 x 64 tiles
+constexpr int64_t kNearSmall = 2048;  // rows below which trailing updates take 64 x 64 tiles
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -743,8 +743,12 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
         if (far > 0) {
           SS_HIP_TRY(hipStreamWaitEvent(sb, evF[p], 0));
           double* Qf = Q + W1 * n;
-          k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(far, kTrail), tiles(far, kTrail), nv), 64 * kTrailWaves, 0, sb>>>(
-              Qf, n, Qf, n, Qf + W + W1, n, far, far, W, -1.0, 1.0, 1, bs, bs, bs);
+          if (far <= kNearSmall)  // a short far update fills the chip only with the smaller tiles
+            k_gemm_nt<kNb, 4><<<dim3(tiles(far, kNb), tiles(far, kNb), nv), 256, 0, sb>>>(
+                Qf, n, Qf, n, Qf + W + W1, n, far, far, W, -1.0, 1.0, 1, bs, bs, bs);
+          else
+            k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(far, kTrail), tiles(far, kTrail), nv), 64 * kTrailWaves, 0,
+                                              sb>>>(Qf, n, Qf, n, Qf + W + W1, n, far, far, W, -1.0, 1.0, 1, bs, bs, bs);
         }
       }
       SS_HIP_TRY(hipEventRecord(evU[p], sb));
