@@ -32,7 +32,7 @@ constexpr int kNb = 64;      // Cholesky block and GEMM tile
 constexpr int kPanel = 256;  // columns per trailing update
 constexpr int kTrail = 128;      // tile of the trailing update
 constexpr int kTrailWaves = 8;   // wavefronts per trailing-update block
-constexpr int64_t kNearSmall = 2048;  // rows below which trailing updates take 64 x 64 tiles
+constexpr int64_t kNearSmall = 4096;  // rows below which trailing updates take 64 x 64 tiles
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
