@@ -138,3 +138,15 @@ def test_replayed_solve_reads_the_current_system():
             pd = torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).cuda()
             got = to_np(native.normal_solve(native.fold(Ad, pd), out=out))
             assert rel_l2(got, want) <= 1e-7
+
+
+def test_split_solve_with_large_trailing_updates():
+    """Halves of 4864 columns: the first panels' near and far trailing
+    updates span more than 4096 rows and take the 128 x 128 tiles (smaller
+    updates take 64 x 64 tiles, which the other tests cover)."""
+    banner("normal equations with 128 x 128 trailing tiles (halves of 4864)")
+    from symm import random_symmetric_sparse
+    rng = np.random.default_rng(61)
+    A = random_symmetric_sparse(rng, 19456, 9728, 0.01)
+    p = (A.astype(np.float64) @ rng.uniform(0, 1, 9728)).astype(np.float32)
+    assert rel_l2(_solve(A, p, True), _oracle_split(A, p)) <= 1e-7
