@@ -158,11 +158,14 @@ __global__ __launch_bounds__(kFormThreads) void k_form_b(const ss_system* sysp, 
 //   D[m][n]: m = g + 4 r (r = 0..3, the accumulator's element), n = l % 16
 // (rows interleaved by 4, unlike the 4 consecutive rows of the FP32 forms).
 constexpr int kKc = 16;
-template <int TM, int NW>
+template <int TM, int NW, bool HI = false>
 __global__ __launch_bounds__(NW * 64) void k_gemm_nt(const double* X, int64_t ldx, const double* Y, int64_t ldy,
                                                  double* C, int64_t ldc, int64_t nr, int64_t nc, int64_t K,
                                                  double alpha, double beta, int lower, int64_t xs_, int64_t ys_,
                                                  int64_t cs_) {
+  // HI: a launch on the factorisation's chain, whose waves share compute
+  // units with the concurrent far update's: they win instruction issue
+  if constexpr (HI) __builtin_amdgcn_s_setprio(3);
   constexpr int NT = NW * 64;                 // threads
   constexpr int WM = TM / 2, WN = 2 * TM / NW;  // this wave's sub-tile
   constexpr int MR = WM / 16, MC = WN / 16;   // 16 x 16 tiles per wave
@@ -283,6 +286,7 @@ constexpr int kDiagTd = 33;       // padded rows of the 32 x 32 product
 __global__ __launch_bounds__(64 * kDiagWaves) void k_potrf_diag(double* B, int64_t ld, int64_t k0, int nb,
                                                                double* Linv, int32_t* flag, int64_t bs,
                                                                int64_t ls) {
+  __builtin_amdgcn_s_setprio(3);  // on the chain: wins issue over the far update's waves
   __shared__ double colj[2][kNb], dj[2], ipj[kNb];
   __shared__ double Ls[kNb * kDiagLd], Xs[kNb * kDiagLd], Ts[32 * kDiagTd];
   const int t = lane_id(), q = wave_id();
@@ -718,11 +722,11 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
         const int64_t below = n - k0 - nb;
         if (below <= 0) continue;  // nb < 64 only for the last block
         double* P = B + (k0 + nb) * n + k0;
-        k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
+        k_gemm_nt<kNb, 4, true><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
                                                                         bs, ls, bs);
         const int64_t pw = K0 + W - (k0 + nb);
         if (pw > 0)
-          k_gemm_nt<kNb, 4><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
+          k_gemm_nt<kNb, 4, true><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
               P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
       }
       SS_HIP_TRY(hipEventRecord(evF[p], st));
@@ -734,10 +738,10 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
         // the near update is on the chain: where it is short, smaller tiles
         // (four times the blocks) finish it sooner
         if (rest <= kNearSmall)
-          k_gemm_nt<kNb, 4><<<dim3(tiles(rest, kNb), tiles(W1, kNb), nv), 256, 0, st>>>(Q, n, Q, n, Q + W, n, rest, W1, W,
+          k_gemm_nt<kNb, 4, true><<<dim3(tiles(rest, kNb), tiles(W1, kNb), nv), 256, 0, st>>>(Q, n, Q, n, Q + W, n, rest, W1, W,
                                                                                      -1.0, 1.0, 1, bs, bs, bs);
         else
-          k_gemm_nt<kTrail, kTrailWaves><<<dim3(tiles(rest, kTrail), tiles(W1, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
+          k_gemm_nt<kTrail, kTrailWaves, true><<<dim3(tiles(rest, kTrail), tiles(W1, kTrail), nv), 64 * kTrailWaves, 0, st>>>(
               Q, n, Q, n, Q + W, n, rest, W1, W, -1.0, 1.0, 1, bs, bs, bs);
         const int64_t far = rest - W1;
         if (far > 0) {
