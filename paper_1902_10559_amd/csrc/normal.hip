@@ -259,6 +259,79 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_nt(const double* X, int64_t ld
       }
 }
 
+// The chain's small products (K <= 64: the panel solve, times L_kk^{-T}, and
+// the in-panel update): C = beta C + alpha X Y^T on 64 x 64 tiles by four
+// wavefronts (a 32 x 32 quarter each, 2 x 2 matrix-core tiles), with all K
+// columns of the tile's X and Y rows loaded at once and staged k-major in
+// shared memory behind one barrier -- one memory latency per launch where
+// k_gemm_nt's chunks of kKc take K / kKc of them in sequence.  Same
+// arguments and conventions as k_gemm_nt (C may be X itself: every X load
+// precedes the barrier, every C store follows it).
+template <bool HI>
+__global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                                                    double* C, int64_t ldc, int64_t nr, int64_t nc, int64_t K,
+                                                    double alpha, double beta, int lower, int64_t xs_, int64_t ys_,
+                                                    int64_t cs_) {
+  if constexpr (HI) __builtin_amdgcn_s_setprio(3);
+  constexpr int TM = kNb, NT = 256, PER = TM * TM / NT, LD = TM + 1;
+  const int64_t ti = blockIdx.x, tj = blockIdx.y;
+  if (lower && tj > ti) return;
+  X += blockIdx.z * xs_;  // the half
+  Y += blockIdx.z * ys_;
+  C += blockIdx.z * cs_;
+  const int64_t r0 = ti * TM, c0 = tj * TM;
+  __shared__ double xs[TM * LD], ys[TM * LD];  // [k][row]
+  const int lane = lane_id(), w = wave_id(), g = lane / 16, l16 = lane % 16;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  // element e = tid + NT p: row e / TM, column k = e % TM (a row's K
+  // columns are read by consecutive threads)
+  double vx[PER], vy[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + NT * p, rr = e / TM, k = e % TM;
+    const int64_t xi = r0 + rr, yi = c0 + rr;
+    vx[p] = (xi < nr && k < K) ? X[xi * ldx + k] : 0.0;
+    vy[p] = (yi < nc && k < K) ? Y[yi * ldy + k] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + NT * p, rr = e / TM, k = e % TM;
+    xs[k * LD + rr] = vx[p];
+    ys[k * LD + rr] = vy[p];
+  }
+  __syncthreads();
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[a][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < TM; kk += 4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = xs[(kk + g) * LD + wr + 16 * a + l16];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) bv[q] = ys[(kk + g) * LD + wc + 16 * q + l16];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[q], acc[a][q], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = r0 + wr + 16 * a + g + 4 * r;
+        const int64_t j = c0 + wc + 16 * q + l16;
+        if (i < nr && j < nc && (!lower || j <= i)) {
+          double* cp = C + i * ldc + j;
+          *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[a][q][r];
+        }
+      }
+}
+
 // Cholesky of the diagonal block B[k0.., k0..] (size nb <= 64), padded to
 // 64 with the identity, and the inverse of its factor, by kDiagWaves
 // wavefronts.  The factorisation: thread (t, q) (q = wavefront) holds
@@ -722,11 +795,11 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
         const int64_t below = n - k0 - nb;
         if (below <= 0) continue;  // nb < 64 only for the last block
         double* P = B + (k0 + nb) * n + k0;
-        k_gemm_nt<kNb, 4, true><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
+        k_gemm_nt_k64<true><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
                                                                         bs, ls, bs);
         const int64_t pw = K0 + W - (k0 + nb);
         if (pw > 0)
-          k_gemm_nt<kNb, 4, true><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
+          k_gemm_nt_k64<true><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
               P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
       }
       SS_HIP_TRY(hipEventRecord(evF[p], st));
