@@ -243,7 +243,8 @@ def main():
         log(f"16-bit weights: {out['weights_16bit']}")
 
     # time to relative residuals 1e-2 and 1e-3 on the workload itself
-    # (capped at 10000 iterations): split vs unsplit FP32, and 16-bit weights
+    # (capped at 10000 and 20000 iterations): split vs unsplit FP32, and
+    # 16-bit weights
     ttr = {}
     ascending_order(slices, systems)
     if not args.no_ttr:
@@ -560,10 +561,10 @@ def dtype_record(args, slices, systems, opts, lanes, wdtype, iters, nnz_full, ti
             "roofline": roofline_of(kern, argparse.Namespace(**dict(vars(args), wdtype=wdtype)))}
 
 
-def workload_time_to_tol(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tols=(1e-2, 1e-3), cap=10000):
-    """workload_time_to_tol_one for each tolerance."""
+def workload_time_to_tol(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, caps=((1e-2, 10000), (1e-3, 20000))):
+    """workload_time_to_tol_one for each (tolerance, iteration cap)."""
     return {f"{tol:g}": workload_time_to_tol_one(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tol, cap)
-            for tol in tols}
+            for tol, cap in caps}
 
 
 def workload_time_to_tol_one(slices, systems, unsplit, low, opts, uopts, lanes, lam, dev, tol, cap):
