@@ -47,7 +47,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // next rays are in flight while the current ray is added.  Products of FP32
 // values are exact in FP64.  The system's descriptor is read from device
 // memory (a replayed solve reads the system of the current call).
-constexpr int kFormCols = 8192;
+constexpr int kFormCols = 4096;  // columns per pass: 39 KB of shared memory, four blocks per CU
 constexpr int kFormRays = 256;
 constexpr int kFormAhead = 4;  // rays whose entries are loaded ahead
 constexpr int kFormThreads = 256;
