@@ -707,12 +707,11 @@ def pick_line_order(args, slices, systems, sol, scratch):
 
 
 def ascending_order(slices, systems):
-    """Folds the systems back into ascending line order where the step
-    stored the interleaved one: the ordered-subset build needs each column's
-    rows ascending."""
+    """Folds the systems again, in ascending line order: the ordered-subset
+    build needs each column's rows ascending.  Always refolds: the arrays
+    may hold the order of the last configuration the search tried, whatever
+    the order fields say."""
     from paper_1902_10559_amd import native
-    if not any(S.row_lanes or S.col_lanes for S in systems):
-        return
     for S in systems:
         S.row_lanes = S.col_lanes = 0
     if len(slices) > 1:
