@@ -12,7 +12,9 @@
 // right-looking blocked Cholesky of B in place (64 x 64 diagonal blocks
 // factored in registers, their inverses formed on the FP64 matrix cores,
 // panel solves, trailing updates by an FP64 matrix-core GEMM,
-// v_mfma_f64_16x16x4f64); forward and back substitution, block by block.
+// v_mfma_f64_16x16x4f64), the forward substitution riding on the
+// factorisation's diagonal blocks and panel solves; back substitution, block
+// by block.
 // The whole solve is replayed from a captured graph.
 
 #include <algorithm>
@@ -271,7 +273,7 @@ template <bool HI>
 __global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ldx, const double* Y, int64_t ldy,
                                                     double* C, int64_t ldc, int64_t nr, int64_t nc, int64_t K,
                                                     double alpha, double beta, int lower, int64_t xs_, int64_t ys_,
-                                                    int64_t cs_) {
+                                                    int64_t cs_, const double* yv, double* cv, int64_t vs_) {
   if constexpr (HI) __builtin_amdgcn_s_setprio(3);
   constexpr int TM = kNb, NT = 256, PER = TM * TM / NT, LD = TM + 1;
   const int64_t ti = blockIdx.x, tj = blockIdx.y;
@@ -281,6 +283,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ld
   C += blockIdx.z * cs_;
   const int64_t r0 = ti * TM, c0 = tj * TM;
   __shared__ double xs[TM * LD], ys[TM * LD];  // [k][row]
+  __shared__ double ysub[TM], red[2][TM];
+  if (cv) {  // the forward substitution's update rides on the panel solve
+    yv += blockIdx.z * vs_;
+    cv += blockIdx.z * vs_;
+    if (threadIdx.x < TM) ysub[threadIdx.x] = yv[threadIdx.x];
+  }
   const int lane = lane_id(), w = wave_id(), g = lane / 16, l16 = lane % 16;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   // element e = tid + NT p: row e / TM, column k = e % TM (a row's K
@@ -330,6 +338,24 @@ __global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ld
           *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[a][q][r];
         }
       }
+  // with cv (the panel solve, C = X Y^T = the new rows of L's column block
+  // k): c[i] -= sum_j L[i][j] y_k[j] for the tile's rows, a lane's 2 x 16
+  // columns, then the 16 lanes of a row, then the two column halves
+  if (cv) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = acc[a][0][r] * ysub[wc + l16] + acc[a][1][r] * ysub[wc + 16 + l16];
+        v += __shfl_xor(v, 1, kWave);
+        v += __shfl_xor(v, 2, kWave);
+        v += __shfl_xor(v, 4, kWave);
+        v += __shfl_xor(v, 8, kWave);
+        if (l16 == 0) red[w & 1][wr + 16 * a + g + 4 * r] = v;
+      }
+    __syncthreads();
+    if (threadIdx.x < TM && r0 + threadIdx.x < nr) cv[r0 + threadIdx.x] -= red[0][threadIdx.x] + red[1][threadIdx.x];
+  }
 }
 
 // Cholesky of the diagonal block B[k0.., k0..] (size nb <= 64), padded to
@@ -358,13 +384,17 @@ constexpr int kDiagLd = kNb + 1;  // padded rows of L and X in shared memory
 constexpr int kDiagTd = 33;       // padded rows of the 32 x 32 product
 __global__ __launch_bounds__(64 * kDiagWaves) void k_potrf_diag(double* B, int64_t ld, int64_t k0, int nb,
                                                                double* Linv, int32_t* flag, int64_t bs,
-                                                               int64_t ls) {
+                                                               int64_t ls, const double* c, double* y, int64_t vs) {
   __builtin_amdgcn_s_setprio(3);  // on the chain: wins issue over the far update's waves
-  __shared__ double colj[2][kNb], dj[2], ipj[kNb];
+  __shared__ double colj[2][kNb], dj[2], ipj[kNb], cv[kNb];
   __shared__ double Ls[kNb * kDiagLd], Xs[kNb * kDiagLd], Ts[32 * kDiagTd];
   const int t = lane_id(), q = wave_id();
   B += blockIdx.z * bs;  // the half
   Linv += blockIdx.z * ls;
+  c += blockIdx.z * vs;
+  y += blockIdx.z * vs;
+  // c_k, final here: every earlier block's panel solve has updated it
+  if (threadIdx.x < kNb) cv[threadIdx.x] = threadIdx.x < static_cast<unsigned>(nb) ? c[k0 + threadIdx.x] : 0.0;
   double row[kSeg];
 #pragma unroll
   for (int cc = 0; cc < kSeg; ++cc) {
@@ -470,31 +500,32 @@ __global__ __launch_bounds__(64 * kDiagWaves) void k_potrf_diag(double* B, int64
   }
   __syncthreads();
   for (int e = threadIdx.x; e < kNb * kNb; e += 64 * kDiagWaves) {
-    const int i = e / kNb, c = e % kNb;
-    Linv[e] = (c <= i) ? Xs[i * kDiagLd + c] : 0.0;
+    const int i = e / kNb, cc = e % kNb;
+    Linv[e] = (cc <= i) ? Xs[i * kDiagLd + cc] : 0.0;
   }
-}
-
-// Substitutions.  y_k = L_kk^{-1} c_k for the first block, and x_k =
-// L_kk^{-T} y_k for the last, by one block each (thread (t, quarter) sums
-// 16 terms, the quarters added across adjacent lanes in a fixed order).
-__global__ __launch_bounds__(256) void k_diag_fwd(const double* Linv, const double* c, double* y, int64_t k0, int nb,
-                                                  int64_t ls, int64_t vs) {
-  Linv += blockIdx.z * ls;  // the half
-  c += blockIdx.z * vs;
-  y += blockIdx.z * vs;
-  const int t = threadIdx.x / 4, qp = (threadIdx.x % 4) * 16;
-  double a = 0.0;
+  // the forward substitution's block: y_k = L_kk^{-1} c_k, thread (row,
+  // part) summing 8 columns, the 8 parts added across adjacent lanes in a
+  // fixed order
+  {
+    const int r = threadIdx.x / 8, part = threadIdx.x % 8;
+    double a = 0.0;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int q = qp + u;
-    a += Linv[t * kNb + q] * (q < nb ? c[k0 + q] : 0.0);
+    for (int u = 0; u < 8; ++u) {
+      const int cc = 8 * part + u;  // Xs above the diagonal blocks was never written
+      if (cc <= r) a += Xs[r * kDiagLd + cc] * cv[cc];
+    }
+    a += __shfl_xor(a, 1, kWave);
+    a += __shfl_xor(a, 2, kWave);
+    a += __shfl_xor(a, 4, kWave);
+    if (part == 0 && r < nb) y[k0 + r] = a;
   }
-  a += __shfl_xor(a, 1, kWave);
-  a += __shfl_xor(a, 2, kWave);
-  if (threadIdx.x % 4 == 0 && t < nb) y[k0 + t] = a;
 }
 
+// Back substitution's first block: x_k = L_kk^{-T} y_k for the last block
+// (the four wavefronts' partial sums added in wavefront order).  The forward
+// substitution L y = c has no kernels of its own: each diagonal block's
+// kernel forms y_k = L_kk^{-1} c_k, and each panel solve subtracts
+// L[rows below, k] y_k from c.
 __global__ __launch_bounds__(256) void k_diag_bwd(const double* Linv, const double* y, double* x, int64_t k0, int nb,
                                                   int64_t ls, int64_t vs) {
   __shared__ double part[4][kNb];
@@ -511,49 +542,6 @@ __global__ __launch_bounds__(256) void k_diag_bwd(const double* Linv, const doub
   part[w][t] = a;
   __syncthreads();
   if (threadIdx.x < kNb && t < nb) x[k0 + t] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
-}
-
-// Forward substitution, block k of L y = c (k0 = 64 k, a full block with
-// rows below): with y_k already formed, c[i] -= sum_t L[i, k0+t] y_k[t] for
-// this block's 64 rows i >= k0 + 64 (thread (row, quarter) takes 16
-// consecutive t; quarters added across adjacent lanes in a fixed order).
-// Block 0's rows are block k+1's, which no later step touches: block 0 then
-// forms y_{k+1} = L^{-1}_{k+1,k+1} c_{k+1} for the next step, so no block
-// has to stage an inverse.
-__global__ __launch_bounds__(256) void k_fwd_step(const double* L, int64_t ld, int64_t n, int64_t k0,
-                                                  const double* Linv_next, double* c, double* y, int64_t bs,
-                                                  int64_t ls, int64_t vs) {
-  __shared__ double yk[kNb], cn[kNb];
-  const int tid = threadIdx.x;
-  L += blockIdx.z * bs;  // the half
-  Linv_next += blockIdx.z * ls;
-  c += blockIdx.z * vs;
-  y += blockIdx.z * vs;
-  if (tid < kNb) yk[tid] = y[k0 + tid];
-  __syncthreads();
-  const int r = tid / 4, qp = (tid % 4) * 16;
-  const int64_t i = k0 + kNb + static_cast<int64_t>(blockIdx.x) * kNb + r;
-  const int64_t ic = i < n ? i : n - 1;  // rows past n read a valid row; their result is dropped
-  double a = 0.0;
-#pragma unroll
-  for (int u = 0; u < 16; ++u) a += L[ic * ld + k0 + qp + u] * yk[qp + u];
-  a += __shfl_xor(a, 1, kWave);
-  a += __shfl_xor(a, 2, kWave);
-  double cnew = 0.0;
-  if (i < n) {
-    cnew = c[i] - a;
-    if (tid % 4 == 0) c[i] = cnew;
-  }
-  if (blockIdx.x != 0) return;
-  if (tid % 4 == 0) cn[r] = cnew;  // zero past n: the padded part of block k+1
-  __syncthreads();
-  const int nb_next = static_cast<int>(std::min<int64_t>(kNb, n - k0 - kNb));
-  double b = 0.0;
-#pragma unroll
-  for (int u = 0; u < 16; ++u) b += Linv_next[r * kNb + qp + u] * cn[qp + u];
-  b += __shfl_xor(b, 1, kWave);
-  b += __shfl_xor(b, 2, kWave);
-  if (tid % 4 == 0 && r < nb_next) y[k0 + kNb + r] = b;
 }
 
 // Back substitution, block k of L^T x = y (from the last block; k >= 1):
@@ -791,16 +779,16 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
       for (int64_t k0 = K0; k0 < K0 + W; k0 += kNb) {
         const int nb = static_cast<int>(std::min<int64_t>(kNb, K0 + W - k0));
         double* Lk = Linv + (k0 / kNb) * kNb * kNb;
-        k_potrf_diag<<<dim3(1, 1, nv), 64 * kDiagWaves, 0, st>>>(B, n, k0, nb, Lk, flag, bs, ls);
+        k_potrf_diag<<<dim3(1, 1, nv), 64 * kDiagWaves, 0, st>>>(B, n, k0, nb, Lk, flag, bs, ls, c, y, vs);
         const int64_t below = n - k0 - nb;
         if (below <= 0) continue;  // nb < 64 only for the last block
         double* P = B + (k0 + nb) * n + k0;
         k_gemm_nt_k64<true><<<dim3(tiles(below, kNb), 1, nv), 256, 0, st>>>(P, n, Lk, kNb, P, n, below, nb, nb, 1.0, 0.0, 0,
-                                                                        bs, ls, bs);
+                                                                        bs, ls, bs, y + k0, c + k0 + nb, vs);
         const int64_t pw = K0 + W - (k0 + nb);
         if (pw > 0)
           k_gemm_nt_k64<true><<<dim3(tiles(below, kNb), tiles(pw, kNb), nv), 256, 0, st>>>(
-              P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs);
+              P, n, P, n, P + nb, n, below, pw, nb, -1.0, 1.0, 1, bs, bs, bs, nullptr, nullptr, 0);
       }
       SS_HIP_TRY(hipEventRecord(evF[p], st));
       const int64_t rest = n - K0 - W;
@@ -831,13 +819,9 @@ extern "C" ss_status ss_normal_solve(const ss_system* sys, double* f, void* work
       SS_HIP_TRY(hipEventRecord(evU[p], sb));
     }
     SS_HIP_TRY(hipStreamWaitEvent(st, evU[npanel - 1], 0));
-    // L y = c, then L^T x = y, 64 rows a step
-    k_diag_fwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv, c, y, 0, static_cast<int>(std::min<int64_t>(kNb, n)), ls, vs);
-    for (int64_t k = 0; k + 1 < nt; ++k) {
-      const int64_t k0 = k * kNb;
-      k_fwd_step<<<dim3(blocks(n - k0 - kNb, kNb), 1, nv), 256, 0, st>>>(B, n, n, k0, Linv + (k + 1) * kNb * kNb, c, y,
-                                                                        bs, ls, vs);
-    }
+    // L y = c ran with the factorisation (each diagonal block forms its
+    // y_k, each panel solve updates c below it); now L^T x = y, 64 rows a
+    // step
     {
       const int64_t k0 = (nt - 1) * kNb;
       k_diag_bwd<<<dim3(1, 1, nv), 256, 0, st>>>(Linv + (nt - 1) * kNb * kNb, y, x, k0,
