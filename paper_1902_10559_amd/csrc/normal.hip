@@ -560,16 +560,27 @@ __global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, i
   y += blockIdx.z * vs;
   x += blockIdx.z * vs;
   if (tid < kNb) xk[tid] = tid < nb ? x[k0 + tid] : 0.0;
-  __syncthreads();
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNb + lane_id();  // < k0: the grid covers k0 rows
   const int w = wave_id();
-  double a = 0.0;
+  // the last block's inverse entries, loaded before they are needed (they
+  // do not depend on this step's results)
+  const bool last = blockIdx.x + 1 == gridDim.x;
+  double lv[16];
+  if (last) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lv[u] = Linv_prev[(16 * w + u) * kNb + lane_id()];
+  }
+  // this block's L entries too: in flight with x_k's loads, before the barrier
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNb + lane_id();  // < k0: the grid covers k0 rows
+  double lk[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    const int q = 16 * w + u;
-    const int64_t row = std::min<int64_t>(k0 + q, n - 1);  // past n: x_k is 0 there
-    a += L[row * ld + i] * xk[q];
+    const int64_t row = std::min<int64_t>(k0 + 16 * w + u, n - 1);  // past n: x_k is 0 there
+    lk[u] = L[row * ld + i];
   }
+  __syncthreads();
+  double a = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) a += lk[u] * xk[16 * w + u];
   part[w][lane_id()] = a;
   __syncthreads();
   double ynew = 0.0;
@@ -577,16 +588,13 @@ __global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, i
     ynew = y[i] - (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]);
     y[i] = ynew;
   }
-  if (blockIdx.x + 1 != gridDim.x) return;
+  if (!last) return;
   if (tid < kNb) yn[tid] = ynew;
   __syncthreads();
   const int t = lane_id();
   double b = 0.0;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int q = 16 * w + u;
-    b += Linv_prev[q * kNb + t] * yn[q];
-  }
+  for (int u = 0; u < 16; ++u) b += lv[u] * yn[16 * w + u];
   part[w][t] = b;
   __syncthreads();
   if (tid < kNb) x[k0 - kNb + t] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
