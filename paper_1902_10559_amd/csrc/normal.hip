@@ -301,6 +301,21 @@ __global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ld
     vx[p] = (xi < nr && k < K) ? X[xi * ldx + k] : 0.0;
     vy[p] = (yi < nc && k < K) ? Y[yi * ldy + k] : 0.0;
   }
+  // C's values too, where they are read (beta != 0): their loads are in
+  // flight with the operands' instead of after the products
+  double cold[2][2][4];
+  if (beta != 0.0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = r0 + wr + 16 * a + g + 4 * r;
+          const int64_t j = c0 + wc + 16 * q + l16;
+          cold[a][q][r] = (i < nr && j < nc && (!lower || j <= i)) ? C[i * ldc + j] : 0.0;
+        }
+  }
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int e = threadIdx.x + NT * p, rr = e / TM, k = e % TM;
@@ -333,10 +348,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ld
       for (int r = 0; r < 4; ++r) {
         const int64_t i = r0 + wr + 16 * a + g + 4 * r;
         const int64_t j = c0 + wc + 16 * q + l16;
-        if (i < nr && j < nc && (!lower || j <= i)) {
-          double* cp = C + i * ldc + j;
-          *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[a][q][r];
-        }
+        if (i < nr && j < nc && (!lower || j <= i))
+          C[i * ldc + j] = (beta == 0.0 ? 0.0 : beta * cold[a][q][r]) + alpha * acc[a][q][r];
       }
   // with cv (the panel solve, C = X Y^T = the new rows of L's column block
   // k): c[i] -= sum_j L[i][j] y_k[j] for the tile's rows, a lane's 2 x 16
