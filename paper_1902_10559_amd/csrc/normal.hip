@@ -284,10 +284,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ld
   const int64_t r0 = ti * TM, c0 = tj * TM;
   __shared__ double xs[TM * LD], ys[TM * LD];  // [k][row]
   __shared__ double ysub[TM], red[2][TM];
+  double cval = 0.0;
   if (cv) {  // the forward substitution's update rides on the panel solve
     yv += blockIdx.z * vs_;
     cv += blockIdx.z * vs_;
     if (threadIdx.x < TM) ysub[threadIdx.x] = yv[threadIdx.x];
+    if (threadIdx.x < TM && r0 + threadIdx.x < nr) cval = cv[r0 + threadIdx.x];  // read early, written last
   }
   const int lane = lane_id(), w = wave_id(), g = lane / 16, l16 = lane % 16;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_k64(const double* X, int64_t ld
         if (l16 == 0) red[w & 1][wr + 16 * a + g + 4 * r] = v;
       }
     __syncthreads();
-    if (threadIdx.x < TM && r0 + threadIdx.x < nr) cv[r0 + threadIdx.x] -= red[0][threadIdx.x] + red[1][threadIdx.x];
+    if (threadIdx.x < TM && r0 + threadIdx.x < nr) cv[r0 + threadIdx.x] = cval - (red[0][threadIdx.x] + red[1][threadIdx.x]);
   }
 }
 
@@ -582,8 +584,10 @@ __global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, i
 #pragma unroll
     for (int u = 0; u < 16; ++u) lv[u] = Linv_prev[(16 * w + u) * kNb + lane_id()];
   }
-  // this block's L entries too: in flight with x_k's loads, before the barrier
+  // this block's L entries and y values too: in flight with x_k's loads,
+  // before the barrier
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kNb + lane_id();  // < k0: the grid covers k0 rows
+  const double yold = tid < kNb ? y[i] : 0.0;
   double lk[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -598,7 +602,7 @@ __global__ __launch_bounds__(256) void k_bwd_step(const double* L, int64_t ld, i
   __syncthreads();
   double ynew = 0.0;
   if (tid < kNb) {
-    ynew = y[i] - (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]);
+    ynew = yold - (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]);
     y[i] = ynew;
   }
   if (!last) return;
