@@ -224,6 +224,25 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_nt(const double* X, int64_t ld
       ys[b][kk + 1][rr] = yr[p].y;
     }
   };
+  // on the chain (HI) with the 64 x 64 tiles, C's values are loaded first,
+  // so that the epilogue does not wait for them after the products (with
+  // the 128 x 128 tiles the registers this holds cost more than it gains)
+  constexpr bool kPre = HI && TM == 64;
+  double cold[MR][MC][4];
+  if constexpr (kPre) {
+    if (beta != 0.0) {
+#pragma unroll
+      for (int a = 0; a < MR; ++a)
+#pragma unroll
+        for (int q = 0; q < MC; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i = r0 + wr + 16 * a + g + 4 * r;
+            const int64_t j = c0 + wc + 16 * q + l16;
+            cold[a][q][r] = (i < nr && j < nc && (!lower || j <= i)) ? C[i * ldc + j] : 0.0;
+          }
+    }
+  }
   const int64_t nch = (K + kKc - 1) / kKc;
   load(0);
   store(0);
@@ -256,7 +275,12 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_nt(const double* X, int64_t ld
         const int64_t j = c0 + wc + 16 * q + l16;
         if (i < nr && j < nc && (!lower || j <= i)) {
           double* cp = C + i * ldc + j;
-          *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[a][q][r];
+          double cv0 = 0.0;
+          if (beta != 0.0) {
+            if constexpr (kPre) cv0 = cold[a][q][r];
+            else cv0 = *cp;
+          }
+          *cp = (beta == 0.0 ? 0.0 : beta * cv0) + alpha * acc[a][q][r];
         }
       }
 }
