@@ -984,39 +984,74 @@ __global__ __launch_bounds__(kWave* kBandWaves) __attribute__((amdgpu_waves_per_
 // The residual of the band-staged forward projection: per row, its
 // segments' sums added in band order (through the row's slots), r = p - q, z = r / W, and the block's FP64
 // partial of |r|^2; the first block of a system moves the iterate index on.
+// One wavefront per block of kFinThreads rows, kFinRows rows per lane: the
+// loads of a lane's rows (their slot ranges, then each row's first slot and
+// partial, p and 1/W) are issued together, so a block waits for the chain
+// offsets -> slot -> partial once rather than once per 64 rows (this kernel
+// is bound by that chain's latencies, not by its bytes).
+constexpr int kFinRows = kFinThreads / kWave;
+
 template <int NV>
-__global__ __launch_bounds__(kFinThreads) void k_band_fin(const SysDesc* __restrict__ table, int nsys,
-                                                          const Params* __restrict__ prm) {
-  __shared__ double red[kFinThreads / kWave];
+__global__ __launch_bounds__(kWave) void k_band_fin(const SysDesc* __restrict__ table, int nsys,
+                                                    const Params* __restrict__ prm) {
   const int s = sys_of<0>(prm, nsys, blockIdx.x);
   const SysDesc& S = table[s];
   if (*gl(&S.st->stop)) return;
   const int64_t lb = static_cast<int64_t>(blockIdx.x) - S.fp_block0;
-  const int64_t i = lb * kFinThreads + threadIdx.x;
+  const int lane = lane_id();
+  // Every load below is unconditional, from a clamped index that is always
+  // valid (row 0; slot and partial 0, which the layout always holds), and
+  // its value is dropped at use where it does not apply: conditional loads
+  // would make the compiler wait for them where the branches meet.
+  int64_t ii[kFinRows], ic[kFinRows];
+  uint32_t q0[kFinRows], q1[kFinRows];
+#pragma unroll
+  for (int rr = 0; rr < kFinRows; ++rr) {
+    ii[rr] = lb * kFinThreads + rr * kWave + lane;
+    ic[rr] = ii[rr] < S.m ? ii[rr] : 0;
+    q0[rr] = gl(S.fb_rseg)[ic[rr]];
+    q1[rr] = gl(S.fb_rseg)[ic[rr] + 1];
+  }
+  Vec<NV> pv[kFinRows], first[kFinRows];
+  float w[kFinRows];
+#pragma unroll
+  for (int rr = 0; rr < kFinRows; ++rr) {
+    pv[rr] = load_vec<NV>(S.p, ic[rr]);
+    w[rr] = gl(S.inv_row)[ic[rr]];
+  }
+  int32_t sl[kFinRows];
+#pragma unroll
+  for (int rr = 0; rr < kFinRows; ++rr) sl[rr] = gl(S.fb_slot)[q0[rr] < q1[rr] ? q0[rr] : 0u];
+#pragma unroll
+  for (int rr = 0; rr < kFinRows; ++rr) first[rr] = load_vec<NV>(S.fb_part, q0[rr] < q1[rr] ? sl[rr] : 0);
   double d = 0.0;
-  if (i < S.m) {
+#pragma unroll
+  for (int rr = 0; rr < kFinRows; ++rr) {
+    if (ii[rr] >= S.m) continue;
+    // the row's segments' sums in slot order, from 0 as before
     float acc[NV];
 #pragma unroll
     for (int h = 0; h < NV; ++h) acc[h] = 0.0f;
-    const uint32_t q0 = gl(S.fb_rseg)[i], q1 = gl(S.fb_rseg)[i + 1];
-    for (uint32_t q = q0; q < q1; ++q) {
-      const Vec<NV> pv = load_vec<NV>(S.fb_part, gl(S.fb_slot)[q]);
+    if (q0[rr] < q1[rr]) {
 #pragma unroll
-      for (int h = 0; h < NV; ++h) acc[h] += pv.v[h];
+      for (int h = 0; h < NV; ++h) acc[h] += first[rr].v[h];
     }
-    const Vec<NV> pv = load_vec<NV>(S.p, i);
-    const float w = gl(S.inv_row)[i];
+    for (uint32_t q = q0[rr] + 1; q < q1[rr]; ++q) {
+      const Vec<NV> v = load_vec<NV>(S.fb_part, gl(S.fb_slot)[q]);
+#pragma unroll
+      for (int h = 0; h < NV; ++h) acc[h] += v.v[h];
+    }
     Vec<NV> zv;
 #pragma unroll
     for (int h = 0; h < NV; ++h) {
-      const float r = pv.v[h] - acc[h];
-      zv.v[h] = r * w;
+      const float r = pv[rr].v[h] - acc[h];
+      zv.v[h] = r * w[rr];
       d += static_cast<double>(r) * static_cast<double>(r);
     }
-    store_vec<NV>(S.z, i, zv);
+    store_vec<NV>(S.z, ii[rr], zv);
   }
-  const double tot = block_sum<kFinThreads / kWave>(d, red);
-  if (threadIdx.x == 0) {
+  const double tot = group_sum<kWave>(d);
+  if (lane == 0) {
     glw(S.partials)[lb] = tot;
     SysState* st = S.st;
     if (lb == 0 && *gl(&st->pending)) {
@@ -1777,7 +1812,7 @@ void launch_band(const Cfg& c, const char* ws, const Layout& L, int nsys, const 
   const size_t lds = band_lds_bytes(NV, c.blg);
   hipExtLaunchKernelGGL(k_band_fp<NV, WT, P>, dim3(g.band_blocks), dim3(kWave * kBandWaves), lds, st, e.start,
                         e.mid0, 0, t, tiles, nt, prm, par);
-  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kFinThreads), 0, st, e.mid1, e.stop, 0, t, nsys, prm);
+  hipExtLaunchKernelGGL(k_band_fin<NV>, dim3(g.fp_blocks), dim3(kWave), 0, st, e.mid1, e.stop, 0, t, nsys, prm);
 }
 
 template <int NV, int WT, int P>
