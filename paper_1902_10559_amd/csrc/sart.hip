@@ -1065,6 +1065,7 @@ __global__ __launch_bounds__(kWave) void k_band_fin(const SysDesc* __restrict__ 
 // bitmap of the rows that the tile's columns touch, its runs of consecutive
 // set bits (first row, first LDS slot), and each entry's rank among the
 // set bits.  LDS: three arrays of ceil(m/32) words.
+constexpr int kPlanAhead = 4;  // entries per thread whose loads are in flight together
 __global__ __launch_bounds__(kStagedThreads) void k_bt_plan(const SysDesc* table, int nsys, const Params* prm) {
   extern __shared__ uint32_t bw[];
   constexpr int T = kStagedThreads;
@@ -1081,9 +1082,21 @@ __global__ __launch_bounds__(kStagedThreads) void k_bt_plan(const SysDesc* table
   for (int w = threadIdx.x; w < words; w += T) bm[w] = 0u;
   __syncthreads();
   const int64_t k0 = gl(S.col_ptr)[j0], k1 = gl(S.col_ptr)[j1];
-  for (int64_t k = k0 + threadIdx.x; k < k1; k += T) {
-    const int32_t r = gl(S.row_idx)[k];
-    if (r >= 0 && r < S.m) atomicOr(&bm[r >> 5], 1u << (r & 31));
+  // kPlanAhead entries per thread and pass, their loads issued together
+  // (from clamped indices, values past the tile dropped): the tile's
+  // entries cost a few memory latencies, not one per entry a thread takes
+  for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += static_cast<int64_t>(T) * kPlanAhead) {
+    int32_t rv[kPlanAhead];
+#pragma unroll
+    for (int u = 0; u < kPlanAhead; ++u) {
+      const int64_t k = kb + static_cast<int64_t>(u) * T;
+      rv[u] = gl(S.row_idx)[k < k1 ? k : k1 - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kPlanAhead; ++u) {
+      const int32_t r = rv[u];
+      if (kb + static_cast<int64_t>(u) * T < k1 && r >= 0 && r < S.m) atomicOr(&bm[r >> 5], 1u << (r & 31));
+    }
   }
   __syncthreads();
   // counts of set bits and of run starts per word, scanned over the words
@@ -1142,11 +1155,22 @@ __global__ __launch_bounds__(kStagedThreads) void k_bt_plan(const SysDesc* table
       ++ri;
     }
   }
-  for (int64_t k = k0 + threadIdx.x; k < k1; k += T) {
-    const int32_t r = gl(S.row_idx)[k];
-    const int32_t rr = r >= 0 && r < S.m ? r : 0;
-    const uint32_t rank = pre[rr >> 5] + __popc(bm[rr >> 5] & ((1u << (rr & 31)) - 1u));
-    glw(S.bt_idx)[k] = static_cast<uint16_t>(rank < rows ? rank : 0u);
+  for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += static_cast<int64_t>(T) * kPlanAhead) {
+    int32_t rv[kPlanAhead];
+#pragma unroll
+    for (int u = 0; u < kPlanAhead; ++u) {
+      const int64_t k = kb + static_cast<int64_t>(u) * T;
+      rv[u] = gl(S.row_idx)[k < k1 ? k : k1 - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kPlanAhead; ++u) {
+      const int64_t k = kb + static_cast<int64_t>(u) * T;
+      if (k >= k1) break;
+      const int32_t r = rv[u];
+      const int32_t rr = r >= 0 && r < S.m ? r : 0;
+      const uint32_t rank = pre[rr >> 5] + __popc(bm[rr >> 5] & ((1u << (rr & 31)) - 1u));
+      glw(S.bt_idx)[k] = static_cast<uint16_t>(rank < rows ? rank : 0u);
+    }
   }
 }
 
